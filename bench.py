@@ -1,0 +1,144 @@
+"""Benchmark of the live WDD per-frame update on one MI355X.
+
+A step is one pass of the whole hot path over one batch of frames: decode and
+project the batch onto the reduced basis, phase-weight and accumulate it into
+the spectrum, Wiener-reduce, inverse DFT, and copy the displayed object to the
+host.  Frames are resident in HBM before the timed region starts.  Prints one
+JSON line (rank 0, one GPU).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "live-update frames/s + p99 frame-to-snapshot latency; % MFMA/HBM peak"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="medium")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
+    return ap.parse_args()
+
+
+def workload_label(wl, n_freq):
+    kind = "uint16 Poisson %.0e e/frame" % wl.dose if wl.dose else "float32 noiseless"
+    return (f"{wl.name}: {wl.sy}x{wl.sx} raster scan, {wl.n}x{wl.n} detector ({kind}), aperture radius "
+            f"{wl.radius:g} px, K={wl.k} Hermite-Gauss functions, {n_freq} kept frequencies, "
+            f"batches of {wl.batch}, snapshot after every batch")
+
+
+def cpu_baseline(wl, frames, pos, seconds):
+    """The FP64 oracle's live path (same step: push one batch, then snapshot) on the host cores."""
+    import oracle.wdd as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    plan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=wl.aperture_amplitude(),
+                       defocus_edge=wl.defocus_edge, step=wl.step)
+    plan_s = time.perf_counter() - t0
+    live = O.Live(plan, "N")
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        b = (done * wl.batch) % len(pos)
+        live.push(frames[b:b + wl.batch], pos[b:b + wl.batch])
+        live.snapshot()
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or done * wl.batch >= len(pos):
+            break
+    return {"value": done * wl.batch / el, "unit": "frames/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{done} steps of {wl.batch} frames (push + snapshot each) of the same workload, FP64 NumPy, "
+                      f"{el:.1f} s; plan build {plan_s:.1f} s excluded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the method's multi-GPU "
+              f"sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2212_01309_amd as wdd
+    import synth
+
+    wl = synth.WORKLOADS[args.workload]
+    pos = synth.raster_positions(wl.sy, wl.sx)
+    t0 = time.perf_counter()
+    frames = wl.frames(pos)
+    gen_s = time.perf_counter() - t0
+    host = frames.view(np.int16) if frames.dtype == np.uint16 else frames
+    dev = torch.from_numpy(host).to("cuda")
+    torch.cuda.synchronize()
+    dtype = wdd.WDD_U16 if frames.dtype == np.uint16 else wdd.WDD_F32
+    plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch)
+    nb = len(pos) // wl.batch
+    batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
+
+    def step(i):
+        fr, ps = batches[i % nb]
+        plan.push(fr, ps)
+        plan.snapshot()
+
+    for i in range(args.warmup):
+        step(i)
+    if not args.no_profile:
+        plan.profile_enable(True)
+    torch.cuda.synchronize()
+    lat = np.empty(args.steps)
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t = time.perf_counter()
+        step(args.warmup + i)
+        lat[i] = time.perf_counter() - t
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = plan.profile_read() if not args.no_profile else None
+    n_freq, k = plan.n_freq, plan.k
+    plan.close()
+
+    fps = args.steps * wl.batch / elapsed
+    out = {
+        "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload_label(wl, n_freq), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
+                   "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype)},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+    }
+    if prof is not None:
+        acc_ms = prof["accumulate_ms"] / max(prof["accumulate_launches"], 1)
+        flops = 4.0 * n_freq * k * wl.batch          # complex phase x real coefficient, per (v, k, frame)
+        achieved = flops / (acc_ms * 1e-3) / 1e12
+        out["roofline"] = {"kernel": "k_accumulate", "bound": "mfma", "achieved": achieved,
+                           "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                           "traffic": None, "avg_us": acc_ms * 1e3}
+        out["stages_us"] = {s: prof[f"{s}_ms"] / max(prof[f"{s}_launches"], 1) * 1e3
+                            for s in ("project", "accumulate", "wiener", "display")}
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds)
+    out["generation_s"] = gen_s
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * wdd.h - C ABI of the live Wigner Distribution Deconvolution per-frame update
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Bangun et al., "Wigner Distribution Deconvolution Adaptation for
+ * Live Ptychography Reconstruction", arXiv 2212.01309):
+ *   - each detector frame I_s is projected onto a reduced Hermite-Gauss basis,
+ *     h_s = Phi^T vec(I_s)                          (Section 5, operator H);
+ *   - it is weighted by its scan-position phase and summed into the spectrum
+ *     A[v, k] += F[v, s] h_s[k],  F = F_y (x) F_x   (Section 6.1, eq. outer_prod;
+ *     modified-WDD algorithm, outer-product step);
+ *   - on demand the spectrum is Wiener-deconvolved by the probe's reduced
+ *     Wigner function, D[v] = sum_k W[v, k] A[v, k] (pre-computed Wiener filter
+ *     algorithm; modified-WDD algorithm, deconvolution and summation steps);
+ *   - and inverse transformed, O~ = conj(IDFT2(D)) / sqrt(|D[0]|)
+ *     (eq. extract; final step of the modified-WDD algorithm).
+ *
+ * Conventions (fixed readings of points the paper leaves open):
+ *   - detector frames are fftshifted (zero frequency at (ny/2, nx/2)), row-major
+ *     [ny][nx]; the aperture is centred there;
+ *   - scan positions are 0-based integer raster indices (y, x) on an sy x sx grid
+ *     with step `step_px` object pixels; repeated positions are summed;
+ *   - scan frequencies are 0-based DFT indices; the scan DFT is unitary;
+ *   - the K basis functions are psi_{n_y}(y) psi_{n_x}(x), n_y, n_x < L =
+ *     ceil(sqrt(K)), ordered by (max(n_y, n_x), n_y + n_x, n_y); psi_n are
+ *     L2-normalised Hermite functions at t = (i - n/2) / sigma, each sampled
+ *     column normalised on the grid; sigma defaults to R / sqrt(2L - 1);
+ *   - eps = eps_rel * max_{v,k} |Phi^T vec(Y_v)|^2;
+ *   - only frequencies whose shifted aperture overlaps the unshifted one on a
+ *     detector pixel are kept (Section 6.2); D is zero elsewhere.
+ *
+ * Memory: complex values are interleaved float pairs (re, im).  "Device"
+ * pointers are HIP device allocations on the plan's device; "host" pointers are
+ * ordinary host memory.  The caller owns every buffer it passes; the plan owns
+ * its device state.  All calls return a wdd_status; on failure
+ * wdd_last_error() returns a message for the calling thread.  A plan is used
+ * by one host thread at a time; distinct plans are independent.
+ */
+#ifndef WDD_H
+#define WDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WDD_OK = 0,
+  WDD_EINVAL = -1,   /* bad argument, size or option */
+  WDD_ENOMEM = -2,   /* host or device allocation failed */
+  WDD_ERANGE = -3,   /* a scan position outside the raster; nothing was applied */
+  WDD_EDEVICE = -4,  /* a HIP call failed; the plan is now unusable */
+  WDD_EBUSY = -5,    /* reserved */
+  WDD_ESTATE = -6    /* call not valid in the plan's state (e.g. after a device error) */
+} wdd_status;
+
+typedef enum { WDD_U16 = 0, WDD_F32 = 1 } wdd_dtype;
+
+typedef enum { WDD_FP32 = 0 } wdd_precision;
+
+/* Fourier-space probe: amplitude * 1[|u| <= radius] * exp(-i defocus_edge_rad |u|^2 / radius^2),
+ * u = detector pixel - (ny/2, nx/2).  Initial probe of the pre-computed Wiener
+ * filter algorithm (initialisation step 1), generated from the aperture radius. */
+typedef struct {
+  double radius_px;
+  double defocus_edge_rad;
+  double amplitude;
+} wdd_probe;
+
+/* Equispaced raster of sy x sx positions, `step_px` object pixels apart (Section 2). */
+typedef struct {
+  int32_t sy, sx;
+  double step_px;
+} wdd_scan;
+
+/* Detector of ny x nx pixels; frames arrive as `dtype` (uint16 counts or float32). */
+typedef struct {
+  int32_t ny, nx;
+  int32_t dtype; /* wdd_dtype */
+} wdd_detector;
+
+typedef struct {
+  double eps_rel;     /* Wiener regularisation relative to the largest |Y^B|^2; default 0.01 */
+  double sigma_px;    /* basis width in detector pixels; <= 0 selects radius / sqrt(2L - 1) */
+  int32_t precision;  /* wdd_precision; default WDD_FP32 */
+  int32_t max_batch;  /* largest n accepted by wdd_push; default 256 */
+} wdd_options;
+
+typedef struct {
+  int64_t n_freq;        /* number of kept scan frequencies */
+  int32_t k;             /* reduced basis size */
+  int32_t l;             /* 1D basis functions per axis */
+  double sigma_px;       /* basis width actually used */
+  double eps_abs;        /* absolute Wiener regularisation */
+  uint64_t frames_seen;  /* frames pushed since the plan was made or reset */
+  int64_t device_bytes;  /* device memory held by the plan */
+} wdd_plan_info;
+
+typedef struct wdd_tables_s* wdd_tables_t;
+typedef struct wdd_plan_s* wdd_plan_t;
+
+/* Message describing the last failure on the calling thread ("" if none).  The
+ * string stays valid until the thread's next wdd_* call. */
+const char* wdd_last_error(void);
+
+/* Fills *opts with the defaults listed in wdd_options. */
+wdd_status wdd_default_options(wdd_options* opts);
+
+/* ------------------------------------------------------------------------- */
+/* Host tables (FP64; no device needed).  The pre-computed quantities of the
+ * pre-computed Wiener filter algorithm: the kept frequencies (Section 6.2), the
+ * sampled Hermite functions (Section 5) and W_v = conj(Y^B_v) / (|Y^B_v|^2 + eps)
+ * with Y^B_v = Phi^T vec(Y_v), Y_v(q) = P(q) conj(P(q + q_v)).                  */
+
+/* Builds the tables.  K in [1, 256]; sy, sx in [1, 4096]; ny, nx in [1, 1024]
+ * with nx a multiple of 8.  `opts` may be NULL (defaults).  WDD_EINVAL on bad
+ * arguments, WDD_ENOMEM if the tables do not fit in host memory. */
+wdd_status wdd_tables_build(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
+                            int32_t K, const wdd_options* opts, wdd_tables_t* out);
+
+/* n_freq, k, l, sigma_px and eps_abs of the tables (other fields zero). */
+wdd_status wdd_tables_info(wdd_tables_t t, wdd_plan_info* info);
+
+/* Copies the tables to host arrays; any pointer may be NULL to skip it.
+ *   freqs  int32  [n_freq][2]   (v_y, v_x), sorted by v_y then v_x; (0, 0) first
+ *   psi_y  double [ny][l]       sampled, grid-normalised Hermite functions
+ *   psi_x  double [nx][l]
+ *   pairs  int32  [k][2]        (n_y, n_x) of each basis function
+ *   w      double [n_freq][k][2] Wiener filter (re, im)                         */
+wdd_status wdd_tables_export(wdd_tables_t t, int32_t* freqs, double* psi_y, double* psi_x,
+                             int32_t* pairs, double* w);
+
+wdd_status wdd_tables_free(wdd_tables_t t);
+
+/* ------------------------------------------------------------------------- */
+/* Live reconstruction on the current HIP device.                            */
+
+/* Creates a plan: builds the host tables, uploads them (FP32), zeroes the
+ * spectrum.  `hip_stream` is the hipStream_t all work is ordered on; NULL makes
+ * the plan create its own stream.  WDD_EINVAL / WDD_ENOMEM / WDD_EDEVICE. */
+wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
+                           int32_t K, const wdd_options* opts, void* hip_stream, wdd_plan_t* out);
+
+/* Adds n frames (modified-WDD algorithm, loop body): projection, phase weighting
+ * and accumulation of the spectrum.
+ *   frames  n x ny x nx values of the detector dtype; device memory if
+ *           frames_on_device != 0 (must stay valid until the work completes:
+ *           wdd_sync or the next wdd_snapshot), else host memory (copied before
+ *           the call returns).
+ *   pos_yx  host int32 [n][2] scan indices.
+ * Asynchronous on the plan stream.  n = 0 is a no-op.  WDD_EINVAL if n < 0 or
+ * n > max_batch; WDD_ERANGE if any position is outside the raster, in which case
+ * no frame of the call is applied. */
+wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
+                    int32_t frames_on_device);
+
+/* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
+ * conjugation and normalisation (eq. extract).  Writes sy x sx complex values
+ * (interleaved float, row-major [y][x]) to `out` (device memory if
+ * out_on_device != 0, else host memory).  Blocks until `out` is written.
+ * Object pixel mapping: out[y][x] is the object at scan position (y, x) shifted
+ * by the probe's centre (ny/2, nx/2) within its window.  frames_seen may be NULL. */
+wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen);
+
+/* Inspection (blocking): the Wiener-reduced spectrum D on the kept frequencies,
+ * n_freq complex values, as computed by the last wdd_snapshot. */
+wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device);
+
+/* Inspection (blocking): the accumulated spectrum A, n_freq x k complex values. */
+wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device);
+
+/* Inspection (blocking): the projections h of the last pushed batch, n x k floats
+ * (n = size of that batch). */
+wdd_status wdd_get_projection(wdd_plan_t p, float* h_out, int32_t on_device);
+
+wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info);
+
+/* Per-stage device time, measured with HIP events recorded on the plan stream
+ * around each kernel launch while profiling is enabled. */
+typedef struct {
+  double project_ms;     /* frame decode + basis projection */
+  double accumulate_ms;  /* phase weighting + spectrum accumulation */
+  double wiener_ms;      /* Wiener reduction */
+  double display_ms;     /* inverse DFT, conjugation and normalisation */
+  int64_t project_launches, accumulate_launches, wiener_launches, display_launches;
+} wdd_profile;
+
+/* Turns stage timing on (on != 0) or off and zeroes the totals. */
+wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on);
+
+/* Totals since profiling was enabled (blocks until the timed work has finished). */
+wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);
+
+/* Zeroes the spectrum and the frame count (asynchronous). */
+wdd_status wdd_reset(wdd_plan_t p);
+
+/* Waits for all work queued on the plan stream. */
+wdd_status wdd_sync(wdd_plan_t p);
+
+/* Releases the plan (waits for its work first).  NULL is accepted. */
+wdd_status wdd_plan_destroy(wdd_plan_t p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDD_H */

@@ -212,26 +212,45 @@ class Plan:
         return len(self.freqs)
 
 
+def reduce_hg(a: np.ndarray, psi_y: np.ndarray, psi_x: np.ndarray, pairs: np.ndarray) -> np.ndarray:
+    """Phi^T vec(A) for the HG basis through the paper's operator H(A) = psi_x^T A^T psi_y
+    (Section 5): entry (n_x, n_y) of H(A) is the coefficient of psi_{n_y}(y) psi_{n_x}(x).
+    `a` may hold a stack of matrices [..., ny, nx]."""
+    red_t = np.swapaxes(psi_y.T @ (a @ psi_x), -1, -2)   # H(A) = psi_x^T A^T psi_y
+    return red_t[..., pairs[:, 1], pairs[:, 0]]
+
+
 def make_plan(sy: int, sx: int, ny: int, nx: int, radius: float, k: Optional[int] = None,
               amplitude: float = 1.0, defocus_edge: float = 0.0, step: float = 1.0,
               eps_rel: float = 0.01, sigma: Optional[float] = None, phi: Optional[np.ndarray] = None,
-              freqs: Optional[np.ndarray] = None) -> Plan:
+              freqs: Optional[np.ndarray] = None, eps_abs: Optional[float] = None, chunk: int = 256) -> Plan:
     """Frequencies with overlap, the reduced probe Wigner functions and the Wiener filter.
 
     For each kept v: Y_v (probe autocorrelation at q + q_v), its reduction
-    Y^B_v = Phi^T vec(Y_v), and W_v = conj(Y^B_v) / (|Y^B_v|^2 + eps).
+    Y^B_v = Phi^T vec(Y_v), and W_v = conj(Y^B_v) / (|Y^B_v|^2 + eps)
+    (pre-computed Wiener filter algorithm).  `freqs` restricts the plan to a
+    subset of the kept frequencies; `eps_abs` then supplies the regularisation
+    of the full set (it is a maximum over all kept v).
     """
-    if phi is None:
+    hg = phi is None
+    if hg:
         if sigma is None:
             sigma = default_sigma(radius, k)
         phi = hg_basis(ny, nx, k, sigma)
+        lsz = basis_size_1d(k)
+        psi_y, psi_x, pairs = sampled_hermite(ny, lsz, sigma), sampled_hermite(nx, lsz, sigma), basis_order(k)
     if freqs is None:
         freqs = nonzero_frequencies(sy, sx, ny, nx, radius, step)
     yb = np.empty((len(freqs), phi.shape[1]), dtype=np.complex128)
-    for i, (vy, vx) in enumerate(freqs):
-        y = probe_wigner(int(vy), int(vx), sy, sx, ny, nx, radius, amplitude, defocus_edge, step)
-        yb[i] = phi.T @ y.ravel()
-    eps_abs = eps_rel * float(np.max(np.abs(yb) ** 2))
+    for c0 in range(0, len(freqs), chunk):
+        ys = np.stack([probe_wigner(int(vy), int(vx), sy, sx, ny, nx, radius, amplitude, defocus_edge, step)
+                       for vy, vx in freqs[c0:c0 + chunk]])
+        if hg:
+            yb[c0:c0 + chunk] = reduce_hg(ys, psi_y, psi_x, pairs)
+        else:
+            yb[c0:c0 + chunk] = ys.reshape(len(ys), -1) @ phi
+    if eps_abs is None:
+        eps_abs = eps_rel * float(np.max(np.abs(yb) ** 2))
     w = np.conj(yb) / (np.abs(yb) ** 2 + eps_abs)
     return Plan(sy, sx, ny, nx, radius, amplitude, defocus_edge, step, eps_rel, freqs, phi, yb, eps_abs, w)
 

@@ -1,0 +1,291 @@
+"""Python binding of libwdd, the live WDD per-frame update for MI355X.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  Device buffers are passed as torch tensors on the GPU (their data
+pointers), host buffers as numpy arrays.  The library must have been built
+(``paper_2212_01309_amd.build.build_library()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libwdd.so")
+_lib: Optional[ctypes.CDLL] = None
+
+WDD_OK, WDD_EINVAL, WDD_ENOMEM, WDD_ERANGE, WDD_EDEVICE, WDD_EBUSY, WDD_ESTATE = 0, -1, -2, -3, -4, -5, -6
+WDD_U16, WDD_F32 = 0, 1
+WDD_FP32 = 0
+
+_STATUS_NAMES = {0: "WDD_OK", -1: "WDD_EINVAL", -2: "WDD_ENOMEM", -3: "WDD_ERANGE", -4: "WDD_EDEVICE",
+                 -5: "WDD_EBUSY", -6: "WDD_ESTATE"}
+
+
+class WddError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Probe(ctypes.Structure):
+    _fields_ = [("radius_px", ctypes.c_double), ("defocus_edge_rad", ctypes.c_double), ("amplitude", ctypes.c_double)]
+
+
+class Scan(ctypes.Structure):
+    _fields_ = [("sy", ctypes.c_int32), ("sx", ctypes.c_int32), ("step_px", ctypes.c_double)]
+
+
+class Detector(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps_rel", ctypes.c_double), ("sigma_px", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_freq", ctypes.c_int64), ("k", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("sigma_px", ctypes.c_double), ("eps_abs", ctypes.c_double), ("frames_seen", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("project_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double), ("wiener_ms", ctypes.c_double),
+                ("display_ms", ctypes.c_double), ("project_launches", ctypes.c_int64),
+                ("accumulate_launches", ctypes.c_int64), ("wiener_launches", ctypes.c_int64),
+                ("display_launches", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "wdd_last_error": (ctypes.c_char_p, []),
+    "wdd_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
+    "wdd_tables_build": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
+                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "wdd_tables_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
+    "wdd_tables_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "wdd_tables_free": (ctypes.c_int, [_P]),
+    "wdd_plan_create": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
+                                       ctypes.c_int32, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "wdd_push": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
+    "wdd_snapshot": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "wdd_get_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_get_accumulator": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_get_projection": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
+    "wdd_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "wdd_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
+    "wdd_reset": (ctypes.c_int, [_P]),
+    "wdd_sync": (ctypes.c_int, [_P]),
+    "wdd_plan_destroy": (ctypes.c_int, [_P]),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library() -> ctypes.CDLL:
+    """Loads libwdd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2212_01309_amd.build.build_library()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int) -> None:
+    if code != WDD_OK:
+        msg = load_library().wdd_last_error().decode(errors="replace")
+        raise WddError(code, msg)
+
+
+def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32) -> Options:
+    o = Options()
+    _check(load_library().wdd_default_options(ctypes.byref(o)))
+    o.eps_rel, o.sigma_px, o.max_batch, o.precision = eps_rel, sigma_px, max_batch, precision
+    return o
+
+
+def _is_device_tensor(x) -> bool:
+    return hasattr(x, "data_ptr") and hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _host_array(x, dtype) -> np.ndarray:
+    if hasattr(x, "numpy"):
+        x = x.numpy()
+    return np.ascontiguousarray(x, dtype=dtype)
+
+
+class Tables:
+    """FP64 host tables of a geometry (kept frequencies, basis, Wiener filter)."""
+
+    def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, defocus: float = 0.0,
+                 amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01, sigma: float = 0.0,
+                 dtype: int = WDD_U16):
+        lib = load_library()
+        self._h = _P()
+        _check(lib.wdd_tables_build(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
+                                    ctypes.byref(Detector(ny, nx, dtype)), k,
+                                    ctypes.byref(_options(eps_rel, sigma, 256)), ctypes.byref(self._h)))
+        info = PlanInfo()
+        _check(lib.wdd_tables_info(self._h, ctypes.byref(info)))
+        self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
+        self.sigma, self.eps_abs = float(info.sigma_px), float(info.eps_abs)
+        self.ny, self.nx = ny, nx
+
+    def export(self):
+        """Returns (freqs [n,2] int32, psi_y [ny,l], psi_x [nx,l], pairs [k,2] int32, w [n,k] complex128)."""
+        freqs = np.zeros((self.n_freq, 2), np.int32)
+        psi_y = np.zeros((self.ny, self.l))
+        psi_x = np.zeros((self.nx, self.l))
+        pairs = np.zeros((self.k, 2), np.int32)
+        w = np.zeros((self.n_freq, self.k, 2))
+        _check(load_library().wdd_tables_export(self._h, freqs.ctypes.data, psi_y.ctypes.data, psi_x.ctypes.data,
+                                                pairs.ctypes.data, w.ctypes.data))
+        return freqs, psi_y, psi_x, pairs, w[..., 0] + 1j * w[..., 1]
+
+    def close(self):
+        if self._h:
+            load_library().wdd_tables_free(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A live reconstruction on the current HIP device (wdd_plan_create ... wdd_plan_destroy)."""
+
+    def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
+                 defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
+                 sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None):
+        lib = load_library()
+        self._h = _P()
+        self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
+        self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
+        _check(lib.wdd_plan_create(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
+                                   ctypes.byref(Detector(ny, nx, dtype)), k,
+                                   ctypes.byref(_options(eps_rel, sigma, max_batch)),
+                                   _P(stream) if stream else None, ctypes.byref(self._h)))
+        info = self.info()
+        self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
+        self._last_batch = 0
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self) -> None:
+        if self._h:
+            load_library().wdd_plan_destroy(self._h)
+            self._h = _P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> int:
+        return self._h.value or 0
+
+    def info(self) -> PlanInfo:
+        info = PlanInfo()
+        _check(load_library().wdd_plan_get_info(self._h, ctypes.byref(info)))
+        return info
+
+    # -- hot path ------------------------------------------------------------
+    def push(self, frames, positions) -> None:
+        """frames: [n, ny, nx] (torch GPU tensor or host array of the detector dtype);
+        positions: host int32 [n, 2] scan indices (y, x)."""
+        pos = _host_array(positions, np.int32).reshape(-1, 2)
+        n = pos.shape[0]
+        if _is_device_tensor(frames):
+            if frames.element_size() != np.dtype(self._np_dtype).itemsize:
+                raise ValueError("device frames have the wrong element size for the detector dtype")
+            if frames.numel() != n * self.ny * self.nx:
+                raise ValueError("frames and positions disagree in count or frame shape")
+            if not frames.is_contiguous():
+                raise ValueError("device frames must be contiguous")
+            ptr, on_dev, keep = frames.data_ptr(), 1, frames
+        else:
+            keep = _host_array(frames, self._np_dtype)
+            if keep.size != n * self.ny * self.nx:
+                raise ValueError("frames and positions disagree in count or frame shape")
+            ptr, on_dev = keep.ctypes.data, 0
+        _check(load_library().wdd_push(self._h, ptr, pos.ctypes.data, n, on_dev))
+        if n:
+            self._last_batch = n
+        del keep
+
+    def snapshot(self, out=None):
+        """Displayed estimate [sy, sx] complex64.  With `out` (a torch GPU tensor of
+        sy*sx complex64 or 2*sy*sx float32) it is written on the device and returned."""
+        seen = ctypes.c_uint64()
+        if out is not None and _is_device_tensor(out):
+            _check(load_library().wdd_snapshot(self._h, out.data_ptr(), 1, ctypes.byref(seen)))
+            return out
+        host = np.empty((self.sy, self.sx), np.complex64)
+        _check(load_library().wdd_snapshot(self._h, host.ctypes.data, 0, ctypes.byref(seen)))
+        return host
+
+    def spectrum(self) -> np.ndarray:
+        """D on the kept frequencies from the last snapshot, complex64 [n_freq]."""
+        d = np.empty(self.n_freq, np.complex64)
+        _check(load_library().wdd_get_spectrum(self._h, d.ctypes.data, 0))
+        return d
+
+    def accumulator(self) -> np.ndarray:
+        """A, complex64 [n_freq, k]."""
+        a = np.empty((self.n_freq, self.k), np.complex64)
+        _check(load_library().wdd_get_accumulator(self._h, a.ctypes.data, 0))
+        return a
+
+    def projection(self) -> np.ndarray:
+        """h of the last pushed batch, float32 [n, k]."""
+        h = np.empty((self._last_batch, self.k), np.float32)
+        _check(load_library().wdd_get_projection(self._h, h.ctypes.data, 0))
+        return h
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(load_library().wdd_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        pr = Profile()
+        _check(load_library().wdd_profile_read(self._h, ctypes.byref(pr)))
+        return {f: getattr(pr, f) for f, _ in Profile._fields_}
+
+    def reset(self) -> None:
+        _check(load_library().wdd_reset(self._h))
+        self._last_batch = 0
+
+    def sync(self) -> None:
+        _check(load_library().wdd_sync(self._h))
+
+
+def header_symbols(header: Optional[str] = None) -> Tuple[str, ...]:
+    """Names of the functions declared in include/wdd.h."""
+    import re
+    if header is None:
+        header = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "wdd.h")
+    text = open(header).read()
+    return tuple(sorted(set(re.findall(r"^\s*(?:wdd_status|const char\*)\s+(wdd_\w+)\s*\(", text, re.M))))

@@ -1,0 +1,479 @@
+// C ABI of the live WDD plan: device state, push and snapshot.
+//
+// Device layout of a plan (all on the plan's device):
+//   psi     float  [(ny + nx) * 16]     sampled Hermite functions, columns >= L zero
+//   kmap    int32  [kpad]               16 n_y(k) + n_x(k); -1 for padding columns
+//   freqs   int2   [n_freq_pad]         kept (v_y, v_x); padding rows (0, 0)
+//   w       float2 [n_freq_pad][kpad]   Wiener filter (padding rows/columns zero)
+//   acc     float2 [n_freq_pad][kpad]   accumulated spectrum A
+//   ty, tx  float2 [sy], [sx]           exp(-2 pi i m / S); tx carries 1/sqrt(sy sx)
+//   ey, ex  float2 [sy], [sx]           exp(-2 pi i m / S) for the display DFT
+//   h       float  [max_batch][kpad]    projections of the current batch
+//   pos     int2   [max_batch]          scan positions of the current batch
+//   frames  staging for host frames     [max_batch][ny][nx]
+//   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
+//   z, u, o float2 [sy * sx]            conj(D) grid, row-transformed grid, output
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "wdd_internal.h"
+
+namespace {
+
+constexpr int kRing = 4;  // pinned host staging slots for positions and frames
+
+struct wdd_plan_impl {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool failed = false;
+  int32_t sy = 0, sx = 0, ny = 0, nx = 0, k = 0, kpad = 0, l = 0, dtype = 0, max_batch = 0;
+  int64_t n_freq = 0, n_freq_pad = 0;
+  double sigma = 0, eps_abs = 0;
+  uint64_t frames_seen = 0;
+  int32_t last_batch = 0;
+  int64_t device_bytes = 0;
+  size_t frame_bytes = 0;
+
+  float* psi = nullptr;
+  int32_t* kmap = nullptr;
+  int2* freqs = nullptr;
+  float2* w = nullptr;
+  float2* acc = nullptr;
+  float2 *ty = nullptr, *tx = nullptr, *ey = nullptr, *ex = nullptr;
+  float* h = nullptr;
+  int2* pos = nullptr;
+  void* frames = nullptr;
+  float2 *d = nullptr, *z = nullptr, *u = nullptr, *o = nullptr;
+
+  int2* pin_pos[kRing] = {};
+  void* pin_frames[kRing] = {};
+  hipEvent_t ev[kRing] = {};
+  bool ev_live[kRing] = {};
+  int slot = 0;
+  float2* pin_out = nullptr;
+  std::vector<void*> allocs;
+
+  // stage timing (wdd_profile_*): events around launches, harvested when the stream is idle
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { int stage; hipEvent_t e0, e1; };
+  std::vector<Pending> pending;
+  double stage_ms[4] = {0, 0, 0, 0};
+  int64_t stage_n[4] = {0, 0, 0, 0};
+};
+
+}  // namespace
+
+struct wdd_plan_s : wdd_plan_impl {};
+
+namespace {
+
+wdd_status dev_fail(wdd_plan_s* p, hipError_t e, const char* what) {
+  if (p) p->failed = true;
+  return wdd::fail(WDD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define WDD_HIP(p, call)                                   \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return dev_fail((p), e_, #call); \
+  } while (0)
+
+template <typename T>
+wdd_status dalloc(wdd_plan_s* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return wdd::fail(WDD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  if (e != hipSuccess) return dev_fail(p, e, "hipMalloc");
+  p->allocs.push_back(*ptr);
+  p->device_bytes += (int64_t)bytes;
+  return WDD_OK;
+}
+
+enum Stage { kProject = 0, kAccumulate = 1, kWiener = 2, kDisplay = 3 };
+
+// Opens a timed stage: returns the end event to record after the launches (or null).
+hipError_t stage_begin(wdd_plan_s* p, int stage, hipEvent_t* end) {
+  *end = nullptr;
+  if (!p->profiling) return hipSuccess;
+  hipEvent_t e[2];
+  for (int i = 0; i < 2; ++i) {
+    if (!p->ev_pool.empty()) {
+      e[i] = p->ev_pool.back();
+      p->ev_pool.pop_back();
+    } else {
+      hipError_t err = hipEventCreate(&e[i]);
+      if (err != hipSuccess) return err;
+    }
+  }
+  hipError_t err = hipEventRecord(e[0], p->stream);
+  if (err != hipSuccess) return err;
+  p->pending.push_back({stage, e[0], e[1]});
+  *end = e[1];
+  return hipSuccess;
+}
+
+hipError_t stage_end(wdd_plan_s* p, hipEvent_t end) {
+  if (!end) return hipSuccess;
+  return hipEventRecord(end, p->stream);
+}
+
+// Adds the durations of all recorded stages; the stream must be idle.
+hipError_t harvest(wdd_plan_s* p) {
+  for (auto& x : p->pending) {
+    float ms = 0.f;
+    hipError_t err = hipEventElapsedTime(&ms, x.e0, x.e1);
+    if (err != hipSuccess) return err;
+    p->stage_ms[x.stage] += ms;
+    p->stage_n[x.stage] += 1;
+    p->ev_pool.push_back(x.e0);
+    p->ev_pool.push_back(x.e1);
+  }
+  p->pending.clear();
+  return hipSuccess;
+}
+
+void release(wdd_plan_s* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (auto& x : p->pending) {
+    p->ev_pool.push_back(x.e0);
+    p->ev_pool.push_back(x.e1);
+  }
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  for (void* a : p->allocs) (void)hipFree(a);
+  for (int i = 0; i < kRing; ++i) {
+    if (p->pin_pos[i]) (void)hipHostFree(p->pin_pos[i]);
+    if (p->pin_frames[i]) (void)hipHostFree(p->pin_frames[i]);
+    if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+  }
+  if (p->pin_out) (void)hipHostFree(p->pin_out);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+wdd_status check_usable(wdd_plan_s* p) {
+  if (!p) return wdd::fail(WDD_EINVAL, "null plan");
+  if (p->failed) return wdd::fail(WDD_ESTATE, "plan is unusable after an earlier device error");
+  return WDD_OK;
+}
+
+std::vector<float2> twiddles(int32_t n, double scale) {
+  std::vector<float2> t(n);
+  for (int32_t m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    t[m] = make_float2((float)(std::cos(a) * scale), (float)(std::sin(a) * scale));
+  }
+  return t;
+}
+
+wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts, void* stream) {
+  p->sy = t.sy; p->sx = t.sx; p->ny = t.ny; p->nx = t.nx; p->k = t.k; p->l = t.l;
+  p->kpad = (t.k + 31) / 32 * 32;
+  p->n_freq = t.n_freq();
+  p->n_freq_pad = (p->n_freq + 63) / 64 * 64;
+  p->sigma = t.sigma; p->eps_abs = t.eps_abs;
+  p->max_batch = opts.max_batch;
+  p->frame_bytes = (size_t)t.ny * t.nx * (p->dtype == WDD_U16 ? 2 : 4);
+  WDD_HIP(p, hipGetDevice(&p->device));
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    WDD_HIP(p, hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    p->own_stream = true;
+  }
+
+  // host-side FP32 images of the tables
+  std::vector<float> psi((size_t)(t.ny + t.nx) * 16, 0.f);
+  for (int32_t i = 0; i < t.ny; ++i)
+    for (int32_t m = 0; m < t.l; ++m) psi[(size_t)i * 16 + m] = (float)t.psi_y[(size_t)i * t.l + m];
+  for (int32_t i = 0; i < t.nx; ++i)
+    for (int32_t m = 0; m < t.l; ++m) psi[(size_t)(t.ny + i) * 16 + m] = (float)t.psi_x[(size_t)i * t.l + m];
+  std::vector<int32_t> kmap(p->kpad, -1);
+  for (int32_t k = 0; k < t.k; ++k) kmap[k] = 16 * t.pairs[2 * k] + t.pairs[2 * k + 1];
+  std::vector<int2> freqs(p->n_freq_pad, make_int2(0, 0));
+  for (int64_t j = 0; j < p->n_freq; ++j) freqs[j] = make_int2(t.freqs[2 * j], t.freqs[2 * j + 1]);
+  const std::vector<float2> ty = twiddles(t.sy, 1.0);
+  const std::vector<float2> tx = twiddles(t.sx, 1.0 / std::sqrt((double)t.sy * (double)t.sx));
+  const std::vector<float2> ey = twiddles(t.sy, 1.0);
+  const std::vector<float2> ex = twiddles(t.sx, 1.0);
+
+  const size_t nfk = (size_t)p->n_freq_pad * p->kpad;
+  const size_t grid = (size_t)t.sy * t.sx;
+  wdd_status st;
+#define ALLOC(ptr, n)                                   \
+  if ((st = dalloc(p, &(ptr), (n))) != WDD_OK) return st;
+  ALLOC(p->psi, psi.size());
+  ALLOC(p->kmap, kmap.size());
+  ALLOC(p->freqs, freqs.size());
+  ALLOC(p->w, nfk);
+  ALLOC(p->acc, nfk);
+  ALLOC(p->ty, (size_t)t.sy);
+  ALLOC(p->tx, (size_t)t.sx);
+  ALLOC(p->ey, (size_t)t.sy);
+  ALLOC(p->ex, (size_t)t.sx);
+  ALLOC(p->h, (size_t)p->max_batch * p->kpad);
+  ALLOC(p->pos, (size_t)p->max_batch);
+  {
+    char* fr = nullptr;
+    if ((st = dalloc(p, &fr, (size_t)p->max_batch * p->frame_bytes)) != WDD_OK) return st;
+    p->frames = fr;
+  }
+  ALLOC(p->d, (size_t)p->n_freq_pad);
+  ALLOC(p->z, grid);
+  ALLOC(p->u, grid);
+  ALLOC(p->o, grid);
+#undef ALLOC
+
+  // Wiener filter, FP64 -> FP32, padded
+  {
+    std::vector<float2> w(nfk, make_float2(0.f, 0.f));
+    for (int64_t j = 0; j < p->n_freq; ++j)
+      for (int32_t k = 0; k < t.k; ++k) {
+        const double* s = &t.w[((size_t)j * t.k + k) * 2];
+        w[(size_t)j * p->kpad + k] = make_float2((float)s[0], (float)s[1]);
+      }
+    WDD_HIP(p, hipMemcpyAsync(p->w, w.data(), nfk * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+    WDD_HIP(p, hipStreamSynchronize(p->stream));
+  }
+  WDD_HIP(p, hipMemcpyAsync(p->psi, psi.data(), psi.size() * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->kmap, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->freqs, freqs.data(), freqs.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->ty, ty.data(), ty.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->tx, tx.data(), tx.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->ey, ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipMemcpyAsync(p->ex, ex.data(), ex.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), nfk * 2, p->stream));
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), grid * 2, p->stream));
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
+  WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad, p->stream));
+
+  for (int i = 0; i < kRing; ++i) {
+    WDD_HIP(p, hipHostMalloc((void**)&p->pin_pos[i], (size_t)p->max_batch * sizeof(int2), hipHostMallocDefault));
+    WDD_HIP(p, hipEventCreateWithFlags(&p->ev[i], hipEventDisableTiming));
+  }
+  WDD_HIP(p, hipHostMalloc((void**)&p->pin_out, grid * sizeof(float2), hipHostMallocDefault));
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
+                           const wdd_options* opts_in, void* hip_stream, wdd_plan_t* out) {
+  if (!out) return wdd::fail(WDD_EINVAL, "null output handle");
+  *out = nullptr;
+  wdd_options opts;
+  wdd_default_options(&opts);
+  if (opts_in) opts = *opts_in;
+  if (opts.precision != WDD_FP32) return wdd::fail(WDD_EINVAL, "unsupported precision %d", opts.precision);
+  if (opts.max_batch < 1 || opts.max_batch > 65536)
+    return wdd::fail(WDD_EINVAL, "max_batch = %d outside [1, 65536]", opts.max_batch);
+  wdd_tables_s t;
+  wdd_status st = wdd::build_tables(probe, scan, det, K, &opts, &t);
+  if (st != WDD_OK) return st;
+  wdd_plan_s* p = new (std::nothrow) wdd_plan_s();
+  if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
+  p->dtype = det->dtype;
+  try {
+    st = create(p, t, opts, hip_stream);
+  } catch (const std::bad_alloc&) {
+    st = wdd::fail(WDD_ENOMEM, "out of host memory");
+  }
+  if (st != WDD_OK) {
+    release(p);
+    return st;
+  }
+  *out = p;
+  return WDD_OK;
+}
+
+wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (n < 0 || n > p->max_batch) return wdd::fail(WDD_EINVAL, "n = %d outside [0, %d]", n, p->max_batch);
+  if (n == 0) return WDD_OK;
+  if (!frames || !pos_yx) return wdd::fail(WDD_EINVAL, "null frames or positions");
+  if (frames_on_device && (reinterpret_cast<uintptr_t>(frames) % 16) != 0)
+    return wdd::fail(WDD_EINVAL, "device frames must be 16-byte aligned");
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t y = pos_yx[2 * i], x = pos_yx[2 * i + 1];
+    if (y < 0 || y >= p->sy || x < 0 || x >= p->sx)
+      return wdd::fail(WDD_ERANGE, "position %d = (%d, %d) outside the %d x %d raster", i, y, x, p->sy, p->sx);
+  }
+  // reuse a pinned slot only after the copies that read it have run
+  const int s = p->slot;
+  p->slot = (p->slot + 1) % kRing;
+  if (p->ev_live[s]) WDD_HIP(p, hipEventSynchronize(p->ev[s]));
+  std::memcpy(p->pin_pos[s], pos_yx, (size_t)n * sizeof(int2));
+  WDD_HIP(p, hipMemcpyAsync(p->pos, p->pin_pos[s], (size_t)n * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+  const void* fdev = frames;
+  if (!frames_on_device) {
+    if (!p->pin_frames[s]) {
+      hipError_t e = hipHostMalloc(&p->pin_frames[s], (size_t)p->max_batch * p->frame_bytes, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        p->pin_frames[s] = nullptr;
+        return dev_fail(p, e, "hipHostMalloc");
+      }
+    }
+    std::memcpy(p->pin_frames[s], frames, (size_t)n * p->frame_bytes);
+    WDD_HIP(p, hipMemcpyAsync(p->frames, p->pin_frames[s], (size_t)n * p->frame_bytes, hipMemcpyHostToDevice,
+                              p->stream));
+    fdev = p->frames;
+  }
+  WDD_HIP(p, hipEventRecord(p->ev[s], p->stream));
+  p->ev_live[s] = true;
+  if (p->pending.size() > 4096) {  // bound the events held while nobody snapshots
+    WDD_HIP(p, hipStreamSynchronize(p->stream));
+    WDD_HIP(p, harvest(p));
+  }
+  hipEvent_t end;
+  WDD_HIP(p, stage_begin(p, kProject, &end));
+  WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, p->stream));
+  WDD_HIP(p, stage_end(p, end));
+  WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+  WDD_HIP(p, wdd::launch_accumulate(p->acc, p->kpad, p->n_freq_pad, p->freqs, p->h, p->pos, n, p->ty, p->sy, p->tx,
+                                    p->sx, p->stream));
+  WDD_HIP(p, stage_end(p, end));
+  p->frames_seen += (uint64_t)n;
+  p->last_batch = n;
+  return WDD_OK;
+}
+
+wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  const size_t grid = (size_t)p->sy * p->sx;
+  hipEvent_t end;
+  WDD_HIP(p, stage_begin(p, kWiener, &end));
+  WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sx, p->stream));
+  WDD_HIP(p, stage_end(p, end));
+  WDD_HIP(p, stage_begin(p, kDisplay, &end));
+  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sy, p->sx, p->ex, p->d, 1.f, 0, p->stream));
+  WDD_HIP(p, wdd::launch_dft_rows(p->u, p->o, p->sx, p->sy, p->ey, p->d, (float)((double)p->sy * p->sx), 1,
+                                  p->stream));
+  WDD_HIP(p, stage_end(p, end));
+  if (out_on_device) {
+    WDD_HIP(p, hipMemcpyAsync(out, p->o, grid * sizeof(float2), hipMemcpyDeviceToDevice, p->stream));
+    WDD_HIP(p, hipStreamSynchronize(p->stream));
+  } else {
+    WDD_HIP(p, hipMemcpyAsync(p->pin_out, p->o, grid * sizeof(float2), hipMemcpyDeviceToHost, p->stream));
+    WDD_HIP(p, hipStreamSynchronize(p->stream));
+    std::memcpy(out, p->pin_out, grid * sizeof(float2));
+  }
+  WDD_HIP(p, harvest(p));
+  if (frames_seen) *frames_seen = p->frames_seen;
+  return WDD_OK;
+}
+
+static wdd_status copy_rows(wdd_plan_s* p, void* dst, const void* src, size_t rows, size_t row_bytes,
+                            size_t src_pitch, int32_t on_device) {
+  WDD_HIP(p, hipMemcpy2DAsync(dst, row_bytes, src, src_pitch, row_bytes, rows,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!d_out) return wdd::fail(WDD_EINVAL, "null output");
+  return copy_rows(p, d_out, p->d, 1, (size_t)p->n_freq * sizeof(float2), (size_t)p->n_freq * sizeof(float2),
+                   on_device);
+}
+
+wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!a_out) return wdd::fail(WDD_EINVAL, "null output");
+  return copy_rows(p, a_out, p->acc, (size_t)p->n_freq, (size_t)p->k * sizeof(float2),
+                   (size_t)p->kpad * sizeof(float2), on_device);
+}
+
+wdd_status wdd_get_projection(wdd_plan_t p, float* h_out, int32_t on_device) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!h_out) return wdd::fail(WDD_EINVAL, "null output");
+  if (p->last_batch == 0) return WDD_OK;
+  return copy_rows(p, h_out, p->h, (size_t)p->last_batch, (size_t)p->k * sizeof(float), (size_t)p->kpad * sizeof(float),
+                   on_device);
+}
+
+wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info) {
+  if (!p || !info) return wdd::fail(WDD_EINVAL, "null argument");
+  info->n_freq = p->n_freq;
+  info->k = p->k;
+  info->l = p->l;
+  info->sigma_px = p->sigma;
+  info->eps_abs = p->eps_abs;
+  info->frames_seen = p->frames_seen;
+  info->device_bytes = p->device_bytes;
+  return WDD_OK;
+}
+
+wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  WDD_HIP(p, harvest(p));
+  for (int i = 0; i < 4; ++i) {
+    p->stage_ms[i] = 0;
+    p->stage_n[i] = 0;
+  }
+  p->profiling = on != 0;
+  return WDD_OK;
+}
+
+wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  WDD_HIP(p, harvest(p));
+  out->project_ms = p->stage_ms[kProject];
+  out->accumulate_ms = p->stage_ms[kAccumulate];
+  out->wiener_ms = p->stage_ms[kWiener];
+  out->display_ms = p->stage_ms[kDisplay];
+  out->project_launches = p->stage_n[kProject];
+  out->accumulate_launches = p->stage_n[kAccumulate];
+  out->wiener_launches = p->stage_n[kWiener];
+  out->display_launches = p->stage_n[kDisplay];
+  return WDD_OK;
+}
+
+wdd_status wdd_reset(wdd_plan_t p) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
+  p->frames_seen = 0;
+  p->last_batch = 0;
+  return WDD_OK;
+}
+
+wdd_status wdd_sync(wdd_plan_t p) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+wdd_status wdd_plan_destroy(wdd_plan_t p) {
+  release(p);
+  return WDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Launchers of the HIP kernels (kernels.hip).  All are asynchronous on `st` and
+// return the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wdd.h"
+
+namespace wdd {
+
+// h[b][k] = sum_q Phi[q][k] frames[b][q] for b < n.  psi: [ny][16] then [nx][16]
+// (columns >= L zero); kmap[k] = 16 n_y(k) + n_x(k), or -1 for padding columns.
+hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
+                          int kpad, float* h, hipStream_t st);
+
+// Columns (in blocks of 32) per accumulation workgroup for a padded basis size.
+int accumulate_col_blocks(int kpad);
+
+// acc[j][c] += sum_{b<n} Ty[(v_y(j) s_y(b)) mod sy] Tx[(v_x(j) s_x(b)) mod sx] h[b][c].
+// n_freq_pad is a multiple of 64 and kpad a multiple of 32.
+hipError_t launch_accumulate(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, const float* h,
+                             const int2* pos, int n, const float2* ty, int sy, const float2* tx, int sx,
+                             hipStream_t st);
+
+// d[j] = sum_c w[j][c] acc[j][c]; z[v_y(j)][v_x(j)] = conj(d[j]).
+hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int2* freqs, int64_t n_freq, float2* d,
+                         float2* z, int sx, hipStream_t st);
+
+// out[c][r] = scale * sum_m in[r][m] e[(m c) mod len] for r < rows (see kernels.hip).
+hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
+                           float s_total, int final_scale, hipStream_t st);
+
+hipError_t launch_zero(float* p, size_t n, hipStream_t st);
+
+}  // namespace wdd

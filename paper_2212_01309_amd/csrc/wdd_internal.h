@@ -1,0 +1,34 @@
+// Internal declarations shared by the host table builder, the C ABI and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wdd.h"
+
+struct wdd_tables_s {
+  int32_t sy = 0, sx = 0, ny = 0, nx = 0, k = 0, l = 0;
+  double step = 1.0, radius = 0.0, amplitude = 1.0, defocus = 0.0;
+  double eps_rel = 0.01, sigma = 0.0, eps_abs = 0.0;
+  std::vector<int32_t> freqs;  // [n_freq][2]  (v_y, v_x)
+  std::vector<double> psi_y;   // [ny][l]
+  std::vector<double> psi_x;   // [nx][l]
+  std::vector<int32_t> pairs;  // [k][2]  (n_y, n_x)
+  std::vector<double> w;       // [n_freq][k][2]
+  int64_t n_freq() const { return (int64_t)freqs.size() / 2; }
+};
+
+namespace wdd {
+
+// Thread-local error message handling.
+wdd_status fail(wdd_status code, const char* fmt, ...);
+
+// Host FP64 table construction (validated arguments).
+wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
+                        int32_t K, const wdd_options* opts, wdd_tables_s* t);
+
+// Largest number of columns of psi held on the device per axis (L <= 16).
+constexpr int kMaxL = 16;
+
+}  // namespace wdd

@@ -1,0 +1,175 @@
+"""GPU edge cases through the C ABI: ragged batches, non-square and non-power-of-two
+geometries, degenerate sizes, error paths and state handling."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+from gpu_util import device, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _oracle(radius, sy, sx, ny, nx, k, frames, pos, defocus=0.0, amplitude=1.0, step=1.0):
+    plan = O.make_plan(sy, sx, ny, nx, radius, k, amplitude=amplitude, defocus_edge=defocus, step=step)
+    live = O.Live(plan, "N")
+    live.push(frames, pos)
+    return plan, live.acc, live.spectrum(), live.snapshot()
+
+
+def _random_case(seed, sy, sx, ny, nx, n, dtype):
+    rng = np.random.default_rng(seed)
+    lin = rng.integers(0, sy * sx, size=n)
+    pos = np.stack([lin // sx, lin % sx], axis=1).astype(np.int32)
+    if dtype == wdd.WDD_U16:
+        frames = rng.poisson(20.0, size=(n, ny, nx)).astype(np.uint16)
+    else:
+        frames = rng.uniform(0, 1, size=(n, ny, nx)).astype(np.float32)
+    return frames, pos
+
+
+@pytest.mark.parametrize("case", [
+    # non-square scan and detector, K not a multiple of 32, odd scan lengths (direct DFT path)
+    dict(radius=5.5, sy=24, sx=40, ny=40, nx=48, k=50, defocus=1.1, dtype=wdd.WDD_F32, batches=[7, 33, 1, 64, 0, 95]),
+    dict(radius=3.0, sy=30, sx=18, ny=12, nx=16, k=10, step=0.75, dtype=wdd.WDD_U16, batches=[31, 32, 33, 100]),
+    # K = 1 and a scan of a single position
+    dict(radius=4.0, sy=1, sx=1, ny=16, nx=16, k=1, dtype=wdd.WDD_U16, batches=[3, 1]),
+    dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=256, dtype=wdd.WDD_U16, batches=[256, 5, 200]),
+])
+def test_ragged_batches_and_odd_geometries(case):
+    batches = case.pop("batches")
+    dtype = case.pop("dtype")
+    n = sum(batches)
+    say(f"[api] geometry {case}, batches {batches}")
+    frames, pos = _random_case(1, case["sy"], case["sx"], case["ny"], case["nx"], n, dtype)
+    dev = device(frames)
+    mb = max(batches)
+    with wdd.Plan(case["radius"], case["sy"], case["sx"], case["ny"], case["nx"], case["k"], dtype=dtype,
+                  defocus=case.get("defocus", 0.0), step=case.get("step", 1.0), max_batch=mb) as plan:
+        b0 = 0
+        for nb in batches:
+            plan.push(dev[b0:b0 + nb], pos[b0:b0 + nb])
+            b0 += nb
+        got_o = plan.snapshot()
+        got_a, got_d = plan.accumulator(), plan.spectrum()
+        assert plan.info().frames_seen == n
+    oplan, a, d, o = _oracle(case["radius"], case["sy"], case["sx"], case["ny"], case["nx"], case["k"], frames, pos,
+                             defocus=case.get("defocus", 0.0), step=case.get("step", 1.0))
+    errs = (rel(got_a, a), rel(got_d, d), rel(got_o, o))
+    say(f"[api] errors A/D/O {errs}")
+    assert max(errs) <= TOL
+
+
+def test_decode_of_full_range_counts():
+    """Every uint16 value decodes exactly: one-hot frames of 65535 and a full-range random frame."""
+    ny = nx = 32
+    frames = np.zeros((40, ny, nx), np.uint16)
+    rng = np.random.default_rng(3)
+    for i in range(32):
+        frames[i, rng.integers(0, ny), rng.integers(0, nx)] = 65535 - i
+    frames[32:] = rng.integers(0, 65536, size=(8, ny, nx), dtype=np.uint16)
+    pos = np.zeros((40, 2), np.int32)
+    with wdd.Plan(8.0, 4, 4, ny, nx, 64, dtype=wdd.WDD_U16, max_batch=64) as plan:
+        plan.push(device(frames), pos)
+        h = plan.projection()
+        sig = plan.info().sigma_px
+    ref = O.project(frames, O.hg_basis(ny, nx, 64, sig))
+    for i in range(40):
+        assert rel(h[i], ref[i]) <= 1e-6, i
+
+
+def test_host_and_device_frames_agree_bitwise():
+    frames, pos = _random_case(2, 16, 16, 32, 32, 300, wdd.WDD_U16)
+    out = []
+    for on_dev in (True, False):
+        with wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=128) as plan:
+            src = device(frames) if on_dev else frames
+            for b in range(0, 300, 128):
+                plan.push(src[b:b + 128], pos[b:b + 128])
+            out.append((plan.accumulator(), plan.snapshot()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_deterministic_and_reset():
+    frames, pos = _random_case(4, 16, 16, 32, 32, 200, wdd.WDD_U16)
+    dev = device(frames)
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=100) as p1, wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=100) as p2:
+        for b in range(0, 200, 100):
+            p1.push(dev[b:b + 100], pos[b:b + 100])
+            p2.push(dev[b:b + 100], pos[b:b + 100])
+        a1, a2 = p1.accumulator(), p2.accumulator()
+        assert np.array_equal(a1, a2)
+        p1.reset()
+        assert p1.info().frames_seen == 0
+        assert not np.any(p1.accumulator())
+        for b in range(0, 200, 100):
+            p1.push(dev[b:b + 100], pos[b:b + 100])
+        assert np.array_equal(p1.accumulator(), a1)
+
+
+def test_out_of_range_position_rejects_the_whole_batch():
+    frames, pos = _random_case(5, 16, 16, 32, 32, 64, wdd.WDD_U16)
+    dev = device(frames)
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=64) as plan:
+        plan.push(dev[:32], pos[:32])
+        before = plan.accumulator()
+        bad = pos[32:].copy()
+        bad[7] = (16, 0)
+        with pytest.raises(wdd.WddError) as ei:
+            plan.push(dev[32:], bad)
+        assert ei.value.code == wdd.WDD_ERANGE
+        bad[7] = (0, -1)
+        with pytest.raises(wdd.WddError):
+            plan.push(dev[32:], bad)
+        assert np.array_equal(plan.accumulator(), before)
+        assert plan.info().frames_seen == 32
+        with pytest.raises(wdd.WddError) as ei:
+            plan.push(np.zeros((65, 32, 32), np.uint16), np.zeros((65, 2), np.int32))
+        assert ei.value.code == wdd.WDD_EINVAL
+        plan.push(dev[32:32], pos[32:32])        # n = 0 is a no-op
+        assert np.array_equal(plan.accumulator(), before)
+
+
+def test_snapshot_before_any_frame_is_zero_and_device_output():
+    import torch
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64) as plan:
+        assert not np.any(plan.snapshot())
+        frames, pos = _random_case(6, 16, 16, 32, 32, 50, wdd.WDD_U16)
+        plan.push(device(frames), pos)
+        host = plan.snapshot()
+        out = torch.empty((16, 16), dtype=torch.complex64, device="cuda")
+        plan.snapshot(out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), host)
+
+
+def test_repeated_positions_are_summed():
+    frames, pos = _random_case(7, 8, 8, 16, 16, 10, wdd.WDD_F32)
+    with wdd.Plan(4.0, 8, 8, 16, 16, 16, dtype=wdd.WDD_F32) as once, wdd.Plan(4.0, 8, 8, 16, 16, 16, dtype=wdd.WDD_F32) as twice:
+        once.push(device(frames * 2), pos)
+        twice.push(device(frames), pos)
+        twice.push(device(frames), pos)
+        assert rel(twice.accumulator(), once.accumulator()) <= 1e-6
+
+
+def test_arrival_order_does_not_matter():
+    frames, pos = _random_case(8, 32, 32, 32, 32, 1024, wdd.WDD_U16)
+    perm = np.random.default_rng(9).permutation(1024)
+    res = []
+    for order in (np.arange(1024), perm):
+        with wdd.Plan(8.0, 32, 32, 32, 32, 64, max_batch=256) as plan:
+            fr, ps = device(frames[order]), pos[order]
+            for b in range(0, 1024, 256):
+                plan.push(fr[b:b + 256], ps[b:b + 256])
+            res.append(plan.snapshot())
+    assert rel(res[1], res[0]) <= 1e-6
+
+
+def test_invalid_plans_are_rejected():
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Plan(8.0, 16, 16, 32, 30, 64)
+    assert ei.value.code == wdd.WDD_EINVAL
+    with pytest.raises(wdd.WddError):
+        wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=0)

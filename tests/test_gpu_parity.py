@@ -1,0 +1,92 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
+seeded inputs.  FP32 bar: relative L2 <= 1e-5 for A, D and the displayed object,
+<= 1e-6 for the projections h."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+import synth
+from gpu_util import device, golden_workload, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+TOL_H = 1e-6
+
+
+def _plan_for(wl, max_batch=None):
+    dtype = wdd.WDD_F32 if wl.dose is None else wdd.WDD_U16
+    return wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=max_batch or wl.batch)
+
+
+@pytest.mark.parametrize("name", ["small", "medium"])
+def test_full_raster_every_result(name):
+    """Whole acquisition in the workload's batches: h, A, D and O~ element by element."""
+    wl = synth.WORKLOADS[name]
+    say(f"[parity] {name}: scan {wl.sy}x{wl.sx}, detector {wl.n}, K={wl.k}, batch {wl.batch}")
+    pos = synth.raster_positions(wl.sy, wl.sx)
+    frames = wl.frames(pos)
+    dev = device(frames)
+    with _plan_for(wl) as plan:
+        for b in range(0, len(pos), wl.batch):
+            plan.push(dev[b:b + wl.batch], pos[b:b + wl.batch])
+        got_o = plan.snapshot()
+        got_h = plan.projection()
+        got_a = plan.accumulator()
+        got_d = plan.spectrum()
+        assert plan.info().frames_seen == len(pos)
+    oplan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=wl.aperture_amplitude(),
+                        defocus_edge=wl.defocus_edge, step=wl.step)
+    a, d, o = O.offline_reduced(oplan, frames, pos)
+    h_last = O.project(frames[-wl.batch:], oplan.phi)
+    errs = dict(h=rel(got_h, h_last), A=rel(got_a, a), D=rel(got_d, d), O=rel(got_o, o))
+    say(f"[parity] {name}: {errs}")
+    assert errs["h"] <= TOL_H
+    assert errs["A"] <= TOL and errs["D"] <= TOL and errs["O"] <= TOL
+
+
+def _sampled_case(name, n_frames, n_sample, seed):
+    """Full-size geometry and launch configuration; n_frames frames at random raster
+    positions; A and D compared on a random sample of kept frequencies."""
+    wl = synth.WORKLOADS[name]
+    g = golden_workload(name)
+    rng = np.random.default_rng(seed)
+    lin = rng.choice(wl.sy * wl.sx, size=n_frames, replace=False)
+    pos = np.stack([lin // wl.sx, lin % wl.sx], axis=1).astype(np.int32)
+    say(f"[parity] {name} sampled: {n_frames} frames of {wl.n}x{wl.n}, batch {wl.batch}")
+    frames = wl.frames(pos)
+    dev = device(frames)
+    with _plan_for(wl) as plan:
+        assert plan.n_freq == g["n_freq"]
+        for b in range(0, n_frames, wl.batch):
+            plan.push(dev[b:b + wl.batch], pos[b:b + wl.batch])
+        got_o = plan.snapshot()
+        got_h = plan.projection()
+        got_a = plan.accumulator()
+        got_d = plan.spectrum()
+    all_f = O.nonzero_frequencies(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.step)
+    assert len(all_f) == g["n_freq"]
+    pick = np.concatenate([[0], np.sort(rng.choice(np.arange(1, len(all_f)), size=n_sample, replace=False))])
+    oplan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=wl.aperture_amplitude(),
+                        defocus_edge=wl.defocus_edge, step=wl.step, freqs=all_f[pick], eps_abs=g["eps_abs"])
+    h = O.project(frames, oplan.phi)
+    a = O.scan_phase(oplan.freqs, pos, wl.sy, wl.sx) @ h
+    d = O.extract(oplan, a)
+    errs = dict(h=rel(got_h, h[-wl.batch:]), A=rel(got_a[pick], a), D=rel(got_d[pick], d))
+    # the displayed object is the unitary inverse DFT of D (Parseval) normalised by |D[0]|
+    pars = abs(np.sum(np.abs(got_o.astype(np.complex128)) ** 2) * abs(got_d[0]) /
+               np.sum(np.abs(got_d.astype(np.complex128)) ** 2) - 1)
+    say(f"[parity] {name} sampled: {errs}, parseval {pars:.2e}")
+    assert errs["h"] <= TOL_H
+    assert errs["A"] <= TOL and errs["D"] <= TOL
+    assert pars <= 1e-5
+
+
+def test_large_workload_sampled():
+    _sampled_case("large", 1024, 256, 41)
+
+
+def test_defocus_workload_sampled():
+    _sampled_case("defocus", 2048, 256, 42)

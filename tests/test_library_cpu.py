@@ -1,0 +1,80 @@
+"""Host-side checks of libwdd that need no GPU: the C ABI loads and exports every
+declared symbol, the FP64 host tables agree with the oracle, and bad arguments
+are rejected."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+import synth
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wdd.load_library()
+    names = wdd.header_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding describes each one
+    assert set(names) == set(wdd._SIGNATURES)
+
+
+def _compare(radius, sy, sx, ny, nx, k, defocus=0.0, amplitude=1.0, step=1.0, sigma=None, eps_rel=0.01):
+    t = wdd.Tables(radius, sy, sx, ny, nx, k, defocus=defocus, amplitude=amplitude, step=step,
+                   sigma=sigma or 0.0, eps_rel=eps_rel)
+    freqs, psy, psx, pairs, w = t.export()
+    p = O.make_plan(sy, sx, ny, nx, radius, k, amplitude=amplitude, defocus_edge=defocus, step=step,
+                    sigma=sigma, eps_rel=eps_rel)
+    assert np.array_equal(freqs, p.freqs)
+    assert np.array_equal(pairs, O.basis_order(k))
+    sig = sigma or O.default_sigma(radius, k)
+    assert t.sigma == pytest.approx(sig, rel=1e-15)
+    assert np.max(np.abs(psy - O.sampled_hermite(ny, t.l, sig))) < 1e-13
+    assert np.max(np.abs(psx - O.sampled_hermite(nx, t.l, sig))) < 1e-13
+    assert t.eps_abs == pytest.approx(p.eps_abs, rel=1e-12)
+    assert np.linalg.norm(w - p.w) <= 1e-12 * np.linalg.norm(p.w)
+
+
+@pytest.mark.parametrize("args", [
+    dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=64),
+    dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=64, defocus=np.pi, amplitude=17.0),
+    dict(radius=16.0, sy=64, sx=64, ny=64, nx=64, k=256),
+    dict(radius=5.5, sy=24, sx=40, ny=40, nx=48, k=50, defocus=1.1),     # non-square, ragged K
+    dict(radius=3.0, sy=30, sx=18, ny=12, nx=16, k=10, step=0.75),        # non-power-of-two shifts
+    dict(radius=20.0, sy=16, sx=16, ny=32, nx=32, k=9),                   # aperture clipped by the detector
+    dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=128, sigma=3.0, eps_rel=0.1),
+])
+def test_host_tables_match_oracle(args):
+    _compare(**args)
+
+
+def test_host_tables_medium_workload():
+    wl = synth.WORKLOADS["medium"]
+    t = wdd.Tables(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, amplitude=wl.aperture_amplitude())
+    freqs, *_ = t.export()
+    assert np.array_equal(freqs, O.nonzero_frequencies(wl.sy, wl.sx, wl.n, wl.n, wl.radius))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(k=0), dict(k=257), dict(radius=0.0), dict(radius=-1.0), dict(sy=0), dict(sx=5000),
+    dict(nx=12), dict(ny=0), dict(step=0.0), dict(eps_rel=0.0), dict(amplitude=0.0),
+])
+def test_tables_reject_bad_arguments(bad):
+    args = dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=64)
+    extra = {}
+    for key in ("step", "eps_rel", "amplitude"):
+        if key in bad:
+            extra[key] = bad.pop(key)
+    args.update(bad)
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Tables(args["radius"], args["sy"], args["sx"], args["ny"], args["nx"], args["k"], **extra)
+    assert ei.value.code == wdd.WDD_EINVAL
+    assert wdd.load_library().wdd_last_error()
+
+
+def test_default_options():
+    o = wdd.Options()
+    assert wdd.load_library().wdd_default_options(ctypes.byref(o)) == 0
+    assert o.eps_rel == 0.01 and o.sigma_px == 0.0 and o.max_batch == 256 and o.precision == wdd.WDD_FP32
