@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
+    ap.add_argument("--pool-batches", type=int, default=128,
+                    help="distinct batches generated (steps cycle through them); the medium workload has 128")
     return ap.parse_args()
 
 
@@ -38,7 +40,35 @@ def workload_label(wl, n_freq):
     kind = "uint16 Poisson %.0e e/frame" % wl.dose if wl.dose else "float32 noiseless"
     return (f"{wl.name}: {wl.sy}x{wl.sx} raster scan, {wl.n}x{wl.n} detector ({kind}), aperture radius "
             f"{wl.radius:g} px, K={wl.k} Hermite-Gauss functions, {n_freq} kept frequencies, "
-            f"batches of {wl.batch}, snapshot after every batch")
+            f"batches of {wl.batch} in raster order, snapshot after every batch")
+
+
+def roofline(wl, n_freq, k, prof, stages):
+    """Roofline entry for the stage with the largest time per step, from its algorithmic work."""
+    per_step = {s: stages[s] * prof[f"{s}_launches"] / max(prof["display_launches"], 1) for s in stages}
+    dom = max(per_step, key=per_step.get)
+    us = stages[dom]
+    fused = prof["wiener_launches"] == 0
+    if dom == "accumulate" and prof["rowdft_launches"]:
+        # row-factored update: read and write A, read W when the Wiener reduction is fused
+        nbytes = (24.0 if fused else 16.0) * n_freq * k
+        kernel, bound = "k_row_update" + ("<fused Wiener>" if fused else ""), "hbm"
+    elif dom == "accumulate":
+        flops = 4.0 * n_freq * k * wl.batch            # complex phase x real coefficient per (v, k, frame)
+        ach = flops / (us * 1e-6) / 1e12
+        return {"kernel": "k_accumulate", "bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "avg_us": us}
+    elif dom == "wiener":
+        nbytes, kernel, bound = 16.0 * n_freq * k, "k_wiener", "hbm"
+    elif dom == "project":
+        nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
+        kernel, bound = "k_project", "hbm"
+    else:
+        nbytes = 3 * 8.0 * wl.sy * wl.sx
+        kernel, bound = {"display": "k_dft_rows (x2)", "rowdft": "k_row_dft"}[dom], "hbm"
+    ach = nbytes / (us * 1e-6) / 1e9
+    return {"kernel": kernel, "bound": bound, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": None, "avg_us": us, "algorithmic_bytes": nbytes}
 
 
 def cpu_baseline(wl, frames, pos, seconds):
@@ -81,7 +111,7 @@ def main():
     import synth
 
     wl = synth.WORKLOADS[args.workload]
-    pos = synth.raster_positions(wl.sy, wl.sx)
+    pos = synth.raster_positions(wl.sy, wl.sx)[:args.pool_batches * wl.batch]
     t0 = time.perf_counter()
     frames = wl.frames(pos)
     gen_s = time.perf_counter() - t0
@@ -94,10 +124,11 @@ def main():
     nb = len(pos) // wl.batch
     batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
 
+    shown = np.empty((wl.sy, wl.sx), np.complex64)    # host buffer the display is copied into
+
     def step(i):
         fr, ps = batches[i % nb]
-        plan.push(fr, ps)
-        plan.snapshot()
+        plan.push_snapshot(fr, ps, out=shown)
 
     for i in range(args.warmup):
         step(i)
@@ -126,14 +157,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
     }
     if prof is not None:
-        acc_ms = prof["accumulate_ms"] / max(prof["accumulate_launches"], 1)
-        flops = 4.0 * n_freq * k * wl.batch          # complex phase x real coefficient, per (v, k, frame)
-        achieved = flops / (acc_ms * 1e-3) / 1e12
-        out["roofline"] = {"kernel": "k_accumulate", "bound": "mfma", "achieved": achieved,
-                           "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                           "traffic": None, "avg_us": acc_ms * 1e3}
-        out["stages_us"] = {s: prof[f"{s}_ms"] / max(prof[f"{s}_launches"], 1) * 1e3
-                            for s in ("project", "accumulate", "wiener", "display")}
+        stages = {s: (prof[f"{s}_ms"] / prof[f"{s}_launches"] * 1e3 if prof[f"{s}_launches"] else 0.0)
+                  for s in ("project", "rowdft", "accumulate", "wiener", "display")}
+        out["stages_us"] = stages
+        out["roofline"] = roofline(wl, n_freq, k, prof, stages)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds)
     out["generation_s"] = gen_s

@@ -150,11 +150,21 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
  *           wdd_sync or the next wdd_snapshot), else host memory (copied before
  *           the call returns).
  *   pos_yx  host int32 [n][2] scan indices.
+ * Batches whose frames lie on at most 16 scan rows are accumulated through the
+ * Kronecker factorisation F = F_y (x) F_x (per-row x-DFT, then one pass over the
+ * spectrum); others through the direct phase-weighted sum.  Both give the same
+ * result up to rounding.
  * Asynchronous on the plan stream.  n = 0 is a no-op.  WDD_EINVAL if n < 0 or
  * n > max_batch; WDD_ERANGE if any position is outside the raster, in which case
  * no frame of the call is applied. */
 wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
                     int32_t frames_on_device);
+
+/* wdd_push followed by wdd_snapshot, with the same arguments and results.  When the
+ * batch uses the row-factored update (it touches at most 16 scan rows), the Wiener
+ * reduction is done in the same pass over the spectrum. */
+wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
+                             int32_t frames_on_device, float* out, int32_t out_on_device, uint64_t* frames_seen);
 
 /* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
  * conjugation and normalisation (eq. extract).  Writes sy x sx complex values
@@ -181,10 +191,12 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info);
  * around each kernel launch while profiling is enabled. */
 typedef struct {
   double project_ms;     /* frame decode + basis projection */
-  double accumulate_ms;  /* phase weighting + spectrum accumulation */
-  double wiener_ms;      /* Wiener reduction */
+  double accumulate_ms;  /* spectrum update (direct, or row-factored incl. a fused Wiener reduction) */
+  double wiener_ms;      /* Wiener reduction (when not fused) */
   double display_ms;     /* inverse DFT, conjugation and normalisation */
   int64_t project_launches, accumulate_launches, wiener_launches, display_launches;
+  double rowdft_ms;      /* per-row scan x-DFT of the row-factored update */
+  int64_t rowdft_launches;
 } wdd_profile;
 
 /* Turns stage timing on (on != 0) or off and zeroes the totals. */

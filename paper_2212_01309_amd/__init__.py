@@ -57,7 +57,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("project_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double), ("wiener_ms", ctypes.c_double),
                 ("display_ms", ctypes.c_double), ("project_launches", ctypes.c_int64),
                 ("accumulate_launches", ctypes.c_int64), ("wiener_launches", ctypes.c_int64),
-                ("display_launches", ctypes.c_int64)]
+                ("display_launches", ctypes.c_int64), ("rowdft_ms", ctypes.c_double),
+                ("rowdft_launches", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -73,6 +74,8 @@ _SIGNATURES = {
                                        ctypes.c_int32, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
     "wdd_push": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
     "wdd_snapshot": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "wdd_push_snapshot": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
     "wdd_get_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_get_accumulator": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_get_projection": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -214,9 +217,7 @@ class Plan:
         return info
 
     # -- hot path ------------------------------------------------------------
-    def push(self, frames, positions) -> None:
-        """frames: [n, ny, nx] (torch GPU tensor or host array of the detector dtype);
-        positions: host int32 [n, 2] scan indices (y, x)."""
+    def _frames_arg(self, frames, positions):
         pos = _host_array(positions, np.int32).reshape(-1, 2)
         n = pos.shape[0]
         if _is_device_tensor(frames):
@@ -232,21 +233,53 @@ class Plan:
             if keep.size != n * self.ny * self.nx:
                 raise ValueError("frames and positions disagree in count or frame shape")
             ptr, on_dev = keep.ctypes.data, 0
+        return pos, n, ptr, on_dev, keep
+
+    def push(self, frames, positions) -> None:
+        """frames: [n, ny, nx] (torch GPU tensor or host array of the detector dtype);
+        positions: host int32 [n, 2] scan indices (y, x)."""
+        pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
         _check(load_library().wdd_push(self._h, ptr, pos.ctypes.data, n, on_dev))
         if n:
             self._last_batch = n
         del keep
 
+    def push_snapshot(self, frames, positions, out=None):
+        """push() then snapshot() in one call (one pass over the spectrum when possible)."""
+        pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
+        seen = ctypes.c_uint64()
+        if out is not None and _is_device_tensor(out):
+            _check(load_library().wdd_push_snapshot(self._h, ptr, pos.ctypes.data, n, on_dev, out.data_ptr(), 1,
+                                                    ctypes.byref(seen)))
+            res = out
+        else:
+            res = self._host_out(out)
+            _check(load_library().wdd_push_snapshot(self._h, ptr, pos.ctypes.data, n, on_dev, res.ctypes.data, 0,
+                                                    ctypes.byref(seen)))
+        if n:
+            self._last_batch = n
+        del keep
+        return res
+
     def snapshot(self, out=None):
         """Displayed estimate [sy, sx] complex64.  With `out` (a torch GPU tensor of
-        sy*sx complex64 or 2*sy*sx float32) it is written on the device and returned."""
+        sy*sx complex64 or 2*sy*sx float32, or a host complex64 array) it is written there
+        and returned."""
         seen = ctypes.c_uint64()
         if out is not None and _is_device_tensor(out):
             _check(load_library().wdd_snapshot(self._h, out.data_ptr(), 1, ctypes.byref(seen)))
             return out
-        host = np.empty((self.sy, self.sx), np.complex64)
+        host = self._host_out(out)
         _check(load_library().wdd_snapshot(self._h, host.ctypes.data, 0, ctypes.byref(seen)))
         return host
+
+    def _host_out(self, out):
+        if out is None:
+            return np.empty((self.sy, self.sx), np.complex64)
+        if not (isinstance(out, np.ndarray) and out.dtype == np.complex64 and out.size == self.sy * self.sx
+                and out.flags.c_contiguous):
+            raise ValueError("host output must be a C-contiguous complex64 array of sy*sx elements")
+        return out
 
     def spectrum(self) -> np.ndarray:
         """D on the kept frequencies from the last snapshot, complex64 [n_freq]."""

@@ -3,13 +3,16 @@
 // Device layout of a plan (all on the plan's device):
 //   psi     float  [(ny + nx) * 16]     sampled Hermite functions, columns >= L zero
 //   kmap    int32  [kpad]               16 n_y(k) + n_x(k); -1 for padding columns
+//                                       (kpad = K rounded up to a power of two >= 32)
 //   freqs   int2   [n_freq_pad]         kept (v_y, v_x); padding rows (0, 0)
 //   w       float2 [n_freq_pad][kpad]   Wiener filter (padding rows/columns zero)
 //   acc     float2 [n_freq_pad][kpad]   accumulated spectrum A
 //   ty, tx  float2 [sy], [sx]           exp(-2 pi i m / S); tx carries 1/sqrt(sy sx)
 //   ey, ex  float2 [sy], [sx]           exp(-2 pi i m / S) for the display DFT
 //   h       float  [max_batch][kpad]    projections of the current batch
-//   pos     int2   [max_batch]          scan positions of the current batch
+//   upload  bytes                       per batch: pos int2 [max_batch], order int32 [max_batch],
+//                                       rows int4 [kFactorRows] (one host->device copy)
+//   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs of the row-factored accumulation
 //   frames  staging for host frames     [max_batch][ny][nx]
 //   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
 //   z, u, o float2 [sy * sx]            conj(D) grid, row-transformed grid, output
@@ -26,7 +29,8 @@
 
 namespace {
 
-constexpr int kRing = 4;  // pinned host staging slots for positions and frames
+constexpr int kRing = 4;         // pinned host staging slots for positions and frames
+constexpr int kFactorRows = 16;  // batches touching at most this many scan rows use the row-factored update
 
 struct wdd_plan_impl {
   int device = 0;
@@ -48,11 +52,16 @@ struct wdd_plan_impl {
   float2* acc = nullptr;
   float2 *ty = nullptr, *tx = nullptr, *ey = nullptr, *ex = nullptr;
   float* h = nullptr;
+  char* upload = nullptr;  // pos, order, rows
   int2* pos = nullptr;
+  int32_t* order = nullptr;
+  int4* rows = nullptr;
+  size_t upload_bytes = 0;
+  float2* t = nullptr;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr, *o = nullptr;
 
-  int2* pin_pos[kRing] = {};
+  char* pin_up[kRing] = {};
   void* pin_frames[kRing] = {};
   hipEvent_t ev[kRing] = {};
   bool ev_live[kRing] = {};
@@ -65,8 +74,10 @@ struct wdd_plan_impl {
   std::vector<hipEvent_t> ev_pool;
   struct Pending { int stage; hipEvent_t e0, e1; };
   std::vector<Pending> pending;
-  double stage_ms[4] = {0, 0, 0, 0};
-  int64_t stage_n[4] = {0, 0, 0, 0};
+  double stage_ms[5] = {0, 0, 0, 0, 0};
+  int64_t stage_n[5] = {0, 0, 0, 0, 0};
+  std::vector<int32_t> host_order;
+  std::vector<int4> host_rows;
 };
 
 }  // namespace
@@ -101,7 +112,7 @@ wdd_status dalloc(wdd_plan_s* p, T** ptr, size_t count) {
   return WDD_OK;
 }
 
-enum Stage { kProject = 0, kAccumulate = 1, kWiener = 2, kDisplay = 3 };
+enum Stage { kProject = 0, kAccumulate = 1, kWiener = 2, kDisplay = 3, kRowDft = 4 };
 
 // Opens a timed stage: returns the end event to record after the launches (or null).
 hipError_t stage_begin(wdd_plan_s* p, int stage, hipEvent_t* end) {
@@ -154,7 +165,7 @@ void release(wdd_plan_s* p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
   for (int i = 0; i < kRing; ++i) {
-    if (p->pin_pos[i]) (void)hipHostFree(p->pin_pos[i]);
+    if (p->pin_up[i]) (void)hipHostFree(p->pin_up[i]);
     if (p->pin_frames[i]) (void)hipHostFree(p->pin_frames[i]);
     if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
   }
@@ -180,11 +191,14 @@ std::vector<float2> twiddles(int32_t n, double scale) {
 
 wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts, void* stream) {
   p->sy = t.sy; p->sx = t.sx; p->ny = t.ny; p->nx = t.nx; p->k = t.k; p->l = t.l;
-  p->kpad = (t.k + 31) / 32 * 32;
+  p->kpad = 32;  // a power of two: the row-factored update reduces over kpad / 4 lanes with xor shuffles
+  while (p->kpad < t.k) p->kpad *= 2;
   p->n_freq = t.n_freq();
   p->n_freq_pad = (p->n_freq + 63) / 64 * 64;
   p->sigma = t.sigma; p->eps_abs = t.eps_abs;
   p->max_batch = opts.max_batch;
+  p->host_order.resize(p->max_batch);
+  p->host_rows.reserve(kFactorRows + 1);
   p->frame_bytes = (size_t)t.ny * t.nx * (p->dtype == WDD_U16 ? 2 : 4);
   WDD_HIP(p, hipGetDevice(&p->device));
   if (stream) {
@@ -224,7 +238,12 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   ALLOC(p->ey, (size_t)t.sy);
   ALLOC(p->ex, (size_t)t.sx);
   ALLOC(p->h, (size_t)p->max_batch * p->kpad);
-  ALLOC(p->pos, (size_t)p->max_batch);
+  p->upload_bytes = (size_t)p->max_batch * 12 + 16 + (size_t)kFactorRows * sizeof(int4);
+  ALLOC(p->upload, p->upload_bytes);
+  p->pos = reinterpret_cast<int2*>(p->upload);
+  p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
+  p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 12 + 15) / 16 * 16);
+  ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
   {
     char* fr = nullptr;
     if ((st = dalloc(p, &fr, (size_t)p->max_batch * p->frame_bytes)) != WDD_OK) return st;
@@ -260,7 +279,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad, p->stream));
 
   for (int i = 0; i < kRing; ++i) {
-    WDD_HIP(p, hipHostMalloc((void**)&p->pin_pos[i], (size_t)p->max_batch * sizeof(int2), hipHostMallocDefault));
+    WDD_HIP(p, hipHostMalloc((void**)&p->pin_up[i], p->upload_bytes, hipHostMallocDefault));
     WDD_HIP(p, hipEventCreateWithFlags(&p->ev[i], hipEventDisableTiming));
   }
   WDD_HIP(p, hipHostMalloc((void**)&p->pin_out, grid * sizeof(float2), hipHostMallocDefault));
@@ -301,7 +320,15 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   return WDD_OK;
 }
 
-wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device) {
+}  // extern "C"
+
+namespace {
+
+// Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
+// reduction of the updated spectrum; *fused reports whether it did.
+wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device,
+                     bool fuse_wiener, bool* fused) {
+  if (fused) *fused = false;
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   if (n < 0 || n > p->max_batch) return wdd::fail(WDD_EINVAL, "n = %d outside [0, %d]", n, p->max_batch);
@@ -314,12 +341,33 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
     if (y < 0 || y >= p->sy || x < 0 || x >= p->sx)
       return wdd::fail(WDD_ERANGE, "position %d = (%d, %d) outside the %d x %d raster", i, y, x, p->sy, p->sx);
   }
+  // Group the batch by scan row.  Few rows: row-factored update; otherwise the direct one.
+  int32_t* ord = p->host_order.data();
+  for (int32_t i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord, ord + n, [pos_yx](int32_t a, int32_t b) { return pos_yx[2 * a] < pos_yx[2 * b]; });
+  p->host_rows.clear();
+  for (int32_t i = 0; i < n && (int)p->host_rows.size() <= kFactorRows; ++i) {
+    const int32_t y = pos_yx[2 * ord[i]];
+    if (p->host_rows.empty() || p->host_rows.back().x != y) p->host_rows.push_back(make_int4(y, i, 0, 0));
+    p->host_rows.back().z += 1;
+  }
+  const bool factored = (int)p->host_rows.size() <= kFactorRows;
+  const int nrows = factored ? (int)p->host_rows.size() : 0;
+
   // reuse a pinned slot only after the copies that read it have run
   const int s = p->slot;
   p->slot = (p->slot + 1) % kRing;
   if (p->ev_live[s]) WDD_HIP(p, hipEventSynchronize(p->ev[s]));
-  std::memcpy(p->pin_pos[s], pos_yx, (size_t)n * sizeof(int2));
-  WDD_HIP(p, hipMemcpyAsync(p->pos, p->pin_pos[s], (size_t)n * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+  char* up = p->pin_up[s];
+  std::memcpy(up, pos_yx, (size_t)n * sizeof(int2));
+  size_t up_bytes = (size_t)n * sizeof(int2);
+  if (factored) {
+    std::memcpy(up + (size_t)p->max_batch * 8, ord, (size_t)n * sizeof(int32_t));
+    const size_t roff = reinterpret_cast<char*>(p->rows) - p->upload;
+    std::memcpy(up + roff, p->host_rows.data(), (size_t)nrows * sizeof(int4));
+    up_bytes = roff + (size_t)nrows * sizeof(int4);
+  }
+  WDD_HIP(p, hipMemcpyAsync(p->upload, up, up_bytes, hipMemcpyHostToDevice, p->stream));
   const void* fdev = frames;
   if (!frames_on_device) {
     if (!p->pin_frames[s]) {
@@ -344,24 +392,35 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
   WDD_HIP(p, stage_begin(p, kProject, &end));
   WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, p->stream));
   WDD_HIP(p, stage_end(p, end));
-  WDD_HIP(p, stage_begin(p, kAccumulate, &end));
-  WDD_HIP(p, wdd::launch_accumulate(p->acc, p->kpad, p->n_freq_pad, p->freqs, p->h, p->pos, n, p->ty, p->sy, p->tx,
-                                    p->sx, p->stream));
-  WDD_HIP(p, stage_end(p, end));
+  if (factored) {
+    WDD_HIP(p, stage_begin(p, kRowDft, &end));
+    WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
+    WDD_HIP(p, stage_end(p, end));
+    WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+    WDD_HIP(p, wdd::launch_row_update(p->acc, p->kpad, p->n_freq_pad, p->freqs, p->n_freq, p->t, p->sx, p->rows, nrows,
+                                      p->ty, p->sy, p->w, p->d, p->z, fuse_wiener, p->stream));
+    WDD_HIP(p, stage_end(p, end));
+  } else {
+    WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+    WDD_HIP(p, wdd::launch_accumulate(p->acc, p->kpad, p->n_freq_pad, p->freqs, p->h, p->pos, n, p->ty, p->sy, p->tx,
+                                      p->sx, p->stream));
+    WDD_HIP(p, stage_end(p, end));
+  }
+  if (fused) *fused = factored && fuse_wiener;
   p->frames_seen += (uint64_t)n;
   p->last_batch = n;
   return WDD_OK;
 }
 
-wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
-  wdd_status st = check_usable(p);
-  if (st != WDD_OK) return st;
-  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+// Display step (optionally after the Wiener reduction) and the copy to `out`; blocking.
+wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen, bool reduce) {
   const size_t grid = (size_t)p->sy * p->sx;
   hipEvent_t end;
-  WDD_HIP(p, stage_begin(p, kWiener, &end));
-  WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sx, p->stream));
-  WDD_HIP(p, stage_end(p, end));
+  if (reduce) {
+    WDD_HIP(p, stage_begin(p, kWiener, &end));
+    WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sx, p->stream));
+    WDD_HIP(p, stage_end(p, end));
+  }
   WDD_HIP(p, stage_begin(p, kDisplay, &end));
   WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sy, p->sx, p->ex, p->d, 1.f, 0, p->stream));
   WDD_HIP(p, wdd::launch_dft_rows(p->u, p->o, p->sx, p->sy, p->ey, p->d, (float)((double)p->sy * p->sx), 1,
@@ -378,6 +437,32 @@ wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_
   WDD_HIP(p, harvest(p));
   if (frames_seen) *frames_seen = p->frames_seen;
   return WDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device) {
+  return push_impl(p, frames, pos_yx, n, frames_on_device, false, nullptr);
+}
+
+wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  return snapshot_impl(p, out, out_on_device, frames_seen, true);
+}
+
+wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
+                             int32_t frames_on_device, float* out, int32_t out_on_device, uint64_t* frames_seen) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  bool fused = false;
+  st = push_impl(p, frames, pos_yx, n, frames_on_device, n > 0, &fused);
+  if (st != WDD_OK) return st;
+  return snapshot_impl(p, out, out_on_device, frames_seen, !fused);
 }
 
 static wdd_status copy_rows(wdd_plan_s* p, void* dst, const void* src, size_t rows, size_t row_bytes,
@@ -430,7 +515,7 @@ wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on) {
   if (st != WDD_OK) return st;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   WDD_HIP(p, harvest(p));
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     p->stage_ms[i] = 0;
     p->stage_n[i] = 0;
   }
@@ -445,6 +530,8 @@ wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out) {
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   WDD_HIP(p, harvest(p));
   out->project_ms = p->stage_ms[kProject];
+  out->rowdft_ms = p->stage_ms[kRowDft];
+  out->rowdft_launches = p->stage_n[kRowDft];
   out->accumulate_ms = p->stage_ms[kAccumulate];
   out->wiener_ms = p->stage_ms[kWiener];
   out->display_ms = p->stage_ms[kDisplay];

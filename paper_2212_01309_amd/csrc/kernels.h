@@ -33,6 +33,15 @@ hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
                            float s_total, int final_scale, hipStream_t st);
 
+// Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
+// Tx[(vx x_b) mod sx] h[b][c]; then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
+// optionally followed by the Wiener reduction of launch_wiener in the same pass.
+hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
+                          const float2* tx, int sx, float2* t, hipStream_t st);
+hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
+                             const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
+                             const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st);
+
 hipError_t launch_zero(float* p, size_t n, hipStream_t st);
 
 }  // namespace wdd

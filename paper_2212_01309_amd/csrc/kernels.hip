@@ -32,61 +32,74 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ inline void load8(const T* __restrict__ row, float* v);
-
+struct Chunk;
 template <>
-__device__ inline void load8<uint16_t>(const uint16_t* __restrict__ p, float* v) {
-  const uint4 raw = *reinterpret_cast<const uint4*>(p);
-  const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    v[2 * i] = (float)(w[i] & 0xffffu);
-    v[2 * i + 1] = (float)(w[i] >> 16);
+struct Chunk<uint16_t> {
+  uint4 v;
+  __device__ inline void load(const uint16_t* p) { v = *reinterpret_cast<const uint4*>(p); }
+  __device__ inline void zero() { v = make_uint4(0u, 0u, 0u, 0u); }
+  __device__ inline float get(int j) const {
+    const uint32_t w = (j < 2) ? v.x : (j < 4) ? v.y : (j < 6) ? v.z : v.w;
+    return (float)((j & 1) ? (w >> 16) : (w & 0xffffu));
   }
-}
-
+};
 template <>
-__device__ inline void load8<float>(const float* __restrict__ p, float* v) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
+struct Chunk<float> {
+  float4 a, b;
+  __device__ inline void load(const float* p) {
+    a = *reinterpret_cast<const float4*>(p);
+    b = *reinterpret_cast<const float4*>(p + 4);
+  }
+  __device__ inline void zero() { a = b = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ inline float get(int j) const {
+    switch (j) {
+      case 0: return a.x; case 1: return a.y; case 2: return a.z; case 3: return a.w;
+      case 4: return b.x; case 5: return b.y; case 6: return b.z; default: return b.w;
+    }
+  }
+};
 
+// One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
+// more tiles than waves).  A wave first issues the loads of up to 8 chunks of 32
+// pixels per row (256 columns), then runs their MFMAs, so the loads of a tile are in
+// flight together.
 template <typename T>
-__global__ __launch_bounds__(256) void k_project(const T* __restrict__ frames, int ny, int nx,
-                                                 const float* __restrict__ psi, const int* __restrict__ kmap,
-                                                 int kpad, float* __restrict__ h) {
+__global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
+                                                  const float* __restrict__ psi, const int* __restrict__ kmap,
+                                                  int kpad, float* __restrict__ h) {
   extern __shared__ float smem[];
+  const int nw = blockDim.x >> 6;
   float* lpsy = smem;               // [ny][16]
   float* lpsx = smem + ny * 16;     // [nx][16]
-  float* lg = lpsx + nx * 16;       // [4][256]
+  float* lg = lpsx + nx * 16;       // [nw][256]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < (ny + nx) * 16; i += 256) smem[i] = psi[i];
+  for (int i = tid; i < (ny + nx) * 16; i += blockDim.x) smem[i] = psi[i];
   __syncthreads();
 
   const T* f = frames + (size_t)blockIdx.x * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
   const int ntiles = (ny + 15) >> 4;
-  for (int t = wave; t < ntiles; t += 4) {
+  for (int t = wave; t < ntiles; t += nw) {
     const int y = t * 16 + r16;
     floatx4 tacc = {0.f, 0.f, 0.f, 0.f};
-    for (int x0 = 0; x0 < nx; x0 += 32) {
-      const int xs = x0 + 8 * q;
-      float v[8];
-      const bool ok = (y < ny) && (xs < nx);
-      if (ok) {
-        load8<T>(f + (size_t)y * nx + xs, v);
-      } else {
+    for (int xg = 0; xg < nx; xg += 256) {
+      Chunk<T> ch[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = 0.f;
+      for (int c = 0; c < 8; ++c) {
+        const int xs = xg + 32 * c + 8 * q;
+        if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+        else ch[c].zero();
       }
-      const int xb = (xs < nx) ? xs : 0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float bv = (xs < nx) ? lpsx[(xb + j) * 16 + r16] : 0.f;
-        tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[j], bv, tacc, 0, 0, 0);
+      for (int c = 0; c < 8; ++c) {
+        const int xs = xg + 32 * c + 8 * q;
+        const int xb = (xs < nx) ? xs : 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float bv = (xs < nx) ? lpsx[(xb + j) * 16 + r16] : 0.f;
+          tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j), bv, tacc, 0, 0, 0);
+        }
       }
     }
 #pragma unroll
@@ -99,11 +112,12 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ frames, i
 #pragma unroll
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
-  for (int k = tid; k < kpad; k += 256) {
+  for (int k = tid; k < kpad; k += blockDim.x) {
     const int idx = kmap[k];
-    float s = 0.f;
-    if (idx >= 0) s = (lg[idx] + lg[256 + idx]) + (lg[512 + idx] + lg[768 + idx]);
-    h[(size_t)blockIdx.x * kpad + k] = s;
+    float sum = 0.f;
+    if (idx >= 0)
+      for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+    h[(size_t)blockIdx.x * kpad + k] = sum;
   }
 }
 
@@ -289,6 +303,119 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row-factored accumulation.  The unitary scan DFT matrix is F_y (x) F_x
+// (Section 6.1), so for the frames of a batch that share scan row y_r
+//   T_r[vx][k] = sum_{b in row r} Tx[(vx x_b) mod Sx] h_b[k]        (k_row_dft)
+//   A[v][k]   += sum_r Ty[(vy y_r) mod Sy] T_r[vx(v)][k]            (k_row_update)
+// which is the direct sum over frames, regrouped.  k_row_update streams the
+// accumulator once per batch and is bound by HBM bandwidth.
+// rows[r] = (y_r, first index into `order`, number of frames, 0); order lists the
+// batch's frame indices grouped by row.
+// ---------------------------------------------------------------------------
+// One wave per 64 consecutive (vx, k) outputs of one row.  Per chunk of 64 frames the
+// lanes first stage each frame's index and x-phase(s) in LDS, then every lane sums
+// over the chunk with broadcast LDS reads and coalesced loads of h.
+__global__ __launch_bounds__(64) void k_row_dft(const float* __restrict__ h, int kpad, const int2* __restrict__ pos,
+                                                const int* __restrict__ order, const int4* __restrict__ rows,
+                                                const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
+  __shared__ float2 lph[2][64];
+  __shared__ int lb[64];
+  const int r = blockIdx.y, lane = threadIdx.x;
+  const int4 row = rows[r];
+  const int total = sx * kpad;
+  const int e = blockIdx.x * 64 + lane;
+  const int vx0 = (blockIdx.x * 64) / kpad;
+  const int nvx = kpad >= 64 ? 1 : 64 / kpad;  // kpad is a power of two >= 32
+  const int vx = e / kpad, k = e - vx * kpad;
+  const bool p2 = (sx & (sx - 1)) == 0;
+  const float inv = 1.0f / (float)sx;
+  float re = 0.f, im = 0.f;
+  for (int i0 = 0; i0 < row.z; i0 += 64) {
+    const int cnt = min(64, row.z - i0);
+    __syncthreads();
+    if (lane < cnt) {
+      const int b = order[row.y + i0 + lane];
+      const int x = pos[b].y;
+      lb[lane] = b;
+      for (int q = 0; q < nvx; ++q) {
+        const int vv = vx0 + q;
+        float2 w = make_float2(0.f, 0.f);
+        if (vv < sx) {
+          const int p = vv * x;
+          w = tx[p2 ? (p & (sx - 1)) : mod_small(p, sx, inv)];
+        }
+        lph[q][lane] = w;
+      }
+    }
+    __syncthreads();
+    if (e < total) {
+      const float2* ph = lph[vx - vx0];
+#pragma unroll 8
+      for (int i = 0; i < cnt; ++i) {
+        const float2 w = ph[i];
+        const float hv = h[(size_t)lb[i] * kpad + k];
+        re += w.x * hv;
+        im += w.y * hv;
+      }
+    }
+  }
+  if (e < total) t[((size_t)r * sx + vx) * kpad + k] = make_float2(re, im);
+}
+
+// One group of G = kpad / 4 consecutive lanes per kept frequency; each lane owns 4
+// consecutive complex entries of A.  With FUSE the Wiener reduction of the new A
+// (k_wiener) is done in the same pass.
+template <bool FUSE>
+__global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, int kpad, const int2* __restrict__ freqs,
+                                                    int64_t n_freq, const float2* __restrict__ t, int sx,
+                                                    const int4* __restrict__ rows, int nrows,
+                                                    const float2* __restrict__ ty, int sy,
+                                                    const float2* __restrict__ w, float2* __restrict__ d,
+                                                    float2* __restrict__ z) {
+  const int g = kpad >> 2;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = gid / g;
+  const int c = 4 * (int)(gid - j * g);
+  const int2 v = freqs[j];
+  const bool p2 = (sy & (sy - 1)) == 0;
+  const float inv = 1.0f / (float)sy;
+  float4* a4 = reinterpret_cast<float4*>(acc + j * kpad + c);
+  float4 a0 = a4[0], a1 = a4[1];
+  for (int r = 0; r < nrows; ++r) {
+    const int p = v.x * rows[r].x;
+    const float2 ph = ty[p2 ? (p & (sy - 1)) : mod_small(p, sy, inv)];
+    const float4* t4 = reinterpret_cast<const float4*>(t + ((size_t)r * sx + v.y) * kpad + c);
+    const float4 t0 = t4[0], t1 = t4[1];
+    a0.x += ph.x * t0.x - ph.y * t0.y;
+    a0.y += ph.x * t0.y + ph.y * t0.x;
+    a0.z += ph.x * t0.z - ph.y * t0.w;
+    a0.w += ph.x * t0.w + ph.y * t0.z;
+    a1.x += ph.x * t1.x - ph.y * t1.y;
+    a1.y += ph.x * t1.y + ph.y * t1.x;
+    a1.z += ph.x * t1.z - ph.y * t1.w;
+    a1.w += ph.x * t1.w + ph.y * t1.z;
+  }
+  a4[0] = a0;
+  a4[1] = a1;
+  if (FUSE) {
+    const float4* w4 = reinterpret_cast<const float4*>(w + j * kpad + c);
+    const float4 w0 = w4[0], w1 = w4[1];
+    float re = (a0.x * w0.x - a0.y * w0.y) + (a0.z * w0.z - a0.w * w0.w);
+    float im = (a0.x * w0.y + a0.y * w0.x) + (a0.z * w0.w + a0.w * w0.z);
+    re += (a1.x * w1.x - a1.y * w1.y) + (a1.z * w1.z - a1.w * w1.w);
+    im += (a1.x * w1.y + a1.y * w1.x) + (a1.z * w1.w + a1.w * w1.z);
+    for (int off = g >> 1; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (c == 0 && j < n_freq) {
+      d[j] = make_float2(re, im);
+      z[(size_t)v.x * sx + v.y] = make_float2(re, -im);
+    }
+  }
+}
+
 __global__ void k_zero(float* __restrict__ p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t st = (size_t)gridDim.x * blockDim.x;
@@ -298,14 +425,16 @@ __global__ void k_zero(float* __restrict__ p, size_t n) {
 template <typename T>
 hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap, int kpad,
                             float* h, hipStream_t st) {
-  const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + 4 * 256 * sizeof(float);
+  const int ntiles = (ny + 15) / 16;
+  const int nw = ntiles < 16 ? ntiles : 16;
+  const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_project<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(256), lds, st, static_cast<const T*>(frames), ny, nx, psi, kmap,
+  hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(64 * nw), lds, st, static_cast<const T*>(frames), ny, nx, psi, kmap,
                      kpad, h);
   return hipGetLastError();
 }
@@ -371,6 +500,28 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
   }
   const size_t lds = (size_t)len * sizeof(float2);
   hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, rows, len, lg, e, d0, s_total, final_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
+                          const float2* tx, int sx, float2* t, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((sx * kpad + 63) / 64), (unsigned)nrows);
+  hipLaunchKernelGGL(k_row_dft, grid, dim3(64), 0, st, h, kpad, pos, order, rows, tx, sx, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
+                             const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
+                             const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st) {
+  const int64_t threads = n_freq_pad * (kpad / 4);
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  if (fuse_wiener)
+    hipLaunchKernelGGL(k_row_update<true>, dim3(blocks), dim3(256), 0, st, acc, kpad, freqs, n_freq, t, sx, rows,
+                       nrows, ty, sy, w, d, z);
+  else
+    hipLaunchKernelGGL(k_row_update<false>, dim3(blocks), dim3(256), 0, st, acc, kpad, freqs, n_freq, t, sx, rows,
+                       nrows, ty, sy, w, d, z);
   return hipGetLastError();
 }
 

@@ -173,3 +173,52 @@ def test_invalid_plans_are_rejected():
     assert ei.value.code == wdd.WDD_EINVAL
     with pytest.raises(wdd.WddError):
         wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=0)
+
+
+def _oracle_all(radius, s, n, k, frames, pos):
+    plan = O.make_plan(s, s, n, n, radius, k)
+    live = O.Live(plan, "N")
+    live.push(frames, pos)
+    return live.acc, live.spectrum(), live.snapshot()
+
+
+@pytest.mark.parametrize("rows", [1, 2, 16, 17, 40])
+def test_row_factored_and_direct_updates_agree(rows):
+    """Batches on <= 16 scan rows take the row-factored update, others the direct one;
+    both must reproduce the oracle, also at the boundary."""
+    s, n, k = 48, 32, 64
+    rng = np.random.default_rng(100 + rows)
+    ys = rng.choice(s, size=rows, replace=False)
+    b = 96
+    pos = np.stack([ys[rng.integers(0, rows, size=b)], rng.integers(0, s, size=b)], axis=1).astype(np.int32)
+    frames = rng.poisson(30.0, size=(b, n, n)).astype(np.uint16)
+    with wdd.Plan(8.0, s, s, n, n, k, max_batch=b) as plan:
+        plan.profile_enable(True)
+        plan.push(device(frames), pos)
+        o = plan.snapshot()
+        prof = plan.profile_read()
+        a, d = plan.accumulator(), plan.spectrum()
+    assert prof["rowdft_launches"] == (1 if rows <= 16 else 0)
+    ra, rd, ro = _oracle_all(8.0, s, n, k, frames, pos)
+    errs = (rel(a, ra), rel(d, rd), rel(o, ro))
+    say(f"[api] rows={rows}: A/D/O {errs}")
+    assert max(errs) <= TOL
+
+
+def test_push_snapshot_matches_push_then_snapshot():
+    s, n, k = 32, 32, 100          # K not a power of two
+    rng = np.random.default_rng(11)
+    frames = rng.poisson(10.0, size=(6 * 32, n, n)).astype(np.uint16)
+    lin = np.concatenate([np.arange(32) + 32 * r for r in range(3)] + [rng.integers(0, s * s, size=96)])
+    pos = np.stack([lin // s, lin % s], axis=1).astype(np.int32)
+    dev = device(frames)
+    with wdd.Plan(8.0, s, s, n, n, k, max_batch=32) as p1, wdd.Plan(8.0, s, s, n, n, k, max_batch=32) as p2:
+        for b in range(0, len(pos), 32):
+            p1.push(dev[b:b + 32], pos[b:b + 32])
+            o1 = p1.snapshot()
+            o2 = p2.push_snapshot(dev[b:b + 32], pos[b:b + 32])
+            assert rel(o2, o1) <= 1e-6, b
+            assert rel(p2.spectrum(), p1.spectrum()) <= 1e-6
+        assert np.array_equal(p1.accumulator(), p2.accumulator())
+        o3 = p2.push_snapshot(dev[:0], pos[:0])     # n = 0: a plain snapshot
+        assert rel(o3, o1) <= 1e-6
