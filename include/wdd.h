@@ -169,10 +169,17 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
 /* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
  * conjugation and normalisation (eq. extract).  Writes sy x sx complex values
  * (interleaved float, row-major [y][x]) to `out` (device memory if
- * out_on_device != 0, else host memory).  Blocks until `out` is written.
+ * out_on_device != 0, 8-byte aligned; else host memory).  Blocks until `out` is
+ * written.
  * Object pixel mapping: out[y][x] is the object at scan position (y, x) shifted
  * by the probe's centre (ny/2, nx/2) within its window.  frames_seen may be NULL. */
 wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen);
+
+/* The plan's pinned host buffer of sy x sx complex values that host snapshots are
+ * written through.  Passing it as `out` (out_on_device = 0) skips the final host
+ * copy.  Owned by the plan, valid until wdd_plan_destroy; each host snapshot
+ * overwrites it. */
+wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out);
 
 /* Inspection (blocking): the Wiener-reduced spectrum D on the kept frequencies,
  * n_freq complex values, as computed by the last wdd_snapshot. */
@@ -199,8 +206,19 @@ typedef struct {
   int64_t rowdft_launches;
 } wdd_profile;
 
-/* Turns stage timing on (on != 0) or off and zeroes the totals. */
-wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on);
+/* Stages selectable for timing (bit mask). */
+enum {
+  WDD_STAGE_PROJECT = 1,
+  WDD_STAGE_ACCUMULATE = 2,
+  WDD_STAGE_WIENER = 4,
+  WDD_STAGE_DISPLAY = 8,
+  WDD_STAGE_ROWDFT = 16,
+  WDD_STAGE_ALL = 31
+};
+
+/* Times the stages in the mask `stages` (0 turns timing off) and zeroes the totals.
+ * Each timed launch adds two event records to the plan stream. */
+wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages);
 
 /* Totals since profiling was enabled (blocks until the timed work has finished). */
 wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);

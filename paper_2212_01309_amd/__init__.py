@@ -19,6 +19,7 @@ _lib: Optional[ctypes.CDLL] = None
 WDD_OK, WDD_EINVAL, WDD_ENOMEM, WDD_ERANGE, WDD_EDEVICE, WDD_EBUSY, WDD_ESTATE = 0, -1, -2, -3, -4, -5, -6
 WDD_U16, WDD_F32 = 0, 1
 WDD_FP32 = 0
+STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
 _STATUS_NAMES = {0: "WDD_OK", -1: "WDD_EINVAL", -2: "WDD_ENOMEM", -3: "WDD_ERANGE", -4: "WDD_EDEVICE",
                  -5: "WDD_EBUSY", -6: "WDD_ESTATE"}
@@ -76,6 +77,7 @@ _SIGNATURES = {
     "wdd_snapshot": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "wdd_push_snapshot": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "wdd_snapshot_buffer": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_float))]),
     "wdd_get_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_get_accumulator": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_get_projection": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -281,6 +283,14 @@ class Plan:
             raise ValueError("host output must be a C-contiguous complex64 array of sy*sx elements")
         return out
 
+    def snapshot_buffer(self) -> np.ndarray:
+        """The plan's pinned host array [sy, sx] complex64 that host snapshots pass through;
+        give it as `out` to avoid the final copy.  Overwritten by every host snapshot."""
+        ptr = ctypes.POINTER(ctypes.c_float)()
+        _check(load_library().wdd_snapshot_buffer(self._h, ctypes.byref(ptr)))
+        flat = np.ctypeslib.as_array(ptr, shape=(2 * self.sy * self.sx,))
+        return flat.view(np.complex64).reshape(self.sy, self.sx)
+
     def spectrum(self) -> np.ndarray:
         """D on the kept frequencies from the last snapshot, complex64 [n_freq]."""
         d = np.empty(self.n_freq, np.complex64)
@@ -299,8 +309,9 @@ class Plan:
         _check(load_library().wdd_get_projection(self._h, h.ctypes.data, 0))
         return h
 
-    def profile_enable(self, on: bool = True) -> None:
-        _check(load_library().wdd_profile_enable(self._h, 1 if on else 0))
+    def profile_enable(self, stages: int = 31) -> None:
+        """Time the stages in the bit mask (STAGE_* constants; 0 turns timing off)."""
+        _check(load_library().wdd_profile_enable(self._h, int(stages)))
 
     def profile_read(self) -> dict:
         pr = Profile()

@@ -15,7 +15,7 @@
 //   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs of the row-factored accumulation
 //   frames  staging for host frames     [max_batch][ny][nx]
 //   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
-//   z, u, o float2 [sy * sx]            conj(D) grid, row-transformed grid, output
+//   z, u    float2 [sx][sy], [sy][sx]   conj(D) grid (transposed), grid transformed along y
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,7 +59,7 @@ struct wdd_plan_impl {
   size_t upload_bytes = 0;
   float2* t = nullptr;
   void* frames = nullptr;
-  float2 *d = nullptr, *z = nullptr, *u = nullptr, *o = nullptr;
+  float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
   char* pin_up[kRing] = {};
   void* pin_frames[kRing] = {};
@@ -70,7 +70,7 @@ struct wdd_plan_impl {
   std::vector<void*> allocs;
 
   // stage timing (wdd_profile_*): events around launches, harvested when the stream is idle
-  bool profiling = false;
+  int32_t profile_mask = 0;  // bit i: time stage i (Stage enum)
   std::vector<hipEvent_t> ev_pool;
   struct Pending { int stage; hipEvent_t e0, e1; };
   std::vector<Pending> pending;
@@ -117,7 +117,7 @@ enum Stage { kProject = 0, kAccumulate = 1, kWiener = 2, kDisplay = 3, kRowDft =
 // Opens a timed stage: returns the end event to record after the launches (or null).
 hipError_t stage_begin(wdd_plan_s* p, int stage, hipEvent_t* end) {
   *end = nullptr;
-  if (!p->profiling) return hipSuccess;
+  if (!(p->profile_mask & (1 << stage))) return hipSuccess;
   hipEvent_t e[2];
   for (int i = 0; i < 2; ++i) {
     if (!p->ev_pool.empty()) {
@@ -252,7 +252,6 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   ALLOC(p->d, (size_t)p->n_freq_pad);
   ALLOC(p->z, grid);
   ALLOC(p->u, grid);
-  ALLOC(p->o, grid);
 #undef ALLOC
 
   // Wiener filter, FP64 -> FP32, padded
@@ -327,7 +326,7 @@ namespace {
 // Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
 // reduction of the updated spectrum; *fused reports whether it did.
 wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device,
-                     bool fuse_wiener, bool* fused) {
+                     bool fuse_wiener, bool* fused, bool drained_after = false) {
   if (fused) *fused = false;
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
@@ -367,7 +366,6 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     std::memcpy(up + roff, p->host_rows.data(), (size_t)nrows * sizeof(int4));
     up_bytes = roff + (size_t)nrows * sizeof(int4);
   }
-  WDD_HIP(p, hipMemcpyAsync(p->upload, up, up_bytes, hipMemcpyHostToDevice, p->stream));
   const void* fdev = frames;
   if (!frames_on_device) {
     if (!p->pin_frames[s]) {
@@ -382,16 +380,24 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
                               p->stream));
     fdev = p->frames;
   }
-  WDD_HIP(p, hipEventRecord(p->ev[s], p->stream));
-  p->ev_live[s] = true;
   if (p->pending.size() > 4096) {  // bound the events held while nobody snapshots
     WDD_HIP(p, hipStreamSynchronize(p->stream));
     WDD_HIP(p, harvest(p));
   }
   hipEvent_t end;
   WDD_HIP(p, stage_begin(p, kProject, &end));
-  WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, p->stream));
+  // the projection kernel also brings the pinned upload block (positions, grouping) to the device
+  WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
+                                 up_bytes, p->stream));
   WDD_HIP(p, stage_end(p, end));
+  // slot s (pinned upload and frames) may be refilled once this point of the stream is reached;
+  // a caller that drains the stream before returning needs no marker
+  if (!drained_after) {
+    WDD_HIP(p, hipEventRecord(p->ev[s], p->stream));
+    p->ev_live[s] = true;
+  } else {
+    p->ev_live[s] = false;
+  }
   if (factored) {
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
     WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
@@ -418,22 +424,21 @@ wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint6
   hipEvent_t end;
   if (reduce) {
     WDD_HIP(p, stage_begin(p, kWiener, &end));
-    WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sx, p->stream));
+    WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sy, p->stream));
     WDD_HIP(p, stage_end(p, end));
   }
+  // the second pass writes the displayed object straight to its destination: the caller's
+  // device buffer, or the plan's pinned host buffer (copied to `out` unless it is that buffer)
+  float2* dst = out_on_device ? reinterpret_cast<float2*>(out) : p->pin_out;
   WDD_HIP(p, stage_begin(p, kDisplay, &end));
-  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sy, p->sx, p->ex, p->d, 1.f, 0, p->stream));
-  WDD_HIP(p, wdd::launch_dft_rows(p->u, p->o, p->sx, p->sy, p->ey, p->d, (float)((double)p->sy * p->sx), 1,
+  // z is conj(D) stored [vx][vy]: transform along vy (written transposed, u = [y][vx]), then
+  // along vx, writing whole rows of the output
+  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, 1, p->stream));
+  WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, 0,
                                   p->stream));
   WDD_HIP(p, stage_end(p, end));
-  if (out_on_device) {
-    WDD_HIP(p, hipMemcpyAsync(out, p->o, grid * sizeof(float2), hipMemcpyDeviceToDevice, p->stream));
-    WDD_HIP(p, hipStreamSynchronize(p->stream));
-  } else {
-    WDD_HIP(p, hipMemcpyAsync(p->pin_out, p->o, grid * sizeof(float2), hipMemcpyDeviceToHost, p->stream));
-    WDD_HIP(p, hipStreamSynchronize(p->stream));
-    std::memcpy(out, p->pin_out, grid * sizeof(float2));
-  }
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  if (!out_on_device && reinterpret_cast<float2*>(out) != p->pin_out) std::memcpy(out, p->pin_out, grid * sizeof(float2));
   WDD_HIP(p, harvest(p));
   if (frames_seen) *frames_seen = p->frames_seen;
   return WDD_OK;
@@ -447,10 +452,17 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
   return push_impl(p, frames, pos_yx, n, frames_on_device, false, nullptr);
 }
 
+static wdd_status check_out(const float* out, int32_t out_on_device) {
+  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  if (out_on_device && (reinterpret_cast<uintptr_t>(out) % 8) != 0)
+    return wdd::fail(WDD_EINVAL, "device output must be 8-byte aligned");
+  return WDD_OK;
+}
+
 wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
-  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  if ((st = check_out(out, out_on_device)) != WDD_OK) return st;
   return snapshot_impl(p, out, out_on_device, frames_seen, true);
 }
 
@@ -458,9 +470,9 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
                              int32_t frames_on_device, float* out, int32_t out_on_device, uint64_t* frames_seen) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
-  if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  if ((st = check_out(out, out_on_device)) != WDD_OK) return st;
   bool fused = false;
-  st = push_impl(p, frames, pos_yx, n, frames_on_device, n > 0, &fused);
+  st = push_impl(p, frames, pos_yx, n, frames_on_device, n > 0, &fused, /*drained_after=*/true);
   if (st != WDD_OK) return st;
   return snapshot_impl(p, out, out_on_device, frames_seen, !fused);
 }
@@ -470,6 +482,14 @@ static wdd_status copy_rows(wdd_plan_s* p, void* dst, const void* src, size_t ro
   WDD_HIP(p, hipMemcpy2DAsync(dst, row_bytes, src, src_pitch, row_bytes, rows,
                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
   WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!host_out) return wdd::fail(WDD_EINVAL, "null argument");
+  *host_out = reinterpret_cast<float*>(p->pin_out);
   return WDD_OK;
 }
 
@@ -510,7 +530,8 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info) {
   return WDD_OK;
 }
 
-wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on) {
+wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages) {
+  const int32_t on = stages;
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
@@ -519,7 +540,7 @@ wdd_status wdd_profile_enable(wdd_plan_t p, int32_t on) {
     p->stage_ms[i] = 0;
     p->stage_n[i] = 0;
   }
-  p->profiling = on != 0;
+  p->profile_mask = on & 0x1f;
   return WDD_OK;
 }
 

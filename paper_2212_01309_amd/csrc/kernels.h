@@ -13,8 +13,9 @@ namespace wdd {
 
 // h[b][k] = sum_q Phi[q][k] frames[b][q] for b < n.  psi: [ny][16] then [nx][16]
 // (columns >= L zero); kmap[k] = 16 n_y(k) + n_x(k), or -1 for padding columns.
+// Also copies up_bytes (a multiple of 4) from up_src (pinned host memory) to up_dst.
 hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, hipStream_t st);
+                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st);
 
 // Columns (in blocks of 32) per accumulation workgroup for a padded basis size.
 int accumulate_col_blocks(int kpad);
@@ -25,17 +26,18 @@ hipError_t launch_accumulate(float2* acc, int kpad, int64_t n_freq_pad, const in
                              const int2* pos, int n, const float2* ty, int sy, const float2* tx, int sx,
                              hipStream_t st);
 
-// d[j] = sum_c w[j][c] acc[j][c]; z[v_y(j)][v_x(j)] = conj(d[j]).
+// d[j] = sum_c w[j][c] acc[j][c]; z[v_x(j)][v_y(j)] = conj(d[j]) (z is [sx][sy]).
 hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int2* freqs, int64_t n_freq, float2* d,
-                         float2* z, int sx, hipStream_t st);
+                         float2* z, int sy, hipStream_t st);
 
-// out[c][r] = scale * sum_m in[r][m] e[(m c) mod len] for r < rows (see kernels.hip).
+// out[c][r] (transpose) or out[r][c] = scale * sum_m in[r][m] e[(m c) mod len] for r < rows
+// (see kernels.hip).
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
-                           float s_total, int final_scale, hipStream_t st);
+                           float s_total, int final_scale, int transpose, hipStream_t st);
 
 // Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
 // Tx[(vx x_b) mod sx] h[b][c]; then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
-// optionally followed by the Wiener reduction of launch_wiener in the same pass.
+// optionally followed by the Wiener reduction of launch_wiener in the same pass (z as there).
 hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
                           const float2* tx, int sx, float2* t, hipStream_t st);
 hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,

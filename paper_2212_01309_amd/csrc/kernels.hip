@@ -66,33 +66,48 @@ struct Chunk<float> {
 template <typename T>
 __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
                                                   const float* __restrict__ psi, const int* __restrict__ kmap,
-                                                  int kpad, float* __restrict__ h) {
+                                                  int kpad, float* __restrict__ h, const uint32_t* __restrict__ up_src,
+                                                  uint32_t* __restrict__ up_dst, int up_words) {
   extern __shared__ float smem[];
   const int nw = blockDim.x >> 6;
   float* lpsy = smem;               // [ny][16]
   float* lpsx = smem + ny * 16;     // [nx][16]
   float* lg = lpsx + nx * 16;       // [nw][256]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T* f = frames + (size_t)blockIdx.x * ny * nx;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int ntiles = (ny + 15) >> 4;
+  // loads of this wave's first chunk group go out before anything else
+  Chunk<T> ch[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int y = wave * 16 + r16, xs = 32 * c + 8 * q;
+    if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+    else ch[c].zero();
+  }
+  // the batch's positions / grouping live in pinned host memory; block 0 brings them over
+  if (blockIdx.x == 0)
+    for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
   for (int i = tid; i < (ny + nx) * 16; i += blockDim.x) smem[i] = psi[i];
   __syncthreads();
 
-  const T* f = frames + (size_t)blockIdx.x * ny * nx;
-  const int r16 = lane & 15, q = lane >> 4;
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
-  const int ntiles = (ny + 15) >> 4;
   for (int t = wave; t < ntiles; t += nw) {
     const int y = t * 16 + r16;
     floatx4 tacc = {0.f, 0.f, 0.f, 0.f};
     for (int xg = 0; xg < nx; xg += 256) {
-      Chunk<T> ch[8];
+      if (t != wave || xg != 0) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int xs = xg + 32 * c + 8 * q;
-        if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
-        else ch[c].zero();
+        for (int c = 0; c < 8; ++c) {
+          const int xs = xg + 32 * c + 8 * q;
+          if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+          else ch[c].zero();
+        }
       }
+      const int nch = min(8, (nx - xg + 31) >> 5);  // chunks of 32 columns inside the frame
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
+        if (c >= nch) break;
         const int xs = xg + 32 * c + 8 * q;
         const int xb = (xs < nx) ? xs : 0;
 #pragma unroll
@@ -211,12 +226,12 @@ __global__ __launch_bounds__(256) void k_accumulate(float2* __restrict__ acc, in
 
 // ---------------------------------------------------------------------------
 // Wiener reduction: one wave per kept frequency; D[j] = sum_k W[j][k] A[j][k].
-// Also scatters conj(D[j]) into the sy x sx grid z (zeros elsewhere are set
-// once at plan creation), ready for the forward DFT of the display step.
+// Also scatters conj(D[j]) into the grid z, stored transposed as [sx][sy] (zeros
+// elsewhere are set once at plan creation), ready for the display DFT.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, const float2* __restrict__ w,
                                                 int kpad, const int2* __restrict__ freqs, int64_t n_freq,
-                                                float2* __restrict__ d, float2* __restrict__ z, int sx) {
+                                                float2* __restrict__ d, float2* __restrict__ z, int sy) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + wave;
   if (j >= n_freq) return;
@@ -238,20 +253,21 @@ __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, 
   if (lane == 0) {
     d[j] = make_float2(re, im);
     const int2 v = freqs[j];
-    z[(size_t)v.x * sx + v.y] = make_float2(re, -im);
+    z[(size_t)v.y * sy + v.x] = make_float2(re, -im);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Forward DFT of each row of a rows x len array, written transposed:
-// out[c * rows + r] = scale * sum_m in[r * len + m] * E[(m c) mod len],
+// Forward DFT of each row of a rows x len array, written transposed (out[c * rows + r])
+// or in place order (out[r * len + c]): scale * sum_m in[r * len + m] * E[(m c) mod len],
 // E[m] = exp(-2 pi i m / len) built in FP64 on the host.  Power-of-two
 // lengths use an in-LDS radix-2 decimation-in-time FFT, others a direct sum.
 // With `final_scale` set, scale = 1 / sqrt(S |D[0]|) (0 when D[0] = 0).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int rows,
                                                   int len, int log2len, const float2* __restrict__ e,
-                                                  const float2* __restrict__ d0, float s_total, int final_scale) {
+                                                  const float2* __restrict__ d0, float s_total, int final_scale,
+                                                  int transpose) {
   extern __shared__ float2 lbuf[];  // [len]
   const int r = blockIdx.x, tid = threadIdx.x;
   const float2* src = in + (size_t)r * len;
@@ -283,7 +299,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
     }
     for (int cidx = tid; cidx < len; cidx += 256) {
       const float2 v = lbuf[cidx];
-      out[(size_t)cidx * rows + r] = make_float2(v.x * scale, v.y * scale);
+      out[transpose ? (size_t)cidx * rows + r : (size_t)r * len + cidx] = make_float2(v.x * scale, v.y * scale);
     }
   } else {
     for (int m = tid; m < len; m += 256) lbuf[m] = src[m];
@@ -298,7 +314,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
         idx += cidx;
         idx -= (idx >= len) ? len : 0;
       }
-      out[(size_t)cidx * rows + r] = make_float2(re * scale, im * scale);
+      out[transpose ? (size_t)cidx * rows + r : (size_t)r * len + cidx] = make_float2(re * scale, im * scale);
     }
   }
 }
@@ -313,54 +329,77 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
 // rows[r] = (y_r, first index into `order`, number of frames, 0); order lists the
 // batch's frame indices grouped by row.
 // ---------------------------------------------------------------------------
-// One wave per 64 consecutive (vx, k) outputs of one row.  Per chunk of 64 frames the
-// lanes first stage each frame's index and x-phase(s) in LDS, then every lane sums
-// over the chunk with broadcast LDS reads and coalesced loads of h.
-__global__ __launch_bounds__(64) void k_row_dft(const float* __restrict__ h, int kpad, const int2* __restrict__ pos,
-                                                const int* __restrict__ order, const int4* __restrict__ rows,
-                                                const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
-  __shared__ float2 lph[2][64];
-  __shared__ int lb[64];
-  const int r = blockIdx.y, lane = threadIdx.x;
+// T_r = Fx_r h_r as a real GEMM with rows (vx, re/im) interleaved, on
+// v_mfma_f32_32x32x2_f32.  A workgroup of 4 waves owns one 32 x 32 tile (16 values
+// of vx x 32 columns) of row r.  Per chunk of up to 256 frames the Tx table, the
+// frames' indices and x positions and the chunk's h columns are staged in LDS; wave
+// w takes every fourth frame pair, and the four partial tiles are summed at the end.
+constexpr int kRowChunk = 256;
+
+__global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int2* __restrict__ pos,
+                                                 const int* __restrict__ order, const int4* __restrict__ rows,
+                                                 const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
+  extern __shared__ float2 rsmem[];
+  float2* ltx = rsmem;                                   // [sx]
+  int* lx = reinterpret_cast<int*>(ltx + sx);            // [kRowChunk]
+  int* lb = lx + kRowChunk;                              // [kRowChunk]
+  float* lh = reinterpret_cast<float*>(lb + kRowChunk);  // [kRowChunk][32]; reused for the final sum
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i32 = lane & 31, half = lane >> 5;
+  const int r = blockIdx.z;
   const int4 row = rows[r];
-  const int total = sx * kpad;
-  const int e = blockIdx.x * 64 + lane;
-  const int vx0 = (blockIdx.x * 64) / kpad;
-  const int nvx = kpad >= 64 ? 1 : 64 / kpad;  // kpad is a power of two >= 32
-  const int vx = e / kpad, k = e - vx * kpad;
+  const int vx = blockIdx.x * 16 + (i32 >> 1);
+  const bool im = (i32 & 1) != 0;
+  const int c0 = blockIdx.y * 32;
   const bool p2 = (sx & (sx - 1)) == 0;
   const float inv = 1.0f / (float)sx;
-  float re = 0.f, im = 0.f;
-  for (int i0 = 0; i0 < row.z; i0 += 64) {
-    const int cnt = min(64, row.z - i0);
+  for (int i = tid; i < sx; i += 256) ltx[i] = tx[i];
+  floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int i0 = 0; i0 < row.z; i0 += kRowChunk) {
+    const int cnt = min(kRowChunk, row.z - i0);
     __syncthreads();
-    if (lane < cnt) {
-      const int b = order[row.y + i0 + lane];
-      const int x = pos[b].y;
-      lb[lane] = b;
-      for (int q = 0; q < nvx; ++q) {
-        const int vv = vx0 + q;
-        float2 w = make_float2(0.f, 0.f);
-        if (vv < sx) {
-          const int p = vv * x;
-          w = tx[p2 ? (p & (sx - 1)) : mod_small(p, sx, inv)];
-        }
-        lph[q][lane] = w;
-      }
+    if (tid < cnt) {
+      const int b = order[row.y + i0 + tid];
+      lb[tid] = b;
+      lx[tid] = pos[b].y;
     }
     __syncthreads();
-    if (e < total) {
-      const float2* ph = lph[vx - vx0];
 #pragma unroll 8
-      for (int i = 0; i < cnt; ++i) {
-        const float2 w = ph[i];
-        const float hv = h[(size_t)lb[i] * kpad + k];
-        re += w.x * hv;
-        im += w.y * hv;
+    for (int i = tid; i < kRowChunk * 32; i += 256) {
+      const int f = i >> 5, c = i & 31;
+      lh[i] = (f < cnt) ? h[(size_t)lb[f] * kpad + c0 + c] : 0.f;
+    }
+    __syncthreads();
+    const int nk = (cnt + 1) >> 1;
+    for (int kk = wave; kk < nk; kk += 4) {
+      const int f = 2 * kk + half;
+      float a = 0.f;
+      if (f < cnt && vx < sx) {
+        const int p = vx * lx[f];
+        const float2 w = ltx[p2 ? (p & (sx - 1)) : mod_small(p, sx, inv)];
+        a = im ? w.y : w.x;
       }
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, lh[f * 32 + i32], acc, 0, 0, 0);
     }
   }
-  if (e < total) t[((size_t)r * sx + vx) * kpad + k] = make_float2(re, im);
+  __syncthreads();
+  if (wave > 0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lh[((wave - 1) * 16 + q) * 64 + lane] = acc[q];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+      float re = acc[q], imv = acc[q + 1];
+      for (int w = 0; w < 3; ++w) {
+        re += lh[(w * 16 + q) * 64 + lane];
+        imv += lh[(w * 16 + q + 1) * 64 + lane];
+      }
+      const int rowi = 8 * (q >> 2) + 4 * half + (q & 3);
+      const int v = blockIdx.x * 16 + (rowi >> 1);
+      if (v < sx) t[((size_t)r * sx + v) * kpad + c0 + i32] = make_float2(re, imv);
+    }
+  }
 }
 
 // One group of G = kpad / 4 consecutive lanes per kept frequency; each lane owns 4
@@ -411,7 +450,7 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
     }
     if (c == 0 && j < n_freq) {
       d[j] = make_float2(re, im);
-      z[(size_t)v.x * sx + v.y] = make_float2(re, -im);
+      z[(size_t)v.y * sy + v.x] = make_float2(re, -im);
     }
   }
 }
@@ -424,7 +463,7 @@ __global__ void k_zero(float* __restrict__ p, size_t n) {
 
 template <typename T>
 hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap, int kpad,
-                            float* h, hipStream_t st) {
+                            float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
   const int ntiles = (ny + 15) / 16;
   const int nw = ntiles < 16 ? ntiles : 16;
   const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float);
@@ -435,7 +474,8 @@ hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const flo
     attr = true;
   }
   hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(64 * nw), lds, st, static_cast<const T*>(frames), ny, nx, psi, kmap,
-                     kpad, h);
+                     kpad, h, static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst),
+                     (int)(up_bytes / 4));
   return hipGetLastError();
 }
 
@@ -459,10 +499,11 @@ hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* f
 namespace wdd {
 
 hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, hipStream_t st) {
+                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (dtype == WDD_U16) return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, st);
-  return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, st);
+  if (dtype == WDD_U16)
+    return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
+  return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
 }
 
 int accumulate_col_blocks(int kpad) {
@@ -485,29 +526,37 @@ hipError_t launch_accumulate(float2* acc, int kpad, int64_t n_freq_pad, const in
 }
 
 hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int2* freqs, int64_t n_freq, float2* d,
-                         float2* z, int sx, hipStream_t st) {
+                         float2* z, int sy, hipStream_t st) {
   const unsigned blocks = (unsigned)((n_freq + 3) / 4);
-  hipLaunchKernelGGL(k_wiener, dim3(blocks), dim3(256), 0, st, acc, w, kpad, freqs, n_freq, d, z, sx);
+  hipLaunchKernelGGL(k_wiener, dim3(blocks), dim3(256), 0, st, acc, w, kpad, freqs, n_freq, d, z, sy);
   return hipGetLastError();
 }
 
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
-                           float s_total, int final_scale, hipStream_t st) {
+                           float s_total, int final_scale, int transpose, hipStream_t st) {
   int lg = -1;
   if ((len & (len - 1)) == 0) {
     lg = 0;
     while ((1 << lg) < len) ++lg;
   }
   const size_t lds = (size_t)len * sizeof(float2);
-  hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, rows, len, lg, e, d0, s_total, final_scale);
+  hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, rows, len, lg, e, d0, s_total, final_scale,
+                     transpose);
   return hipGetLastError();
 }
 
 hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
                           const float2* tx, int sx, float2* t, hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
-  dim3 grid((unsigned)((sx * kpad + 63) / 64), (unsigned)nrows);
-  hipLaunchKernelGGL(k_row_dft, grid, dim3(64), 0, st, h, kpad, pos, order, rows, tx, sx, t);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_row_dft, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 32 * sizeof(float);
+  dim3 grid((unsigned)((sx + 15) / 16), (unsigned)(kpad / 32), (unsigned)nrows);
+  hipLaunchKernelGGL(k_row_dft, grid, dim3(256), lds, st, h, kpad, pos, order, rows, tx, sx, t);
   return hipGetLastError();
 }
 

@@ -193,7 +193,7 @@ def test_row_factored_and_direct_updates_agree(rows):
     pos = np.stack([ys[rng.integers(0, rows, size=b)], rng.integers(0, s, size=b)], axis=1).astype(np.int32)
     frames = rng.poisson(30.0, size=(b, n, n)).astype(np.uint16)
     with wdd.Plan(8.0, s, s, n, n, k, max_batch=b) as plan:
-        plan.profile_enable(True)
+        plan.profile_enable(wdd.STAGE_ALL)
         plan.push(device(frames), pos)
         o = plan.snapshot()
         prof = plan.profile_read()
@@ -222,3 +222,17 @@ def test_push_snapshot_matches_push_then_snapshot():
         assert np.array_equal(p1.accumulator(), p2.accumulator())
         o3 = p2.push_snapshot(dev[:0], pos[:0])     # n = 0: a plain snapshot
         assert rel(o3, o1) <= 1e-6
+
+
+def test_snapshot_into_the_plans_pinned_buffer():
+    frames, pos = _random_case(12, 16, 16, 32, 32, 64, wdd.WDD_U16)
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64) as plan:
+        plan.push(device(frames), pos)
+        ref = plan.snapshot()
+        buf = plan.snapshot_buffer()
+        got = plan.snapshot(out=buf)
+        assert got is buf
+        assert np.array_equal(buf, ref)
+        buf[:] = 0
+        again = plan.push_snapshot(device(frames[:0]), pos[:0], out=buf)
+        assert np.array_equal(again, ref)
