@@ -29,6 +29,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="medium")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16_hilo", "fp16_hilo", "bf16", "fp16"],
+                    help="arithmetic of the projection's first stage (FP32 accumulation throughout)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -127,7 +129,7 @@ def main():
     torch.cuda.synchronize()
     dtype = wdd.WDD_U16 if frames.dtype == np.uint16 else wdd.WDD_F32
     plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
-                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch)
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch, precision=args.precision)
     nb = len(pos) // wl.batch
     batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
 
@@ -172,7 +174,9 @@ def main():
     out = {
         "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else f"{args.precision} projection, f32 accumulate",
+        "data": "synthetic",
         "config": {"workload": workload_label(wl, n_freq), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype)},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},

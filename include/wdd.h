@@ -58,7 +58,11 @@ typedef enum {
 
 typedef enum { WDD_U16 = 0, WDD_F32 = 1 } wdd_dtype;
 
-typedef enum { WDD_FP32 = 0 } wdd_precision;
+/* Arithmetic of the projection's first (N^2 L) stage.  WDD_FP32: FP32 MFMA.  The others
+ * need uint16 frames and use BF16 or FP16 MFMA with FP32 accumulation: counts are split
+ * exactly into two digits, the basis is rounded to one (BF16, FP16) or two (_HILO:
+ * hi + lo) 16-bit parts.  Everything after the projection stays FP32. */
+typedef enum { WDD_FP32 = 0, WDD_BF16_HILO = 1, WDD_FP16_HILO = 2, WDD_BF16 = 3, WDD_FP16 = 4 } wdd_precision;
 
 /* Fourier-space probe: amplitude * 1[|u| <= radius] * exp(-i defocus_edge_rad |u|^2 / radius^2),
  * u = detector pixel - (ny/2, nx/2).  Initial probe of the pre-computed Wiener
@@ -222,6 +226,22 @@ wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages);
 
 /* Totals since profiling was enabled (blocks until the timed work has finished). */
 wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);
+
+/* Re-deconvolution: replaces the Wiener filter by the one of `probe` (same aperture
+ * radius; defocus and amplitude may change) and `eps_rel`, built in FP64 as at plan
+ * creation.  The accumulated spectrum A is kept (it does not depend on the probe), so
+ * the next snapshot deconvolves every frame seen so far with the new filter without
+ * re-reading them (Section 10: probe update; Algorithm "pre-computed Wiener filter").
+ * WDD_EINVAL if the radius differs. */
+wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel);
+
+/* Checkpoint of the live state (the spectrum A and the frame count, a sufficient
+ * statistic of all frames pushed).  wdd_checkpoint_size gives the byte size of the
+ * image; wdd_checkpoint_save writes it to host memory (blocking); wdd_checkpoint_load
+ * restores it into a plan of the same geometry and basis (WDD_EINVAL otherwise). */
+wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes);
+wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes);
+wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes);
 
 /* Zeroes the spectrum and the frame count (asynchronous). */
 wdd_status wdd_reset(wdd_plan_t p);

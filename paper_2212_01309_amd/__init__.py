@@ -18,7 +18,9 @@ _lib: Optional[ctypes.CDLL] = None
 
 WDD_OK, WDD_EINVAL, WDD_ENOMEM, WDD_ERANGE, WDD_EDEVICE, WDD_EBUSY, WDD_ESTATE = 0, -1, -2, -3, -4, -5, -6
 WDD_U16, WDD_F32 = 0, 1
-WDD_FP32 = 0
+WDD_FP32, WDD_BF16_HILO, WDD_FP16_HILO, WDD_BF16, WDD_FP16 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP16_HILO, "bf16": WDD_BF16,
+              "fp16": WDD_FP16}
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
 _STATUS_NAMES = {0: "WDD_OK", -1: "WDD_EINVAL", -2: "WDD_ENOMEM", -3: "WDD_ERANGE", -4: "WDD_EDEVICE",
@@ -84,6 +86,10 @@ _SIGNATURES = {
     "wdd_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
     "wdd_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wdd_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
+    "wdd_update_probe": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.c_double]),
+    "wdd_checkpoint_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "wdd_checkpoint_save": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "wdd_checkpoint_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "wdd_reset": (ctypes.c_int, [_P]),
     "wdd_sync": (ctypes.c_int, [_P]),
     "wdd_plan_destroy": (ctypes.c_int, [_P]),
@@ -178,14 +184,16 @@ class Plan:
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
-                 sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None):
+                 sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
         self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
         _check(lib.wdd_plan_create(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
                                    ctypes.byref(Detector(ny, nx, dtype)), k,
-                                   ctypes.byref(_options(eps_rel, sigma, max_batch)),
+                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision)),
                                    _P(stream) if stream else None, ctypes.byref(self._h)))
         info = self.info()
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
@@ -317,6 +325,22 @@ class Plan:
         pr = Profile()
         _check(load_library().wdd_profile_read(self._h, ctypes.byref(pr)))
         return {f: getattr(pr, f) for f, _ in Profile._fields_}
+
+    def update_probe(self, radius: float, defocus: float = 0.0, amplitude: float = 1.0, eps_rel: float = 0.01):
+        """New Wiener filter for the frames already accumulated (same aperture radius)."""
+        _check(load_library().wdd_update_probe(self._h, ctypes.byref(Probe(radius, defocus, amplitude)), eps_rel))
+
+    def checkpoint(self) -> bytes:
+        """Image of the live state (spectrum A and frame count)."""
+        size = ctypes.c_size_t()
+        _check(load_library().wdd_checkpoint_size(self._h, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        _check(load_library().wdd_checkpoint_save(self._h, ctypes.cast(buf, _P), size.value))
+        return buf.raw
+
+    def restore(self, image: bytes) -> None:
+        buf = ctypes.create_string_buffer(image, len(image))
+        _check(load_library().wdd_checkpoint_load(self._h, ctypes.cast(buf, _P), len(image)))
 
     def reset(self) -> None:
         _check(load_library().wdd_reset(self._h))

@@ -46,6 +46,13 @@ struct wdd_plan_impl {
   size_t frame_bytes = 0;
 
   float* psi = nullptr;
+  uint16_t* psix_lp = nullptr;  // [2][16][nx] bf16/fp16 hi and lo parts (reduced-precision projection)
+  float psi_unscale = 1.f;
+  int32_t precision = WDD_FP32;
+  wdd_probe probe = {};
+  wdd_scan scan = {};
+  wdd_detector det = {};
+  wdd_options opts = {};
   int32_t* kmap = nullptr;
   int2* freqs = nullptr;
   float2* w = nullptr;
@@ -180,6 +187,28 @@ wdd_status check_usable(wdd_plan_s* p) {
   return WDD_OK;
 }
 
+// Round to the nearest bf16 / fp16 (ties to even); returns the 16-bit pattern and the value.
+uint16_t to_bf16(double x, double* back) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  const uint16_t b = (uint16_t)(u >> 16);
+  const uint32_t v = (uint32_t)b << 16;
+  float fv;
+  std::memcpy(&fv, &v, 4);
+  *back = fv;
+  return b;
+}
+
+uint16_t to_fp16(double x, double* back) {
+  const _Float16 hv = (_Float16)(float)x;
+  uint16_t b;
+  std::memcpy(&b, &hv, 2);
+  *back = (double)(float)hv;
+  return b;
+}
+
 std::vector<float2> twiddles(int32_t n, double scale) {
   std::vector<float2> t(n);
   for (int32_t m = 0; m < n; ++m) {
@@ -188,6 +217,10 @@ std::vector<float2> twiddles(int32_t n, double scale) {
   }
   return t;
 }
+
+}  // namespace
+static wdd_status upload_wiener(wdd_plan_s* p, const wdd_tables_s& t);
+namespace {
 
 wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts, void* stream) {
   p->sy = t.sy; p->sx = t.sx; p->ny = t.ny; p->nx = t.nx; p->k = t.k; p->l = t.l;
@@ -229,6 +262,26 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
 #define ALLOC(ptr, n)                                   \
   if ((st = dalloc(p, &(ptr), (n))) != WDD_OK) return st;
   ALLOC(p->psi, psi.size());
+  std::vector<uint16_t> psix_lp;
+  if (p->precision != WDD_FP32) {
+    // hi and lo 16-bit parts of psi_x.  No pre-scaling: with |psi| < 1 and count digits
+    // < 2^11, every FP16 product and 32-term partial sum stays far inside the FP16 range
+    // (lo parts below 2^-14 become subnormal, an absolute error under 3e-8).
+    const bool bf = (p->precision == WDD_BF16_HILO || p->precision == WDD_BF16);
+    const int shift = 0;
+    p->psi_unscale = std::ldexp(1.0f, -shift);
+    psix_lp.assign((size_t)2 * 16 * t.nx, 0);
+    for (int32_t m = 0; m < t.l; ++m)
+      for (int32_t i = 0; i < t.nx; ++i) {
+        const double v = std::ldexp(t.psi_x[(size_t)i * t.l + m], shift);
+        double hv = 0, lv = 0;
+        const uint16_t hb = bf ? to_bf16(v, &hv) : to_fp16(v, &hv);
+        const uint16_t lb = bf ? to_bf16(v - hv, &lv) : to_fp16(v - hv, &lv);
+        psix_lp[(size_t)m * t.nx + i] = hb;
+        psix_lp[(size_t)(16 + m) * t.nx + i] = lb;
+      }
+    ALLOC(p->psix_lp, psix_lp.size());
+  }
   ALLOC(p->kmap, kmap.size());
   ALLOC(p->freqs, freqs.size());
   ALLOC(p->w, nfk);
@@ -255,17 +308,11 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
 #undef ALLOC
 
   // Wiener filter, FP64 -> FP32, padded
-  {
-    std::vector<float2> w(nfk, make_float2(0.f, 0.f));
-    for (int64_t j = 0; j < p->n_freq; ++j)
-      for (int32_t k = 0; k < t.k; ++k) {
-        const double* s = &t.w[((size_t)j * t.k + k) * 2];
-        w[(size_t)j * p->kpad + k] = make_float2((float)s[0], (float)s[1]);
-      }
-    WDD_HIP(p, hipMemcpyAsync(p->w, w.data(), nfk * sizeof(float2), hipMemcpyHostToDevice, p->stream));
-    WDD_HIP(p, hipStreamSynchronize(p->stream));
-  }
+  if ((st = upload_wiener(p, t)) != WDD_OK) return st;
   WDD_HIP(p, hipMemcpyAsync(p->psi, psi.data(), psi.size() * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  if (p->psix_lp)
+    WDD_HIP(p, hipMemcpyAsync(p->psix_lp, psix_lp.data(), psix_lp.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
+                              p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->kmap, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->freqs, freqs.data(), freqs.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ty, ty.data(), ty.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
@@ -297,7 +344,10 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   wdd_options opts;
   wdd_default_options(&opts);
   if (opts_in) opts = *opts_in;
-  if (opts.precision != WDD_FP32) return wdd::fail(WDD_EINVAL, "unsupported precision %d", opts.precision);
+  if (opts.precision < WDD_FP32 || opts.precision > WDD_FP16)
+    return wdd::fail(WDD_EINVAL, "unknown precision %d", opts.precision);
+  if (opts.precision != WDD_FP32 && det && det->dtype != WDD_U16)
+    return wdd::fail(WDD_EINVAL, "reduced-precision projection needs uint16 frames");
   if (opts.max_batch < 1 || opts.max_batch > 65536)
     return wdd::fail(WDD_EINVAL, "max_batch = %d outside [1, 65536]", opts.max_batch);
   wdd_tables_s t;
@@ -306,6 +356,11 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   wdd_plan_s* p = new (std::nothrow) wdd_plan_s();
   if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
   p->dtype = det->dtype;
+  p->precision = opts.precision;
+  p->probe = *probe;
+  p->scan = *scan;
+  p->det = *det;
+  p->opts = opts;
   try {
     st = create(p, t, opts, hip_stream);
   } catch (const std::bad_alloc&) {
@@ -387,8 +442,13 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   hipEvent_t end;
   WDD_HIP(p, stage_begin(p, kProject, &end));
   // the projection kernel also brings the pinned upload block (positions, grouping) to the device
-  WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
-                                 up_bytes, p->stream));
+  if (p->precision == WDD_FP32) {
+    WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
+                                   up_bytes, p->stream));
+  } else {
+    WDD_HIP(p, wdd::launch_project_lp(p->precision, fdev, n, p->ny, p->nx, p->psi, p->psix_lp, p->psi_unscale, p->kmap,
+                                      p->kpad, p->h, up, p->upload, up_bytes, p->stream));
+  }
   WDD_HIP(p, stage_end(p, end));
   // slot s (pinned upload and frames) may be refilled once this point of the stream is reached;
   // a caller that drains the stream before returning needs no marker
@@ -560,6 +620,102 @@ wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out) {
   out->accumulate_launches = p->stage_n[kAccumulate];
   out->wiener_launches = p->stage_n[kWiener];
   out->display_launches = p->stage_n[kDisplay];
+  return WDD_OK;
+}
+
+// Uploads the FP64 Wiener filter of `t` as FP32 into the plan's padded layout.
+static wdd_status upload_wiener(wdd_plan_s* p, const wdd_tables_s& t) {
+  const size_t nfk = (size_t)p->n_freq_pad * p->kpad;
+  std::vector<float2> w(nfk, make_float2(0.f, 0.f));
+  for (int64_t j = 0; j < p->n_freq; ++j)
+    for (int32_t k = 0; k < t.k; ++k) {
+      const double* v = &t.w[((size_t)j * t.k + k) * 2];
+      w[(size_t)j * p->kpad + k] = make_float2((float)v[0], (float)v[1]);
+    }
+  WDD_HIP(p, hipMemcpyAsync(p->w, w.data(), nfk * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (!probe) return wdd::fail(WDD_EINVAL, "null probe");
+  if (probe->radius_px != p->probe.radius_px)
+    return wdd::fail(WDD_EINVAL, "the aperture radius fixes the kept frequencies and cannot change");
+  wdd_options o = p->opts;
+  o.eps_rel = eps_rel;
+  o.sigma_px = p->sigma;
+  wdd_tables_s t;
+  try {
+    if ((st = wdd::build_tables(probe, &p->scan, &p->det, p->k, &o, &t)) != WDD_OK) return st;
+    if (t.n_freq() != p->n_freq) return wdd::fail(WDD_EINVAL, "kept frequency set changed");
+    if ((st = upload_wiener(p, t)) != WDD_OK) return st;
+  } catch (const std::bad_alloc&) {
+    return wdd::fail(WDD_ENOMEM, "out of host memory");
+  }
+  p->probe = *probe;
+  p->opts.eps_rel = eps_rel;
+  p->eps_abs = t.eps_abs;
+  return WDD_OK;
+}
+
+namespace {
+struct CheckpointHeader {
+  char magic[8];
+  int32_t version, sy, sx, ny, nx, k, dtype, precision;
+  int64_t n_freq;
+  uint64_t frames_seen;
+  double radius, step, sigma;
+};
+constexpr char kMagic[8] = {'W', 'D', 'D', 'A', 'C', 'C', '0', '1'};
+}  // namespace
+
+wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return wdd::fail(WDD_EINVAL, "null argument");
+  *bytes = sizeof(CheckpointHeader) + (size_t)p->n_freq * p->k * sizeof(float2);
+  return WDD_OK;
+}
+
+wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  size_t need = 0;
+  wdd_checkpoint_size(p, &need);
+  if (!host_buf || bytes < need) return wdd::fail(WDD_EINVAL, "checkpoint buffer needs %zu bytes", need);
+  CheckpointHeader hd = {};
+  std::memcpy(hd.magic, kMagic, 8);
+  hd.version = 1; hd.sy = p->sy; hd.sx = p->sx; hd.ny = p->ny; hd.nx = p->nx; hd.k = p->k;
+  hd.dtype = p->dtype; hd.precision = p->precision; hd.n_freq = p->n_freq; hd.frames_seen = p->frames_seen;
+  hd.radius = p->probe.radius_px; hd.step = p->scan.step_px; hd.sigma = p->sigma;
+  std::memcpy(host_buf, &hd, sizeof(hd));
+  char* dst = static_cast<char*>(host_buf) + sizeof(hd);
+  WDD_HIP(p, hipMemcpy2DAsync(dst, (size_t)p->k * sizeof(float2), p->acc, (size_t)p->kpad * sizeof(float2),
+                              (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyDeviceToHost, p->stream));
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  return WDD_OK;
+}
+
+wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  size_t need = 0;
+  wdd_checkpoint_size(p, &need);
+  if (!host_buf || bytes < need) return wdd::fail(WDD_EINVAL, "checkpoint image needs %zu bytes", need);
+  CheckpointHeader hd;
+  std::memcpy(&hd, host_buf, sizeof(hd));
+  if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1)
+    return wdd::fail(WDD_EINVAL, "not a checkpoint image of this library");
+  if (hd.sy != p->sy || hd.sx != p->sx || hd.ny != p->ny || hd.nx != p->nx || hd.k != p->k ||
+      hd.n_freq != p->n_freq || hd.radius != p->probe.radius_px || hd.step != p->scan.step_px || hd.sigma != p->sigma)
+    return wdd::fail(WDD_EINVAL, "checkpoint geometry or basis differs from the plan's");
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
+  const char* src = static_cast<const char*>(host_buf) + sizeof(hd);
+  WDD_HIP(p, hipMemcpy2DAsync(p->acc, (size_t)p->kpad * sizeof(float2), src, (size_t)p->k * sizeof(float2),
+                              (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyHostToDevice, p->stream));
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  p->frames_seen = hd.frames_seen;
+  p->last_batch = 0;
   return WDD_OK;
 }
 

@@ -17,6 +17,14 @@ namespace wdd {
 hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
                           int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st);
 
+// Reduced-precision form of launch_project for uint16 frames (precision = WDD_BF16_HILO,
+// WDD_FP16_HILO, WDD_BF16 or WDD_FP16).  psix_lp: [2][16][nx] bf16/fp16 words, the hi and
+// lo parts of psi_x * 2^shift (columns >= L zero); psi_unscale = 2^-shift.  psi holds the
+// FP32 psi_y in its first ny * 16 entries.
+hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
+                             const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
+                             const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st);
+
 // Columns (in blocks of 32) per accumulation workgroup for a padded basis size.
 int accumulate_col_blocks(int kpad);
 

@@ -136,6 +136,139 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   }
 }
 
+// Reduced-precision projection of uint16 frames.  Stage 1 runs on
+// v_mfma_f32_16x16x32_{bf16,f16}: the 8 consecutive pixels a lane loads are exactly
+// its A operand (row r16, k-slots 8q .. 8q+7 of the 32-pixel chunk).  Counts are split
+// exactly into two digits I = hi * 2^S + lo (S = 8 for bf16, 11 for fp16, both digits
+// representable); the basis is given as hi (+ lo) parts; products accumulate in FP32,
+// the hi-digit MFMAs are skipped for chunks where the wave has no nonzero hi digit.
+// Stage 2 and the selection of h are FP32 as in k_project.  psix_lp: [2][16][nx]
+// 16-bit words (hi part, lo part), pre-scaled by 2^psi_shift.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+template <bool BF>
+struct LpTraits;
+template <>
+struct LpTraits<true> {
+  typedef bf16x8 vec;
+  typedef __bf16 elem;
+  static constexpr int kShift = 8;
+  __device__ static inline floatx4 mfma(vec a, vec b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct LpTraits<false> {
+  typedef halfx8 vec;
+  typedef _Float16 elem;
+  static constexpr int kShift = 11;
+  __device__ static inline floatx4 mfma(vec a, vec b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <bool BF, bool HILO>
+__global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict__ frames, int ny, int nx,
+                                                     const float* __restrict__ psi, const uint16_t* __restrict__ psix_lp,
+                                                     float psi_unscale, const int* __restrict__ kmap, int kpad,
+                                                     float* __restrict__ h, const uint32_t* __restrict__ up_src,
+                                                     uint32_t* __restrict__ up_dst, int up_words) {
+  typedef LpTraits<BF> Tr;
+  typedef typename Tr::vec V;
+  typedef typename Tr::elem E;
+  constexpr int S = Tr::kShift;
+  extern __shared__ float smem[];
+  const int nw = blockDim.x >> 6;
+  const int nxp = nx + 8;                                              // padded row of the 16-bit basis
+  float* lpsy = smem;                                                  // [ny][16] FP32
+  float* lg = lpsy + ny * 16;                                          // [nw][256]
+  uint16_t* lpx = reinterpret_cast<uint16_t*>(lg + nw * 256);          // [2][16][nxp]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint16_t* f = frames + (size_t)blockIdx.x * ny * nx;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int ntiles = (ny + 15) >> 4;
+  Chunk<uint16_t> ch[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int y = wave * 16 + r16, xs = 32 * c + 8 * q;
+    if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+    else ch[c].zero();
+  }
+  if (blockIdx.x == 0)
+    for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
+  for (int i = tid; i < ny * 16; i += blockDim.x) lpsy[i] = psi[i];
+  const int parts = HILO ? 2 : 1;
+  for (int i = tid; i < parts * 16 * nx; i += blockDim.x) {
+    const int row = i / nx, x = i - row * nx;
+    lpx[row * nxp + x] = psix_lp[i];
+  }
+  __syncthreads();
+
+  floatx4 g = {0.f, 0.f, 0.f, 0.f};
+  const V vzero = {};
+  for (int t = wave; t < ntiles; t += nw) {
+    const int y = t * 16 + r16;
+    floatx4 tlo = {0.f, 0.f, 0.f, 0.f}, thi = {0.f, 0.f, 0.f, 0.f};
+    for (int xg = 0; xg < nx; xg += 256) {
+      if (t != wave || xg != 0) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int xs = xg + 32 * c + 8 * q;
+          if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+          else ch[c].zero();
+        }
+      }
+      const int nch = min(8, (nx - xg + 31) >> 5);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c >= nch) break;
+        const int xs = xg + 32 * c + 8 * q;
+        V alo, ahi;
+        uint32_t any_hi = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t v = (uint32_t)ch[c].get(j);
+          const uint32_t hi = v >> S;
+          any_hi |= hi;
+          alo[j] = (E)(float)(v & ((1u << S) - 1u));
+          ahi[j] = (E)(float)hi;
+        }
+        V bhi = vzero, blo = vzero;
+        if (xs < nx) {
+          bhi = *reinterpret_cast<const V*>(lpx + r16 * nxp + xs);
+          if (HILO) blo = *reinterpret_cast<const V*>(lpx + (16 + r16) * nxp + xs);
+        }
+        tlo = Tr::mfma(alo, bhi, tlo);
+        if (HILO) tlo = Tr::mfma(alo, blo, tlo);
+        if (__any(any_hi != 0u)) {
+          thi = Tr::mfma(ahi, bhi, thi);
+          if (HILO) thi = Tr::mfma(ahi, blo, thi);
+        }
+      }
+    }
+    floatx4 tacc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tacc[r] = (tlo[r] + thi[r] * (float)(1 << S)) * psi_unscale;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int yy = t * 16 + 4 * q + r;
+      const float av = (yy < ny) ? lpsy[yy * 16 + r16] : 0.f;
+      g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, tacc[r], g, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
+  __syncthreads();
+  for (int k = tid; k < kpad; k += blockDim.x) {
+    const int idx = kmap[k];
+    float sum = 0.f;
+    if (idx >= 0)
+      for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+    h[(size_t)blockIdx.x * kpad + k] = sum;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Accumulation: A[j][c] += sum_b F[j][b] h[b][c] over the kept frequencies j.
 // Viewed as a real GEMM with rows (j, re/im) interleaved: row 2j is Re F, row
@@ -479,6 +612,27 @@ hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const flo
   return hipGetLastError();
 }
 
+template <bool BF, bool HILO>
+hipError_t launch_project_lp_t(const void* frames, int n, int ny, int nx, const float* psi, const uint16_t* psix_lp,
+                               float psi_unscale, const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
+                               size_t up_bytes, hipStream_t st) {
+  const int ntiles = (ny + 15) / 16;
+  const int nw = ntiles < 16 ? ntiles : 16;
+  const size_t lds = (size_t)ny * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) +
+                     (size_t)2 * 16 * (nx + 8) * sizeof(uint16_t);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_project_lp<BF, HILO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_project_lp<BF, HILO>), dim3(n), dim3(64 * nw), lds, st, static_cast<const uint16_t*>(frames),
+                     ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, static_cast<const uint32_t*>(up_src),
+                     static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4));
+  return hipGetLastError();
+}
+
 template <int NCB>
 hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, const float* h,
                         const int2* pos, int n, const float2* ty, int sy, const float2* tx, int sx, hipStream_t st) {
@@ -504,6 +658,26 @@ hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, 
   if (dtype == WDD_U16)
     return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
   return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
+}
+
+hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
+                             const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
+                             const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (precision) {
+    case WDD_BF16_HILO:
+      return launch_project_lp_t<true, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
+                                             up_dst, up_bytes, st);
+    case WDD_FP16_HILO:
+      return launch_project_lp_t<false, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
+                                              up_dst, up_bytes, st);
+    case WDD_BF16:
+      return launch_project_lp_t<true, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
+                                              up_dst, up_bytes, st);
+    default:
+      return launch_project_lp_t<false, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
+                                               up_dst, up_bytes, st);
+  }
 }
 
 int accumulate_col_blocks(int kpad) {

@@ -1,0 +1,90 @@
+"""Reduced-precision projection (BF16 / FP16 MFMA, FP32 accumulation) against the FP64
+oracle: the error of every result is stated per mode, and the FP32 path is run on
+the same frames beside it."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+import synth
+from gpu_util import device, golden_workload, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# bound on the relative L2 error of h, A and D for each projection arithmetic:
+# basis rounding 2^-9 (bf16), 2^-12 (fp16), ~2^-17 (bf16 hi+lo), ~2^-22 (fp16 hi+lo)
+BOUNDS = {"fp32": 1e-5, "bf16_hilo": 3e-5, "fp16_hilo": 2e-6, "bf16": 6e-3, "fp16": 8e-4}
+
+
+@pytest.fixture(scope="module")
+def defocus_case():
+    wl = synth.WORKLOADS["defocus"]
+    g = golden_workload("defocus")
+    rng = np.random.default_rng(77)
+    lin = np.concatenate([np.arange(256) + 256 * 100, rng.choice(wl.sy * wl.sx, size=512, replace=False)])
+    pos = np.stack([lin // wl.sx, lin % wl.sx], axis=1).astype(np.int32)
+    frames = wl.frames(pos)
+    all_f = O.nonzero_frequencies(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.step)
+    pick = np.concatenate([[0], np.sort(rng.choice(np.arange(1, len(all_f)), size=200, replace=False))])
+    oplan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=wl.aperture_amplitude(),
+                        defocus_edge=wl.defocus_edge, step=wl.step, freqs=all_f[pick], eps_abs=g["eps_abs"])
+    h = O.project(frames, oplan.phi)
+    a = O.scan_phase(oplan.freqs, pos, wl.sy, wl.sx) @ h
+    d = O.extract(oplan, a)
+    return wl, pos, frames, pick, h, a, d
+
+
+@pytest.mark.parametrize("mode", list(BOUNDS))
+def test_projection_precision_against_oracle(defocus_case, mode):
+    wl, pos, frames, pick, h, a, d = defocus_case
+    dev = device(frames)
+    with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=wdd.WDD_U16, defocus=wl.defocus_edge,
+                  amplitude=wl.aperture_amplitude(), max_batch=wl.batch, precision=mode) as plan:
+        hs = []
+        for b in range(0, len(pos), wl.batch):
+            plan.push(dev[b:b + wl.batch], pos[b:b + wl.batch])
+            hs.append(plan.projection())
+        plan.snapshot()
+        got_a, got_d = plan.accumulator()[pick], plan.spectrum()[pick]
+    errs = dict(h=rel(np.concatenate(hs), h), A=rel(got_a, a), D=rel(got_d, d))
+    say(f"[precision] {mode}: {errs}")
+    assert max(errs.values()) <= BOUNDS[mode]
+
+
+# Full-range counts (up to 65535) through one-hot frames: every coefficient is
+# count * psi_y * psi_x at one pixel, including pixels in the basis tails where the
+# 16-bit parts of psi_x lose precision (FP16 flushes values below 6e-8).  The error of a
+# frame is measured relative to max(||h_ref||, 1e-3 * count).
+FULL_RANGE_BOUNDS = {"bf16_hilo": 2e-5, "fp16_hilo": 1e-4, "bf16": 6e-3, "fp16": 2e-3}
+
+
+@pytest.mark.parametrize("mode", list(FULL_RANGE_BOUNDS))
+def test_full_range_counts_split_exactly(mode):
+    """Counts above 2^8 / 2^11 take the two-digit split; one-hot frames isolate it."""
+    ny = nx = 64
+    frames = np.zeros((48, ny, nx), np.uint16)
+    rng = np.random.default_rng(5)
+    for i in range(32):
+        frames[i, rng.integers(0, ny), rng.integers(0, nx)] = 65535 - 997 * i
+    frames[32:] = rng.integers(0, 65536, size=(16, ny, nx), dtype=np.uint16)
+    with wdd.Plan(16.0, 8, 8, ny, nx, 256, dtype=wdd.WDD_U16, max_batch=64, precision=mode) as plan:
+        plan.push(device(frames), np.zeros((48, 2), np.int32))
+        got = plan.projection()
+        sig = plan.info().sigma_px
+    ref = O.project(frames, O.hg_basis(ny, nx, 256, sig))
+    errs = [float(np.linalg.norm(got[i] - ref[i]) /
+                  max(np.linalg.norm(ref[i]), 1e-3 * float(frames[i].max()))) for i in range(48)]
+    bad = [i for i, e in enumerate(errs) if not e <= FULL_RANGE_BOUNDS[mode]]
+    if bad:
+        i = bad[0]
+        say(f"[precision] {mode}: frame {i} max|got| {np.max(np.abs(got[i])):.3e} max|ref| {np.max(np.abs(ref[i])):.3e} "
+            f"finite {np.all(np.isfinite(got[i]))}")
+    err = float(np.max(errs))
+    say(f"[precision] {mode} full-range counts: worst frame {err:.2e}")
+    assert err <= FULL_RANGE_BOUNDS[mode]
+
+
+def test_reduced_precision_needs_uint16_frames():
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Plan(8.0, 16, 16, 32, 32, 64, dtype=wdd.WDD_F32, precision="bf16")
+    assert ei.value.code == wdd.WDD_EINVAL
