@@ -252,6 +252,69 @@ wdd_status wdd_sync(wdd_plan_t p);
 /* Releases the plan (waits for its work first).  NULL is accepted. */
 wdd_status wdd_plan_destroy(wdd_plan_t p);
 
+/* ------------------------------------------------------------------------- */
+/* Serving: many concurrent acquisitions on one GPU.
+ *
+ * Each acquisition is a plan (spectrum resident in HBM).  wdd_server_open admits an
+ * acquisition if the device memory of all open plans stays within the budget and
+ * returns WDD_EBUSY otherwise (the caller retries after another closes).  Frames are
+ * submitted as device memory and queued; wdd_server_step takes every queued frame of
+ * every acquisition (continuous batching), queues the updates of different
+ * acquisitions on their own streams so they overlap on the device, and snapshots the
+ * acquisitions whose last snapshot is older than the snapshot interval, fusing the
+ * Wiener reduction into the last update where possible.  The time from submit to the
+ * snapshot that contains a frame is recorded per frame.  A server is used by one
+ * host thread at a time. */
+
+typedef struct wdd_server_s* wdd_server_t;
+
+typedef struct {
+  int64_t hbm_budget_bytes;     /* admission limit on the plans' device memory; <= 0: none.  Default 1 GiB */
+  double snapshot_interval_us;  /* least time between snapshots of one acquisition.  Default 1000 */
+  int32_t batch_frames;         /* largest batch pushed at once.  Default 256 */
+} wdd_server_options;
+
+typedef struct {
+  uint64_t frames, batches, snapshots, steps;
+  int32_t open;                 /* acquisitions open */
+  int64_t device_bytes;         /* device memory of the open plans */
+  int64_t pending_frames;       /* submitted, not yet pushed */
+  int64_t latency_samples;      /* frames that reached a snapshot */
+  double latency_p50_us, latency_p99_us, latency_max_us;  /* submit -> snapshot ready */
+} wdd_server_stats;
+
+wdd_status wdd_server_default_options(wdd_server_options* opts);
+wdd_status wdd_server_create(const wdd_server_options* opts, wdd_server_t* out);
+
+/* Opens an acquisition (arguments as wdd_plan_create; max_batch is raised to the
+ * server's batch_frames).  WDD_EBUSY when it does not fit the budget now. */
+wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
+                           int32_t K, const wdd_options* opts, int32_t* acq_id);
+
+/* Queues n device-resident frames (contiguous, 16-byte aligned; they must stay valid
+ * until a later wdd_server_step or wdd_server_snapshot has pushed them) with host
+ * positions pos_yx [n][2].  WDD_ERANGE (nothing queued) for a position off the raster. */
+wdd_status wdd_server_submit(wdd_server_t s, int32_t acq, const void* frames, const int32_t* pos_yx, int32_t n);
+
+/* One scheduling round (see above); *frames_processed = frames pushed (may be NULL). */
+wdd_status wdd_server_step(wdd_server_t s, int32_t* frames_processed);
+
+/* Pushes the acquisition's queued frames, takes a snapshot now and copies it to host
+ * memory `out` (sy x sx complex, interleaved float).  Blocking. */
+wdd_status wdd_server_snapshot(wdd_server_t s, int32_t acq, float* out, uint64_t* frames_seen);
+
+/* Scan size of an open acquisition. */
+wdd_status wdd_server_acq_shape(wdd_server_t s, int32_t acq, int32_t* sy, int32_t* sx);
+
+/* Closes an acquisition and returns its device memory to the budget (queued frames
+ * that were not pushed are dropped). */
+wdd_status wdd_server_close(wdd_server_t s, int32_t acq);
+
+wdd_status wdd_server_get_stats(wdd_server_t s, wdd_server_stats* out);
+
+/* Closes every acquisition and frees the server.  NULL is accepted. */
+wdd_status wdd_server_destroy(wdd_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

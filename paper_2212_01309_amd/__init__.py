@@ -64,6 +64,19 @@ class Profile(ctypes.Structure):
                 ("rowdft_launches", ctypes.c_int64)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("snapshot_interval_us", ctypes.c_double),
+                ("batch_frames", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("snapshots", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("open", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("pending_frames", ctypes.c_int64), ("latency_samples", ctypes.c_int64),
+                ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
+                ("latency_max_us", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "wdd_last_error": (ctypes.c_char_p, []),
@@ -93,6 +106,18 @@ _SIGNATURES = {
     "wdd_reset": (ctypes.c_int, [_P]),
     "wdd_sync": (ctypes.c_int, [_P]),
     "wdd_plan_destroy": (ctypes.c_int, [_P]),
+    "wdd_server_default_options": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
+    "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
+    "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
+                                       ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32)]),
+    "wdd_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "wdd_server_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "wdd_server_snapshot": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "wdd_server_acq_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "wdd_server_close": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "wdd_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
+    "wdd_server_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -348,6 +373,87 @@ class Plan:
 
     def sync(self) -> None:
         _check(load_library().wdd_sync(self._h))
+
+
+class Server:
+    """Many concurrent acquisitions with continuous batching (wdd_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, snapshot_interval_us: float = 1000.0, batch_frames: int = 256):
+        lib = load_library()
+        o = ServerOptions()
+        _check(lib.wdd_server_default_options(ctypes.byref(o)))
+        o.hbm_budget_bytes, o.snapshot_interval_us, o.batch_frames = hbm_budget_bytes, snapshot_interval_us, batch_frames
+        self._h = _P()
+        _check(lib.wdd_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def open(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
+             defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
+             sigma: float = 0.0, precision=WDD_FP32) -> Optional[int]:
+        """Acquisition id, or None when it does not fit the memory budget now."""
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        aid = ctypes.c_int32()
+        code = load_library().wdd_server_open(self._h, ctypes.byref(Probe(radius, defocus, amplitude)),
+                                              ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)),
+                                              k, ctypes.byref(_options(eps_rel, sigma, 256, precision)),
+                                              ctypes.byref(aid))
+        if code == WDD_EBUSY:
+            return None
+        _check(code)
+        self._keep[aid.value] = []
+        return aid.value
+
+    def submit(self, acq: int, frames, positions) -> None:
+        """frames: contiguous torch GPU tensor [n, ny, nx]; kept referenced until pushed."""
+        if not _is_device_tensor(frames) or not frames.is_contiguous():
+            raise ValueError("server frames must be a contiguous GPU tensor")
+        pos = _host_array(positions, np.int32).reshape(-1, 2)
+        _check(load_library().wdd_server_submit(self._h, acq, frames.data_ptr(), pos.ctypes.data, pos.shape[0]))
+        self._keep[acq].append(frames)
+
+    def step(self) -> int:
+        """One scheduling round; returns the number of frames pushed.  Submitted tensors stay
+        referenced until the acquisition's next snapshot() or close()."""
+        n = ctypes.c_int32()
+        _check(load_library().wdd_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def snapshot(self, acq: int) -> np.ndarray:
+        sy, sx = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().wdd_server_acq_shape(self._h, acq, ctypes.byref(sy), ctypes.byref(sx)))
+        out = np.empty((sy.value, sx.value), np.complex64)
+        seen = ctypes.c_uint64()
+        _check(load_library().wdd_server_snapshot(self._h, acq, out.ctypes.data, ctypes.byref(seen)))
+        self._keep[acq].clear()
+        return out
+
+    def close(self, acq: int) -> None:
+        _check(load_library().wdd_server_close(self._h, acq))
+        self._keep.pop(acq, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().wdd_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def destroy(self) -> None:
+        if self._h:
+            load_library().wdd_server_destroy(self._h)
+            self._h = _P()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def header_symbols(header: Optional[str] = None) -> Tuple[str, ...]:

@@ -325,7 +325,8 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad, p->stream));
 
   for (int i = 0; i < kRing; ++i) {
-    WDD_HIP(p, hipHostMalloc((void**)&p->pin_up[i], p->upload_bytes, hipHostMallocDefault));
+    WDD_HIP(p, hipHostMalloc((void**)&p->pin_up[i], p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t),
+                             hipHostMallocDefault));
     WDD_HIP(p, hipEventCreateWithFlags(&p->ev[i], hipEventDisableTiming));
   }
   WDD_HIP(p, hipHostMalloc((void**)&p->pin_out, grid * sizeof(float2), hipHostMallocDefault));
@@ -337,22 +338,36 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
 
 extern "C" {
 
-wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
-                           const wdd_options* opts_in, void* hip_stream, wdd_plan_t* out) {
-  if (!out) return wdd::fail(WDD_EINVAL, "null output handle");
-  *out = nullptr;
-  wdd_options opts;
-  wdd_default_options(&opts);
-  if (opts_in) opts = *opts_in;
+}  // extern "C"
+
+namespace wdd {
+
+wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) {
   if (opts.precision < WDD_FP32 || opts.precision > WDD_FP16)
     return wdd::fail(WDD_EINVAL, "unknown precision %d", opts.precision);
   if (opts.precision != WDD_FP32 && det && det->dtype != WDD_U16)
     return wdd::fail(WDD_EINVAL, "reduced-precision projection needs uint16 frames");
   if (opts.max_batch < 1 || opts.max_batch > 65536)
     return wdd::fail(WDD_EINVAL, "max_batch = %d outside [1, 65536]", opts.max_batch);
-  wdd_tables_s t;
-  wdd_status st = wdd::build_tables(probe, scan, det, K, &opts, &t);
-  if (st != WDD_OK) return st;
+  return WDD_OK;
+}
+
+int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_t dtype) {
+  int64_t kpad = 32;
+  while (kpad < t.k) kpad *= 2;
+  const int64_t nfp = (t.n_freq() + 63) / 64 * 64, mb = opts.max_batch, grid = (int64_t)t.sy * t.sx;
+  auto a = [](int64_t bytes) { return std::max<int64_t>(bytes, 256); };
+  int64_t b = a((int64_t)(t.ny + t.nx) * 16 * 4) + a(kpad * 4) + a(nfp * 8) + 2 * a(nfp * kpad * 8);
+  if (opts.precision != WDD_FP32) b += a((int64_t)2 * 16 * t.nx * 2);
+  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 12 + 16 + kFactorRows * 16);
+  b += a((int64_t)kFactorRows * t.sx * kpad * 8) + a(mb * (int64_t)t.ny * t.nx * (dtype == WDD_U16 ? 2 : 4));
+  b += a(nfp * 8) + 2 * a(grid * 8);
+  return b;
+}
+
+wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe, const wdd_scan* scan,
+                                   const wdd_detector* det, const wdd_options& opts, void* hip_stream, wdd_plan_t* out) {
+  *out = nullptr;
   wdd_plan_s* p = new (std::nothrow) wdd_plan_s();
   if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
   p->dtype = det->dtype;
@@ -361,6 +376,7 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   p->scan = *scan;
   p->det = *det;
   p->opts = opts;
+  wdd_status st;
   try {
     st = create(p, t, opts, hip_stream);
   } catch (const std::bad_alloc&) {
@@ -374,6 +390,28 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   return WDD_OK;
 }
 
+}  // namespace wdd
+
+extern "C" {
+
+wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
+                           const wdd_options* opts_in, void* hip_stream, wdd_plan_t* out) {
+  if (!out) return wdd::fail(WDD_EINVAL, "null output handle");
+  *out = nullptr;
+  wdd_options opts;
+  wdd_default_options(&opts);
+  if (opts_in) opts = *opts_in;
+  wdd_status st0 = wdd::check_plan_options(det, opts);
+  if (st0 != WDD_OK) return st0;
+  wdd_tables_s t;
+  try {
+    if ((st0 = wdd::build_tables(probe, scan, det, K, &opts, &t)) != WDD_OK) return st0;
+  } catch (const std::bad_alloc&) {
+    return wdd::fail(WDD_ENOMEM, "out of host memory");
+  }
+  return wdd::plan_create_from_tables(t, probe, scan, det, opts, hip_stream, out);
+}
+
 }  // extern "C"
 
 namespace {
@@ -381,15 +419,20 @@ namespace {
 // Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
 // reduction of the updated spectrum; *fused reports whether it did.
 wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device,
-                     bool fuse_wiener, bool* fused, bool drained_after = false) {
+                     bool fuse_wiener, bool* fused, bool drained_after = false,
+                     const uint64_t* frame_addrs = nullptr) {
   if (fused) *fused = false;
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   if (n < 0 || n > p->max_batch) return wdd::fail(WDD_EINVAL, "n = %d outside [0, %d]", n, p->max_batch);
   if (n == 0) return WDD_OK;
-  if (!frames || !pos_yx) return wdd::fail(WDD_EINVAL, "null frames or positions");
-  if (frames_on_device && (reinterpret_cast<uintptr_t>(frames) % 16) != 0)
+  if ((!frames && !frame_addrs) || !pos_yx) return wdd::fail(WDD_EINVAL, "null frames or positions");
+  if (frame_addrs) {
+    for (int32_t i = 0; i < n; ++i)
+      if (frame_addrs[i] % 16 != 0) return wdd::fail(WDD_EINVAL, "device frames must be 16-byte aligned");
+  } else if (frames_on_device && (reinterpret_cast<uintptr_t>(frames) % 16) != 0) {
     return wdd::fail(WDD_EINVAL, "device frames must be 16-byte aligned");
+  }
   for (int32_t i = 0; i < n; ++i) {
     const int32_t y = pos_yx[2 * i], x = pos_yx[2 * i + 1];
     if (y < 0 || y >= p->sy || x < 0 || x >= p->sx)
@@ -422,7 +465,12 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     up_bytes = roff + (size_t)nrows * sizeof(int4);
   }
   const void* fdev = frames;
-  if (!frames_on_device) {
+  const uint64_t* ftab = nullptr;
+  if (frame_addrs) {  // frames scattered over device memory: the projection reads this pinned table
+    uint64_t* tab = reinterpret_cast<uint64_t*>(up + p->upload_bytes);
+    std::memcpy(tab, frame_addrs, (size_t)n * sizeof(uint64_t));
+    ftab = tab;
+  } else if (!frames_on_device) {
     if (!p->pin_frames[s]) {
       hipError_t e = hipHostMalloc(&p->pin_frames[s], (size_t)p->max_batch * p->frame_bytes, hipHostMallocDefault);
       if (e != hipSuccess) {
@@ -444,10 +492,10 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   // the projection kernel also brings the pinned upload block (positions, grouping) to the device
   if (p->precision == WDD_FP32) {
     WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
-                                   up_bytes, p->stream));
+                                   up_bytes, ftab, p->stream));
   } else {
     WDD_HIP(p, wdd::launch_project_lp(p->precision, fdev, n, p->ny, p->nx, p->psi, p->psix_lp, p->psi_unscale, p->kmap,
-                                      p->kpad, p->h, up, p->upload, up_bytes, p->stream));
+                                      p->kpad, p->h, up, p->upload, up_bytes, ftab, p->stream));
   }
   WDD_HIP(p, stage_end(p, end));
   // slot s (pinned upload and frames) may be refilled once this point of the stream is reached;
@@ -478,9 +526,8 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   return WDD_OK;
 }
 
-// Display step (optionally after the Wiener reduction) and the copy to `out`; blocking.
-wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen, bool reduce) {
-  const size_t grid = (size_t)p->sy * p->sx;
+// Queues the display step (optionally after the Wiener reduction) writing to `out`.
+wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_device, bool reduce) {
   hipEvent_t end;
   if (reduce) {
     WDD_HIP(p, stage_begin(p, kWiener, &end));
@@ -497,6 +544,12 @@ wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint6
   WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, 0,
                                   p->stream));
   WDD_HIP(p, stage_end(p, end));
+  return WDD_OK;
+}
+
+// Waits for the queued snapshot and copies it out of the pinned buffer if needed.
+wdd_status snapshot_finish_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
+  const size_t grid = (size_t)p->sy * p->sx;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   if (!out_on_device && reinterpret_cast<float2*>(out) != p->pin_out) std::memcpy(out, p->pin_out, grid * sizeof(float2));
   WDD_HIP(p, harvest(p));
@@ -504,7 +557,42 @@ wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint6
   return WDD_OK;
 }
 
+// Display step and the copy to `out`; blocking.
+wdd_status snapshot_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen, bool reduce) {
+  wdd_status st = snapshot_enqueue_impl(p, out, out_on_device, reduce);
+  if (st != WDD_OK) return st;
+  return snapshot_finish_impl(p, out, out_on_device, frames_seen);
+}
+
 }  // namespace
+
+namespace wdd {
+
+wdd_status push_table(wdd_plan_t p, const uint64_t* frame_addrs, const int32_t* pos_yx, int32_t n, bool fuse_wiener,
+                      bool* fused) {
+  return push_impl(p, nullptr, pos_yx, n, 1, fuse_wiener, fused, false, frame_addrs);
+}
+
+wdd_status snapshot_enqueue(wdd_plan_t p, bool reduce) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  return snapshot_enqueue_impl(p, reinterpret_cast<float*>(p->pin_out), 0, reduce);
+}
+
+wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx) {
+  if (!p || !sy || !sx) return wdd::fail(WDD_EINVAL, "null argument");
+  *sy = p->sy;
+  *sx = p->sx;
+  return WDD_OK;
+}
+
+wdd_status snapshot_finish(wdd_plan_t p, uint64_t* frames_seen) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  return snapshot_finish_impl(p, reinterpret_cast<float*>(p->pin_out), 0, frames_seen);
+}
+
+}  // namespace wdd
 
 extern "C" {
 

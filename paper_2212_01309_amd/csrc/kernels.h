@@ -13,9 +13,12 @@ namespace wdd {
 
 // h[b][k] = sum_q Phi[q][k] frames[b][q] for b < n.  psi: [ny][16] then [nx][16]
 // (columns >= L zero); kmap[k] = 16 n_y(k) + n_x(k), or -1 for padding columns.
-// Also copies up_bytes (a multiple of 4) from up_src (pinned host memory) to up_dst.
+// Also copies up_bytes (a multiple of 4) from up_src (pinned host memory) to up_dst.  With fptr
+// (pinned host table of n device addresses) frame b is read from fptr[b], else from
+// frames + b * ny * nx.
 hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st);
+                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
+                          hipStream_t st);
 
 // Reduced-precision form of launch_project for uint16 frames (precision = WDD_BF16_HILO,
 // WDD_FP16_HILO, WDD_BF16 or WDD_FP16).  psix_lp: [2][16][nx] bf16/fp16 words, the hi and
@@ -23,7 +26,7 @@ hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, 
 // FP32 psi_y in its first ny * 16 entries.
 hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
                              const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
-                             const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st);
+                             const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr, hipStream_t st);
 
 // Columns (in blocks of 32) per accumulation workgroup for a padded basis size.
 int accumulate_col_blocks(int kpad);

@@ -67,14 +67,16 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
                                                   const float* __restrict__ psi, const int* __restrict__ kmap,
                                                   int kpad, float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                                  uint32_t* __restrict__ up_dst, int up_words) {
+                                                  uint32_t* __restrict__ up_dst, int up_words,
+                                                  const uint64_t* __restrict__ fptr) {
   extern __shared__ float smem[];
   const int nw = blockDim.x >> 6;
   float* lpsy = smem;               // [ny][16]
   float* lpsx = smem + ny * 16;     // [nx][16]
   float* lg = lpsx + nx * 16;       // [nw][256]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const T* f = frames + (size_t)blockIdx.x * ny * nx;
+  // frame b: contiguous after `frames`, or at the address listed in fptr[b] (pinned host table)
+  const T* f = fptr ? reinterpret_cast<const T*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
   // loads of this wave's first chunk group go out before anything else
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
                                                      const float* __restrict__ psi, const uint16_t* __restrict__ psix_lp,
                                                      float psi_unscale, const int* __restrict__ kmap, int kpad,
                                                      float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                                     uint32_t* __restrict__ up_dst, int up_words) {
+                                                     uint32_t* __restrict__ up_dst, int up_words,
+                                                     const uint64_t* __restrict__ fptr) {
   typedef LpTraits<BF> Tr;
   typedef typename Tr::vec V;
   typedef typename Tr::elem E;
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
   float* lg = lpsy + ny * 16;                                          // [nw][256]
   uint16_t* lpx = reinterpret_cast<uint16_t*>(lg + nw * 256);          // [2][16][nxp]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint16_t* f = frames + (size_t)blockIdx.x * ny * nx;
+  const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
   Chunk<uint16_t> ch[8];
@@ -596,7 +599,8 @@ __global__ void k_zero(float* __restrict__ p, size_t n) {
 
 template <typename T>
 hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap, int kpad,
-                            float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
+                            float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
+                            hipStream_t st) {
   const int ntiles = (ny + 15) / 16;
   const int nw = ntiles < 16 ? ntiles : 16;
   const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float);
@@ -608,14 +612,14 @@ hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const flo
   }
   hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(64 * nw), lds, st, static_cast<const T*>(frames), ny, nx, psi, kmap,
                      kpad, h, static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst),
-                     (int)(up_bytes / 4));
+                     (int)(up_bytes / 4), fptr);
   return hipGetLastError();
 }
 
 template <bool BF, bool HILO>
 hipError_t launch_project_lp_t(const void* frames, int n, int ny, int nx, const float* psi, const uint16_t* psix_lp,
                                float psi_unscale, const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
-                               size_t up_bytes, hipStream_t st) {
+                               size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
   const int ntiles = (ny + 15) / 16;
   const int nw = ntiles < 16 ? ntiles : 16;
   const size_t lds = (size_t)ny * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) +
@@ -629,7 +633,7 @@ hipError_t launch_project_lp_t(const void* frames, int n, int ny, int nx, const 
   }
   hipLaunchKernelGGL((k_project_lp<BF, HILO>), dim3(n), dim3(64 * nw), lds, st, static_cast<const uint16_t*>(frames),
                      ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, static_cast<const uint32_t*>(up_src),
-                     static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4));
+                     static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4), fptr);
   return hipGetLastError();
 }
 
@@ -653,30 +657,31 @@ hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* f
 namespace wdd {
 
 hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
+                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
+                          hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (dtype == WDD_U16)
-    return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
-  return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, st);
+    return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, st);
+  return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, st);
 }
 
 hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
                              const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
-                             const void* up_src, void* up_dst, size_t up_bytes, hipStream_t st) {
+                             const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   switch (precision) {
     case WDD_BF16_HILO:
       return launch_project_lp_t<true, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                             up_dst, up_bytes, st);
+                                             up_dst, up_bytes, fptr, st);
     case WDD_FP16_HILO:
       return launch_project_lp_t<false, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                              up_dst, up_bytes, st);
+                                              up_dst, up_bytes, fptr, st);
     case WDD_BF16:
       return launch_project_lp_t<true, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                              up_dst, up_bytes, st);
+                                              up_dst, up_bytes, fptr, st);
     default:
       return launch_project_lp_t<false, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                               up_dst, up_bytes, st);
+                                               up_dst, up_bytes, fptr, st);
   }
 }
 

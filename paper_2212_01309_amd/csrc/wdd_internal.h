@@ -28,6 +28,21 @@ wdd_status fail(wdd_status code, const char* fmt, ...);
 wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
                         int32_t K, const wdd_options* opts, wdd_tables_s* t);
 
+// Plan operations used by the serving runtime (api.hip).
+wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts);
+// Device bytes a plan of these tables allocates.
+int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_t dtype);
+wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe, const wdd_scan* scan,
+                                   const wdd_detector* det, const wdd_options& opts, void* hip_stream, wdd_plan_t* out);
+// Queues a batch whose frames sit at the given device addresses (16-byte aligned).
+wdd_status push_table(wdd_plan_t p, const uint64_t* frame_addrs, const int32_t* pos_yx, int32_t n, bool fuse_wiener,
+                      bool* fused);
+// Queues a snapshot into the plan's pinned host buffer (with the Wiener reduction unless it
+// was fused into the last push); snapshot_finish waits for it.
+wdd_status snapshot_enqueue(wdd_plan_t p, bool reduce);
+wdd_status snapshot_finish(wdd_plan_t p, uint64_t* frames_seen);
+wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx);
+
 // Largest number of columns of psi held on the device per axis (L <= 16).
 constexpr int kMaxL = 16;
 

@@ -1,0 +1,92 @@
+"""Serving runtime: admission by device-memory budget, continuous batching of many
+acquisitions of different geometries, and results that are the same alone and in
+the mix (FP32, relative L2 <= 1e-6; batch boundaries differ, so not bitwise)."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+from gpu_util import device, rel, say
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = [  # (radius, scan, detector, K)
+    (8.0, 32, 32, 64),
+    (6.0, 48, 32, 36),
+    (16.0, 64, 64, 128),
+    (8.0, 40, 32, 64),
+]
+
+
+def _acquisition(i, radius, s, n, k):
+    rng = np.random.default_rng(500 + i)
+    count = s * s if s <= 48 else 1500
+    lin = rng.permutation(s * s)[:count]
+    pos = np.stack([lin // s, lin % s], axis=1).astype(np.int32)
+    frames = rng.poisson(15.0 + 5 * i, size=(count, n, n)).astype(np.uint16)
+    return frames, pos
+
+
+def test_admission_by_memory_budget():
+    radius, s, n, k = 8.0, 32, 32, 64
+    with wdd.Server(hbm_budget_bytes=0) as probe_srv:
+        a = probe_srv.open(radius, s, s, n, n, k)
+        per_plan = probe_srv.stats()["device_bytes"]
+    with wdd.Server(hbm_budget_bytes=int(2.5 * per_plan)) as srv:
+        a = srv.open(radius, s, s, n, n, k)
+        b = srv.open(radius, s, s, n, n, k)
+        assert a is not None and b is not None
+        assert srv.open(radius, s, s, n, n, k) is None        # over budget: deferred
+        assert srv.stats()["open"] == 2
+        srv.close(a)
+        c = srv.open(radius, s, s, n, n, k)                   # memory freed: admitted
+        assert c is not None and srv.stats()["open"] == 2
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
+    rng = np.random.default_rng(9)
+    data = [_acquisition(i, *g) for i, g in enumerate(GEOMS)]
+    devs = [device(f) for f, _ in data]
+    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=200.0, batch_frames=256) as srv:
+        ids = [srv.open(r, s, s, n, n, k) for (r, s, n, k) in GEOMS]
+        cursor = [0] * len(GEOMS)
+        while any(c < len(d[1]) for c, d in zip(cursor, data)):
+            for _ in range(3):
+                i = int(rng.integers(0, len(GEOMS)))
+                c = cursor[i]
+                if c >= len(data[i][1]):
+                    continue
+                nb = int(min(rng.integers(1, 65), len(data[i][1]) - c))
+                srv.submit(ids[i], devs[i][c:c + nb], data[i][1][c:c + nb])
+                cursor[i] += nb
+            srv.step()
+        mixed = [srv.snapshot(a) for a in ids]
+        st = srv.stats()
+    total = sum(len(p) for _, p in data)
+    assert st["frames"] == total and st["latency_samples"] == total
+    assert 0 < st["latency_p50_us"] <= st["latency_p99_us"] <= st["latency_max_us"]
+    say(f"[serving] mix of {len(GEOMS)} acquisitions, {total} frames, {st['batches']} batches, "
+        f"{st['snapshots']} snapshots, latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
+    for i, (r, s, n, k) in enumerate(GEOMS):
+        frames, pos = data[i]
+        with wdd.Plan(r, s, s, n, n, k, max_batch=256) as plan:
+            for b in range(0, len(pos), 256):
+                plan.push(devs[i][b:b + 256], pos[b:b + 256])
+            alone = plan.snapshot()
+        e = rel(mixed[i], alone)
+        say(f"[serving] acquisition {i}: mix vs alone {e:.2e}")
+        assert e <= 1e-6
+    r, s, n, k = GEOMS[0]
+    live = O.Live(O.make_plan(s, s, n, n, r, k), "N")
+    live.push(*data[0])
+    assert rel(mixed[0], live.snapshot()) <= 1e-5
+
+
+def test_submit_rejects_positions_off_the_raster():
+    with wdd.Server(hbm_budget_bytes=0) as srv:
+        a = srv.open(8.0, 16, 16, 32, 32, 64)
+        fr = device(np.zeros((4, 32, 32), np.uint16))
+        with pytest.raises(wdd.WddError) as ei:
+            srv.submit(a, fr, np.array([[0, 0], [1, 1], [16, 2], [3, 3]], np.int32))
+        assert ei.value.code == wdd.WDD_ERANGE
+        assert srv.stats()["pending_frames"] == 0
