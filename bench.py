@@ -35,6 +35,12 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
+    ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the single acquisition")
+    ap.add_argument("--serving-acquisitions", type=int, default=24)
+    ap.add_argument("--serving-budget-mb", type=int, default=1024)
+    ap.add_argument("--serving-precision", default="bf16_hilo")
+    ap.add_argument("--serving-saturate", action="store_true", help="submit frames as fast as possible")
+    ap.add_argument("--serving-limit-s", type=float, default=150.0)
     ap.add_argument("--pool-batches", type=int, default=128,
                     help="distinct batches generated (steps cycle through them); the medium workload has 128")
     return ap.parse_args()
@@ -99,8 +105,106 @@ def cpu_baseline(wl, frames, pos, seconds):
                       f"{el:.1f} s; plan build {plan_s:.1f} s excluded"}
 
 
+def serving(args):
+    """Serving mix: acquisitions arriving as a Poisson process, each streaming frames at its
+    own rate in random delivery sizes, admitted by an HBM budget, served by one server with
+    continuous batching.  Prints one JSON line."""
+    import torch
+
+    import paper_2212_01309_amd as wdd
+    import synth
+
+    rng = np.random.default_rng(2024)
+    n_acq = args.serving_acquisitions
+    arrivals = np.cumsum(rng.exponential(0.5, size=n_acq))          # mean 2 arrivals per second
+    if args.serving_saturate:
+        arrivals[:] = 0.0                                              # everything is there at once
+    pools = {}
+    for n in (64, 128, 256):                                          # frame pools per detector size
+        radius = n / 4 if n <= 128 else 48.0
+        wl = synth.Workload(f"pool{n}", 32, 32, n, radius, 64, 256, 2 * n, 30, (1.0, 3.0), (0.2, 0.5), 5e3, seed=n)
+        fr = wl.frames(synth.raster_positions(16, 32))               # 512 frames
+        pools[n] = torch.from_numpy(fr.view(np.int16)).to("cuda")
+    torch.cuda.synchronize()
+    acqs = []
+    for i in range(n_acq):
+        s = int(rng.choice([64, 128, 256, 512]))
+        n = int(rng.choice([64, 128, 256]))
+        acqs.append(dict(i=i, t_arrive=float(arrivals[i]), s=s, n=n, k=64 if n <= 128 else 128,
+                         radius=n / 4 if n <= 128 else 48.0, rate=float(rng.uniform(1e4, 5e4)),
+                         dose=float(rng.uniform(1e3, 1e4)), total=s * s, sent=0, id=None, t_start=None,
+                         next_chunk=int(rng.integers(1, 513)), pos=synth.raster_positions(s, s)))
+    srv = wdd.Server(hbm_budget_bytes=args.serving_budget_mb << 20, snapshot_interval_us=1000.0, batch_frames=512)
+    waiting, active, done = list(acqs), [], []
+    deferred = 0
+    t0 = time.perf_counter()
+    last_print = t0
+    while waiting or active:
+        t = time.perf_counter() - t0
+        while waiting and waiting[0]["t_arrive"] <= t:
+            a = waiting[0]
+            aid = srv.open(a["radius"], a["s"], a["s"], a["n"], a["n"], a["k"], precision=args.serving_precision)
+            if aid is None:
+                if not a.get("deferred"):
+                    a["deferred"] = True
+                    deferred += 1
+                break                                              # admitted in arrival order once memory frees
+            a["id"], a["t_start"] = aid, t
+            active.append(waiting.pop(0))
+        for a in list(active):
+            due = a["total"] if args.serving_saturate else min(a["total"], int((t - a["t_start"]) * a["rate"]))
+            while a["sent"] < a["total"] and a["sent"] + min(a["next_chunk"], a["total"] - a["sent"]) <= due:
+                nb = min(a["next_chunk"], a["total"] - a["sent"])
+                pool = pools[a["n"]]
+                off = a["sent"] % len(pool)
+                nb = min(nb, len(pool) - off)                        # a delivery does not wrap the pool
+                srv.submit(a["id"], pool[off:off + nb], a["pos"][a["sent"]:a["sent"] + nb])
+                a["sent"] += nb
+                a["next_chunk"] = int(rng.integers(1, 513))
+            if a["sent"] >= a["total"]:
+                srv.snapshot(a["id"])
+                srv.close(a["id"])
+                a["t_end"] = time.perf_counter() - t0
+                active.remove(a)
+                done.append(a)
+        srv.step()
+        if time.perf_counter() - last_print > 5.0:
+            st = srv.stats()
+            print(f"[serving] t={t:.1f}s open={st['open']} done={len(done)} frames={st['frames']} "
+                  f"pending={st['pending_frames']}", file=sys.stderr, flush=True)
+            last_print = time.perf_counter()
+        if time.perf_counter() - t0 > args.serving_limit_s:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.destroy()
+    offered = sum(a["rate"] for a in acqs)
+    out = {
+        "metric": "serving mix: aggregate frames/s and frame-to-snapshot latency",
+        "value": st["frames"] / wall, "unit": "frames/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": f"{args.serving_precision} projection, f32 accumulate", "data": "synthetic",
+        "config": {"workload": f"{n_acq} acquisitions, {'arriving together' if args.serving_saturate else 'Poisson arrivals (mean 2/s)'}, scans 64^2..512^2, detectors "
+                               f"64^2..256^2, {'all frames available at t=0' if args.serving_saturate else '10k-50k frames/s each'}, "
+                               f"deliveries of 1-512 frames, HBM budget {args.serving_budget_mb} MiB, "
+                               f"snapshot every >= 1 ms per acquisition",
+                   "acquisitions_done": len(done), "deferred_admissions": deferred,
+                   "offered_frames_per_s_sum_of_rates": offered},
+        "frames": st["frames"], "wall_s": wall, "batches": st["batches"], "snapshots": st["snapshots"],
+        "latency_ms": {"p50": st["latency_p50_us"] / 1e3, "p99": st["latency_p99_us"] / 1e3,
+                       "max": st["latency_max_us"] / 1e3},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.serving:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        serving(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the method's multi-GPU "
               f"sharding is described in DESIGN.md, not built).", file=sys.stderr)

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -45,8 +46,20 @@ struct Acq {
 
 }  // namespace
 
+// Host tables keyed by everything they depend on; acquisitions of a repeated geometry
+// skip the FP64 table build.
+struct TableKey {
+  double radius, defocus, amplitude, step, eps_rel, sigma;
+  int32_t sy, sx, ny, nx, dtype, k, precision;
+  bool operator<(const TableKey& o) const {
+    return std::memcmp(this, &o, sizeof(TableKey)) < 0;
+  }
+};
+
 struct wdd_server_s {
   wdd_server_options opts;
+  std::map<TableKey, std::shared_ptr<wdd_tables_s>> tables;
+  size_t table_bytes = 0;
   int64_t used = 0;
   int32_t next_id = 1;
   std::map<int32_t, Acq*> acqs;
@@ -133,12 +146,32 @@ wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_sca
   opts.max_batch = std::max(opts.max_batch, s->opts.batch_frames);
   wdd_status st = wdd::check_plan_options(det, opts);
   if (st != WDD_OK) return st;
-  wdd_tables_s t;
-  try {
-    if ((st = wdd::build_tables(probe, scan, det, K, &opts, &t)) != WDD_OK) return st;
-  } catch (const std::bad_alloc&) {
-    return wdd::fail(WDD_ENOMEM, "out of host memory");
+  TableKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.radius = probe->radius_px; key.defocus = probe->defocus_edge_rad; key.amplitude = probe->amplitude;
+  key.step = scan->step_px; key.eps_rel = opts.eps_rel; key.sigma = opts.sigma_px;
+  key.sy = scan->sy; key.sx = scan->sx; key.ny = det->ny; key.nx = det->nx; key.dtype = det->dtype; key.k = K;
+  key.precision = opts.precision;
+  std::shared_ptr<wdd_tables_s> tp;
+  auto it = s->tables.find(key);
+  if (it != s->tables.end()) {
+    tp = it->second;
+  } else {
+    try {
+      tp = std::make_shared<wdd_tables_s>();
+      if ((st = wdd::build_tables(probe, scan, det, K, &opts, tp.get())) != WDD_OK) return st;
+    } catch (const std::bad_alloc&) {
+      return wdd::fail(WDD_ENOMEM, "out of host memory");
+    }
+    const size_t tb = tp->w.size() * sizeof(double) + tp->freqs.size() * sizeof(int32_t);
+    if (s->table_bytes + tb > ((size_t)4 << 30)) {  // keep at most 4 GiB of cached host tables
+      s->tables.clear();
+      s->table_bytes = 0;
+    }
+    s->tables[key] = tp;
+    s->table_bytes += tb;
   }
+  const wdd_tables_s& t = *tp;
   const int64_t need = wdd::plan_device_bytes(t, opts, det->dtype);
   if (s->opts.hbm_budget_bytes > 0 && s->used + need > s->opts.hbm_budget_bytes)
     return wdd::fail(WDD_EBUSY, "acquisition needs %lld bytes; %lld of %lld in use", (long long)need,
