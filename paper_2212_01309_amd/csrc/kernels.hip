@@ -466,10 +466,10 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
 // batch's frame indices grouped by row.
 // ---------------------------------------------------------------------------
 // T_r = Fx_r h_r as a real GEMM with rows (vx, re/im) interleaved, on
-// v_mfma_f32_32x32x2_f32.  A workgroup of 4 waves owns one 32 x 32 tile (16 values
-// of vx x 32 columns) of row r.  Per chunk of up to 256 frames the Tx table, the
-// frames' indices and x positions and the chunk's h columns are staged in LDS; wave
-// w takes every fourth frame pair, and the four partial tiles are summed at the end.
+// v_mfma_f32_16x16x4_f32.  A workgroup of 4 waves owns one 16 x 16 tile (8 values of
+// vx x 16 columns) of row r.  Per chunk of up to 256 frames the Tx table, the frames'
+// indices and x positions and the chunk's h columns are staged in LDS; wave w takes a
+// quarter of the frames, and the four partial tiles are summed at the end.
 constexpr int kRowChunk = 256;
 
 __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int2* __restrict__ pos,
@@ -479,17 +479,17 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
   float2* ltx = rsmem;                                   // [sx]
   int* lx = reinterpret_cast<int*>(ltx + sx);            // [kRowChunk]
   int* lb = lx + kRowChunk;                              // [kRowChunk]
-  float* lh = reinterpret_cast<float*>(lb + kRowChunk);  // [kRowChunk][32]; reused for the final sum
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i32 = lane & 31, half = lane >> 5;
+  float* lh = reinterpret_cast<float*>(lb + kRowChunk);  // [kRowChunk][16]; reused for the final sum
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15, q = lane >> 4;
   const int r = blockIdx.z;
   const int4 row = rows[r];
-  const int vx = blockIdx.x * 16 + (i32 >> 1);
-  const bool im = (i32 & 1) != 0;
-  const int c0 = blockIdx.y * 32;
+  const int vx = blockIdx.x * 8 + (r16 >> 1);            // A-operand row r16 = 2 * (vx - vx0) + (re/im)
+  const bool im = (r16 & 1) != 0;
+  const int c0 = blockIdx.y * 16;
   const bool p2 = (sx & (sx - 1)) == 0;
   const float inv = 1.0f / (float)sx;
   for (int i = tid; i < sx; i += 256) ltx[i] = tx[i];
-  floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int i0 = 0; i0 < row.z; i0 += kRowChunk) {
     const int cnt = min(kRowChunk, row.z - i0);
     __syncthreads();
@@ -499,41 +499,45 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
       lx[tid] = pos[b].y;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int i = tid; i < kRowChunk * 32; i += 256) {
-      const int f = i >> 5, c = i & 31;
+#pragma unroll
+    for (int j = 0; j < kRowChunk * 16 / 256; ++j) {
+      const int i = tid + 256 * j;
+      const int f = i >> 4, c = i & 15;
       lh[i] = (f < cnt) ? h[(size_t)lb[f] * kpad + c0 + c] : 0.f;
     }
     __syncthreads();
-    const int nk = (cnt + 1) >> 1;
-    for (int kk = wave; kk < nk; kk += 4) {
-      const int f = 2 * kk + half;
-      float a = 0.f;
-      if (f < cnt && vx < sx) {
-        const int p = vx * lx[f];
-        const float2 w = ltx[p2 ? (p & (sx - 1)) : mod_small(p, sx, inv)];
-        a = im ? w.y : w.x;
+    // wave w takes frames [w * per, (w + 1) * per), 4 per MFMA (k-slot q <-> frame f0 + q)
+    const int per = ((cnt + 15) / 16) * 4;
+    const int fbeg = wave * per, fend = min(cnt, fbeg + per);
+    for (int f0 = fbeg; f0 < fend; f0 += 4) {
+      const int f = f0 + q;
+      float a = 0.f, bv = 0.f;
+      if (f < fend) {
+        if (vx < sx) {
+          const int p = vx * lx[f];
+          const float2 w = ltx[p2 ? (p & (sx - 1)) : mod_small(p, sx, inv)];
+          a = im ? w.y : w.x;
+        }
+        bv = lh[f * 16 + r16];
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, lh[f * 32 + i32], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
     }
   }
   __syncthreads();
   if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lh[((wave - 1) * 16 + q) * 64 + lane] = acc[q];
+    for (int j = 0; j < 4; ++j) lh[((wave - 1) * 4 + j) * 64 + lane] = acc[j];
   }
   __syncthreads();
   if (wave == 0) {
 #pragma unroll
-    for (int q = 0; q < 16; q += 2) {
-      float re = acc[q], imv = acc[q + 1];
-      for (int w = 0; w < 3; ++w) {
-        re += lh[(w * 16 + q) * 64 + lane];
-        imv += lh[(w * 16 + q + 1) * 64 + lane];
-      }
-      const int rowi = 8 * (q >> 2) + 4 * half + (q & 3);
-      const int v = blockIdx.x * 16 + (rowi >> 1);
-      if (v < sx) t[((size_t)r * sx + v) * kpad + c0 + i32] = make_float2(re, imv);
+    for (int j = 0; j < 4; ++j)
+      for (int w = 0; w < 3; ++w) acc[j] += lh[(w * 4 + j) * 64 + lane];
+    // lane (q, r16) holds rows 4q .. 4q + 3 of column r16: vx = vx0 + 2q (+1), (re, im) pairs
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+      const int v = blockIdx.x * 8 + 2 * q + (j >> 1);
+      if (v < sx) t[((size_t)r * sx + v) * kpad + c0 + r16] = make_float2(acc[j], acc[j + 1]);
     }
   }
 }
@@ -733,8 +737,8 @@ hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* 
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 32 * sizeof(float);
-  dim3 grid((unsigned)((sx + 15) / 16), (unsigned)(kpad / 32), (unsigned)nrows);
+  const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
+  dim3 grid((unsigned)((sx + 7) / 8), (unsigned)(kpad / 16), (unsigned)nrows);
   hipLaunchKernelGGL(k_row_dft, grid, dim3(256), lds, st, h, kpad, pos, order, rows, tx, sx, t);
   return hipGetLastError();
 }
