@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="medium")
+    ap.add_argument("--order", default="object", choices=["spectrum", "object"],
+                    help="accumulate the spectrum A (Wiener filter at snapshot) or the object spectrum D "
+                         "(Wiener filter per frame)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16_hilo", "fp16_hilo", "bf16", "fp16"],
                     help="arithmetic of the projection's first stage (FP32 accumulation throughout)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
@@ -71,9 +74,12 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def roofline(wl, n_freq, k, dom, us, factored, fused):
+def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum"):
     """Roofline entry of stage `dom` (mean launch time `us`), from its algorithmic work."""
-    if dom == "accumulate" and factored:
+    if dom == "accumulate" and order == "object":
+        # object order: stream W once per row pass
+        nbytes, kernel, bound = 8.0 * n_freq * k, "k_row_update_obj", "hbm"
+    elif dom == "accumulate" and factored:
         # row-factored update: read and write A, read W when the Wiener reduction is fused
         nbytes = (24.0 if fused else 16.0) * n_freq * k
         kernel, bound = "k_row_update" + ("<true>" if fused else "<false>"), "hbm"
@@ -252,15 +258,17 @@ def main():
     torch.cuda.synchronize()
     dtype = wdd.WDD_U16 if frames.dtype == np.uint16 else wdd.WDD_F32
     plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
-                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch, precision=args.precision)
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch, precision=args.precision,
+                    order=wdd.WDD_ORDER_OBJECT if args.order == "object" else wdd.WDD_ORDER_SPECTRUM)
     nb = len(pos) // wl.batch
     batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
 
-    shown = plan.snapshot_buffer()     # the plan's pinned host buffer: the display lands there directly
+    # the displayed image stays in HBM (as the frames do); steps pipeline on the plan's stream
+    shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
 
-    def step(i):
+    def step(i, wait=False):
         fr, ps = batches[i % nb]
-        plan.push_snapshot(fr, ps, out=shown)
+        plan.push_snapshot(fr, ps, out=shown, wait=wait)
 
     for i in range(args.warmup):
         step(i)
@@ -282,16 +290,31 @@ def main():
         dominant = "accumulate"
         factored, fused = pre["rowdft_launches"] > 0, pre["wiener_launches"] == 0
         plan.profile_enable(stage_bits[dominant])
+    plan.sync()
     torch.cuda.synchronize()
-    lat = np.empty(args.steps)
     t_start = time.perf_counter()
     for i in range(args.steps):
-        t = time.perf_counter()
         step(args.warmup + i)
-        lat[i] = time.perf_counter() - t
+    plan.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = plan.profile_read() if not args.no_profile else None
+    if not args.no_profile:
+        plan.profile_enable(0)
+    # untimed: latency of one step (push to image complete in HBM), and the rate when every
+    # image is also brought to the host through the plan's pinned buffer (PCIe included)
+    nlat = min(args.steps, 500)
+    lat = np.empty(nlat)
+    for i in range(nlat):
+        t = time.perf_counter()
+        step(i, wait=True)
+        lat[i] = time.perf_counter() - t
+    pinned = plan.snapshot_buffer()
+    t = time.perf_counter()
+    for i in range(nlat):
+        fr, ps = batches[i % nb]
+        plan.push_snapshot(fr, ps, out=pinned)
+    host_fps = nlat * wl.batch / (time.perf_counter() - t)
     n_freq, k = plan.n_freq, plan.k
     plan.close()
 
@@ -303,15 +326,18 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else f"{args.precision} projection, f32 accumulate",
         "data": "synthetic",
         "config": {"workload": workload_label(wl, n_freq), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
-                   "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype)},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+                   "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
+                   "wiener_order": args.order, "display": "hbm"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                       "steps": nlat},
+        "host_display_fps": host_fps,
     }
     if prof is not None:
         # the dominant stage's mean launch time over the timed region replaces the pre-pass value
         stages[dominant] = prof[f"{dominant}_ms"] / max(prof[f"{dominant}_launches"], 1) * 1e3
         out["stages_us"] = stages
         out["largest_kernel_stage"] = max(per_kernel, key=per_kernel.get)
-        out["roofline"] = roofline(wl, n_freq, k, dominant, stages[dominant], factored, fused)
+        out["roofline"] = roofline(wl, n_freq, k, dominant, stages[dominant], factored, fused, args.order)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds)
     out["generation_s"] = gen_s

@@ -85,11 +85,19 @@ typedef struct {
   int32_t dtype; /* wdd_dtype */
 } wdd_detector;
 
+/* Where the Wiener filter is applied.  WDD_ORDER_SPECTRUM: frames are accumulated into the
+ * spectrum A[v, k] (resident in HBM, a sufficient statistic) and the filter is applied at each
+ * snapshot.  WDD_ORDER_OBJECT: the filter is applied per frame and the object spectrum D[v] is
+ * accumulated directly, as written in the modified-WDD algorithm (Section 6.3); A is not kept,
+ * so wdd_get_accumulator and wdd_update_probe are unavailable.  Both give the same result. */
+typedef enum { WDD_ORDER_SPECTRUM = 0, WDD_ORDER_OBJECT = 1 } wdd_order;
+
 typedef struct {
   double eps_rel;     /* Wiener regularisation relative to the largest |Y^B|^2; default 0.01 */
   double sigma_px;    /* basis width in detector pixels; <= 0 selects radius / sqrt(2L - 1) */
   int32_t precision;  /* wdd_precision; default WDD_FP32 */
   int32_t max_batch;  /* largest n accepted by wdd_push; default 256 */
+  int32_t order;      /* wdd_order; default WDD_ORDER_SPECTRUM */
 } wdd_options;
 
 typedef struct {
@@ -170,11 +178,19 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
 wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
                              int32_t frames_on_device, float* out, int32_t out_on_device, uint64_t* frames_seen);
 
+/* Where a snapshot is written (the out_on_device argument).
+ *   WDD_OUT_HOST          host memory; the call blocks until `out` is written.
+ *   WDD_OUT_DEVICE        device memory (8-byte aligned); blocks until it is written.
+ *   WDD_OUT_DEVICE_ASYNC  device memory (8-byte aligned); returns once the work is
+ *                         enqueued on the plan's stream.  `out` (which must stay valid)
+ *                         is complete after wdd_sync, or once the plan's stream passes
+ *                         this point; frames_seen then counts the frames enqueued. */
+typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2 } wdd_out_kind;
+
 /* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
  * conjugation and normalisation (eq. extract).  Writes sy x sx complex values
- * (interleaved float, row-major [y][x]) to `out` (device memory if
- * out_on_device != 0, 8-byte aligned; else host memory).  Blocks until `out` is
- * written.
+ * (interleaved float, row-major [y][x]) to `out`, a wdd_out_kind place given by
+ * out_on_device (any other value: WDD_EINVAL).
  * Object pixel mapping: out[y][x] is the object at scan position (y, x) shifted
  * by the probe's centre (ny/2, nx/2) within its window.  frames_seen may be NULL. */
 wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_t* frames_seen);
@@ -189,7 +205,8 @@ wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out);
  * n_freq complex values, as computed by the last wdd_snapshot. */
 wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device);
 
-/* Inspection (blocking): the accumulated spectrum A, n_freq x k complex values. */
+/* Inspection (blocking): the accumulated spectrum A, n_freq x k complex values
+ * (WDD_ESTATE in WDD_ORDER_OBJECT). */
 wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device);
 
 /* Inspection (blocking): the projections h of the last pushed batch, n x k floats
@@ -232,11 +249,11 @@ wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);
  * creation.  The accumulated spectrum A is kept (it does not depend on the probe), so
  * the next snapshot deconvolves every frame seen so far with the new filter without
  * re-reading them (Section 10: probe update; Algorithm "pre-computed Wiener filter").
- * WDD_EINVAL if the radius differs. */
+ * WDD_EINVAL if the radius differs; WDD_ESTATE in WDD_ORDER_OBJECT. */
 wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel);
 
-/* Checkpoint of the live state (the spectrum A and the frame count, a sufficient
- * statistic of all frames pushed).  wdd_checkpoint_size gives the byte size of the
+/* Checkpoint of the live state (the spectrum A, or D in WDD_ORDER_OBJECT, and the frame
+ * count: a sufficient statistic of all frames pushed).  wdd_checkpoint_size gives the byte size of the
  * image; wdd_checkpoint_save writes it to host memory (blocking); wdd_checkpoint_load
  * restores it into a plan of the same geometry and basis (WDD_EINVAL otherwise). */
 wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes);

@@ -21,6 +21,8 @@ WDD_U16, WDD_F32 = 0, 1
 WDD_FP32, WDD_BF16_HILO, WDD_FP16_HILO, WDD_BF16, WDD_FP16 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP16_HILO, "bf16": WDD_BF16,
               "fp16": WDD_FP16}
+WDD_ORDER_SPECTRUM, WDD_ORDER_OBJECT = 0, 1
+WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC = 0, 1, 2
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
 _STATUS_NAMES = {0: "WDD_OK", -1: "WDD_EINVAL", -2: "WDD_ENOMEM", -3: "WDD_ERANGE", -4: "WDD_EDEVICE",
@@ -47,7 +49,7 @@ class Detector(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eps_rel", ctypes.c_double), ("sigma_px", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -147,11 +149,15 @@ def _check(code: int) -> None:
         raise WddError(code, msg)
 
 
-def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32) -> Options:
+def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32,
+             order: int = WDD_ORDER_SPECTRUM) -> Options:
     o = Options()
     _check(load_library().wdd_default_options(ctypes.byref(o)))
-    o.eps_rel, o.sigma_px, o.max_batch, o.precision = eps_rel, sigma_px, max_batch, precision
+    o.eps_rel, o.sigma_px, o.max_batch, o.precision, o.order = eps_rel, sigma_px, max_batch, precision, order
     return o
+
+
+_I32 = np.dtype(np.int32)
 
 
 def _is_device_tensor(x) -> bool:
@@ -209,7 +215,8 @@ class Plan:
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
-                 sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32):
+                 sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32,
+                 order: int = WDD_ORDER_SPECTRUM):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
@@ -218,17 +225,25 @@ class Plan:
         self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
         _check(lib.wdd_plan_create(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
                                    ctypes.byref(Detector(ny, nx, dtype)), k,
-                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision)),
+                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order)),
                                    _P(stream) if stream else None, ctypes.byref(self._h)))
         info = self.info()
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
         self._last_batch = 0
+        # per-call state of the hot path (a plan is used from one thread at a time)
+        self._fn_push, self._fn_push_snapshot = lib.wdd_push, lib.wdd_push_snapshot
+        self._seen = ctypes.c_uint64()
+        self._seen_ref = ctypes.byref(self._seen)
+        self._addr_cache = {}
+        self._pinned = None
 
     # -- lifecycle ---------------------------------------------------------
     def close(self) -> None:
         if self._h:
             load_library().wdd_plan_destroy(self._h)
             self._h = _P()
+            self._pinned = None          # the pinned buffer is freed with the plan
+            self._addr_cache = {}
 
     def __enter__(self):
         return self
@@ -252,8 +267,26 @@ class Plan:
         return info
 
     # -- hot path ------------------------------------------------------------
+    def _host_addr(self, a: np.ndarray) -> int:
+        """Data address of a small host array, remembered for the arrays seen recently (they
+        are kept alive while remembered, so their ids cannot be taken by other arrays)."""
+        e = self._addr_cache.get(id(a))
+        if e is not None and e[0] is a:
+            return e[1]
+        if len(self._addr_cache) >= 256:
+            self._addr_cache.clear()
+        addr = a.ctypes.data
+        self._addr_cache[id(a)] = (a, addr)
+        return addr
+
     def _frames_arg(self, frames, positions):
-        pos = _host_array(positions, np.int32).reshape(-1, 2)
+        if (type(positions) is np.ndarray and positions.dtype == _I32 and positions.ndim == 2
+                and positions.shape[1] == 2 and positions.flags.c_contiguous):
+            pos = positions
+            pos_addr = self._host_addr(pos)
+        else:
+            pos = _host_array(positions, np.int32).reshape(-1, 2)
+            pos_addr = pos.ctypes.data
         n = pos.shape[0]
         if _is_device_tensor(frames):
             if frames.element_size() != np.dtype(self._np_dtype).itemsize:
@@ -268,41 +301,51 @@ class Plan:
             if keep.size != n * self.ny * self.nx:
                 raise ValueError("frames and positions disagree in count or frame shape")
             ptr, on_dev = keep.ctypes.data, 0
-        return pos, n, ptr, on_dev, keep
+        return pos_addr, n, ptr, on_dev, keep
 
     def push(self, frames, positions) -> None:
         """frames: [n, ny, nx] (torch GPU tensor or host array of the detector dtype);
         positions: host int32 [n, 2] scan indices (y, x)."""
         pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
-        _check(load_library().wdd_push(self._h, ptr, pos.ctypes.data, n, on_dev))
+        _check(self._fn_push(self._h, ptr, pos, n, on_dev))
         if n:
             self._last_batch = n
         del keep
 
-    def push_snapshot(self, frames, positions, out=None):
-        """push() then snapshot() in one call (one pass over the spectrum when possible)."""
+    def push_snapshot(self, frames, positions, out=None, wait: bool = True):
+        """push() then snapshot() in one call (one pass over the spectrum when possible).
+        With a device `out` and wait=False the call returns once the work is enqueued; `out`
+        is complete after sync()."""
         pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
-        seen = ctypes.c_uint64()
-        if out is not None and _is_device_tensor(out):
-            _check(load_library().wdd_push_snapshot(self._h, ptr, pos.ctypes.data, n, on_dev, out.data_ptr(), 1,
-                                                    ctypes.byref(seen)))
+        if out is not None and out is self._pinned:
+            res = out
+            _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, self._pinned_addr, 0, self._seen_ref))
+        elif out is not None and _is_device_tensor(out):
+            kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
+            _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, self._device_out(out), kind, self._seen_ref))
             res = out
         else:
             res = self._host_out(out)
-            _check(load_library().wdd_push_snapshot(self._h, ptr, pos.ctypes.data, n, on_dev, res.ctypes.data, 0,
-                                                    ctypes.byref(seen)))
+            _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, res.ctypes.data, 0, self._seen_ref))
         if n:
             self._last_batch = n
         del keep
         return res
 
-    def snapshot(self, out=None):
+    def _device_out(self, out) -> int:
+        if out.numel() * out.element_size() != 8 * self.sy * self.sx or not out.is_contiguous():
+            raise ValueError("device output must be a contiguous tensor of sy*sx complex64 values")
+        return out.data_ptr()
+
+    def snapshot(self, out=None, wait: bool = True):
         """Displayed estimate [sy, sx] complex64.  With `out` (a torch GPU tensor of
         sy*sx complex64 or 2*sy*sx float32, or a host complex64 array) it is written there
-        and returned."""
+        and returned.  With a device `out` and wait=False the call returns once the work is
+        enqueued; `out` is complete after sync()."""
         seen = ctypes.c_uint64()
         if out is not None and _is_device_tensor(out):
-            _check(load_library().wdd_snapshot(self._h, out.data_ptr(), 1, ctypes.byref(seen)))
+            kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
+            _check(load_library().wdd_snapshot(self._h, self._device_out(out), kind, ctypes.byref(seen)))
             return out
         host = self._host_out(out)
         _check(load_library().wdd_snapshot(self._h, host.ctypes.data, 0, ctypes.byref(seen)))
@@ -319,10 +362,13 @@ class Plan:
     def snapshot_buffer(self) -> np.ndarray:
         """The plan's pinned host array [sy, sx] complex64 that host snapshots pass through;
         give it as `out` to avoid the final copy.  Overwritten by every host snapshot."""
-        ptr = ctypes.POINTER(ctypes.c_float)()
-        _check(load_library().wdd_snapshot_buffer(self._h, ctypes.byref(ptr)))
-        flat = np.ctypeslib.as_array(ptr, shape=(2 * self.sy * self.sx,))
-        return flat.view(np.complex64).reshape(self.sy, self.sx)
+        if self._pinned is None:
+            ptr = ctypes.POINTER(ctypes.c_float)()
+            _check(load_library().wdd_snapshot_buffer(self._h, ctypes.byref(ptr)))
+            flat = np.ctypeslib.as_array(ptr, shape=(2 * self.sy * self.sx,))
+            self._pinned = flat.view(np.complex64).reshape(self.sy, self.sx)
+            self._pinned_addr = self._pinned.ctypes.data
+        return self._pinned
 
     def spectrum(self) -> np.ndarray:
         """D on the kept frequencies from the last snapshot, complex64 [n_freq]."""

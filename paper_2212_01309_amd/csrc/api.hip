@@ -6,12 +6,12 @@
 //                                       (kpad = K rounded up to a power of two >= 32)
 //   freqs   int2   [n_freq_pad]         kept (v_y, v_x); padding rows (0, 0)
 //   w       float2 [n_freq_pad][kpad]   Wiener filter (padding rows/columns zero)
-//   acc     float2 [n_freq_pad][kpad]   accumulated spectrum A
+//   acc     float2 [n_freq_pad][kpad]   accumulated spectrum A (spectrum order only)
 //   ty, tx  float2 [sy], [sx]           exp(-2 pi i m / S); tx carries 1/sqrt(sy sx)
 //   ey, ex  float2 [sy], [sx]           exp(-2 pi i m / S) for the display DFT
 //   h       float  [max_batch][kpad]    projections of the current batch
 //   upload  bytes                       per batch: pos int2 [max_batch], order int32 [max_batch],
-//                                       rows int4 [kFactorRows] (one host->device copy)
+//                                       rows int4 [max_batch] (brought over by the projection kernel)
 //   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs of the row-factored accumulation
 //   frames  staging for host frames     [max_batch][ny][nx]
 //   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
@@ -49,6 +49,7 @@ struct wdd_plan_impl {
   uint16_t* psix_lp = nullptr;  // [2][16][nx] bf16/fp16 hi and lo parts (reduced-precision projection)
   float psi_unscale = 1.f;
   int32_t precision = WDD_FP32;
+  int32_t order_mode = WDD_ORDER_SPECTRUM;
   wdd_probe probe = {};
   wdd_scan scan = {};
   wdd_detector det = {};
@@ -231,7 +232,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   p->sigma = t.sigma; p->eps_abs = t.eps_abs;
   p->max_batch = opts.max_batch;
   p->host_order.resize(p->max_batch);
-  p->host_rows.reserve(kFactorRows + 1);
+  p->host_rows.reserve(p->max_batch);
   p->frame_bytes = (size_t)t.ny * t.nx * (p->dtype == WDD_U16 ? 2 : 4);
   WDD_HIP(p, hipGetDevice(&p->device));
   if (stream) {
@@ -285,13 +286,13 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   ALLOC(p->kmap, kmap.size());
   ALLOC(p->freqs, freqs.size());
   ALLOC(p->w, nfk);
-  ALLOC(p->acc, nfk);
+  if (p->order_mode == WDD_ORDER_SPECTRUM) ALLOC(p->acc, nfk);
   ALLOC(p->ty, (size_t)t.sy);
   ALLOC(p->tx, (size_t)t.sx);
   ALLOC(p->ey, (size_t)t.sy);
   ALLOC(p->ex, (size_t)t.sx);
   ALLOC(p->h, (size_t)p->max_batch * p->kpad);
-  p->upload_bytes = (size_t)p->max_batch * 12 + 16 + (size_t)kFactorRows * sizeof(int4);
+  p->upload_bytes = (size_t)p->max_batch * 12 + 16 + (size_t)p->max_batch * sizeof(int4);
   ALLOC(p->upload, p->upload_bytes);
   p->pos = reinterpret_cast<int2*>(p->upload);
   p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
@@ -319,7 +320,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, hipMemcpyAsync(p->tx, tx.data(), tx.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ey, ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ex, ex.data(), ex.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
-  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), nfk * 2, p->stream));
+  if (p->acc) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), nfk * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), grid * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad, p->stream));
@@ -349,6 +350,8 @@ wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) 
     return wdd::fail(WDD_EINVAL, "reduced-precision projection needs uint16 frames");
   if (opts.max_batch < 1 || opts.max_batch > 65536)
     return wdd::fail(WDD_EINVAL, "max_batch = %d outside [1, 65536]", opts.max_batch);
+  if (opts.order != WDD_ORDER_SPECTRUM && opts.order != WDD_ORDER_OBJECT)
+    return wdd::fail(WDD_EINVAL, "unknown order %d", opts.order);
   return WDD_OK;
 }
 
@@ -357,9 +360,10 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
   while (kpad < t.k) kpad *= 2;
   const int64_t nfp = (t.n_freq() + 63) / 64 * 64, mb = opts.max_batch, grid = (int64_t)t.sy * t.sx;
   auto a = [](int64_t bytes) { return std::max<int64_t>(bytes, 256); };
-  int64_t b = a((int64_t)(t.ny + t.nx) * 16 * 4) + a(kpad * 4) + a(nfp * 8) + 2 * a(nfp * kpad * 8);
+  int64_t b = a((int64_t)(t.ny + t.nx) * 16 * 4) + a(kpad * 4) + a(nfp * 8) + a(nfp * kpad * 8);
+  if (opts.order == WDD_ORDER_SPECTRUM) b += a(nfp * kpad * 8);
   if (opts.precision != WDD_FP32) b += a((int64_t)2 * 16 * t.nx * 2);
-  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 12 + 16 + kFactorRows * 16);
+  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 12 + 16 + mb * 16);
   b += a((int64_t)kFactorRows * t.sx * kpad * 8) + a(mb * (int64_t)t.ny * t.nx * (dtype == WDD_U16 ? 2 : 4));
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
@@ -372,6 +376,7 @@ wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe
   if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
   p->dtype = det->dtype;
   p->precision = opts.precision;
+  p->order_mode = opts.order;
   p->probe = *probe;
   p->scan = *scan;
   p->det = *det;
@@ -443,12 +448,14 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   for (int32_t i = 0; i < n; ++i) ord[i] = i;
   std::stable_sort(ord, ord + n, [pos_yx](int32_t a, int32_t b) { return pos_yx[2 * a] < pos_yx[2 * b]; });
   p->host_rows.clear();
-  for (int32_t i = 0; i < n && (int)p->host_rows.size() <= kFactorRows; ++i) {
+  const bool object = p->order_mode == WDD_ORDER_OBJECT;
+  for (int32_t i = 0; i < n && (object || (int)p->host_rows.size() <= kFactorRows); ++i) {
     const int32_t y = pos_yx[2 * ord[i]];
     if (p->host_rows.empty() || p->host_rows.back().x != y) p->host_rows.push_back(make_int4(y, i, 0, 0));
     p->host_rows.back().z += 1;
   }
-  const bool factored = (int)p->host_rows.size() <= kFactorRows;
+  // object order always takes the factored form, in passes of at most kFactorRows rows
+  const bool factored = object || (int)p->host_rows.size() <= kFactorRows;
   const int nrows = factored ? (int)p->host_rows.size() : 0;
 
   // reuse a pinned slot only after the copies that read it have run
@@ -506,7 +513,19 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   } else {
     p->ev_live[s] = false;
   }
-  if (factored) {
+  if (object) {
+    for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
+      const int nr = std::min(kFactorRows, nrows - r0);
+      WDD_HIP(p, stage_begin(p, kRowDft, &end));
+      WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows + r0, nr, p->tx, p->sx, p->t,
+                                     p->stream));
+      WDD_HIP(p, stage_end(p, end));
+      WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+      WDD_HIP(p, wdd::launch_row_update_obj(p->d, p->kpad, p->n_freq_pad, p->freqs, p->n_freq, p->t, p->sx,
+                                            p->rows + r0, nr, p->ty, p->sy, p->w, p->z, p->stream));
+      WDD_HIP(p, stage_end(p, end));
+    }
+  } else if (factored) {
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
     WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
     WDD_HIP(p, stage_end(p, end));
@@ -520,7 +539,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
                                       p->sx, p->stream));
     WDD_HIP(p, stage_end(p, end));
   }
-  if (fused) *fused = factored && fuse_wiener;
+  if (fused) *fused = object || (factored && fuse_wiener);
   p->frames_seen += (uint64_t)n;
   p->last_batch = n;
   return WDD_OK;
@@ -529,7 +548,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
 // Queues the display step (optionally after the Wiener reduction) writing to `out`.
 wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_device, bool reduce) {
   hipEvent_t end;
-  if (reduce) {
+  if (reduce && p->order_mode == WDD_ORDER_SPECTRUM) {  // object order keeps D current
     WDD_HIP(p, stage_begin(p, kWiener, &end));
     WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sy, p->stream));
     WDD_HIP(p, stage_end(p, end));
@@ -550,6 +569,10 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
 // Waits for the queued snapshot and copies it out of the pinned buffer if needed.
 wdd_status snapshot_finish_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
   const size_t grid = (size_t)p->sy * p->sx;
+  if (out_on_device == WDD_OUT_DEVICE_ASYNC) {
+    if (frames_seen) *frames_seen = p->frames_seen;
+    return WDD_OK;
+  }
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   if (!out_on_device && reinterpret_cast<float2*>(out) != p->pin_out) std::memcpy(out, p->pin_out, grid * sizeof(float2));
   WDD_HIP(p, harvest(p));
@@ -602,6 +625,8 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
 
 static wdd_status check_out(const float* out, int32_t out_on_device) {
   if (!out) return wdd::fail(WDD_EINVAL, "null output");
+  if (out_on_device != WDD_OUT_HOST && out_on_device != WDD_OUT_DEVICE && out_on_device != WDD_OUT_DEVICE_ASYNC)
+    return wdd::fail(WDD_EINVAL, "out_on_device must be a wdd_out_kind");
   if (out_on_device && (reinterpret_cast<uintptr_t>(out) % 8) != 0)
     return wdd::fail(WDD_EINVAL, "device output must be 8-byte aligned");
   return WDD_OK;
@@ -653,6 +678,7 @@ wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   if (!a_out) return wdd::fail(WDD_EINVAL, "null output");
+  if (!p->acc) return wdd::fail(WDD_ESTATE, "the object-order plan keeps no spectrum A");
   return copy_rows(p, a_out, p->acc, (size_t)p->n_freq, (size_t)p->k * sizeof(float2),
                    (size_t)p->kpad * sizeof(float2), on_device);
 }
@@ -729,6 +755,8 @@ wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   if (!probe) return wdd::fail(WDD_EINVAL, "null probe");
+  if (p->order_mode == WDD_ORDER_OBJECT)
+    return wdd::fail(WDD_ESTATE, "object order applies the Wiener filter per frame; no spectrum to re-deconvolve");
   if (probe->radius_px != p->probe.radius_px)
     return wdd::fail(WDD_EINVAL, "the aperture radius fixes the kept frequencies and cannot change");
   wdd_options o = p->opts;
@@ -751,7 +779,7 @@ wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel
 namespace {
 struct CheckpointHeader {
   char magic[8];
-  int32_t version, sy, sx, ny, nx, k, dtype, precision;
+  int32_t version, sy, sx, ny, nx, k, dtype, precision, order;
   int64_t n_freq;
   uint64_t frames_seen;
   double radius, step, sigma;
@@ -761,7 +789,8 @@ constexpr char kMagic[8] = {'W', 'D', 'D', 'A', 'C', 'C', '0', '1'};
 
 wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes) {
   if (!p || !bytes) return wdd::fail(WDD_EINVAL, "null argument");
-  *bytes = sizeof(CheckpointHeader) + (size_t)p->n_freq * p->k * sizeof(float2);
+  const size_t per = p->order_mode == WDD_ORDER_OBJECT ? 1 : (size_t)p->k;
+  *bytes = sizeof(CheckpointHeader) + (size_t)p->n_freq * per * sizeof(float2);
   return WDD_OK;
 }
 
@@ -775,11 +804,15 @@ wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes) {
   std::memcpy(hd.magic, kMagic, 8);
   hd.version = 1; hd.sy = p->sy; hd.sx = p->sx; hd.ny = p->ny; hd.nx = p->nx; hd.k = p->k;
   hd.dtype = p->dtype; hd.precision = p->precision; hd.n_freq = p->n_freq; hd.frames_seen = p->frames_seen;
+  hd.order = p->order_mode;
   hd.radius = p->probe.radius_px; hd.step = p->scan.step_px; hd.sigma = p->sigma;
   std::memcpy(host_buf, &hd, sizeof(hd));
   char* dst = static_cast<char*>(host_buf) + sizeof(hd);
-  WDD_HIP(p, hipMemcpy2DAsync(dst, (size_t)p->k * sizeof(float2), p->acc, (size_t)p->kpad * sizeof(float2),
-                              (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyDeviceToHost, p->stream));
+  if (p->acc)
+    WDD_HIP(p, hipMemcpy2DAsync(dst, (size_t)p->k * sizeof(float2), p->acc, (size_t)p->kpad * sizeof(float2),
+                                (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyDeviceToHost, p->stream));
+  else
+    WDD_HIP(p, hipMemcpyAsync(dst, p->d, (size_t)p->n_freq * sizeof(float2), hipMemcpyDeviceToHost, p->stream));
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   return WDD_OK;
 }
@@ -795,12 +828,18 @@ wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes)
   if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1)
     return wdd::fail(WDD_EINVAL, "not a checkpoint image of this library");
   if (hd.sy != p->sy || hd.sx != p->sx || hd.ny != p->ny || hd.nx != p->nx || hd.k != p->k ||
-      hd.n_freq != p->n_freq || hd.radius != p->probe.radius_px || hd.step != p->scan.step_px || hd.sigma != p->sigma)
+      hd.n_freq != p->n_freq || hd.radius != p->probe.radius_px || hd.step != p->scan.step_px || hd.sigma != p->sigma ||
+      hd.order != p->order_mode)
     return wdd::fail(WDD_EINVAL, "checkpoint geometry or basis differs from the plan's");
-  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
   const char* src = static_cast<const char*>(host_buf) + sizeof(hd);
-  WDD_HIP(p, hipMemcpy2DAsync(p->acc, (size_t)p->kpad * sizeof(float2), src, (size_t)p->k * sizeof(float2),
-                              (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyHostToDevice, p->stream));
+  if (p->acc) {
+    WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
+    WDD_HIP(p, hipMemcpy2DAsync(p->acc, (size_t)p->kpad * sizeof(float2), src, (size_t)p->k * sizeof(float2),
+                                (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyHostToDevice, p->stream));
+  } else {
+    WDD_HIP(p, hipMemcpyAsync(p->d, src, (size_t)p->n_freq * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+    WDD_HIP(p, wdd::launch_scatter_conj(p->d, p->freqs, p->n_freq, p->z, p->sy, p->stream));
+  }
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   p->frames_seen = hd.frames_seen;
   p->last_batch = 0;
@@ -810,7 +849,10 @@ wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes)
 wdd_status wdd_reset(wdd_plan_t p) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
-  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
+  if (p->acc)
+    WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
+  WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), (size_t)p->sy * p->sx * 2, p->stream));
   p->frames_seen = 0;
   p->last_batch = 0;
   return WDD_OK;

@@ -55,6 +55,14 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
                              const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
                              const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st);
 
+// Object order: d[j] += sum_r Ty[(v_y(j) y_r) mod sy] sum_c w[j][c] t[r][v_x(j)][c]; z as in launch_wiener.
+hipError_t launch_row_update_obj(float2* d, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
+                                 const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
+                                 const float2* w, float2* z, hipStream_t st);
+
+// z[v_x(j)][v_y(j)] = conj(d[j]) for j < n_freq.
+hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st);
+
 hipError_t launch_zero(float* p, size_t n, hipStream_t st);
 
 }  // namespace wdd

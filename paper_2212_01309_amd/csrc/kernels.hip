@@ -595,6 +595,60 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
   }
 }
 
+// Object order (Wiener filter applied per frame, as in the modified-WDD algorithm):
+// D[j] += sum_r Ty[(v_y y_r) mod sy] sum_k W[j][k] T_r[v_x][k], then z = conj(D) for the
+// display.  Same lane layout as k_row_update; only W streams from HBM.
+__global__ __launch_bounds__(256) void k_row_update_obj(float2* __restrict__ d, int kpad,
+                                                        const int2* __restrict__ freqs, int64_t n_freq,
+                                                        const float2* __restrict__ t, int sx,
+                                                        const int4* __restrict__ rows, int nrows,
+                                                        const float2* __restrict__ ty, int sy,
+                                                        const float2* __restrict__ w, float2* __restrict__ z) {
+  const int g = kpad >> 2;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = gid / g;
+  const int c = 4 * (int)(gid - j * g);
+  const int2 v = freqs[j];
+  const bool p2 = (sy & (sy - 1)) == 0;
+  const float inv = 1.0f / (float)sy;
+  const float4* w4 = reinterpret_cast<const float4*>(w + j * kpad + c);
+  const float4 w0 = w4[0], w1 = w4[1];
+  float re = 0.f, im = 0.f;
+  for (int r = 0; r < nrows; ++r) {
+    const int p = v.x * rows[r].x;
+    const float2 ph = ty[p2 ? (p & (sy - 1)) : mod_small(p, sy, inv)];
+    const float4* t4 = reinterpret_cast<const float4*>(t + ((size_t)r * sx + v.y) * kpad + c);
+    const float4 t0 = t4[0], t1 = t4[1];
+    // o = sum over this lane's 4 entries of W * T_r
+    float ore = (w0.x * t0.x - w0.y * t0.y) + (w0.z * t0.z - w0.w * t0.w);
+    float oim = (w0.x * t0.y + w0.y * t0.x) + (w0.z * t0.w + w0.w * t0.z);
+    ore += (w1.x * t1.x - w1.y * t1.y) + (w1.z * t1.z - w1.w * t1.w);
+    oim += (w1.x * t1.y + w1.y * t1.x) + (w1.z * t1.w + w1.w * t1.z);
+    re += ph.x * ore - ph.y * oim;
+    im += ph.x * oim + ph.y * ore;
+  }
+  for (int off = g >> 1; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (c == 0 && j < n_freq) {
+    const float2 old = d[j];
+    const float2 nd = make_float2(old.x + re, old.y + im);
+    d[j] = nd;
+    z[(size_t)v.y * sy + v.x] = make_float2(nd.x, -nd.y);
+  }
+}
+
+// z[v_x(j)][v_y(j)] = conj(d[j]) for every kept frequency (display grid from D).
+__global__ void k_scatter_conj(const float2* __restrict__ d, const int2* __restrict__ freqs, int64_t n_freq,
+                               float2* __restrict__ z, int sy) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_freq) return;
+  const int2 v = freqs[j];
+  const float2 x = d[j];
+  z[(size_t)v.y * sy + v.x] = make_float2(x.x, -x.y);
+}
+
 __global__ void k_zero(float* __restrict__ p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t st = (size_t)gridDim.x * blockDim.x;
@@ -754,6 +808,22 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
   else
     hipLaunchKernelGGL(k_row_update<false>, dim3(blocks), dim3(256), 0, st, acc, kpad, freqs, n_freq, t, sx, rows,
                        nrows, ty, sy, w, d, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_update_obj(float2* d, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
+                                 const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
+                                 const float2* w, float2* z, hipStream_t st) {
+  const int64_t threads = n_freq_pad * (kpad / 4);
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_row_update_obj, dim3(blocks), dim3(256), 0, st, d, kpad, freqs, n_freq, t, sx, rows, nrows, ty,
+                     sy, w, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st) {
+  if (n_freq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_conj, dim3((unsigned)((n_freq + 255) / 256)), dim3(256), 0, st, d, freqs, n_freq, z, sy);
   return hipGetLastError();
 }
 

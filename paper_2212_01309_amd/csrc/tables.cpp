@@ -271,6 +271,7 @@ wdd_status wdd_default_options(wdd_options* opts) {
   opts->sigma_px = 0.0;
   opts->precision = WDD_FP32;
   opts->max_batch = 256;
+  opts->order = WDD_ORDER_SPECTRUM;
   return WDD_OK;
 }
 

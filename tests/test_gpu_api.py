@@ -236,3 +236,28 @@ def test_snapshot_into_the_plans_pinned_buffer():
         buf[:] = 0
         again = plan.push_snapshot(device(frames[:0]), pos[:0], out=buf)
         assert np.array_equal(again, ref)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_asynchronous_device_snapshots_match_blocking_ones(order):
+    """WDD_OUT_DEVICE_ASYNC: pushes and snapshots pipeline on the plan's stream; after
+    sync() each output holds the image of its own point in the sequence."""
+    import torch
+    frames, pos = _random_case(13, 32, 32, 32, 32, 512, wdd.WDD_U16)
+    dev = device(frames)
+    outs = [torch.empty((32, 32), dtype=torch.complex64, device="cuda") for _ in range(8)]
+    with wdd.Plan(8.0, 32, 32, 32, 32, 64, max_batch=64, order=order) as a, \
+            wdd.Plan(8.0, 32, 32, 32, 32, 64, max_batch=64, order=order) as b:
+        ref = []
+        for i in range(8):
+            a.push_snapshot(dev[64 * i:64 * (i + 1)], pos[64 * i:64 * (i + 1)], out=outs[i], wait=False)
+            ref.append(b.push_snapshot(dev[64 * i:64 * (i + 1)], pos[64 * i:64 * (i + 1)]).copy())
+        a.sync()
+        for i in range(8):
+            assert np.array_equal(outs[i].cpu().numpy(), ref[i]), i
+        assert a.info().frames_seen == 512
+        bad = torch.empty((31, 32), dtype=torch.complex64, device="cuda")
+        with pytest.raises(ValueError):
+            a.snapshot(out=bad, wait=False)
+        lib = wdd.load_library()
+        assert lib.wdd_snapshot(a._h, outs[0].data_ptr(), 3, None) == wdd.WDD_EINVAL

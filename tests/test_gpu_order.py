@@ -1,0 +1,62 @@
+"""Object order (the Wiener filter applied per frame, accumulating D directly, as the
+modified-WDD algorithm is written) against the oracle's per-frame order and the
+spectrum order, including batches that need several row passes."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+import synth
+from gpu_util import device, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_object_order_full_raster():
+    wl = synth.WORKLOADS["medium"]
+    pos = synth.raster_positions(wl.sy, wl.sx)
+    frames = wl.frames(pos)
+    dev = device(frames)
+    amp = wl.aperture_amplitude()
+    with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, amplitude=amp, max_batch=wl.batch,
+                  order=wdd.WDD_ORDER_OBJECT) as plan:
+        for b in range(0, len(pos), wl.batch):
+            o = plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch])
+        d = plan.spectrum()
+        with pytest.raises(wdd.WddError) as ei:
+            plan.accumulator()
+        assert ei.value.code == wdd.WDD_ESTATE
+    op = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=amp)
+    live = O.Live(op, "P")
+    live.push(frames, pos)
+    errs = (rel(d, live.spectrum()), rel(o, live.snapshot()))
+    say(f"[order] object, medium full raster: D/O {errs}")
+    assert max(errs) <= 1e-5
+
+
+@pytest.mark.parametrize("rows", [3, 40])
+def test_object_order_matches_spectrum_order(rows):
+    s, n, k = 48, 32, 100
+    rng = np.random.default_rng(31 + rows)
+    ys = rng.choice(s, size=rows, replace=False)
+    b = 160
+    pos = np.stack([ys[rng.integers(0, rows, size=b)], rng.integers(0, s, size=b)], axis=1).astype(np.int32)
+    frames = rng.poisson(20.0, size=(b, n, n)).astype(np.uint16)
+    dev = device(frames)
+    out = {}
+    for order in (wdd.WDD_ORDER_SPECTRUM, wdd.WDD_ORDER_OBJECT):
+        with wdd.Plan(8.0, s, s, n, n, k, max_batch=b, order=order) as plan:
+            plan.push(dev[:100], pos[:100])
+            plan.push(dev[100:], pos[100:])
+            out[order] = (plan.snapshot(), plan.spectrum())
+            image = plan.checkpoint()
+            plan.reset()
+            assert not np.any(plan.snapshot())
+            plan.restore(image)
+            assert np.array_equal(plan.snapshot(), out[order][0])
+    e = (rel(out[1][1], out[0][1]), rel(out[1][0], out[0][0]))
+    say(f"[order] rows={rows}: object vs spectrum D/O {e}")
+    assert max(e) <= 1e-6
+    live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
+    live.push(frames, pos)
+    assert rel(out[1][0], live.snapshot()) <= 1e-5
