@@ -77,8 +77,9 @@ def measured_traffic(workload, kernel):
 def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum"):
     """Roofline entry of stage `dom` (mean launch time `us`), from its algorithmic work."""
     if dom == "accumulate" and order == "object":
-        # object order: stream W once per row pass
-        nbytes, kernel, bound = 8.0 * n_freq * k, "k_row_update_obj", "hbm"
+        # object order: stream W once per row pass (D, the frames' projections and the
+        # twiddles are a few hundred kB)
+        nbytes, kernel, bound = 8.0 * n_freq * k, "k_row_fused_obj", "hbm"
     elif dom == "accumulate" and factored:
         # row-factored update: read and write A, read W when the Wiener reduction is fused
         nbytes = (24.0 if fused else 16.0) * n_freq * k
@@ -95,7 +96,7 @@ def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum"):
         kernel, bound = "k_project", "hbm"
     else:
         nbytes = 3 * 8.0 * wl.sy * wl.sx
-        kernel, bound = {"display": "k_dft_rows (x2)", "rowdft": "k_row_dft"}[dom], "hbm"
+        kernel, bound = "k_dft_rows (x2)", "hbm"
     ach = nbytes / (us * 1e-6) / 1e9
     return {"kernel": kernel, "bound": bound, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(wl.name, kernel), "avg_us": us,
@@ -288,7 +289,7 @@ def main():
         # kernel in the rocprofv3 summaries); the others are reported per launch beside it
         per_kernel = {s: stages[s] / (2.0 if s == "display" else 1.0) for s in stages}
         dominant = "accumulate"
-        factored, fused = pre["rowdft_launches"] > 0, pre["wiener_launches"] == 0
+        factored, fused = pre["factored_launches"] > 0, pre["wiener_launches"] == 0
         plan.profile_enable(stage_bits[dominant])
     plan.sync()
     torch.cuda.synchronize()

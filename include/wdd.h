@@ -219,11 +219,14 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info);
  * around each kernel launch while profiling is enabled. */
 typedef struct {
   double project_ms;     /* frame decode + basis projection */
-  double accumulate_ms;  /* spectrum update (direct, or row-factored incl. a fused Wiener reduction) */
+  double accumulate_ms;  /* update of D (object order; the scan x-DFT fused in) or of A (spectrum
+                            order: direct, or row-factored after the rowdft stage, with the Wiener
+                            reduction when fused) */
   double wiener_ms;      /* Wiener reduction (when not fused) */
   double display_ms;     /* inverse DFT, conjugation and normalisation */
   int64_t project_launches, accumulate_launches, wiener_launches, display_launches;
-  double rowdft_ms;      /* per-row scan x-DFT of the row-factored update */
+  int64_t factored_launches; /* accumulate launches that took the row-factored form */
+  double rowdft_ms;          /* per-row scan x-DFT of the spectrum-order row-factored update */
   int64_t rowdft_launches;
 } wdd_profile;
 

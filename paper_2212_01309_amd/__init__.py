@@ -62,8 +62,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("project_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double), ("wiener_ms", ctypes.c_double),
                 ("display_ms", ctypes.c_double), ("project_launches", ctypes.c_int64),
                 ("accumulate_launches", ctypes.c_int64), ("wiener_launches", ctypes.c_int64),
-                ("display_launches", ctypes.c_int64), ("rowdft_ms", ctypes.c_double),
-                ("rowdft_launches", ctypes.c_int64)]
+                ("display_launches", ctypes.c_int64), ("factored_launches", ctypes.c_int64),
+                ("rowdft_ms", ctypes.c_double), ("rowdft_launches", ctypes.c_int64)]
 
 
 class ServerOptions(ctypes.Structure):

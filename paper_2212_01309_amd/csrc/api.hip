@@ -11,8 +11,12 @@
 //   ey, ex  float2 [sy], [sx]           exp(-2 pi i m / S) for the display DFT
 //   h       float  [max_batch][kpad]    projections of the current batch
 //   upload  bytes                       per batch: pos int2 [max_batch], order int32 [max_batch],
-//                                       rows int4 [max_batch] (brought over by the projection kernel)
-//   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs of the row-factored accumulation
+//                                       xs int32 [max_batch] (scan x of frame order[i]), rows int4
+//                                       [max_batch] (brought over by the projection kernel)
+//   jlist   int32  [n_freq]             kept-frequency indices grouped by v_x (ascending v_x, v_y)
+//   chunks  int4   [nchunks]            (v_x, first jlist index, count <= max_chunk, 0): the
+//                                       workgroups of the object-order update (object order only)
+//   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs (spectrum order, fused Wiener reduction)
 //   frames  staging for host frames     [max_batch][ny][nx]
 //   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
 //   z, u    float2 [sx][sy], [sy][sx]   conj(D) grid (transposed), grid transformed along y
@@ -31,6 +35,8 @@ namespace {
 
 constexpr int kRing = 4;         // pinned host staging slots for positions and frames
 constexpr int kFactorRows = 16;  // batches touching at most this many scan rows use the row-factored update
+static_assert(kFactorRows <= wdd::kRowSetMax, "a row pass must fit the kernel-argument row set");
+constexpr int kMinChunk = 16, kMaxChunk = 512;  // kept frequencies per workgroup of the row-factored update
 
 struct wdd_plan_impl {
   int device = 0;
@@ -63,9 +69,13 @@ struct wdd_plan_impl {
   char* upload = nullptr;  // pos, order, rows
   int2* pos = nullptr;
   int32_t* order = nullptr;
+  int32_t* xs = nullptr;
   int4* rows = nullptr;
   size_t upload_bytes = 0;
   float2* t = nullptr;
+  int32_t* jlist = nullptr;
+  int4* chunks = nullptr;
+  int32_t nchunks = 0, max_chunk = 0;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
@@ -84,6 +94,7 @@ struct wdd_plan_impl {
   std::vector<Pending> pending;
   double stage_ms[5] = {0, 0, 0, 0, 0};
   int64_t stage_n[5] = {0, 0, 0, 0, 0};
+  int64_t factored_n = 0;  // timed accumulate launches that were row-factored
   std::vector<int32_t> host_order;
   std::vector<int4> host_rows;
 };
@@ -252,6 +263,27 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   for (int32_t k = 0; k < t.k; ++k) kmap[k] = 16 * t.pairs[2 * k] + t.pairs[2 * k + 1];
   std::vector<int2> freqs(p->n_freq_pad, make_int2(0, 0));
   for (int64_t j = 0; j < p->n_freq; ++j) freqs[j] = make_int2(t.freqs[2 * j], t.freqs[2 * j + 1]);
+  // workgroups of the object-order update: runs of kept frequencies with one v_x, cut into
+  // chunks of at most max_chunk (about two workgroups per compute unit over the whole list)
+  std::vector<int32_t> jlist(p->n_freq);
+  for (int64_t j = 0; j < p->n_freq; ++j) jlist[j] = (int32_t)j;
+  std::stable_sort(jlist.begin(), jlist.end(), [&freqs](int32_t a, int32_t b) {
+    return freqs[a].y != freqs[b].y ? freqs[a].y < freqs[b].y : freqs[a].x < freqs[b].x;
+  });
+  p->max_chunk = (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(kMinChunk, (p->n_freq + 511) / 512));
+  std::vector<int4> chunks;
+  for (int64_t i = 0; i < p->n_freq;) {
+    const int32_t vx = freqs[jlist[i]].y;
+    int64_t e = i;
+    while (e < p->n_freq && freqs[jlist[e]].y == vx) ++e;
+    const int64_t pieces = (e - i + p->max_chunk - 1) / p->max_chunk;
+    for (int64_t c = 0; c < pieces; ++c) {
+      const int64_t b0 = i + (e - i) * c / pieces, b1 = i + (e - i) * (c + 1) / pieces;
+      chunks.push_back(make_int4(vx, (int32_t)b0, (int32_t)(b1 - b0), 0));
+    }
+    i = e;
+  }
+  p->nchunks = (int32_t)chunks.size();
   const std::vector<float2> ty = twiddles(t.sy, 1.0);
   const std::vector<float2> tx = twiddles(t.sx, 1.0 / std::sqrt((double)t.sy * (double)t.sx));
   const std::vector<float2> ey = twiddles(t.sy, 1.0);
@@ -292,12 +324,17 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   ALLOC(p->ey, (size_t)t.sy);
   ALLOC(p->ex, (size_t)t.sx);
   ALLOC(p->h, (size_t)p->max_batch * p->kpad);
-  p->upload_bytes = (size_t)p->max_batch * 12 + 16 + (size_t)p->max_batch * sizeof(int4);
+  p->upload_bytes = (size_t)p->max_batch * 16 + 16 + (size_t)p->max_batch * sizeof(int4);
   ALLOC(p->upload, p->upload_bytes);
   p->pos = reinterpret_cast<int2*>(p->upload);
   p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
-  p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 12 + 15) / 16 * 16);
-  ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
+  p->xs = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 12);
+  p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 16 + 15) / 16 * 16);
+  if (p->order_mode == WDD_ORDER_SPECTRUM) ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
+  if (p->order_mode == WDD_ORDER_OBJECT) {
+    ALLOC(p->jlist, jlist.size());
+    ALLOC(p->chunks, chunks.size());
+  }
   {
     char* fr = nullptr;
     if ((st = dalloc(p, &fr, (size_t)p->max_batch * p->frame_bytes)) != WDD_OK) return st;
@@ -316,6 +353,12 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
                               p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->kmap, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->freqs, freqs.data(), freqs.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+  if (p->jlist) {
+    WDD_HIP(p, hipMemcpyAsync(p->jlist, jlist.data(), jlist.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              p->stream));
+    WDD_HIP(p, hipMemcpyAsync(p->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice,
+                              p->stream));
+  }
   WDD_HIP(p, hipMemcpyAsync(p->ty, ty.data(), ty.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->tx, tx.data(), tx.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ey, ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
@@ -363,8 +406,14 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
   int64_t b = a((int64_t)(t.ny + t.nx) * 16 * 4) + a(kpad * 4) + a(nfp * 8) + a(nfp * kpad * 8);
   if (opts.order == WDD_ORDER_SPECTRUM) b += a(nfp * kpad * 8);
   if (opts.precision != WDD_FP32) b += a((int64_t)2 * 16 * t.nx * 2);
-  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 12 + 16 + mb * 16);
-  b += a((int64_t)kFactorRows * t.sx * kpad * 8) + a(mb * (int64_t)t.ny * t.nx * (dtype == WDD_U16 ? 2 : 4));
+  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 16 + 16 + mb * 16);
+  b += a(mb * (int64_t)t.ny * t.nx * (dtype == WDD_U16 ? 2 : 4));
+  if (opts.order == WDD_ORDER_SPECTRUM) {
+    b += a((int64_t)kFactorRows * t.sx * kpad * 8);
+  } else {
+    const int64_t nchunks_max = t.n_freq() / kMinChunk + t.sx + 1;  // upper bound of the chunk count
+    b += a(t.n_freq() * 4) + a(nchunks_max * 16);
+  }
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
 }
@@ -467,6 +516,8 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   size_t up_bytes = (size_t)n * sizeof(int2);
   if (factored) {
     std::memcpy(up + (size_t)p->max_batch * 8, ord, (size_t)n * sizeof(int32_t));
+    int32_t* xs = reinterpret_cast<int32_t*>(up + (size_t)p->max_batch * 12);
+    for (int32_t i = 0; i < n; ++i) xs[i] = pos_yx[2 * ord[i] + 1];
     const size_t roff = reinterpret_cast<char*>(p->rows) - p->upload;
     std::memcpy(up + roff, p->host_rows.data(), (size_t)nrows * sizeof(int4));
     up_bytes = roff + (size_t)nrows * sizeof(int4);
@@ -514,18 +565,21 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     p->ev_live[s] = false;
   }
   if (object) {
+    // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
-      WDD_HIP(p, stage_begin(p, kRowDft, &end));
-      WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows + r0, nr, p->tx, p->sx, p->t,
-                                     p->stream));
-      WDD_HIP(p, stage_end(p, end));
+      if (p->profile_mask & (1 << kAccumulate)) p->factored_n += 1;
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
-      WDD_HIP(p, wdd::launch_row_update_obj(p->d, p->kpad, p->n_freq_pad, p->freqs, p->n_freq, p->t, p->sx,
-                                            p->rows + r0, nr, p->ty, p->sy, p->w, p->z, p->stream));
+      wdd::RowSet rs;
+      for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
+      WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tx, p->sx, p->ty, p->sy,
+                                           p->chunks, p->nchunks, p->max_chunk, p->jlist, p->freqs, p->w, p->d, p->z,
+                                           p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
   } else if (factored) {
+    // per-row x-DFTs, then one pass over A (with the Wiener reduction when asked)
+    if (p->profile_mask & (1 << kAccumulate)) p->factored_n += 1;
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
     WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
     WDD_HIP(p, stage_end(p, end));
@@ -710,6 +764,7 @@ wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages) {
   if (st != WDD_OK) return st;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   WDD_HIP(p, harvest(p));
+  p->factored_n = 0;
   for (int i = 0; i < 5; ++i) {
     p->stage_ms[i] = 0;
     p->stage_n[i] = 0;
@@ -725,6 +780,7 @@ wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out) {
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   WDD_HIP(p, harvest(p));
   out->project_ms = p->stage_ms[kProject];
+  out->factored_launches = p->factored_n;
   out->rowdft_ms = p->stage_ms[kRowDft];
   out->rowdft_launches = p->stage_n[kRowDft];
   out->accumulate_ms = p->stage_ms[kAccumulate];

@@ -55,10 +55,20 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
                              const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
                              const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st);
 
-// Object order: d[j] += sum_r Ty[(v_y(j) y_r) mod sy] sum_c w[j][c] t[r][v_x(j)][c]; z as in launch_wiener.
-hipError_t launch_row_update_obj(float2* d, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
-                                 const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
-                                 const float2* w, float2* z, hipStream_t st);
+// Object-order row-factored update with the per-row x-DFT fused in (one workgroup per chunk
+// of kept frequencies sharing an x-frequency): d[j] += sum_r Ty[(v_y(j) y_r) mod sy] sum_c
+// w[j][c] T_r[v_x(j)][c], z as in launch_wiener.  rows.r[r] = (y_r, first index into order
+// and xs, frame count, 0) for r < nrows <= kRowSetMax; xs[i] is the scan x of frame order[i].
+// chunks[c] = (vx, first index into jlist, count <= max_chunk, 0).
+constexpr int kRowSetMax = 16;
+struct RowSet {
+  int4 r[kRowSetMax];
+};
+size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
+hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
+                                int nrows, const float2* tx, int sx, const float2* ty, int sy, const int4* chunks,
+                                int nchunks, int max_chunk, const int* jlist, const int2* freqs, const float2* w,
+                                float2* d, float2* z, hipStream_t st);
 
 // z[v_x(j)][v_y(j)] = conj(d[j]) for j < n_freq.
 hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st);

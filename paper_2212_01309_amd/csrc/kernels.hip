@@ -16,6 +16,10 @@
 
 namespace {
 
+using wdd::RowSet;
+using wdd::kRowSetMax;
+
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -543,8 +547,8 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
 }
 
 // One group of G = kpad / 4 consecutive lanes per kept frequency; each lane owns 4
-// consecutive complex entries of A.  With FUSE the Wiener reduction of the new A
-// (k_wiener) is done in the same pass.
+// consecutive complex entries of A.  With FUSE the Wiener reduction of the new A (as
+// k_wiener) is done in the same pass.
 template <bool FUSE>
 __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, int kpad, const int2* __restrict__ freqs,
                                                     int64_t n_freq, const float2* __restrict__ t, int sx,
@@ -595,49 +599,162 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
   }
 }
 
-// Object order (Wiener filter applied per frame, as in the modified-WDD algorithm):
-// D[j] += sum_r Ty[(v_y y_r) mod sy] sum_k W[j][k] T_r[v_x][k], then z = conj(D) for the
-// display.  Same lane layout as k_row_update; only W streams from HBM.
-__global__ __launch_bounds__(256) void k_row_update_obj(float2* __restrict__ d, int kpad,
-                                                        const int2* __restrict__ freqs, int64_t n_freq,
-                                                        const float2* __restrict__ t, int sx,
-                                                        const int4* __restrict__ rows, int nrows,
-                                                        const float2* __restrict__ ty, int sy,
-                                                        const float2* __restrict__ w, float2* __restrict__ z) {
-  const int g = kpad >> 2;
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t j = gid / g;
-  const int c = 4 * (int)(gid - j * g);
-  const int2 v = freqs[j];
-  const bool p2 = (sy & (sy - 1)) == 0;
-  const float inv = 1.0f / (float)sy;
-  const float4* w4 = reinterpret_cast<const float4*>(w + j * kpad + c);
-  const float4 w0 = w4[0], w1 = w4[1];
-  float re = 0.f, im = 0.f;
+// ---------------------------------------------------------------------------
+// Row-factored update with the x-DFT fused in.  Workgroup b owns the chunk
+// chunks[b] = (vx, i0, cnt): the kept frequencies jlist[i0 .. i0 + cnt), which all have
+// x-frequency vx.  It first forms, for every row r of the pass,
+//   T_r[k] = sum_{frames f of row r} Tx[(vx x_f) mod Sx] h_f[k]
+// in LDS (the x-DFT restricted to its own vx), then streams its frequencies once:
+//   D[j] += sum_r Ty[(vy y_r) mod Sy] sum_k W[j][k] T_r[k];  z = conj(D)
+// (object order: the Wiener filter applied to every frame's contribution).
+// Phase 1 splits the frames over G = 1024 / kpad groups of kpad / 4 threads (4
+// consecutive k each, float4 loads of h) and sums the groups in LDS; phase 2 gives each
+// frequency kpad / 4 consecutive lanes (4 entries each), G frequencies at a time.
+// ---------------------------------------------------------------------------
+constexpr int kFusedThreads = 512;
+constexpr int kFusedFrames = 512;  // frames staged in LDS per round of phase 1
+
+__device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
+  a0.x += c.x * h.x; a0.y += c.y * h.x; a0.z += c.x * h.y; a0.w += c.y * h.y;
+  a1.x += c.x * h.z; a1.y += c.y * h.z; a1.z += c.x * h.w; a1.w += c.y * h.w;
+}
+
+// s = sum_r ph_r T_r over this lane's 4 entries (T_r from LDS)
+__device__ inline void phase_sum(float4& s0, float4& s1, const float4* __restrict__ lt, int q, int kq, int nrows,
+                                 const RowSet& rs, int vy, const float2* __restrict__ ty, int sy, bool py2,
+                                 float invy) {
+  s0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  s1 = s0;
   for (int r = 0; r < nrows; ++r) {
-    const int p = v.x * rows[r].x;
-    const float2 ph = ty[p2 ? (p & (sy - 1)) : mod_small(p, sy, inv)];
-    const float4* t4 = reinterpret_cast<const float4*>(t + ((size_t)r * sx + v.y) * kpad + c);
-    const float4 t0 = t4[0], t1 = t4[1];
-    // o = sum over this lane's 4 entries of W * T_r
-    float ore = (w0.x * t0.x - w0.y * t0.y) + (w0.z * t0.z - w0.w * t0.w);
-    float oim = (w0.x * t0.y + w0.y * t0.x) + (w0.z * t0.w + w0.w * t0.z);
-    ore += (w1.x * t1.x - w1.y * t1.y) + (w1.z * t1.z - w1.w * t1.w);
-    oim += (w1.x * t1.y + w1.y * t1.x) + (w1.z * t1.w + w1.w * t1.z);
-    re += ph.x * ore - ph.y * oim;
-    im += ph.x * oim + ph.y * ore;
-  }
-  for (int off = g >> 1; off > 0; off >>= 1) {
-    re += __shfl_xor(re, off, 64);
-    im += __shfl_xor(im, off, 64);
-  }
-  if (c == 0 && j < n_freq) {
-    const float2 old = d[j];
-    const float2 nd = make_float2(old.x + re, old.y + im);
-    d[j] = nd;
-    z[(size_t)v.y * sy + v.x] = make_float2(nd.x, -nd.y);
+    const int p = vy * rs.r[r].x;
+    const float2 ph = ty[py2 ? (p & (sy - 1)) : mod_small(p, sy, invy)];
+    const float4 t0 = lt[(size_t)(r * q + kq) * 2], t1 = lt[(size_t)(r * q + kq) * 2 + 1];
+    s0.x += ph.x * t0.x - ph.y * t0.y; s0.y += ph.x * t0.y + ph.y * t0.x;
+    s0.z += ph.x * t0.z - ph.y * t0.w; s0.w += ph.x * t0.w + ph.y * t0.z;
+    s1.x += ph.x * t1.x - ph.y * t1.y; s1.y += ph.x * t1.y + ph.y * t1.x;
+    s1.z += ph.x * t1.z - ph.y * t1.w; s1.w += ph.x * t1.w + ph.y * t1.z;
   }
 }
+
+__device__ inline float2 cdot4(const float4 w0, const float4 w1, const float4 v0, const float4 v1) {
+  float re = (w0.x * v0.x - w0.y * v0.y) + (w0.z * v0.z - w0.w * v0.w);
+  float im = (w0.x * v0.y + w0.y * v0.x) + (w0.z * v0.w + w0.w * v0.z);
+  re += (w1.x * v1.x - w1.y * v1.y) + (w1.z * v1.z - w1.w * v1.w);
+  im += (w1.x * v1.y + w1.y * v1.x) + (w1.z * v1.w + w1.w * v1.z);
+  return make_float2(re, im);
+}
+
+__device__ inline void add4(float4& a, const float4 b) {
+  a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __restrict__ h, int kpad,
+                                                                 const int* __restrict__ order,
+                                                                 const int* __restrict__ xs, RowSet rs, int nrows,
+                                                                 const float2* __restrict__ tx, int sx,
+                                                                 const float2* __restrict__ ty, int sy,
+                                                                 const int4* __restrict__ chunks,
+                                                                 const int* __restrict__ jlist,
+                                                                 const int2* __restrict__ freqs,
+                                                                 const float2* __restrict__ w,
+                                                                 float2* __restrict__ d, float2* __restrict__ z,
+                                                                 int max_chunk) {
+  extern __shared__ float4 fsm[];
+  const int q = kpad >> 2, G = kFusedThreads / q;
+  const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
+  float4* lt = fsm;                                           // [nrows][q][2]: T_r, 4 complex per float4 pair
+  float4* lsum = lt + (size_t)nrows * q * 2;                  // [kFusedThreads][2]: group partial sums
+  float2* lw = reinterpret_cast<float2*>(lsum + 2 * kFusedThreads);  // [kFusedFrames] twiddles of staged frames
+  int* lb = reinterpret_cast<int*>(lw + kFusedFrames);        // [kFusedFrames] their batch indices
+  int* lj = lb + kFusedFrames;                                // [max_chunk] the chunk's frequencies
+  int* lvy = lj + max_chunk;                                  // [max_chunk] their y-frequencies
+  const int4 ch = chunks[blockIdx.x];
+  const int vx = ch.x, i0 = ch.y, cnt = ch.z;
+  const bool px2 = (sx & (sx - 1)) == 0, py2 = (sy & (sy - 1)) == 0;
+  const float invx = 1.0f / (float)sx, invy = 1.0f / (float)sy;
+
+  for (int i = tid; i < cnt; i += kFusedThreads) {
+    const int j = jlist[i0 + i];
+    lj[i] = j;
+    lvy[i] = freqs[j].x;
+  }
+
+  // phase 1: T_r for this vx
+  const float4* h4 = reinterpret_cast<const float4*>(h);
+  for (int r = 0; r < nrows; ++r) {
+    const int4 row = rs.r[r];
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+    for (int f0 = 0; f0 < row.z; f0 += kFusedFrames) {
+      const int n = min(kFusedFrames, row.z - f0);
+      __syncthreads();
+      if (tid < n) {
+        const int at = row.y + f0 + tid;
+        const int p = vx * xs[at];
+        lw[tid] = tx[px2 ? (p & (sx - 1)) : mod_small(p, sx, invx)];
+        lb[tid] = order[at];
+      }
+      __syncthreads();
+      int i = grp;
+      for (; i + 7 * G < n; i += 8 * G) {
+        float4 hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = h4[(size_t)lb[i + u * G] * q + kq];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[i + u * G], hv[u]);
+      }
+      for (; i < n; i += G) cmac4(a0, a1, lw[i], h4[(size_t)lb[i] * q + kq]);
+    }
+    lsum[2 * tid] = a0;
+    lsum[2 * tid + 1] = a1;
+    __syncthreads();
+    if (grp == 0) {
+      for (int g = 1; g < G; ++g) {
+        add4(a0, lsum[2 * (g * q + kq)]);
+        add4(a1, lsum[2 * (g * q + kq) + 1]);
+      }
+      lt[(size_t)(r * q + kq) * 2] = a0;
+      lt[(size_t)(r * q + kq) * 2 + 1] = a1;
+    }
+    __syncthreads();
+  }
+
+  // phase 2: stream the chunk's frequencies, two per lane group per round with all their
+  // loads issued first
+  for (int i = grp; i < cnt; i += 2 * G) {
+    const bool two = i + G < cnt;
+    const int ja = lj[i], jb = two ? lj[i + G] : ja;
+    const float4* wa = reinterpret_cast<const float4*>(w + (size_t)ja * kpad + 4 * kq);
+    const float4* wb = reinterpret_cast<const float4*>(w + (size_t)jb * kpad + 4 * kq);
+    const float4 wa0 = wa[0], wa1 = wa[1], wb0 = wb[0], wb1 = wb[1];
+    float2 da = make_float2(0.f, 0.f), db = da;
+    if (kq == 0) {
+      da = d[ja];
+      db = d[jb];
+    }
+    const int vya = lvy[i], vyb = two ? lvy[i + G] : vya;
+    float4 sa0, sa1, sb0, sb1;
+    phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, ty, sy, py2, invy);
+    phase_sum(sb0, sb1, lt, q, kq, nrows, rs, vyb, ty, sy, py2, invy);
+    float2 oa = cdot4(wa0, wa1, sa0, sa1), ob = cdot4(wb0, wb1, sb0, sb1);
+    for (int off = q >> 1; off > 0; off >>= 1) {
+      oa.x += __shfl_xor(oa.x, off, 64);
+      oa.y += __shfl_xor(oa.y, off, 64);
+      ob.x += __shfl_xor(ob.x, off, 64);
+      ob.y += __shfl_xor(ob.y, off, 64);
+    }
+    if (kq == 0) {
+      const float2 na = make_float2(da.x + oa.x, da.y + oa.y);
+      d[ja] = na;
+      z[(size_t)vx * sy + vya] = make_float2(na.x, -na.y);
+      if (two) {
+        const float2 nb = make_float2(db.x + ob.x, db.y + ob.y);
+        d[jb] = nb;
+        z[(size_t)vx * sy + vyb] = make_float2(nb.x, -nb.y);
+      }
+    }
+  }
+}
+
 
 // z[v_x(j)][v_y(j)] = conj(d[j]) for every kept frequency (display grid from D).
 __global__ void k_scatter_conj(const float2* __restrict__ d, const int2* __restrict__ freqs, int64_t n_freq,
@@ -811,13 +928,19 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
   return hipGetLastError();
 }
 
-hipError_t launch_row_update_obj(float2* d, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
-                                 const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,
-                                 const float2* w, float2* z, hipStream_t st) {
-  const int64_t threads = n_freq_pad * (kpad / 4);
-  const unsigned blocks = (unsigned)((threads + 255) / 256);
-  hipLaunchKernelGGL(k_row_update_obj, dim3(blocks), dim3(256), 0, st, d, kpad, freqs, n_freq, t, sx, rows, nrows, ty,
-                     sy, w, z);
+size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
+  return (size_t)nrows * (kpad / 4) * 32 + (size_t)kFusedThreads * 32 + (size_t)kFusedFrames * 12 +
+         (size_t)max_chunk * 8;
+}
+
+hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
+                                int nrows, const float2* tx, int sx, const float2* ty, int sy, const int4* chunks,
+                                int nchunks, int max_chunk, const int* jlist, const int2* freqs, const float2* w,
+                                float2* d, float2* z, hipStream_t st) {
+  if (nrows < 1 || nrows > kRowSetMax || nchunks < 1) return hipErrorInvalidValue;
+  const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
+  hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
+                     tx, sx, ty, sy, chunks, jlist, freqs, w, d, z, max_chunk);
   return hipGetLastError();
 }
 

@@ -198,7 +198,7 @@ def test_row_factored_and_direct_updates_agree(rows):
         o = plan.snapshot()
         prof = plan.profile_read()
         a, d = plan.accumulator(), plan.spectrum()
-    assert prof["rowdft_launches"] == (1 if rows <= 16 else 0)
+    assert prof["factored_launches"] == (1 if rows <= 16 else 0)
     ra, rd, ro = _oracle_all(8.0, s, n, k, frames, pos)
     errs = (rel(a, ra), rel(d, rd), rel(o, ro))
     say(f"[api] rows={rows}: A/D/O {errs}")
