@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16_hilo", "fp16_hilo", "bf16", "fp16"],
                     help="arithmetic of the projection's first stage (FP32 accumulation throughout)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
+    ap.add_argument("--profile-period", type=int, default=8,
+                    help="time the dominant stage with HIP events on one step in every N of the timed region")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
@@ -290,6 +292,9 @@ def main():
         per_kernel = {s: stages[s] / (2.0 if s == "display" else 1.0) for s in stages}
         dominant = "accumulate"
         factored, fused = pre["factored_launches"] > 0, pre["wiener_launches"] == 0
+        # events on one step in every `period` of the timed region (each timed launch costs two
+        # event records, about 6 us of a 30 us step)
+        plan.profile_period(args.profile_period)
         plan.profile_enable(stage_bits[dominant])
     plan.sync()
     torch.cuda.synchronize()
@@ -302,6 +307,7 @@ def main():
     prof = plan.profile_read() if not args.no_profile else None
     if not args.no_profile:
         plan.profile_enable(0)
+        plan.profile_period(1)
     # untimed: latency of one step (push to image complete in HBM), and the rate when every
     # image is also brought to the host through the plan's pinned buffer (PCIe included)
     nlat = min(args.steps, 500)

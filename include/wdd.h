@@ -244,6 +244,11 @@ enum {
  * Each timed launch adds two event records to the plan stream. */
 wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages);
 
+/* Times only one push in every `period` (>= 1; default 1), with the snapshot that follows
+ * it, so that the event records disturb a long run less.  Zeroes the totals.  Counts in
+ * wdd_profile are then of the sampled launches. */
+wdd_status wdd_profile_period(wdd_plan_t p, int32_t period);
+
 /* Totals since profiling was enabled (blocks until the timed work has finished). */
 wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);
 

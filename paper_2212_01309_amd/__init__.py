@@ -100,6 +100,7 @@ _SIGNATURES = {
     "wdd_get_projection": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
     "wdd_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "wdd_profile_period": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wdd_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
     "wdd_update_probe": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.c_double]),
     "wdd_checkpoint_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
@@ -391,6 +392,10 @@ class Plan:
     def profile_enable(self, stages: int = 31) -> None:
         """Time the stages in the bit mask (STAGE_* constants; 0 turns timing off)."""
         _check(load_library().wdd_profile_enable(self._h, int(stages)))
+
+    def profile_period(self, period: int) -> None:
+        """Time one push in every `period` (and the snapshot after it); zeroes the totals."""
+        _check(load_library().wdd_profile_period(self._h, int(period)))
 
     def profile_read(self) -> dict:
         pr = Profile()

@@ -89,6 +89,9 @@ struct wdd_plan_impl {
 
   // stage timing (wdd_profile_*): events around launches, harvested when the stream is idle
   int32_t profile_mask = 0;  // bit i: time stage i (Stage enum)
+  int32_t profile_period = 1;  // time one push (and its snapshot) in every profile_period
+  int64_t profile_tick = 0;    // pushes since profiling was (re)configured
+  bool profile_now = true;     // the current push is sampled
   std::vector<hipEvent_t> ev_pool;
   struct Pending { int stage; hipEvent_t e0, e1; };
   std::vector<Pending> pending;
@@ -136,7 +139,7 @@ enum Stage { kProject = 0, kAccumulate = 1, kWiener = 2, kDisplay = 3, kRowDft =
 // Opens a timed stage: returns the end event to record after the launches (or null).
 hipError_t stage_begin(wdd_plan_s* p, int stage, hipEvent_t* end) {
   *end = nullptr;
-  if (!(p->profile_mask & (1 << stage))) return hipSuccess;
+  if (!(p->profile_mask & (1 << stage)) || !p->profile_now) return hipSuccess;
   hipEvent_t e[2];
   for (int i = 0; i < 2; ++i) {
     if (!p->ev_pool.empty()) {
@@ -545,6 +548,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     WDD_HIP(p, hipStreamSynchronize(p->stream));
     WDD_HIP(p, harvest(p));
   }
+  p->profile_now = (p->profile_tick++ % p->profile_period) == 0;
   hipEvent_t end;
   WDD_HIP(p, stage_begin(p, kProject, &end));
   // the projection kernel also brings the pinned upload block (positions, grouping) to the device
@@ -568,7 +572,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
-      if (p->profile_mask & (1 << kAccumulate)) p->factored_n += 1;
+      if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
       wdd::RowSet rs;
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
@@ -579,7 +583,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     }
   } else if (factored) {
     // per-row x-DFTs, then one pass over A (with the Wiener reduction when asked)
-    if (p->profile_mask & (1 << kAccumulate)) p->factored_n += 1;
+    if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
     WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
     WDD_HIP(p, stage_end(p, end));
@@ -770,6 +774,25 @@ wdd_status wdd_profile_enable(wdd_plan_t p, int32_t stages) {
     p->stage_n[i] = 0;
   }
   p->profile_mask = on & 0x1f;
+  p->profile_tick = 0;
+  p->profile_now = true;
+  return WDD_OK;
+}
+
+wdd_status wdd_profile_period(wdd_plan_t p, int32_t period) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if (period < 1) return wdd::fail(WDD_EINVAL, "profile period must be >= 1");
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  WDD_HIP(p, harvest(p));
+  for (int i = 0; i < 5; ++i) {
+    p->stage_ms[i] = 0;
+    p->stage_n[i] = 0;
+  }
+  p->factored_n = 0;
+  p->profile_period = period;
+  p->profile_tick = 0;
+  p->profile_now = true;
   return WDD_OK;
 }
 

@@ -78,6 +78,7 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   float* lpsy = smem;               // [ny][16]
   float* lpsx = smem + ny * 16;     // [nx][16]
   float* lg = lpsx + nx * 16;       // [nw][256]
+  int* lkmap = reinterpret_cast<int*>(lg + nw * 256);  // [kpad]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // frame b: contiguous after `frames`, or at the address listed in fptr[b] (pinned host table)
   const T* f = fptr ? reinterpret_cast<const T*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   if (blockIdx.x == 0)
     for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
   for (int i = tid; i < (ny + nx) * 16; i += blockDim.x) smem[i] = psi[i];
+  for (int i = tid; i < kpad; i += blockDim.x) lkmap[i] = kmap[i];
   __syncthreads();
 
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
   for (int k = tid; k < kpad; k += blockDim.x) {
-    const int idx = kmap[k];
+    const int idx = lkmap[k];
     float sum = 0.f;
     if (idx >= 0)
       for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
@@ -190,7 +192,8 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
   const int nxp = nx + 8;                                              // padded row of the 16-bit basis
   float* lpsy = smem;                                                  // [ny][16] FP32
   float* lg = lpsy + ny * 16;                                          // [nw][256]
-  uint16_t* lpx = reinterpret_cast<uint16_t*>(lg + nw * 256);          // [2][16][nxp]
+  int* lkmap = reinterpret_cast<int*>(lg + nw * 256);                  // [kpad]
+  uint16_t* lpx = reinterpret_cast<uint16_t*>(lkmap + kpad);           // [2][16][nxp]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
   if (blockIdx.x == 0)
     for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
   for (int i = tid; i < ny * 16; i += blockDim.x) lpsy[i] = psi[i];
+  for (int i = tid; i < kpad; i += blockDim.x) lkmap[i] = kmap[i];
   const int parts = HILO ? 2 : 1;
   for (int i = tid; i < parts * 16 * nx; i += blockDim.x) {
     const int row = i / nx, x = i - row * nx;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
   for (int k = tid; k < kpad; k += blockDim.x) {
-    const int idx = kmap[k];
+    const int idx = lkmap[k];
     float sum = 0.f;
     if (idx >= 0)
       for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
@@ -778,7 +782,8 @@ hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const flo
                             hipStream_t st) {
   const int ntiles = (ny + 15) / 16;
   const int nw = ntiles < 16 ? ntiles : 16;
-  const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float);
+  const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) +
+                     (size_t)kpad * sizeof(int);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_project<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -797,7 +802,7 @@ hipError_t launch_project_lp_t(const void* frames, int n, int ny, int nx, const 
                                size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
   const int ntiles = (ny + 15) / 16;
   const int nw = ntiles < 16 ? ntiles : 16;
-  const size_t lds = (size_t)ny * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) +
+  const size_t lds = (size_t)ny * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) + (size_t)kpad * sizeof(int) +
                      (size_t)2 * 16 * (nx + 8) * sizeof(uint16_t);
   static bool attr = false;
   if (!attr) {

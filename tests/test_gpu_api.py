@@ -261,3 +261,20 @@ def test_asynchronous_device_snapshots_match_blocking_ones(order):
             a.snapshot(out=bad, wait=False)
         lib = wdd.load_library()
         assert lib.wdd_snapshot(a._h, outs[0].data_ptr(), 3, None) == wdd.WDD_EINVAL
+
+
+def test_profile_period_samples_one_push_in_n():
+    frames, pos = _random_case(14, 16, 16, 32, 32, 256, wdd.WDD_U16)
+    dev = device(frames)
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64, max_batch=32, order=wdd.WDD_ORDER_OBJECT) as plan:
+        plan.profile_period(4)
+        plan.profile_enable(wdd.STAGE_ALL)
+        for b in range(0, 256, 32):
+            plan.push(dev[b:b + 32], pos[b:b + 32])
+        prof = plan.profile_read()
+        assert prof["project_launches"] == 2 and prof["accumulate_launches"] >= 2
+        assert prof["factored_launches"] == prof["accumulate_launches"]
+        assert prof["accumulate_ms"] > 0
+        with pytest.raises(wdd.WddError) as ei:
+            plan.profile_period(0)
+        assert ei.value.code == wdd.WDD_EINVAL

@@ -34,9 +34,11 @@ def test_object_order_full_raster():
     assert max(errs) <= 1e-5
 
 
-@pytest.mark.parametrize("rows", [3, 40])
-def test_object_order_matches_spectrum_order(rows):
-    s, n, k = 48, 32, 100
+@pytest.mark.parametrize("rows,k", [(3, 100), (40, 100), (5, 20), (7, 64)])
+def test_object_order_matches_spectrum_order(rows, k):
+    """K = 20, 64, 100 give 8, 16 and 32 lanes per kept frequency in the fused update;
+    40 rows take three passes."""
+    s, n = 48, 32
     rng = np.random.default_rng(31 + rows)
     ys = rng.choice(s, size=rows, replace=False)
     b = 160
@@ -60,3 +62,18 @@ def test_object_order_matches_spectrum_order(rows):
     live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
     live.push(frames, pos)
     assert rel(out[1][0], live.snapshot()) <= 1e-5
+
+
+def test_object_order_long_row():
+    """One scan row with more frames than the fused update stages at once (positions repeat)."""
+    s, n, k, b = 48, 32, 64, 700
+    rng = np.random.default_rng(77)
+    pos = np.stack([np.full(b, 17), rng.integers(0, s, size=b)], axis=1).astype(np.int32)
+    frames = rng.poisson(12.0, size=(b, n, n)).astype(np.uint16)
+    with wdd.Plan(8.0, s, s, n, n, k, max_batch=b, order=wdd.WDD_ORDER_OBJECT) as plan:
+        got = plan.push_snapshot(device(frames), pos)
+    live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
+    live.push(frames, pos)
+    err = rel(got, live.snapshot())
+    say(f"[order] one row of {b} frames: {err:.2e}")
+    assert err <= 1e-5
