@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--serving-acquisitions", type=int, default=24)
     ap.add_argument("--serving-budget-mb", type=int, default=1024)
     ap.add_argument("--serving-precision", default="bf16_hilo")
+    ap.add_argument("--serving-order", default="object", choices=["spectrum", "object"])
     ap.add_argument("--serving-saturate", action="store_true", help="submit frames as fast as possible")
     ap.add_argument("--serving-limit-s", type=float, default=150.0)
     ap.add_argument("--pool-batches", type=int, default=128,
@@ -171,7 +172,8 @@ def serving(args):
         t = time.perf_counter() - t0
         while waiting and waiting[0]["t_arrive"] <= t:
             a = waiting[0]
-            aid = srv.open(a["radius"], a["s"], a["s"], a["n"], a["n"], a["k"], precision=args.serving_precision)
+            aid = srv.open(a["radius"], a["s"], a["s"], a["n"], a["n"], a["k"], precision=args.serving_precision,
+                           order=wdd.WDD_ORDER_OBJECT if args.serving_order == "object" else wdd.WDD_ORDER_SPECTRUM)
             if aid is None:
                 if not a.get("deferred"):
                     a["deferred"] = True
@@ -216,6 +218,7 @@ def serving(args):
                                f"64^2..256^2, {'all frames available at t=0' if args.serving_saturate else '10k-50k frames/s each'}, "
                                f"deliveries of 1-512 frames, HBM budget {args.serving_budget_mb} MiB, "
                                f"snapshot every >= 1 ms per acquisition",
+                   "wiener_order": args.serving_order,
                    "acquisitions_done": len(done), "deferred_admissions": deferred,
                    "offered_frames_per_s_sum_of_rates": offered},
         "frames": st["frames"], "wall_s": wall, "batches": st["batches"], "snapshots": st["snapshots"],

@@ -135,6 +135,14 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2212_01309_amd.build.build_library()")
+    # PyTorch ships its own HIP runtime and names it without the version suffix.  Loaded after
+    # libwdd.so (which binds the system runtime, libamdhip64.so.7), it would come in as a
+    # second runtime that sees no device; loaded first, libwdd.so binds to it and the process
+    # has one HIP runtime, whose device pointers both sides share.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(_LIB_PATH)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)
@@ -440,14 +448,14 @@ class Server:
 
     def open(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
              defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
-             sigma: float = 0.0, precision=WDD_FP32) -> Optional[int]:
+             sigma: float = 0.0, precision=WDD_FP32, order: int = WDD_ORDER_SPECTRUM) -> Optional[int]:
         """Acquisition id, or None when it does not fit the memory budget now."""
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         aid = ctypes.c_int32()
         code = load_library().wdd_server_open(self._h, ctypes.byref(Probe(radius, defocus, amplitude)),
                                               ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)),
-                                              k, ctypes.byref(_options(eps_rel, sigma, 256, precision)),
+                                              k, ctypes.byref(_options(eps_rel, sigma, 256, precision, order)),
                                               ctypes.byref(aid))
         if code == WDD_EBUSY:
             return None

@@ -77,3 +77,21 @@ def test_object_order_long_row():
     err = rel(got, live.snapshot())
     say(f"[order] one row of {b} frames: {err:.2e}")
     assert err <= 1e-5
+
+
+def test_object_order_host_frames_and_float32():
+    """Host-memory float32 frames through the staging copy; wdd_update_probe needs A."""
+    s, n, k = 16, 32, 36
+    rng = np.random.default_rng(5)
+    pos = np.stack([np.repeat(np.arange(s), s), np.tile(np.arange(s), s)], axis=1).astype(np.int32)
+    frames = rng.random((s * s, n, n)).astype(np.float32)
+    with wdd.Plan(8.0, s, s, n, n, k, dtype=wdd.WDD_F32, max_batch=64, order=wdd.WDD_ORDER_OBJECT) as plan:
+        for b in range(0, s * s, 64):
+            plan.push(frames[b:b + 64], pos[b:b + 64])
+        got = plan.snapshot()
+        with pytest.raises(wdd.WddError) as ei:
+            plan.update_probe(8.0, defocus=0.5)
+        assert ei.value.code == wdd.WDD_ESTATE
+    live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
+    live.push(frames, pos)
+    assert rel(got, live.snapshot()) <= 1e-5

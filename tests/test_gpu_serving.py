@@ -43,12 +43,13 @@ def test_admission_by_memory_budget():
         assert c is not None and srv.stats()["open"] == 2
 
 
-def test_each_result_is_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("order", [wdd.WDD_ORDER_SPECTRUM, wdd.WDD_ORDER_OBJECT])
+def test_each_result_is_the_same_alone_and_in_the_mix(order):
     rng = np.random.default_rng(9)
     data = [_acquisition(i, *g) for i, g in enumerate(GEOMS)]
     devs = [device(f) for f, _ in data]
     with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=200.0, batch_frames=256) as srv:
-        ids = [srv.open(r, s, s, n, n, k) for (r, s, n, k) in GEOMS]
+        ids = [srv.open(r, s, s, n, n, k, order=order) for (r, s, n, k) in GEOMS]
         cursor = [0] * len(GEOMS)
         while any(c < len(d[1]) for c, d in zip(cursor, data)):
             for _ in range(3):
@@ -69,12 +70,12 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
         f"{st['snapshots']} snapshots, latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
     for i, (r, s, n, k) in enumerate(GEOMS):
         frames, pos = data[i]
-        with wdd.Plan(r, s, s, n, n, k, max_batch=256) as plan:
+        with wdd.Plan(r, s, s, n, n, k, max_batch=256, order=order) as plan:
             for b in range(0, len(pos), 256):
                 plan.push(devs[i][b:b + 256], pos[b:b + 256])
             alone = plan.snapshot()
         e = rel(mixed[i], alone)
-        say(f"[serving] acquisition {i}: mix vs alone {e:.2e}")
+        say(f"[serving] order {order}, acquisition {i}: mix vs alone {e:.2e}")
         assert e <= 1e-6
     r, s, n, k = GEOMS[0]
     live = O.Live(O.make_plan(s, s, n, n, r, k), "N")
