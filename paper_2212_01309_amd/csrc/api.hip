@@ -19,7 +19,7 @@
 //   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs (spectrum order, fused Wiener reduction)
 //   frames  staging for host frames     [max_batch][ny][nx]
 //   d       float2 [n_freq_pad]         Wiener-reduced spectrum D
-//   z, u    float2 [sx][sy], [sy][sx]   conj(D) grid (transposed), grid transformed along y
+//   z, u    float2 [sx][sy], [sx][sy]   conj(D) grid (transposed), grid transformed along y
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -615,11 +615,11 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   // device buffer, or the plan's pinned host buffer (copied to `out` unless it is that buffer)
   float2* dst = out_on_device ? reinterpret_cast<float2*>(out) : p->pin_out;
   WDD_HIP(p, stage_begin(p, kDisplay, &end));
-  // z is conj(D) stored [vx][vy]: transform along vy (written transposed, u = [y][vx]), then
-  // along vx, writing whole rows of the output
-  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, 1, p->stream));
-  WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, 0,
-                                  p->stream));
+  // z is conj(D) stored [vx][vy]: transform its rows along vy (u = [vx][y], written in row
+  // order), then the columns of u along vx, each workgroup writing one whole output row
+  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, p->sy, 1, p->sy, 1, p->stream));
+  WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, 1, p->sy,
+                                  p->sx, 1, p->stream));
   WDD_HIP(p, stage_end(p, end));
   return WDD_OK;
 }

@@ -41,10 +41,11 @@ hipError_t launch_accumulate(float2* acc, int kpad, int64_t n_freq_pad, const in
 hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int2* freqs, int64_t n_freq, float2* d,
                          float2* z, int sy, hipStream_t st);
 
-// out[c][r] (transpose) or out[r][c] = scale * sum_m in[r][m] e[(m c) mod len] for r < rows
-// (see kernels.hip).
+// out[r * out_sr + c * out_sc] = scale * sum_m in[r * in_sr + m * in_sm] e[(m c) mod len] for
+// r < rows, c < len (see kernels.hip).
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
-                           float s_total, int final_scale, int transpose, hipStream_t st);
+                           float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc,
+                           hipStream_t st);
 
 // Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
 // Tx[(vx x_b) mod sx] h[b][c]; then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],

@@ -402,19 +402,20 @@ __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, 
 }
 
 // ---------------------------------------------------------------------------
-// Forward DFT of each row of a rows x len array, written transposed (out[c * rows + r])
-// or in place order (out[r * len + c]): scale * sum_m in[r * len + m] * E[(m c) mod len],
-// E[m] = exp(-2 pi i m / len) built in FP64 on the host.  Power-of-two
-// lengths use an in-LDS radix-2 decimation-in-time FFT, others a direct sum.
-// With `final_scale` set, scale = 1 / sqrt(S |D[0]|) (0 when D[0] = 0).
+// Forward DFT of each of `rows` rows of length len:
+//   out[r * out_sr + c * out_sc] = scale * sum_m in[r * in_sr + m * in_sm] * E[(m c) mod len],
+// E[m] = exp(-2 pi i m / len) built in FP64 on the host.  Power-of-two lengths use an
+// in-LDS radix-2 decimation-in-time FFT with the twiddles staged in LDS, others a direct
+// sum.  With `final_scale` set, scale = 1 / sqrt(S |D[0]|) (0 when D[0] = 0).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int rows,
-                                                  int len, int log2len, const float2* __restrict__ e,
+__global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int len,
+                                                  int log2len, const float2* __restrict__ e,
                                                   const float2* __restrict__ d0, float s_total, int final_scale,
-                                                  int transpose) {
-  extern __shared__ float2 lbuf[];  // [len]
+                                                  int in_sr, int in_sm, int out_sr, int out_sc) {
+  extern __shared__ float2 lbuf[];  // [len] data, then [len / 2] twiddles (power-of-two lengths)
   const int r = blockIdx.x, tid = threadIdx.x;
-  const float2* src = in + (size_t)r * len;
+  const float2* src = in + (size_t)r * in_sr;
+  float2* dst = out + (size_t)r * out_sr;
   float scale = 1.0f;
   if (final_scale) {
     const float2 dd = d0[0];
@@ -422,10 +423,12 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
     scale = mag > 0.f ? 1.0f / sqrtf(s_total * mag) : 0.f;
   }
   if (log2len >= 0) {
+    float2* ltw = lbuf + len;
     for (int m = tid; m < len; m += 256) {
       const int rev = log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0;
-      lbuf[rev] = src[m];
+      lbuf[rev] = src[(size_t)m * in_sm];
     }
+    for (int m = tid; m < len / 2; m += 256) ltw[m] = e[m];
     __syncthreads();
     for (int s = 1; s <= log2len; ++s) {
       const int half = 1 << (s - 1);
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
       for (int k = tid; k < len / 2; k += 256) {
         const int grp = k >> (s - 1), p = k & (half - 1);
         const int i0 = grp * (half << 1) + p, i1 = i0 + half;
-        const float2 tw = e[p * stride];
+        const float2 tw = ltw[p * stride];
         const float2 x1 = lbuf[i1], x0 = lbuf[i0];
         const float2 tt = make_float2(tw.x * x1.x - tw.y * x1.y, tw.x * x1.y + tw.y * x1.x);
         lbuf[i0] = make_float2(x0.x + tt.x, x0.y + tt.y);
@@ -441,24 +444,24 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
       }
       __syncthreads();
     }
-    for (int cidx = tid; cidx < len; cidx += 256) {
-      const float2 v = lbuf[cidx];
-      out[transpose ? (size_t)cidx * rows + r : (size_t)r * len + cidx] = make_float2(v.x * scale, v.y * scale);
+    for (int c = tid; c < len; c += 256) {
+      const float2 v = lbuf[c];
+      dst[(size_t)c * out_sc] = make_float2(v.x * scale, v.y * scale);
     }
   } else {
-    for (int m = tid; m < len; m += 256) lbuf[m] = src[m];
+    for (int m = tid; m < len; m += 256) lbuf[m] = src[(size_t)m * in_sm];
     __syncthreads();
-    for (int cidx = tid; cidx < len; cidx += 256) {
+    for (int c = tid; c < len; c += 256) {
       float re = 0.f, im = 0.f;
       int idx = 0;
       for (int m = 0; m < len; ++m) {
         const float2 x = lbuf[m], tw = e[idx];
         re += x.x * tw.x - x.y * tw.y;
         im += x.x * tw.y + x.y * tw.x;
-        idx += cidx;
+        idx += c;
         idx -= (idx >= len) ? len : 0;
       }
-      out[transpose ? (size_t)cidx * rows + r : (size_t)r * len + cidx] = make_float2(re * scale, im * scale);
+      dst[(size_t)c * out_sc] = make_float2(re * scale, im * scale);
     }
   }
 }
@@ -892,15 +895,16 @@ hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int
 }
 
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
-                           float s_total, int final_scale, int transpose, hipStream_t st) {
+                           float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc,
+                           hipStream_t st) {
   int lg = -1;
   if ((len & (len - 1)) == 0) {
     lg = 0;
     while ((1 << lg) < len) ++lg;
   }
-  const size_t lds = (size_t)len * sizeof(float2);
-  hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, rows, len, lg, e, d0, s_total, final_scale,
-                     transpose);
+  const size_t lds = (size_t)len * sizeof(float2) + (lg >= 0 ? (size_t)(len / 2) * sizeof(float2) : 0);
+  hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale, in_sr,
+                     in_sm, out_sr, out_sc);
   return hipGetLastError();
 }
 
