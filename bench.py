@@ -32,6 +32,9 @@ def parse():
     ap.add_argument("--order", default="object", choices=["spectrum", "object"],
                     help="accumulate the spectrum A (Wiener filter at snapshot) or the object spectrum D "
                          "(Wiener filter per frame)")
+    ap.add_argument("--basis", default="hermite-gauss", choices=["hermite-gauss", "fourier"],
+                    help="reduced Hermite-Gauss basis of K functions, or the full Fourier basis (K = N^2: "
+                         "conventional WDD; detectors up to 64x64)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16_hilo", "fp16_hilo", "bf16", "fp16"],
                     help="arithmetic of the projection's first stage (FP32 accumulation throughout)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
@@ -52,10 +55,11 @@ def parse():
     return ap.parse_args()
 
 
-def workload_label(wl, n_freq):
+def workload_label(wl, n_freq, k, fourier=False):
     kind = "uint16 Poisson %.0e e/frame" % wl.dose if wl.dose else "float32 noiseless"
+    basis = (f"full Fourier basis K={k} (conventional WDD)" if fourier else f"K={k} Hermite-Gauss functions")
     return (f"{wl.name}: {wl.sy}x{wl.sx} raster scan, {wl.n}x{wl.n} detector ({kind}), aperture radius "
-            f"{wl.radius:g} px, K={wl.k} Hermite-Gauss functions, {n_freq} kept frequencies, "
+            f"{wl.radius:g} px, {basis}, {n_freq} kept frequencies, "
             f"batches of {wl.batch} in raster order, snapshot after every batch")
 
 
@@ -77,9 +81,15 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum"):
+def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum", fourier=False):
     """Roofline entry of stage `dom` (mean launch time `us`), from its algorithmic work."""
-    if dom == "accumulate" and order == "object":
+    if dom == "accumulate" and fourier:
+        # one workgroup per kept frequency streams its W row (object order) or its A row
+        # (read and write; W too when the Wiener reduction is fused)
+        nbytes = (8.0 if order == "object" else (24.0 if fused else 16.0)) * n_freq * k
+        kernel = "k_update_c<%d>" % (0 if order == "object" else (2 if fused else 1))
+        bound = "hbm"
+    elif dom == "accumulate" and order == "object":
         # object order: stream W once per row pass (D, the frames' projections and the
         # twiddles are a few hundred kB)
         nbytes, kernel, bound = 8.0 * n_freq * k, "k_row_fused_obj", "hbm"
@@ -106,7 +116,7 @@ def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum"):
             "algorithmic_bytes": nbytes}
 
 
-def cpu_baseline(wl, frames, pos, seconds):
+def cpu_baseline(wl, frames, pos, seconds, fourier=False):
     """The FP64 oracle's live path (same step: push one batch, then snapshot) on the host cores."""
     import oracle.wdd as O
     try:
@@ -115,8 +125,9 @@ def cpu_baseline(wl, frames, pos, seconds):
     except Exception:
         cores = os.cpu_count() or 1
     t0 = time.perf_counter()
-    plan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=wl.aperture_amplitude(),
-                       defocus_edge=wl.defocus_edge, step=wl.step)
+    plan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, None if fourier else wl.k,
+                       amplitude=wl.aperture_amplitude(), defocus_edge=wl.defocus_edge, step=wl.step,
+                       phi=O.fourier_basis(wl.n, wl.n) if fourier else None)
     plan_s = time.perf_counter() - t0
     live = O.Live(plan, "N")
     done = 0
@@ -263,9 +274,12 @@ def main():
     dev = torch.from_numpy(host).to("cuda")
     torch.cuda.synchronize()
     dtype = wdd.WDD_U16 if frames.dtype == np.uint16 else wdd.WDD_F32
-    plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
-                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch, precision=args.precision,
-                    order=wdd.WDD_ORDER_OBJECT if args.order == "object" else wdd.WDD_ORDER_SPECTRUM)
+    fourier = args.basis == "fourier"
+    plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.n * wl.n if fourier else wl.k, dtype=dtype,
+                    defocus=wl.defocus_edge, amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch,
+                    precision=args.precision,
+                    order=wdd.WDD_ORDER_OBJECT if args.order == "object" else wdd.WDD_ORDER_SPECTRUM,
+                    basis=wdd.WDD_BASIS_FOURIER if fourier else wdd.WDD_BASIS_HERMITE_GAUSS)
     nb = len(pos) // wl.batch
     batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
 
@@ -335,9 +349,9 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else f"{args.precision} projection, f32 accumulate",
         "data": "synthetic",
-        "config": {"workload": workload_label(wl, n_freq), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
+        "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
-                   "wiener_order": args.order, "display": "hbm"},
+                   "wiener_order": args.order, "basis": args.basis, "display": "hbm"},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "steps": nlat},
         "host_display_fps": host_fps,
@@ -347,9 +361,9 @@ def main():
         stages[dominant] = prof[f"{dominant}_ms"] / max(prof[f"{dominant}_launches"], 1) * 1e3
         out["stages_us"] = stages
         out["largest_kernel_stage"] = max(per_kernel, key=per_kernel.get)
-        out["roofline"] = roofline(wl, n_freq, k, dominant, stages[dominant], factored, fused, args.order)
+        out["roofline"] = roofline(wl, n_freq, k, dominant, stages[dominant], factored, fused, args.order, fourier)
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds, fourier)
     out["generation_s"] = gen_s
     print(json.dumps(out), flush=True)
 

@@ -92,12 +92,21 @@ typedef struct {
  * so wdd_get_accumulator and wdd_update_probe are unavailable.  Both give the same result. */
 typedef enum { WDD_ORDER_SPECTRUM = 0, WDD_ORDER_OBJECT = 1 } wdd_order;
 
+/* The reduced basis Phi (Sections 4-5).  WDD_BASIS_HERMITE_GAUSS: K real Hermite-Gauss
+ * functions (1 <= K <= 256, shell order).  WDD_BASIS_FOURIER: the full Fourier basis
+ * Phi[q, k] = exp(+2 pi i (q_y k_y / ny + q_x k_x / nx)) / (ny nx), k = k_y nx + k_x, with
+ * K = ny nx: the method then computes conventional WDD exactly (Section 5 remarks that the
+ * Fourier basis is the conventional case).  Needs ny, nx powers of two in [8, 64], FP32
+ * precision; projections h are complex. */
+typedef enum { WDD_BASIS_HERMITE_GAUSS = 0, WDD_BASIS_FOURIER = 1 } wdd_basis;
+
 typedef struct {
   double eps_rel;     /* Wiener regularisation relative to the largest |Y^B|^2; default 0.01 */
   double sigma_px;    /* basis width in detector pixels; <= 0 selects radius / sqrt(2L - 1) */
   int32_t precision;  /* wdd_precision; default WDD_FP32 */
   int32_t max_batch;  /* largest n accepted by wdd_push; default 256 */
   int32_t order;      /* wdd_order; default WDD_ORDER_SPECTRUM */
+  int32_t basis;      /* wdd_basis; default WDD_BASIS_HERMITE_GAUSS */
 } wdd_options;
 
 typedef struct {
@@ -140,7 +149,8 @@ wdd_status wdd_tables_info(wdd_tables_t t, wdd_plan_info* info);
  *   psi_y  double [ny][l]       sampled, grid-normalised Hermite functions
  *   psi_x  double [nx][l]
  *   pairs  int32  [k][2]        (n_y, n_x) of each basis function
- *   w      double [n_freq][k][2] Wiener filter (re, im)                         */
+ *   w      double [n_freq][k][2] Wiener filter (re, im)
+ * With the Fourier basis l = 0 and psi_y, psi_x, pairs are left untouched.      */
 wdd_status wdd_tables_export(wdd_tables_t t, int32_t* freqs, double* psi_y, double* psi_x,
                              int32_t* pairs, double* w);
 

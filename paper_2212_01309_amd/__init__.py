@@ -22,6 +22,7 @@ WDD_FP32, WDD_BF16_HILO, WDD_FP16_HILO, WDD_BF16, WDD_FP16 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP16_HILO, "bf16": WDD_BF16,
               "fp16": WDD_FP16}
 WDD_ORDER_SPECTRUM, WDD_ORDER_OBJECT = 0, 1
+WDD_BASIS_HERMITE_GAUSS, WDD_BASIS_FOURIER = 0, 1
 WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC = 0, 1, 2
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
@@ -49,7 +50,7 @@ class Detector(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eps_rel", ctypes.c_double), ("sigma_px", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("order", ctypes.c_int32), ("basis", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -159,10 +160,11 @@ def _check(code: int) -> None:
 
 
 def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32,
-             order: int = WDD_ORDER_SPECTRUM) -> Options:
+             order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS) -> Options:
     o = Options()
     _check(load_library().wdd_default_options(ctypes.byref(o)))
     o.eps_rel, o.sigma_px, o.max_batch, o.precision, o.order = eps_rel, sigma_px, max_batch, precision, order
+    o.basis = basis
     return o
 
 
@@ -184,12 +186,12 @@ class Tables:
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, defocus: float = 0.0,
                  amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01, sigma: float = 0.0,
-                 dtype: int = WDD_U16):
+                 dtype: int = WDD_U16, basis: int = WDD_BASIS_HERMITE_GAUSS):
         lib = load_library()
         self._h = _P()
         _check(lib.wdd_tables_build(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
                                     ctypes.byref(Detector(ny, nx, dtype)), k,
-                                    ctypes.byref(_options(eps_rel, sigma, 256)), ctypes.byref(self._h)))
+                                    ctypes.byref(_options(eps_rel, sigma, 256, basis=basis)), ctypes.byref(self._h)))
         info = PlanInfo()
         _check(lib.wdd_tables_info(self._h, ctypes.byref(info)))
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
@@ -225,16 +227,17 @@ class Plan:
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
                  sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32,
-                 order: int = WDD_ORDER_SPECTRUM):
+                 order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
+        self.basis = basis
         _check(lib.wdd_plan_create(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
                                    ctypes.byref(Detector(ny, nx, dtype)), k,
-                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order)),
+                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order, basis)),
                                    _P(stream) if stream else None, ctypes.byref(self._h)))
         info = self.info()
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
@@ -392,8 +395,8 @@ class Plan:
         return a
 
     def projection(self) -> np.ndarray:
-        """h of the last pushed batch, float32 [n, k]."""
-        h = np.empty((self._last_batch, self.k), np.float32)
+        """h of the last pushed batch: float32 [n, k], or complex64 [n, k] with the Fourier basis."""
+        h = np.empty((self._last_batch, self.k), np.complex64 if self.basis == WDD_BASIS_FOURIER else np.float32)
         _check(load_library().wdd_get_projection(self._h, h.ctypes.data, 0))
         return h
 
@@ -448,14 +451,15 @@ class Server:
 
     def open(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
              defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
-             sigma: float = 0.0, precision=WDD_FP32, order: int = WDD_ORDER_SPECTRUM) -> Optional[int]:
+             sigma: float = 0.0, precision=WDD_FP32, order: int = WDD_ORDER_SPECTRUM,
+             basis: int = WDD_BASIS_HERMITE_GAUSS) -> Optional[int]:
         """Acquisition id, or None when it does not fit the memory budget now."""
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         aid = ctypes.c_int32()
         code = load_library().wdd_server_open(self._h, ctypes.byref(Probe(radius, defocus, amplitude)),
                                               ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)),
-                                              k, ctypes.byref(_options(eps_rel, sigma, 256, precision, order)),
+                                              k, ctypes.byref(_options(eps_rel, sigma, 256, precision, order, basis)),
                                               ctypes.byref(aid))
         if code == WDD_EBUSY:
             return None

@@ -9,7 +9,9 @@
 //   acc     float2 [n_freq_pad][kpad]   accumulated spectrum A (spectrum order only)
 //   ty, tx  float2 [sy], [sx]           exp(-2 pi i m / S); tx carries 1/sqrt(sy sx)
 //   ey, ex  float2 [sy], [sx]           exp(-2 pi i m / S) for the display DFT
-//   h       float  [max_batch][kpad]    projections of the current batch
+//   h       float  [max_batch][kpad]    projections of the current batch (float2 for the
+//                                       Fourier basis, whose projections are complex)
+//   fy, fx  float2 [ny/2], [nx/2]       exp(+2 pi i m / n) (Fourier basis only)
 //   upload  bytes                       per batch: pos int2 [max_batch], order int32 [max_batch],
 //                                       xs int32 [max_batch] (scan x of frame order[i]), rows int4
 //                                       [max_batch] (brought over by the projection kernel)
@@ -56,6 +58,7 @@ struct wdd_plan_impl {
   float psi_unscale = 1.f;
   int32_t precision = WDD_FP32;
   int32_t order_mode = WDD_ORDER_SPECTRUM;
+  bool fourier = false;  // full Fourier basis: K = ny nx, complex projections
   wdd_probe probe = {};
   wdd_scan scan = {};
   wdd_detector det = {};
@@ -65,6 +68,7 @@ struct wdd_plan_impl {
   float2* w = nullptr;
   float2* acc = nullptr;
   float2 *ty = nullptr, *tx = nullptr, *ey = nullptr, *ex = nullptr;
+  float2 *fy = nullptr, *fx = nullptr;
   float* h = nullptr;
   char* upload = nullptr;  // pos, order, rows
   int2* pos = nullptr;
@@ -263,7 +267,8 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   for (int32_t i = 0; i < t.nx; ++i)
     for (int32_t m = 0; m < t.l; ++m) psi[(size_t)(t.ny + i) * 16 + m] = (float)t.psi_x[(size_t)i * t.l + m];
   std::vector<int32_t> kmap(p->kpad, -1);
-  for (int32_t k = 0; k < t.k; ++k) kmap[k] = 16 * t.pairs[2 * k] + t.pairs[2 * k + 1];
+  if (!p->fourier)
+    for (int32_t k = 0; k < t.k; ++k) kmap[k] = 16 * t.pairs[2 * k] + t.pairs[2 * k + 1];
   std::vector<int2> freqs(p->n_freq_pad, make_int2(0, 0));
   for (int64_t j = 0; j < p->n_freq; ++j) freqs[j] = make_int2(t.freqs[2 * j], t.freqs[2 * j + 1]);
   // workgroups of the object-order update: runs of kept frequencies with one v_x, cut into
@@ -326,15 +331,19 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   ALLOC(p->tx, (size_t)t.sx);
   ALLOC(p->ey, (size_t)t.sy);
   ALLOC(p->ex, (size_t)t.sx);
-  ALLOC(p->h, (size_t)p->max_batch * p->kpad);
+  ALLOC(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1));
+  if (p->fourier) {
+    ALLOC(p->fy, (size_t)std::max(1, t.ny / 2));
+    ALLOC(p->fx, (size_t)std::max(1, t.nx / 2));
+  }
   p->upload_bytes = (size_t)p->max_batch * 16 + 16 + (size_t)p->max_batch * sizeof(int4);
   ALLOC(p->upload, p->upload_bytes);
   p->pos = reinterpret_cast<int2*>(p->upload);
   p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
   p->xs = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 12);
   p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 16 + 15) / 16 * 16);
-  if (p->order_mode == WDD_ORDER_SPECTRUM) ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
-  if (p->order_mode == WDD_ORDER_OBJECT) {
+  if (p->order_mode == WDD_ORDER_SPECTRUM || p->fourier) ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
+  if (p->order_mode == WDD_ORDER_OBJECT && !p->fourier) {
     ALLOC(p->jlist, jlist.size());
     ALLOC(p->chunks, chunks.size());
   }
@@ -366,10 +375,21 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, hipMemcpyAsync(p->tx, tx.data(), tx.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ey, ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->ex, ex.data(), ex.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+  std::vector<float2> fy, fx;
+  if (p->fourier) {  // exp(+2 pi i m / n), the conjugates of the forward twiddles
+    fy = twiddles(t.ny, 1.0);
+    fx = twiddles(t.nx, 1.0);
+    for (auto& v : fy) v.y = -v.y;
+    for (auto& v : fx) v.y = -v.y;
+    WDD_HIP(p, hipMemcpyAsync(p->fy, fy.data(), (size_t)(t.ny / 2) * sizeof(float2), hipMemcpyHostToDevice,
+                              p->stream));
+    WDD_HIP(p, hipMemcpyAsync(p->fx, fx.data(), (size_t)(t.nx / 2) * sizeof(float2), hipMemcpyHostToDevice,
+                              p->stream));
+  }
   if (p->acc) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), nfk * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), grid * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
-  WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad, p->stream));
+  WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
 
   for (int i = 0; i < kRing; ++i) {
     WDD_HIP(p, hipHostMalloc((void**)&p->pin_up[i], p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t),
@@ -398,6 +418,10 @@ wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) 
     return wdd::fail(WDD_EINVAL, "max_batch = %d outside [1, 65536]", opts.max_batch);
   if (opts.order != WDD_ORDER_SPECTRUM && opts.order != WDD_ORDER_OBJECT)
     return wdd::fail(WDD_EINVAL, "unknown order %d", opts.order);
+  if (opts.basis != WDD_BASIS_HERMITE_GAUSS && opts.basis != WDD_BASIS_FOURIER)
+    return wdd::fail(WDD_EINVAL, "unknown basis %d", opts.basis);
+  if (opts.basis == WDD_BASIS_FOURIER && opts.precision != WDD_FP32)
+    return wdd::fail(WDD_EINVAL, "the Fourier basis runs in FP32 only");
   return WDD_OK;
 }
 
@@ -409,9 +433,11 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
   int64_t b = a((int64_t)(t.ny + t.nx) * 16 * 4) + a(kpad * 4) + a(nfp * 8) + a(nfp * kpad * 8);
   if (opts.order == WDD_ORDER_SPECTRUM) b += a(nfp * kpad * 8);
   if (opts.precision != WDD_FP32) b += a((int64_t)2 * 16 * t.nx * 2);
-  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * 4) + a(mb * 16 + 16 + mb * 16);
+  const bool fourier = t.basis == WDD_BASIS_FOURIER;
+  b += 2 * a((int64_t)t.sy * 8) + 2 * a((int64_t)t.sx * 8) + a(mb * kpad * (fourier ? 8 : 4)) + a(mb * 16 + 16 + mb * 16);
   b += a(mb * (int64_t)t.ny * t.nx * (dtype == WDD_U16 ? 2 : 4));
-  if (opts.order == WDD_ORDER_SPECTRUM) {
+  if (fourier) b += a((int64_t)std::max(1, t.ny / 2) * 8) + a((int64_t)std::max(1, t.nx / 2) * 8);
+  if (opts.order == WDD_ORDER_SPECTRUM || fourier) {
     b += a((int64_t)kFactorRows * t.sx * kpad * 8);
   } else {
     const int64_t nchunks_max = t.n_freq() / kMinChunk + t.sx + 1;  // upper bound of the chunk count
@@ -429,6 +455,7 @@ wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe
   p->dtype = det->dtype;
   p->precision = opts.precision;
   p->order_mode = opts.order;
+  p->fourier = t.basis == WDD_BASIS_FOURIER;
   p->probe = *probe;
   p->scan = *scan;
   p->det = *det;
@@ -501,13 +528,14 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   std::stable_sort(ord, ord + n, [pos_yx](int32_t a, int32_t b) { return pos_yx[2 * a] < pos_yx[2 * b]; });
   p->host_rows.clear();
   const bool object = p->order_mode == WDD_ORDER_OBJECT;
-  for (int32_t i = 0; i < n && (object || (int)p->host_rows.size() <= kFactorRows); ++i) {
+  const bool passes = object || p->fourier;  // always row-factored, in passes of <= kFactorRows rows
+  for (int32_t i = 0; i < n && (passes || (int)p->host_rows.size() <= kFactorRows); ++i) {
     const int32_t y = pos_yx[2 * ord[i]];
     if (p->host_rows.empty() || p->host_rows.back().x != y) p->host_rows.push_back(make_int4(y, i, 0, 0));
     p->host_rows.back().z += 1;
   }
   // object order always takes the factored form, in passes of at most kFactorRows rows
-  const bool factored = object || (int)p->host_rows.size() <= kFactorRows;
+  const bool factored = passes || (int)p->host_rows.size() <= kFactorRows;
   const int nrows = factored ? (int)p->host_rows.size() : 0;
 
   // reuse a pinned slot only after the copies that read it have run
@@ -552,7 +580,11 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   hipEvent_t end;
   WDD_HIP(p, stage_begin(p, kProject, &end));
   // the projection kernel also brings the pinned upload block (positions, grouping) to the device
-  if (p->precision == WDD_FP32) {
+  if (p->fourier) {
+    WDD_HIP(p, wdd::launch_project_fourier(p->dtype, fdev, n, p->ny, p->nx, p->fy, p->fx,
+                                           reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
+                                           p->stream));
+  } else if (p->precision == WDD_FP32) {
     WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
                                    up_bytes, ftab, p->stream));
   } else {
@@ -568,7 +600,28 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   } else {
     p->ev_live[s] = false;
   }
-  if (object) {
+  bool wiener_done = object;
+  if (p->fourier) {
+    // complex per-row x-DFTs, then one update per pass of at most kFactorRows rows; the
+    // Wiener reduction rides in the update when one pass covers the batch
+    const bool one_pass = nrows <= kFactorRows;
+    const int mode = object ? 0 : (fuse_wiener && one_pass ? 2 : 1);
+    wiener_done = object || mode == 2;
+    for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
+      const int nr = std::min(kFactorRows, nrows - r0);
+      wdd::RowSet rs;
+      for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
+      if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
+      WDD_HIP(p, stage_begin(p, kRowDft, &end));
+      WDD_HIP(p, wdd::launch_row_dft_c(reinterpret_cast<const float2*>(p->h), p->kpad, p->order, p->xs, rs, nr, p->tx,
+                                       p->sx, p->t, p->stream));
+      WDD_HIP(p, stage_end(p, end));
+      WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+      WDD_HIP(p, wdd::launch_update_c(mode, p->t, p->kpad, rs, nr, p->ty, p->sy, p->sx, p->freqs, p->n_freq, p->w,
+                                      p->acc, p->d, p->z, p->stream));
+      WDD_HIP(p, stage_end(p, end));
+    }
+  } else if (object) {
     // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
@@ -583,6 +636,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     }
   } else if (factored) {
     // per-row x-DFTs, then one pass over A (with the Wiener reduction when asked)
+    wiener_done = fuse_wiener;
     if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
     WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
@@ -597,7 +651,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
                                       p->sx, p->stream));
     WDD_HIP(p, stage_end(p, end));
   }
-  if (fused) *fused = object || (factored && fuse_wiener);
+  if (fused) *fused = wiener_done;
   p->frames_seen += (uint64_t)n;
   p->last_batch = n;
   return WDD_OK;
@@ -746,7 +800,8 @@ wdd_status wdd_get_projection(wdd_plan_t p, float* h_out, int32_t on_device) {
   if (st != WDD_OK) return st;
   if (!h_out) return wdd::fail(WDD_EINVAL, "null output");
   if (p->last_batch == 0) return WDD_OK;
-  return copy_rows(p, h_out, p->h, (size_t)p->last_batch, (size_t)p->k * sizeof(float), (size_t)p->kpad * sizeof(float),
+  const size_t esz = p->fourier ? sizeof(float2) : sizeof(float);
+  return copy_rows(p, h_out, p->h, (size_t)p->last_batch, (size_t)p->k * esz, (size_t)p->kpad * esz,
                    on_device);
 }
 

@@ -71,6 +71,21 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
                                 int nchunks, int max_chunk, const int* jlist, const int2* freqs, const float2* w,
                                 float2* d, float2* z, hipStream_t st);
 
+// Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
+// = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,
+// fy/fx = exp(+2 pi i m / n) for m < n / 2.  Row DFT: t[r][vx][k] = sum over the frames of
+// row r of Tx[(vx x_b) mod sx] h[b][k].  Update (one workgroup per kept frequency): mode 0
+// object order (d += sum_k w s), 1 spectrum order (acc += s), 2 spectrum order with the
+// Wiener reduction (acc += s; d = sum_k w acc), s[k] = sum_r Ty[(v_y y_r) mod sy] t[r][v_x][k].
+hipError_t launch_project_fourier(int dtype, const void* frames, int n, int ny, int nx, const float2* fy,
+                                  const float2* fx, float2* h, int kpad, const void* up_src, void* up_dst,
+                                  size_t up_bytes, const uint64_t* fptr, hipStream_t st);
+hipError_t launch_row_dft_c(const float2* h, int kpad, const int* order, const int* xs, const RowSet& rows, int nrows,
+                            const float2* tx, int sx, float2* t, hipStream_t st);
+hipError_t launch_update_c(int mode, const float2* t, int kpad, const RowSet& rows, int nrows, const float2* ty, int sy,
+                           int sx, const int2* freqs, int64_t n_freq, const float2* w, float2* acc, float2* d,
+                           float2* z, hipStream_t st);
+
 // z[v_x(j)][v_y(j)] = conj(d[j]) for j < n_freq.
 hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st);
 

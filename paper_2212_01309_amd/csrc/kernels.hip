@@ -620,6 +620,7 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 512;
 constexpr int kFusedFrames = 512;  // frames staged in LDS per round of phase 1
+static_assert(kFusedFrames <= kFusedThreads, "phase 1 stages one frame per thread");
 
 __device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
   a0.x += c.x * h.x; a0.y += c.y * h.x; a0.z += c.x * h.y; a0.w += c.y * h.y;
@@ -762,6 +763,178 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Full Fourier basis (K = ny nx).  Projection: h_b[k_y nx + k_x] = sum_q I_b[q]
+// exp(+2 pi i (q_y k_y / ny + q_x k_x / nx)) / (ny nx), a 2D FFT of the frame in LDS (radix-2
+// decimation in time along x with the columns loaded in bit-reversed order, rows
+// bit-reverse permuted, then along y).  fy, fx: exp(+2 pi i m / n) for m < n / 2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_project_fourier(const T* __restrict__ frames, int ny, int nx, int lny,
+                                                         int lnx, const float2* __restrict__ fy,
+                                                         const float2* __restrict__ fx, float2* __restrict__ h,
+                                                         int kpad, const uint32_t* __restrict__ up_src,
+                                                         uint32_t* __restrict__ up_dst, int up_words,
+                                                         const uint64_t* __restrict__ fptr) {
+  extern __shared__ float2 fbuf[];  // [ny][nx], then fy [ny / 2], fx [nx / 2]
+  float2* lfy = fbuf + ny * nx;
+  float2* lfx = lfy + ny / 2;
+  const int tid = threadIdx.x, cells = ny * nx;
+  const T* f = fptr ? reinterpret_cast<const T*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * cells;
+  for (int e = tid; e < cells; e += 256) {
+    const int y = e >> lnx, x = e & (nx - 1);
+    const int rx = (int)(__brev((unsigned)x) >> (32 - lnx));
+    fbuf[y * nx + rx] = make_float2((float)f[e], 0.f);
+  }
+  if (blockIdx.x == 0)
+    for (int i = tid; i < up_words; i += 256) up_dst[i] = up_src[i];
+  for (int i = tid; i < ny / 2; i += 256) lfy[i] = fy[i];
+  for (int i = tid; i < nx / 2; i += 256) lfx[i] = fx[i];
+  __syncthreads();
+  for (int s = 1; s <= lnx; ++s) {
+    const int half = 1 << (s - 1), stride = nx >> s;
+    for (int k = tid; k < cells / 2; k += 256) {
+      const int row = k >> (lnx - 1), bk = k & ((nx >> 1) - 1);
+      const int i0 = row * nx + (bk >> (s - 1)) * (half << 1) + (bk & (half - 1));
+      const float2 tw = lfx[(bk & (half - 1)) * stride];
+      const float2 x0 = fbuf[i0], x1 = fbuf[i0 + half];
+      const float2 tt = make_float2(tw.x * x1.x - tw.y * x1.y, tw.x * x1.y + tw.y * x1.x);
+      fbuf[i0] = make_float2(x0.x + tt.x, x0.y + tt.y);
+      fbuf[i0 + half] = make_float2(x0.x - tt.x, x0.y - tt.y);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < cells; e += 256) {
+    const int y = e >> lnx, x = e & (nx - 1);
+    const int ry = (int)(__brev((unsigned)y) >> (32 - lny));
+    if (y < ry) {
+      const float2 a = fbuf[y * nx + x];
+      fbuf[y * nx + x] = fbuf[ry * nx + x];
+      fbuf[ry * nx + x] = a;
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s <= lny; ++s) {
+    const int half = 1 << (s - 1), stride = ny >> s;
+    for (int k = tid; k < cells / 2; k += 256) {
+      const int col = k & (nx - 1), bk = k >> lnx;
+      const int i0 = ((bk >> (s - 1)) * (half << 1) + (bk & (half - 1))) * nx + col;
+      const float2 tw = lfy[(bk & (half - 1)) * stride];
+      const float2 x0 = fbuf[i0], x1 = fbuf[i0 + half * nx];
+      const float2 tt = make_float2(tw.x * x1.x - tw.y * x1.y, tw.x * x1.y + tw.y * x1.x);
+      fbuf[i0] = make_float2(x0.x + tt.x, x0.y + tt.y);
+      fbuf[i0 + half * nx] = make_float2(x0.x - tt.x, x0.y - tt.y);
+    }
+    __syncthreads();
+  }
+  const float norm = 1.0f / (float)cells;
+  float2* hb = h + (size_t)blockIdx.x * kpad;
+  for (int e = tid; e < cells; e += 256) {
+    const float2 v = fbuf[e];
+    hb[e] = make_float2(v.x * norm, v.y * norm);
+  }
+}
+
+// Complex per-row x-DFT: t[r][vx][k] = sum_{frames b of row r} Tx[(vx x_b) mod sx] h_b[k].
+// Workgroup (k-block, vx, r); the row's frames are staged (index, twiddle) in LDS.
+__global__ __launch_bounds__(256) void k_row_dft_c(const float2* __restrict__ h, int kpad,
+                                                   const int* __restrict__ order, const int* __restrict__ xs,
+                                                   RowSet rs, const float2* __restrict__ tx, int sx,
+                                                   float2* __restrict__ t) {
+  __shared__ float2 lw[256];
+  __shared__ int lb[256];
+  const int tid = threadIdx.x, k = blockIdx.x * 256 + tid, vx = blockIdx.y, r = blockIdx.z;
+  const int4 row = rs.r[r];
+  const bool px2 = (sx & (sx - 1)) == 0;
+  const float invx = 1.0f / (float)sx;
+  float re = 0.f, im = 0.f;
+  for (int f0 = 0; f0 < row.z; f0 += 256) {
+    const int n = min(256, row.z - f0);
+    __syncthreads();
+    if (tid < n) {
+      const int at = row.y + f0 + tid;
+      const int p = vx * xs[at];
+      lw[tid] = tx[px2 ? (p & (sx - 1)) : mod_small(p, sx, invx)];
+      lb[tid] = order[at];
+    }
+    __syncthreads();
+    if (k < kpad)
+      for (int i = 0; i < n; ++i) {
+        const float2 c = lw[i], v = h[(size_t)lb[i] * kpad + k];
+        re += c.x * v.x - c.y * v.y;
+        im += c.x * v.y + c.y * v.x;
+      }
+  }
+  if (k < kpad) t[((size_t)r * sx + vx) * kpad + k] = make_float2(re, im);
+}
+
+// Complex update, one workgroup per kept frequency j (each thread a stride of k):
+//   s[k] = sum_r Ty[(vy y_r) mod sy] t[r][vx][k]
+//   MODE 0 (object order):   D[j] += sum_k W[j][k] s[k]
+//   MODE 1 (spectrum order): A[j][k] += s[k]
+//   MODE 2 (spectrum order, Wiener reduction fused): A[j][k] += s[k]; D[j] = sum_k W[j][k] A[j][k]
+// and z = conj(D) for modes 0 and 2.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_update_c(const float2* __restrict__ t, int kpad, RowSet rs, int nrows,
+                                                  const float2* __restrict__ ty, int sy, int sx,
+                                                  const int2* __restrict__ freqs, const float2* __restrict__ w,
+                                                  float2* __restrict__ acc, float2* __restrict__ d,
+                                                  float2* __restrict__ z) {
+  __shared__ float2 lph[kRowSetMax];
+  __shared__ float lre[4], lim[4];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int2 v = freqs[j];
+  const bool py2 = (sy & (sy - 1)) == 0;
+  if (tid < nrows) {
+    const int p = v.x * rs.r[tid].x;
+    lph[tid] = ty[py2 ? (p & (sy - 1)) : mod_small(p, sy, 1.0f / (float)sy)];
+  }
+  __syncthreads();
+  float re = 0.f, im = 0.f;
+  for (int k = tid; k < kpad; k += 256) {
+    float sr = 0.f, si = 0.f;
+    for (int r = 0; r < nrows; ++r) {
+      const float2 ph = lph[r], x = t[((size_t)r * sx + v.y) * kpad + k];
+      sr += ph.x * x.x - ph.y * x.y;
+      si += ph.x * x.y + ph.y * x.x;
+    }
+    if (MODE != 0) {
+      float2 a = acc[(size_t)j * kpad + k];
+      a.x += sr;
+      a.y += si;
+      acc[(size_t)j * kpad + k] = a;
+      sr = a.x;
+      si = a.y;
+    }
+    if (MODE != 1) {
+      const float2 c = w[(size_t)j * kpad + k];
+      re += c.x * sr - c.y * si;
+      im += c.x * si + c.y * sr;
+    }
+  }
+  if (MODE == 1) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    lre[wave] = re;
+    lim[wave] = im;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    re = (lre[0] + lre[1]) + (lre[2] + lre[3]);
+    im = (lim[0] + lim[1]) + (lim[2] + lim[3]);
+    float2 nd = make_float2(re, im);
+    if (MODE == 0) {
+      const float2 old = d[j];
+      nd = make_float2(old.x + re, old.y + im);
+    }
+    d[j] = nd;
+    z[(size_t)v.y * sy + v.x] = make_float2(nd.x, -nd.y);
+  }
+}
 
 // z[v_x(j)][v_y(j)] = conj(d[j]) for every kept frequency (display grid from D).
 __global__ void k_scatter_conj(const float2* __restrict__ d, const int2* __restrict__ freqs, int64_t n_freq,
@@ -950,6 +1123,52 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
                      tx, sx, ty, sy, chunks, jlist, freqs, w, d, z, max_chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_fourier(int dtype, const void* frames, int n, int ny, int nx, const float2* fy,
+                                  const float2* fx, float2* h, int kpad, const void* up_src, void* up_dst,
+                                  size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int lny = 0, lnx = 0;
+  while ((1 << lny) < ny) ++lny;
+  while ((1 << lnx) < nx) ++lnx;
+  if ((1 << lny) != ny || (1 << lnx) != nx || ny < 2 || nx < 2 || ny * nx > kpad || ny * nx > 4096)
+    return hipErrorInvalidValue;
+  const size_t lds = ((size_t)ny * nx + ny / 2 + nx / 2) * sizeof(float2);
+  if (dtype == WDD_U16)
+    hipLaunchKernelGGL(k_project_fourier<uint16_t>, dim3(n), dim3(256), lds, st,
+                       static_cast<const uint16_t*>(frames), ny, nx, lny, lnx, fy, fx, h, kpad,
+                       static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4),
+                       fptr);
+  else
+    hipLaunchKernelGGL(k_project_fourier<float>, dim3(n), dim3(256), lds, st, static_cast<const float*>(frames), ny,
+                       nx, lny, lnx, fy, fx, h, kpad, static_cast<const uint32_t*>(up_src),
+                       static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4), fptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_dft_c(const float2* h, int kpad, const int* order, const int* xs, const RowSet& rows, int nrows,
+                            const float2* tx, int sx, float2* t, hipStream_t st) {
+  if (nrows < 1 || nrows > kRowSetMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_row_dft_c, dim3((unsigned)((kpad + 255) / 256), (unsigned)sx, (unsigned)nrows), dim3(256), 0,
+                     st, h, kpad, order, xs, rows, tx, sx, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_c(int mode, const float2* t, int kpad, const RowSet& rows, int nrows, const float2* ty, int sy,
+                           int sx, const int2* freqs, int64_t n_freq, const float2* w, float2* acc, float2* d,
+                           float2* z, hipStream_t st) {
+  if (nrows < 1 || nrows > kRowSetMax || n_freq < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)n_freq);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_update_c<0>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_update_c<1>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+  else if (mode == 2)
+    hipLaunchKernelGGL(k_update_c<2>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

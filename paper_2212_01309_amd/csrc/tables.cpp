@@ -73,6 +73,84 @@ struct Geometry {
   }
 };
 
+// W = conj(Y^B) / (|Y^B|^2 + eps_abs), eps_abs = eps_rel max |Y^B|^2 (pre-computed Wiener
+// filter algorithm, relative regularisation), in place over t->w which holds Y^B.
+void wiener_from_reduced(wdd_tables_s* t) {
+  double mx = 0.0;
+  for (size_t i = 0; i < t->w.size(); i += 2) mx = std::max(mx, t->w[i] * t->w[i] + t->w[i + 1] * t->w[i + 1]);
+  t->eps_abs = t->eps_rel * mx;
+  for (size_t i = 0; i < t->w.size(); i += 2) {
+    const double re = t->w[i], im = t->w[i + 1];
+    const double den = re * re + im * im + t->eps_abs;
+    t->w[i] = re / den;
+    t->w[i + 1] = -im / den;
+  }
+}
+
+// Y^B_v[k] = sum_q Y_v[q] exp(+2 pi i (q_y k_y / ny + q_x k_x / nx)) / (ny nx) for the full
+// Fourier basis, by separable sums over the pixels of the aperture overlap (FP64).
+void fourier_wigner(wdd_tables_s* t, const Geometry& geo) {
+  const int32_t ny = t->ny, nx = t->nx, K = ny * nx;
+  const int64_t nf = t->n_freq();
+  t->w.assign((size_t)nf * K * 2, 0.0);
+  std::vector<cd> ey(ny), ex(nx);
+  for (int32_t m = 0; m < ny; ++m) ey[m] = std::polar(1.0, 2.0 * M_PI * m / ny);
+  for (int32_t m = 0; m < nx; ++m) ex[m] = std::polar(1.0, 2.0 * M_PI * m / nx);
+  const double amp = t->amplitude, phi_e = t->defocus, r2 = t->radius * t->radius;
+  auto quad_phase = [&](double u) { return cd(std::cos(phi_e * u * u / r2), -std::sin(phi_e * u * u / r2)); };
+  const double norm = 1.0 / ((double)ny * nx);
+  auto work = [&](int64_t f0, int64_t f1) {
+    std::vector<cd> row((size_t)nx), part((size_t)ny * nx);
+    for (int64_t f = f0; f < f1; ++f) {
+      const int64_t vy = t->freqs[2 * f], vx = t->freqs[2 * f + 1];
+      const double dy = (double)signed_freq(vy, t->sy) * ny / (t->sy * t->step);
+      const double dx = (double)signed_freq(vx, t->sx) * nx / (t->sx * t->step);
+      std::fill(part.begin(), part.end(), cd(0, 0));
+      for (int64_t uy = geo.uy_lo; uy <= geo.uy_hi; ++uy) {
+        const int64_t lo = geo.row_lo[uy - geo.uy_lo], hi = geo.row_hi[uy - geo.uy_lo];
+        if (lo > hi) continue;
+        const double ry = (double)uy + dy;
+        const double rem = r2 - ry * ry;
+        if (rem < 0) continue;
+        const cd rowf = quad_phase((double)uy) * std::conj(quad_phase(ry));
+        bool any = false;
+        std::fill(row.begin(), row.end(), cd(0, 0));
+        for (int64_t ux = lo; ux <= hi; ++ux) {
+          const double rx = (double)ux + dx;
+          if (rx * rx > rem) continue;
+          // Y = P(u) conj(P(u + d)); |P| = amp inside both discs
+          const cd y = amp * amp * rowf * quad_phase((double)ux) * std::conj(quad_phase(rx));
+          const int64_t qx = ux + geo.cx;
+          for (int32_t kx = 0; kx < nx; ++kx) row[kx] += y * ex[(qx * kx) % nx];
+          any = true;
+        }
+        if (!any) continue;
+        const int64_t qy = uy + geo.cy;
+        for (int32_t ky = 0; ky < ny; ++ky) {
+          const cd e = ey[(qy * ky) % ny];
+          cd* dst = &part[(size_t)ky * nx];
+          for (int32_t kx = 0; kx < nx; ++kx) dst[kx] += e * row[kx];
+        }
+      }
+      double* out = &t->w[(size_t)f * K * 2];
+      for (int32_t k = 0; k < K; ++k) {
+        out[2 * k] = part[k].real() * norm;
+        out[2 * k + 1] = part[k].imag() * norm;
+      }
+    }
+  };
+  unsigned nth = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+  if (nf < 64) nth = 1;
+  std::vector<std::thread> pool;
+  const int64_t chunk = (nf + nth - 1) / nth;
+  for (unsigned i = 0; i < nth; ++i) {
+    const int64_t f0 = i * chunk, f1 = std::min<int64_t>(nf, f0 + chunk);
+    if (f0 >= f1) break;
+    pool.emplace_back(work, f0, f1);
+  }
+  for (auto& th : pool) th.join();
+}
+
 }  // namespace
 
 namespace wdd {
@@ -104,16 +182,29 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
   if (det->ny < 1 || det->nx < 1 || det->ny > 1024 || det->nx > 1024 || det->nx % 8 != 0)
     return fail(WDD_EINVAL, "detector %d x %d: need 1 <= ny, nx <= 1024 and nx a multiple of 8", det->ny, det->nx);
   if (det->dtype != WDD_U16 && det->dtype != WDD_F32) return fail(WDD_EINVAL, "unknown frame dtype %d", det->dtype);
-  if (K < 1 || K > 256) return fail(WDD_EINVAL, "K = %d outside [1, 256]", K);
+  const bool fourier = opts.basis == WDD_BASIS_FOURIER;
+  if (opts.basis != WDD_BASIS_HERMITE_GAUSS && !fourier) return fail(WDD_EINVAL, "unknown basis %d", opts.basis);
+  auto pow2 = [](int32_t n) { return n > 0 && (n & (n - 1)) == 0; };
+  if (fourier) {
+    if (!pow2(det->ny) || !pow2(det->nx) || det->ny < 8 || det->nx < 8 || det->ny > 64 || det->nx > 64)
+      return fail(WDD_EINVAL, "the Fourier basis needs ny, nx powers of two in [8, 64] (got %d x %d)", det->ny,
+                  det->nx);
+    if (K != det->ny * det->nx) return fail(WDD_EINVAL, "the Fourier basis has K = ny nx = %d (got %d)",
+                                            det->ny * det->nx, K);
+  } else if (K < 1 || K > 256) {
+    return fail(WDD_EINVAL, "K = %d outside [1, 256]", K);
+  }
   if (!(opts.eps_rel > 0) || !std::isfinite(opts.eps_rel)) return fail(WDD_EINVAL, "eps_rel must be > 0");
   if (!std::isfinite(opts.sigma_px)) return fail(WDD_EINVAL, "sigma must be finite");
 
   int32_t L = 1;
   while (L * L < K) ++L;
+  if (fourier) L = 0;
   t->sy = scan->sy; t->sx = scan->sx; t->ny = det->ny; t->nx = det->nx; t->k = K; t->l = L;
   t->step = scan->step_px; t->radius = radius; t->amplitude = probe->amplitude;
   t->defocus = probe->defocus_edge_rad; t->eps_rel = opts.eps_rel;
-  t->sigma = opts.sigma_px > 0 ? opts.sigma_px : radius / std::sqrt(2.0 * L - 1.0);
+  t->sigma = fourier ? 0.0 : (opts.sigma_px > 0 ? opts.sigma_px : radius / std::sqrt(2.0 * L - 1.0));
+  t->basis = opts.basis;
 
   try {
     // --- kept frequencies -------------------------------------------------
@@ -132,6 +223,12 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
           t->freqs.push_back((int32_t)vx);
         }
       }
+    }
+
+    if (fourier) {
+      fourier_wigner(t, geo);
+      wiener_from_reduced(t);
+      return WDD_OK;
     }
 
     // --- Hermite-Gauss basis ---------------------------------------------
@@ -241,16 +338,7 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
     }
     for (auto& th : pool) th.join();
 
-    // --- Wiener filter ------------------------------------------------------
-    double mx = 0.0;
-    for (size_t i = 0; i < t->w.size(); i += 2) mx = std::max(mx, t->w[i] * t->w[i] + t->w[i + 1] * t->w[i + 1]);
-    t->eps_abs = t->eps_rel * mx;
-    for (size_t i = 0; i < t->w.size(); i += 2) {
-      const double re = t->w[i], im = t->w[i + 1];
-      const double den = re * re + im * im + t->eps_abs;
-      t->w[i] = re / den;
-      t->w[i + 1] = -im / den;
-    }
+    wiener_from_reduced(t);
   } catch (const std::bad_alloc&) {
     return fail(WDD_ENOMEM, "host tables do not fit in memory");
   } catch (const std::system_error&) {
@@ -272,6 +360,7 @@ wdd_status wdd_default_options(wdd_options* opts) {
   opts->precision = WDD_FP32;
   opts->max_batch = 256;
   opts->order = WDD_ORDER_SPECTRUM;
+  opts->basis = WDD_BASIS_HERMITE_GAUSS;
   return WDD_OK;
 }
 

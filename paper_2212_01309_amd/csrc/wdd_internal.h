@@ -11,6 +11,7 @@ struct wdd_tables_s {
   int32_t sy = 0, sx = 0, ny = 0, nx = 0, k = 0, l = 0;
   double step = 1.0, radius = 0.0, amplitude = 1.0, defocus = 0.0;
   double eps_rel = 0.01, sigma = 0.0, eps_abs = 0.0;
+  int32_t basis = WDD_BASIS_HERMITE_GAUSS;
   std::vector<int32_t> freqs;  // [n_freq][2]  (v_y, v_x)
   std::vector<double> psi_y;   // [ny][l]
   std::vector<double> psi_x;   // [nx][l]

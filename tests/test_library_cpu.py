@@ -78,3 +78,31 @@ def test_default_options():
     o = wdd.Options()
     assert wdd.load_library().wdd_default_options(ctypes.byref(o)) == 0
     assert o.eps_rel == 0.01 and o.sigma_px == 0.0 and o.max_batch == 256 and o.precision == wdd.WDD_FP32
+    assert o.order == wdd.WDD_ORDER_SPECTRUM and o.basis == wdd.WDD_BASIS_HERMITE_GAUSS
+
+
+@pytest.mark.parametrize("radius,s,ny,nx,defocus", [
+    (8.0, 32, 32, 32, 0.0), (4.0, 24, 16, 8, 0.7), (2.5, 16, 8, 16, 0.0), (12.0, 20, 32, 64, np.pi),
+])
+def test_fourier_tables_match_oracle(radius, s, ny, nx, defocus):
+    """Full Fourier basis: Y^B = the oracle's reduction with fourier_basis (numpy ifft2)."""
+    t = wdd.Tables(radius, s, s, ny, nx, ny * nx, defocus=defocus, basis=wdd.WDD_BASIS_FOURIER)
+    freqs, psy, psx, pairs, w = t.export()
+    p = O.make_plan(s, s, ny, nx, radius, defocus_edge=defocus, phi=O.fourier_basis(ny, nx))
+    assert t.l == 0 and t.k == ny * nx and psy.size == 0
+    assert np.array_equal(freqs, p.freqs)
+    assert t.eps_abs == pytest.approx(p.eps_abs, rel=1e-12)
+    assert np.linalg.norm(w - p.w) <= 1e-12 * np.linalg.norm(p.w)
+
+
+@pytest.mark.parametrize("ny,nx,k", [(32, 32, 1000), (48, 32, 48 * 32), (128, 128, 128 * 128), (4, 8, 32)])
+def test_fourier_tables_reject_bad_shapes(ny, nx, k):
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Tables(4.0, 16, 16, ny, nx, k, basis=wdd.WDD_BASIS_FOURIER)
+    assert ei.value.code == wdd.WDD_EINVAL
+
+
+def test_fourier_plan_rejects_reduced_precision_before_touching_a_device():
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Plan(8.0, 16, 16, 32, 32, 1024, basis=wdd.WDD_BASIS_FOURIER, precision=wdd.WDD_BF16_HILO)
+    assert ei.value.code == wdd.WDD_EINVAL
