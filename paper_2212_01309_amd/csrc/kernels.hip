@@ -1,9 +1,16 @@
 // HIP kernels of the live WDD per-frame update for gfx950 (CDNA4, wave64).
 //
-//   k_project      frames -> h = Phi^T vec(I)      (Section 5 reduction; FP32 MFMA)
-//   k_accumulate   A[v,k] += sum_b F[v,b] h[b,k]   (Section 6.1 outer-product sum; FP32 MFMA)
-//   k_wiener       D[v] = sum_k W[v,k] A[v,k]      (modified-WDD deconvolution + summation)
-//   k_dft_rows     row DFTs for O~ = conj(IDFT2(D)) / sqrt(|D[0]|)   (eq. extract)
+//   k_project, k_project_lp   frames -> h = Phi^T vec(I)  (Section 5 reduction; FP32, or
+//                             BF16/FP16 MFMA with FP32 accumulation)
+//   k_row_fused_obj   object order: D[v] += sum_b F[v,b] sum_k W[v,k] h[b,k], row-factored
+//                     with the scan x-DFT fused in (modified-WDD algorithm, Section 6.3)
+//   k_row_dft, k_row_update   spectrum order, row-factored: A[v,k] += sum_b F[v,b] h[b,k]
+//                     (Section 6.1 F = F_y (x) F_x), optionally with D = sum_k W A fused
+//   k_accumulate      spectrum order, direct: the same sum on FP32 MFMA
+//   k_wiener          D[v] = sum_k W[v,k] A[v,k]  (deconvolution + summation)
+//   k_project_fourier, k_row_dft_c, k_update_c   the same path with the full Fourier basis
+//                     (K = ny nx, complex h): conventional WDD
+//   k_dft_rows        row DFTs for O~ = conj(IDFT2(D)) / sqrt(|D[0]|)   (eq. extract)
 //
 // Complex values are float2 (re, im).  No atomics: every output element has a
 // single owner, so results are deterministic for fixed batch boundaries.
@@ -23,6 +30,73 @@ using wdd::kRowSetMax;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Loads through global-address-space pointers.  Frames may be reached through a table of
+// addresses (generic pointers); device and pinned host memory are both global memory here,
+// and global loads, unlike flat ones, do not hold up waits on LDS traffic.
+#define WDD_GLOBAL(T) const __attribute__((address_space(1))) T*
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ inline float gload(const float* p) { return *(WDD_GLOBAL(float))p; }
+__device__ inline uint16_t gload(const uint16_t* p) { return *(WDD_GLOBAL(uint16_t))p; }
+__device__ inline uint32_t gload(const uint32_t* p) { return *(WDD_GLOBAL(uint32_t))p; }
+__device__ inline int gload(const int* p) { return *(WDD_GLOBAL(int))p; }
+__device__ inline uint4 gload(const uint4* p) {
+  const u32x4 v = *(WDD_GLOBAL(u32x4))p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float4 gload(const float4* p) {
+  const floatx4 v = *(WDD_GLOBAL(floatx4))p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float2 gload(const float2* p) {
+  const f32x2 v = *(WDD_GLOBAL(f32x2))p;
+  return make_float2(v.x, v.y);
+}
+#undef WDD_GLOBAL
+
+// The batch's upload block (pinned host memory, read by workgroup 0 of the projection): the
+// loads of the first 4 * nthreads words are issued by upload_issue, before the tables are
+// staged, and their stores (and the rest of a long block) done by upload_finish, so the
+// PCIe round trip overlaps the other loads.
+struct UploadWords {
+  uint32_t v[4];
+};
+__device__ inline void upload_issue(UploadWords& u, const uint32_t* src, int n, int tid, int nthreads) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = k * nthreads + tid;
+    if (i < n) u.v[k] = gload(src + i);
+  }
+}
+__device__ inline void upload_finish(const UploadWords& u, uint32_t* dst, const uint32_t* src, int n, int tid,
+                                     int nthreads) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = k * nthreads + tid;
+    if (i < n) dst[i] = u.v[k];
+  }
+  for (int i = 4 * nthreads + tid; i < n; i += nthreads) dst[i] = gload(src + i);
+}
+
+// dst[i] = src[i] for i < n by `nthreads` threads, U loads in flight per thread before any
+// store (a plain strided copy loop waits for each load in turn).
+template <int U, typename T, typename D>
+__device__ inline void stage_copy(D* dst, const T* src, int n, int tid, int nthreads) {
+  for (int base = 0; base < n; base += U * nthreads) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nthreads + tid;
+      if (i < n) v[u] = gload(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nthreads + tid;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Projection.  Per frame G = psi_y^T I psi_x (L x L, L <= 16) is formed with
 // v_mfma_f32_16x16x4_f32 in two stages, then h[k] = G[n_y(k)][n_x(k)].
@@ -40,7 +114,7 @@ struct Chunk;
 template <>
 struct Chunk<uint16_t> {
   uint4 v;
-  __device__ inline void load(const uint16_t* p) { v = *reinterpret_cast<const uint4*>(p); }
+  __device__ inline void load(const uint16_t* p) { v = gload(reinterpret_cast<const uint4*>(p)); }
   __device__ inline void zero() { v = make_uint4(0u, 0u, 0u, 0u); }
   __device__ inline float get(int j) const {
     const uint32_t w = (j < 2) ? v.x : (j < 4) ? v.y : (j < 6) ? v.z : v.w;
@@ -51,8 +125,8 @@ template <>
 struct Chunk<float> {
   float4 a, b;
   __device__ inline void load(const float* p) {
-    a = *reinterpret_cast<const float4*>(p);
-    b = *reinterpret_cast<const float4*>(p + 4);
+    a = gload(reinterpret_cast<const float4*>(p));
+    b = gload(reinterpret_cast<const float4*>(p + 4));
   }
   __device__ inline void zero() { a = b = make_float4(0.f, 0.f, 0.f, 0.f); }
   __device__ inline float get(int j) const {
@@ -93,10 +167,12 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
     else ch[c].zero();
   }
   // the batch's positions / grouping live in pinned host memory; block 0 brings them over
-  if (blockIdx.x == 0)
-    for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
-  for (int i = tid; i < (ny + nx) * 16; i += blockDim.x) smem[i] = psi[i];
-  for (int i = tid; i < kpad; i += blockDim.x) lkmap[i] = kmap[i];
+  UploadWords upw;
+  const bool uploader = blockIdx.x == 0;
+  if (uploader) upload_issue(upw, up_src, up_words, tid, blockDim.x);
+  stage_copy<8>(smem, psi, (ny + nx) * 16, tid, blockDim.x);
+  stage_copy<1>(lkmap, kmap, kpad, tid, blockDim.x);
+  if (uploader) upload_finish(upw, up_dst, up_src, up_words, tid, blockDim.x);
   __syncthreads();
 
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
@@ -113,17 +189,24 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
         }
       }
       const int nch = min(8, (nx - xg + 31) >> 5);  // chunks of 32 columns inside the frame
+      // per chunk: its 8 basis values first (LDS), then 8 MFMAs alternating between two
+      // accumulators, so neither the LDS reads nor one MFMA chain serialise the loop
+      floatx4 tacc2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         if (c >= nch) break;
         const int xs = xg + 32 * c + 8 * q;
         const int xb = (xs < nx) ? xs : 0;
+        float bv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float bv = (xs < nx) ? lpsx[(xb + j) * 16 + r16] : 0.f;
-          tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j), bv, tacc, 0, 0, 0);
+        for (int j = 0; j < 8; ++j) bv[j] = (xs < nx) ? lpsx[(xb + j) * 16 + r16] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j), bv[j], tacc, 0, 0, 0);
+          tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j + 1), bv[j + 1], tacc2, 0, 0, 0);
         }
       }
+      tacc += tacc2;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -205,14 +288,28 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
     if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
     else ch[c].zero();
   }
-  if (blockIdx.x == 0)
-    for (int i = tid; i < up_words; i += blockDim.x) up_dst[i] = up_src[i];
-  for (int i = tid; i < ny * 16; i += blockDim.x) lpsy[i] = psi[i];
-  for (int i = tid; i < kpad; i += blockDim.x) lkmap[i] = kmap[i];
-  const int parts = HILO ? 2 : 1;
-  for (int i = tid; i < parts * 16 * nx; i += blockDim.x) {
-    const int row = i / nx, x = i - row * nx;
-    lpx[row * nxp + x] = psix_lp[i];
+  UploadWords upw;
+  const bool uploader = blockIdx.x == 0;
+  if (uploader) upload_issue(upw, up_src, up_words, tid, blockDim.x);
+  stage_copy<4>(lpsy, psi, ny * 16, tid, blockDim.x);
+  stage_copy<1>(lkmap, kmap, kpad, tid, blockDim.x);
+  if (uploader) upload_finish(upw, up_dst, up_src, up_words, tid, blockDim.x);
+  const int parts = HILO ? 2 : 1, total = parts * 16 * nx;
+  for (int base = 0; base < total; base += 4 * (int)blockDim.x) {  // loads first, then the padded stores
+    uint16_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + u * blockDim.x + tid;
+      if (i < total) v[u] = gload(psix_lp + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + u * blockDim.x + tid;
+      if (i < total) {
+        const int row = i / nx, x = i - row * nx;
+        lpx[row * nxp + x] = v[u];
+      }
+    }
   }
   __syncthreads();
 
@@ -424,11 +521,20 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
   }
   if (log2len >= 0) {
     float2* ltw = lbuf + len;
-    for (int m = tid; m < len; m += 256) {
-      const int rev = log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0;
-      lbuf[rev] = src[(size_t)m * in_sm];
+    for (int base = 0; base < len; base += 8 * 256) {  // loads first, then the bit-reversed stores
+      float2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int m = base + u * 256 + tid;
+        if (m < len) v[u] = gload(src + (size_t)m * in_sm);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int m = base + u * 256 + tid;
+        if (m < len) lbuf[log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0] = v[u];
+      }
     }
-    for (int m = tid; m < len / 2; m += 256) ltw[m] = e[m];
+    stage_copy<4>(ltw, e, len / 2, tid, 256);
     __syncthreads();
     for (int s = 1; s <= log2len; ++s) {
       const int half = 1 << (s - 1);
@@ -499,7 +605,7 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
   const int c0 = blockIdx.y * 16;
   const bool p2 = (sx & (sx - 1)) == 0;
   const float inv = 1.0f / (float)sx;
-  for (int i = tid; i < sx; i += 256) ltx[i] = tx[i];
+  stage_copy<4>(ltx, tx, sx, tid, 256);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int i0 = 0; i0 < row.z; i0 += kRowChunk) {
     const int cnt = min(kRowChunk, row.z - i0);
@@ -782,15 +888,26 @@ __global__ __launch_bounds__(256) void k_project_fourier(const T* __restrict__ f
   float2* lfx = lfy + ny / 2;
   const int tid = threadIdx.x, cells = ny * nx;
   const T* f = fptr ? reinterpret_cast<const T*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * cells;
-  for (int e = tid; e < cells; e += 256) {
-    const int y = e >> lnx, x = e & (nx - 1);
-    const int rx = (int)(__brev((unsigned)x) >> (32 - lnx));
-    fbuf[y * nx + rx] = make_float2((float)f[e], 0.f);
+  for (int base = 0; base < cells; base += 16 * 256) {  // up to 16 loads in flight per thread
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * 256 + tid;
+      if (e < cells) v[u] = gload(f + e);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u * 256 + tid;
+      if (e < cells) {
+        const int y = e >> lnx, x = e & (nx - 1);
+        const int rx = (int)(__brev((unsigned)x) >> (32 - lnx));
+        fbuf[y * nx + rx] = make_float2((float)v[u], 0.f);
+      }
+    }
   }
-  if (blockIdx.x == 0)
-    for (int i = tid; i < up_words; i += 256) up_dst[i] = up_src[i];
-  for (int i = tid; i < ny / 2; i += 256) lfy[i] = fy[i];
-  for (int i = tid; i < nx / 2; i += 256) lfx[i] = fx[i];
+  if (blockIdx.x == 0) stage_copy<4>(up_dst, up_src, up_words, tid, 256);
+  stage_copy<1>(lfy, fy, ny / 2, tid, 256);
+  stage_copy<1>(lfx, fx, nx / 2, tid, 256);
   __syncthreads();
   for (int s = 1; s <= lnx; ++s) {
     const int half = 1 << (s - 1), stride = nx >> s;
