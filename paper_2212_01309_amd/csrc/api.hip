@@ -15,8 +15,9 @@
 //   upload  bytes                       per batch: pos int2 [max_batch], order int32 [max_batch],
 //                                       xs int32 [max_batch] (scan x of frame order[i]), rows int4
 //                                       [max_batch] (brought over by the projection kernel)
-//   jlist   int32  [n_freq]             kept-frequency indices grouped by v_x (ascending v_x, v_y)
-//   chunks  int4   [nchunks]            (v_x, first jlist index, count <= max_chunk, 0): the
+//   jv      int2   [n_freq]             (j, v_y) of the kept frequencies grouped by v_x (ascending
+//                                       v_x, v_y; object order only)
+//   chunks  int4   [nchunks]            (v_x, first jv index, count <= max_chunk, 0): the
 //                                       workgroups of the object-order update (object order only)
 //   t       float2 [kFactorRows][sx][kpad]  per-row x-DFTs (spectrum order, fused Wiener reduction)
 //   frames  staging for host frames     [max_batch][ny][nx]
@@ -77,7 +78,8 @@ struct wdd_plan_impl {
   int4* rows = nullptr;
   size_t upload_bytes = 0;
   float2* t = nullptr;
-  int32_t* jlist = nullptr;
+  int2* jv = nullptr;  // (j, v_y) of the kept frequencies grouped by v_x (object order)
+  float tscale = 1.f;  // 1 / sqrt(sy sx), the unitary scan DFT's factor
   int4* chunks = nullptr;
   int32_t nchunks = 0, max_chunk = 0;
   void* frames = nullptr;
@@ -247,6 +249,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   while (p->kpad < t.k) p->kpad *= 2;
   p->n_freq = t.n_freq();
   p->n_freq_pad = (p->n_freq + 63) / 64 * 64;
+  p->tscale = (float)(1.0 / std::sqrt((double)t.sy * (double)t.sx));
   p->sigma = t.sigma; p->eps_abs = t.eps_abs;
   p->max_batch = opts.max_batch;
   p->host_order.resize(p->max_batch);
@@ -344,7 +347,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 16 + 15) / 16 * 16);
   if (p->order_mode == WDD_ORDER_SPECTRUM || p->fourier) ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
   if (p->order_mode == WDD_ORDER_OBJECT && !p->fourier) {
-    ALLOC(p->jlist, jlist.size());
+    ALLOC(p->jv, jlist.size());
     ALLOC(p->chunks, chunks.size());
   }
   {
@@ -365,9 +368,10 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
                               p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->kmap, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   WDD_HIP(p, hipMemcpyAsync(p->freqs, freqs.data(), freqs.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
-  if (p->jlist) {
-    WDD_HIP(p, hipMemcpyAsync(p->jlist, jlist.data(), jlist.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                              p->stream));
+  if (p->jv) {
+    std::vector<int2> jv(jlist.size());
+    for (size_t i = 0; i < jlist.size(); ++i) jv[i] = make_int2(jlist[i], freqs[jlist[i]].x);
+    WDD_HIP(p, hipMemcpyAsync(p->jv, jv.data(), jv.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
     WDD_HIP(p, hipMemcpyAsync(p->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice,
                               p->stream));
   }
@@ -441,7 +445,7 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
     b += a((int64_t)kFactorRows * t.sx * kpad * 8);
   } else {
     const int64_t nchunks_max = t.n_freq() / kMinChunk + t.sx + 1;  // upper bound of the chunk count
-    b += a(t.n_freq() * 4) + a(nchunks_max * 16);
+    b += a(t.n_freq() * 8) + a(nchunks_max * 16);
   }
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
@@ -629,9 +633,8 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
       wdd::RowSet rs;
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
-      WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tx, p->sx, p->ty, p->sy,
-                                           p->chunks, p->nchunks, p->max_chunk, p->jlist, p->freqs, p->w, p->d, p->z,
-                                           p->stream));
+      WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
+                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->z, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
   } else if (factored) {

@@ -57,19 +57,21 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
                              const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st);
 
 // Object-order row-factored update with the per-row x-DFT fused in (one workgroup per chunk
-// of kept frequencies sharing an x-frequency): d[j] += sum_r Ty[(v_y(j) y_r) mod sy] sum_c
-// w[j][c] T_r[v_x(j)][c], z as in launch_wiener.  rows.r[r] = (y_r, first index into order
-// and xs, frame count, 0) for r < nrows <= kRowSetMax; xs[i] is the scan x of frame order[i].
-// chunks[c] = (vx, first index into jlist, count <= max_chunk, 0).
+// of kept frequencies sharing an x-frequency): d[j] += sum_r E_sy(v_y(j) y_r) sum_c w[j][c]
+// T_r[v_x(j)][c] with T_r[vx][c] = sum_{frames b of row r} tscale E_sx(vx x_b) h[b][c],
+// E_s(m) = exp(-2 pi i m / s); z as in launch_wiener.  rows.r[r] = (y_r, first index into
+// order and xs, frame count, 0) for r < nrows <= kRowSetMax; xs[i] is the scan x of frame
+// order[i].  chunks[c] = (vx, first index into jv, count <= max_chunk <= 512, 0); jv[i] =
+// (j, v_y(j)).
 constexpr int kRowSetMax = 16;
 struct RowSet {
   int4 r[kRowSetMax];
 };
 size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
-                                int nrows, const float2* tx, int sx, const float2* ty, int sy, const int4* chunks,
-                                int nchunks, int max_chunk, const int* jlist, const int2* freqs, const float2* w,
-                                float2* d, float2* z, hipStream_t st);
+                                int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
+                                hipStream_t st);
 
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
 // = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,

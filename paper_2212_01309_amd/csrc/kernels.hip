@@ -52,6 +52,11 @@ __device__ inline float2 gload(const float2* p) {
   const f32x2 v = *(WDD_GLOBAL(f32x2))p;
   return make_float2(v.x, v.y);
 }
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+__device__ inline int2 gload(const int2* p) {
+  const i32x2 v = *(WDD_GLOBAL(i32x2))p;
+  return make_int2(v.x, v.y);
+}
 #undef WDD_GLOBAL
 
 // The batch's upload block (pinned host memory, read by workgroup 0 of the projection): the
@@ -388,6 +393,13 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
 // ---------------------------------------------------------------------------
 
 // (p mod s) for 0 <= p < 2^24 via a float reciprocal and one correction.
+// exp(-2 pi i m / s) * scale for 0 <= m < s, from the device's sincospi (no table gather).
+__device__ inline float2 twiddle(int m, int s, float scale) {
+  float sn, cs;
+  sincospif(2.0f * (float)m / (float)s, &sn, &cs);
+  return make_float2(cs * scale, -sn * scale);
+}
+
 __device__ inline int mod_small(int p, int s, float inv) {
   int qq = (int)((float)p * inv);
   int r = p - qq * s;
@@ -735,13 +747,12 @@ __device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
 
 // s = sum_r ph_r T_r over this lane's 4 entries (T_r from LDS)
 __device__ inline void phase_sum(float4& s0, float4& s1, const float4* __restrict__ lt, int q, int kq, int nrows,
-                                 const RowSet& rs, int vy, const float2* __restrict__ ty, int sy, bool py2,
-                                 float invy) {
+                                 const RowSet& rs, int vy, int sy, bool py2, float invy) {
   s0 = make_float4(0.f, 0.f, 0.f, 0.f);
   s1 = s0;
   for (int r = 0; r < nrows; ++r) {
     const int p = vy * rs.r[r].x;
-    const float2 ph = ty[py2 ? (p & (sy - 1)) : mod_small(p, sy, invy)];
+    const float2 ph = twiddle(py2 ? (p & (sy - 1)) : mod_small(p, sy, invy), sy, 1.0f);
     const float4 t0 = lt[(size_t)(r * q + kq) * 2], t1 = lt[(size_t)(r * q + kq) * 2 + 1];
     s0.x += ph.x * t0.x - ph.y * t0.y; s0.y += ph.x * t0.y + ph.y * t0.x;
     s0.z += ph.x * t0.z - ph.y * t0.w; s0.w += ph.x * t0.w + ph.y * t0.z;
@@ -765,11 +776,9 @@ __device__ inline void add4(float4& a, const float4 b) {
 __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __restrict__ h, int kpad,
                                                                  const int* __restrict__ order,
                                                                  const int* __restrict__ xs, RowSet rs, int nrows,
-                                                                 const float2* __restrict__ tx, int sx,
-                                                                 const float2* __restrict__ ty, int sy,
+                                                                 float tscale, int sx, int sy,
                                                                  const int4* __restrict__ chunks,
-                                                                 const int* __restrict__ jlist,
-                                                                 const int2* __restrict__ freqs,
+                                                                 const int2* __restrict__ jv,
                                                                  const float2* __restrict__ w,
                                                                  float2* __restrict__ d, float2* __restrict__ z,
                                                                  int max_chunk) {
@@ -787,11 +796,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   const bool px2 = (sx & (sx - 1)) == 0, py2 = (sy & (sy - 1)) == 0;
   const float invx = 1.0f / (float)sx, invy = 1.0f / (float)sy;
 
-  for (int i = tid; i < cnt; i += kFusedThreads) {
-    const int j = jlist[i0 + i];
-    lj[i] = j;
-    lvy[i] = freqs[j].x;
-  }
+  // this thread's (j, v_y) of the chunk (cnt <= kFusedThreads): loaded now, stored to LDS
+  // after phase 1, so that its round trip hides under phase 1's
+  int2 myjv = make_int2(0, 0);
+  if (tid < cnt) myjv = gload(jv + i0 + tid);
 
   // phase 1: T_r for this vx
   const float4* h4 = reinterpret_cast<const float4*>(h);
@@ -803,9 +811,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
       __syncthreads();
       if (tid < n) {
         const int at = row.y + f0 + tid;
-        const int p = vx * xs[at];
-        lw[tid] = tx[px2 ? (p & (sx - 1)) : mod_small(p, sx, invx)];
-        lb[tid] = order[at];
+        const int b = order[at], p = vx * xs[at];
+        lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+        lb[tid] = b;
       }
       __syncthreads();
       int i = grp;
@@ -832,6 +840,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     __syncthreads();
   }
 
+  if (tid < cnt) {
+    lj[tid] = myjv.x;
+    lvy[tid] = myjv.y;
+  }
+  __syncthreads();
+
   // phase 2: stream the chunk's frequencies, two per lane group per round with all their
   // loads issued first
   for (int i = grp; i < cnt; i += 2 * G) {
@@ -847,8 +861,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     }
     const int vya = lvy[i], vyb = two ? lvy[i + G] : vya;
     float4 sa0, sa1, sb0, sb1;
-    phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, ty, sy, py2, invy);
-    phase_sum(sb0, sb1, lt, q, kq, nrows, rs, vyb, ty, sy, py2, invy);
+    phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, sy, py2, invy);
+    phase_sum(sb0, sb1, lt, q, kq, nrows, rs, vyb, sy, py2, invy);
     float2 oa = cdot4(wa0, wa1, sa0, sa1), ob = cdot4(wb0, wb1, sb0, sb1);
     for (int off = q >> 1; off > 0; off >>= 1) {
       oa.x += __shfl_xor(oa.x, off, 64);
@@ -1233,13 +1247,14 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
 }
 
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
-                                int nrows, const float2* tx, int sx, const float2* ty, int sy, const int4* chunks,
-                                int nchunks, int max_chunk, const int* jlist, const int2* freqs, const float2* w,
-                                float2* d, float2* z, hipStream_t st) {
-  if (nrows < 1 || nrows > kRowSetMax || nchunks < 1) return hipErrorInvalidValue;
+                                int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
+                                hipStream_t st) {
+  if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
+    return hipErrorInvalidValue;
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
-                     tx, sx, ty, sy, chunks, jlist, freqs, w, d, z, max_chunk);
+                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk);
   return hipGetLastError();
 }
 
