@@ -67,7 +67,6 @@ constexpr int kRowSetMax = 16;
 struct RowSet {
   int4 r[kRowSetMax];
 };
-size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
