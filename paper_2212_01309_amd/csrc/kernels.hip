@@ -400,6 +400,15 @@ __device__ inline float2 twiddle(int m, int s, float scale) {
   return make_float2(cs * scale, -sn * scale);
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) in turn: workgroup b runs on
+// XCD b mod 8.  This maps b to the row it handles so that each XCD takes a contiguous
+// range of rows (a bijection of [0, n)); rows that share cache lines then share an L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_row(int b, int n) {
+  const int per = n / kXcds;
+  return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
+}
+
 __device__ inline int mod_small(int p, int s, float inv) {
   int qq = (int)((float)p * inv);
   int r = p - qq * s;
@@ -520,9 +529,9 @@ __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, 
 __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int len,
                                                   int log2len, const float2* __restrict__ e,
                                                   const float2* __restrict__ d0, float s_total, int final_scale,
-                                                  int in_sr, int in_sm, int out_sr, int out_sc) {
+                                                  int in_sr, int in_sm, int out_sr, int out_sc, int xcd_map) {
   extern __shared__ float2 lbuf[];  // [len] data, then [len / 2] twiddles (power-of-two lengths)
-  const int r = blockIdx.x, tid = threadIdx.x;
+  const int r = xcd_map ? xcd_row(blockIdx.x, gridDim.x) : (int)blockIdx.x, tid = threadIdx.x;
   const float2* src = in + (size_t)r * in_sr;
   float2* dst = out + (size_t)r * out_sr;
   float scale = 1.0f;
@@ -1207,8 +1216,11 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
     while ((1 << lg) < len) ++lg;
   }
   const size_t lds = (size_t)len * sizeof(float2) + (lg >= 0 ? (size_t)(len / 2) * sizeof(float2) : 0);
+  // grids of 64 Ki cells and more: rows per XCD in contiguous ranges (a column gather would
+  // otherwise bring every cache line into all 8 L2s); smaller grids gain nothing from it
+  const int xcd_map = (int64_t)rows * len >= 65536;
   hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale, in_sr,
-                     in_sm, out_sr, out_sc);
+                     in_sm, out_sr, out_sc, xcd_map);
   return hipGetLastError();
 }
 
