@@ -184,7 +184,11 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
 
 /* wdd_push followed by wdd_snapshot, with the same arguments and results.  When the
  * batch uses the row-factored update (it touches at most 16 scan rows), the Wiener
- * reduction is done in the same pass over the spectrum. */
+ * reduction is done in the same pass over the spectrum.  In object order with power-of-two
+ * scan sides (Sy <= 1024) the update also performs the first pass of the display's inverse
+ * DFT, split over its workgroups; the image then equals that of wdd_push + wdd_snapshot up
+ * to FP32 rounding (a different summation order), and a wdd_snapshot before the next push
+ * returns it again bit for bit. */
 wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
                              int32_t frames_on_device, float* out, int32_t out_on_device, uint64_t* frames_seen);
 

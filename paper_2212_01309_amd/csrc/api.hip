@@ -82,6 +82,11 @@ struct wdd_plan_impl {
   float tscale = 1.f;  // 1 / sqrt(sy sx), the unitary scan DFT's factor
   int4* chunks = nullptr;
   int32_t nchunks = 0, max_chunk = 0;
+  // object order: the update also leaves the display's first pass as nslot partial rows per
+  // v_x in `up` (sx * nslot * sy values); up_valid while they match the current D
+  float2* up = nullptr;
+  int32_t nslot = 1;
+  bool up_valid = false;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
@@ -290,11 +295,17 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     const int64_t pieces = (e - i + p->max_chunk - 1) / p->max_chunk;
     for (int64_t c = 0; c < pieces; ++c) {
       const int64_t b0 = i + (e - i) * c / pieces, b1 = i + (e - i) * (c + 1) / pieces;
-      chunks.push_back(make_int4(vx, (int32_t)b0, (int32_t)(b1 - b0), 0));
+      chunks.push_back(make_int4(vx, (int32_t)b0, (int32_t)(b1 - b0), (int32_t)c));
     }
+    p->nslot = std::max<int32_t>(p->nslot, (int32_t)pieces);
     i = e;
   }
   p->nchunks = (int32_t)chunks.size();
+  // partial display rows: power-of-two scan sides (the radix-2 passes), Sy up to the row the
+  // update's workgroup transforms in LDS, at most kMaxSlots chunks per v_x
+  const bool pow2 = (t.sy & (t.sy - 1)) == 0 && (t.sx & (t.sx - 1)) == 0;
+  const bool partial_rows = p->order_mode == WDD_ORDER_OBJECT && !p->fourier && pow2 && t.sy <= wdd::kDisplayRowMax &&
+                            p->nslot <= wdd::kMaxSlots;
   const std::vector<float2> ty = twiddles(t.sy, 1.0);
   const std::vector<float2> tx = twiddles(t.sx, 1.0 / std::sqrt((double)t.sy * (double)t.sx));
   const std::vector<float2> ey = twiddles(t.sy, 1.0);
@@ -350,6 +361,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     ALLOC(p->jv, jlist.size());
     ALLOC(p->chunks, chunks.size());
   }
+  if (partial_rows) ALLOC(p->up, (size_t)t.sx * p->nslot * t.sy);
   {
     char* fr = nullptr;
     if ((st = dalloc(p, &fr, (size_t)p->max_batch * p->frame_bytes)) != WDD_OK) return st;
@@ -392,6 +404,8 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   }
   if (p->acc) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), nfk * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), grid * 2, p->stream));
+  // slots that no chunk owns stay zero for the plan's life
+  if (p->up) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->up), (size_t)t.sx * p->nslot * t.sy * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
 
@@ -626,17 +640,22 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       WDD_HIP(p, stage_end(p, end));
     }
   } else if (object) {
-    // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D
+    // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D;
+    // before a snapshot the last pass also leaves the display's first pass in `up`
+    const bool rows_for_display = fuse_wiener && p->up;
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
+      float2* up_pass = rows_for_display && r0 + kFactorRows >= nrows ? p->up : nullptr;
       if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
       wdd::RowSet rs;
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
       WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
-                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->z, p->stream));
+                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->z, up_pass,
+                                           p->nslot, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
+    p->up_valid = rows_for_display;
   } else if (factored) {
     // per-row x-DFTs, then one pass over A (with the Wiener reduction when asked)
     wiener_done = fuse_wiener;
@@ -673,10 +692,19 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   float2* dst = out_on_device ? reinterpret_cast<float2*>(out) : p->pin_out;
   WDD_HIP(p, stage_begin(p, kDisplay, &end));
   // z is conj(D) stored [vx][vy]: transform its rows along vy (u = [vx][y], written in row
-  // order), then the columns of u along vx, each workgroup writing one whole output row
-  WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, p->sy, 1, p->sy, 1, p->stream));
-  WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, 1, p->sy,
-                                  p->sx, 1, p->stream));
+  // order), then the columns of u along vx, each workgroup writing one whole output row.
+  // When the object-order update has left the first pass as partial rows (up, [y][vx][slot]),
+  // the column pass sums each vx's partials as it reads them.
+  const float s_total = (float)((double)p->sy * p->sx);
+  if (p->up_valid) {
+    WDD_HIP(p, wdd::launch_dft_rows(p->up, dst, p->sy, p->sx, p->ex, p->d, s_total, 1, p->sx * p->nslot, p->nslot,
+                                    p->sx, 1, p->nslot, 1, p->stream));
+  } else {
+    WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, p->sy, 1, p->sy, 1, 1, 0,
+                                    p->stream));
+    WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, s_total, 1, 1, p->sy, p->sx, 1, 1, 0,
+                                    p->stream));
+  }
   WDD_HIP(p, stage_end(p, end));
   return WDD_OK;
 }
@@ -977,6 +1005,7 @@ wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes)
     WDD_HIP(p, hipMemcpyAsync(p->d, src, (size_t)p->n_freq * sizeof(float2), hipMemcpyHostToDevice, p->stream));
     WDD_HIP(p, wdd::launch_scatter_conj(p->d, p->freqs, p->n_freq, p->z, p->sy, p->stream));
   }
+  p->up_valid = false;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   p->frames_seen = hd.frames_seen;
   p->last_batch = 0;
@@ -990,6 +1019,7 @@ wdd_status wdd_reset(wdd_plan_t p) {
     WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), (size_t)p->sy * p->sx * 2, p->stream));
+  p->up_valid = false;
   p->frames_seen = 0;
   p->last_batch = 0;
   return WDD_OK;

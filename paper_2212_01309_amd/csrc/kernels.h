@@ -42,10 +42,13 @@ hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int
                          float2* z, int sy, hipStream_t st);
 
 // out[r * out_sr + c * out_sc] = scale * sum_m in[r * in_sr + m * in_sm] e[(m c) mod len] for
-// r < rows, c < len (see kernels.hip).
+// r < rows, c < len (see kernels.hip).  nslot > 1 (power-of-two len): each input value is the
+// sum of the nslot partials at slot_stride apart.
+constexpr int kMaxSlots = 8;         // partial display rows per x-frequency
+constexpr int kDisplayRowMax = 1024;  // longest row the object-order update transforms for the display
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
-                           float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc,
-                           hipStream_t st);
+                           float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc, int nslot,
+                           int slot_stride, hipStream_t st);
 
 // Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
 // Tx[(vx x_b) mod sx] h[b][c]; then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
@@ -61,8 +64,10 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
 // T_r[v_x(j)][c] with T_r[vx][c] = sum_{frames b of row r} tscale E_sx(vx x_b) h[b][c],
 // E_s(m) = exp(-2 pi i m / s); z as in launch_wiener.  rows.r[r] = (y_r, first index into
 // order and xs, frame count, 0) for r < nrows <= kRowSetMax; xs[i] is the scan x of frame
-// order[i].  chunks[c] = (vx, first index into jv, count <= max_chunk <= 512, 0); jv[i] =
-// (j, v_y(j)).
+// order[i].  chunks[c] = (vx, first index into jv, count <= max_chunk <= 512, slot < nslot);
+// jv[i] = (j, v_y(j)).  With up set (power-of-two sy <= kDisplayRowMax, nslot <= kMaxSlots),
+// up[(y sx + vx) nslot + slot] = sum_{j of chunk c} conj(d[j]) E_sy(v_y(j) y) after the update:
+// the display's first pass split over the chunks.
 constexpr int kRowSetMax = 16;
 struct RowSet {
   int4 r[kRowSetMax];
@@ -70,7 +75,7 @@ struct RowSet {
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
-                                hipStream_t st);
+                                float2* up, int nslot, hipStream_t st);
 
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
 // = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,

@@ -25,6 +25,8 @@ namespace {
 
 using wdd::RowSet;
 using wdd::kRowSetMax;
+using wdd::kDisplayRowMax;
+using wdd::kMaxSlots;
 
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -392,7 +394,6 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
 // from LDS tables built in FP64 on the host (Tx carries the 1/sqrt(S) factor).
 // ---------------------------------------------------------------------------
 
-// (p mod s) for 0 <= p < 2^24 via a float reciprocal and one correction.
 // exp(-2 pi i m / s) * scale for 0 <= m < s, from the device's sincospi (no table gather).
 __device__ inline float2 twiddle(int m, int s, float scale) {
   float sn, cs;
@@ -409,6 +410,7 @@ __device__ inline int xcd_row(int b, int n) {
   return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
 }
 
+// (p mod s) for 0 <= p < 2^24 via a float reciprocal and one correction.
 __device__ inline int mod_small(int p, int s, float inv) {
   int qq = (int)((float)p * inv);
   int r = p - qq * s;
@@ -519,17 +521,43 @@ __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, 
   }
 }
 
+// In-place radix-2 decimation-in-time FFT of buf[0 .. len) (stored in bit-reversed order)
+// with the twiddles tw[m] = E[m], m < len / 2, in LDS; the NT threads of the workgroup take
+// part, and every stage ends at a workgroup barrier.
+template <int NT>
+__device__ inline void lds_fft(float2* buf, const float2* tw, int len, int log2len, int tid) {
+  for (int s = 1; s <= log2len; ++s) {
+    const int half = 1 << (s - 1);
+    const int stride = len >> s;  // twiddle index step
+    for (int k = tid; k < len / 2; k += NT) {
+      const int grp = k >> (s - 1), p = k & (half - 1);
+      const int i0 = grp * (half << 1) + p, i1 = i0 + half;
+      const float2 t = tw[p * stride];
+      const float2 x1 = buf[i1], x0 = buf[i0];
+      const float2 tt = make_float2(t.x * x1.x - t.y * x1.y, t.x * x1.y + t.y * x1.x);
+      buf[i0] = make_float2(x0.x + tt.x, x0.y + tt.y);
+      buf[i1] = make_float2(x0.x - tt.x, x0.y - tt.y);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Forward DFT of each of `rows` rows of length len:
 //   out[r * out_sr + c * out_sc] = scale * sum_m in[r * in_sr + m * in_sm] * E[(m c) mod len],
 // E[m] = exp(-2 pi i m / len) built in FP64 on the host.  Power-of-two lengths use an
 // in-LDS radix-2 decimation-in-time FFT with the twiddles staged in LDS, others a direct
-// sum.  With `final_scale` set, scale = 1 / sqrt(S |D[0]|) (0 when D[0] = 0).
+// sum.  With `final_scale` set, scale = 1 / sqrt(S |D[0]|) (0 when D[0] = 0).  SLOTS
+// (launched for nslot > 1, power-of-two lengths only): each input value is the sum of the
+// nslot partials in[r * in_sr + m * in_sm + s * slot_stride], s < nslot <= kMaxSlots, added
+// in order of s.
 // ---------------------------------------------------------------------------
+template <bool SLOTS>
 __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int len,
                                                   int log2len, const float2* __restrict__ e,
                                                   const float2* __restrict__ d0, float s_total, int final_scale,
-                                                  int in_sr, int in_sm, int out_sr, int out_sc, int xcd_map) {
+                                                  int in_sr, int in_sm, int out_sr, int out_sc, int xcd_map,
+                                                  int nslot, int slot_stride) {
   extern __shared__ float2 lbuf[];  // [len] data, then [len / 2] twiddles (power-of-two lengths)
   const int r = xcd_map ? xcd_row(blockIdx.x, gridDim.x) : (int)blockIdx.x, tid = threadIdx.x;
   const float2* src = in + (size_t)r * in_sr;
@@ -542,7 +570,32 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
   }
   if (log2len >= 0) {
     float2* ltw = lbuf + len;
-    for (int base = 0; base < len; base += 8 * 256) {  // loads first, then the bit-reversed stores
+    if (SLOTS) {  // the partials of two values of m per thread: all loads first, then the sums in order
+      for (int base = 0; base < len; base += 2 * 256) {
+        float2 v[2][kMaxSlots];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int m = base + u * 256 + tid;
+#pragma unroll
+          for (int q = 0; q < kMaxSlots; ++q)
+            if (m < len && q < nslot) v[u][q] = gload(src + (size_t)m * in_sm + (size_t)q * slot_stride);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int m = base + u * 256 + tid;
+          if (m >= len) continue;
+          float2 a = v[u][0];
+#pragma unroll
+          for (int q = 1; q < kMaxSlots; ++q)
+            if (q < nslot) {
+              a.x += v[u][q].x;
+              a.y += v[u][q].y;
+            }
+          lbuf[log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0] = a;
+        }
+      }
+    }
+    for (int base = 0; !SLOTS && base < len; base += 8 * 256) {  // loads first, then the bit-reversed stores
       float2 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -557,20 +610,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
     }
     stage_copy<4>(ltw, e, len / 2, tid, 256);
     __syncthreads();
-    for (int s = 1; s <= log2len; ++s) {
-      const int half = 1 << (s - 1);
-      const int stride = len >> s;  // twiddle index step
-      for (int k = tid; k < len / 2; k += 256) {
-        const int grp = k >> (s - 1), p = k & (half - 1);
-        const int i0 = grp * (half << 1) + p, i1 = i0 + half;
-        const float2 tw = ltw[p * stride];
-        const float2 x1 = lbuf[i1], x0 = lbuf[i0];
-        const float2 tt = make_float2(tw.x * x1.x - tw.y * x1.y, tw.x * x1.y + tw.y * x1.x);
-        lbuf[i0] = make_float2(x0.x + tt.x, x0.y + tt.y);
-        lbuf[i1] = make_float2(x0.x - tt.x, x0.y - tt.y);
-      }
-      __syncthreads();
-    }
+    lds_fft<256>(lbuf, ltw, len, log2len, tid);
     for (int c = tid; c < len; c += 256) {
       const float2 v = lbuf[c];
       dst[(size_t)c * out_sc] = make_float2(v.x * scale, v.y * scale);
@@ -741,13 +781,21 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
 // in LDS (the x-DFT restricted to its own vx), then streams its frequencies once:
 //   D[j] += sum_r Ty[(vy y_r) mod Sy] sum_k W[j][k] T_r[k];  z = conj(D)
 // (object order: the Wiener filter applied to every frame's contribution).
-// Phase 1 splits the frames over G = 1024 / kpad groups of kpad / 4 threads (4
+// Phase 1 splits the frames over G = 2048 / kpad groups of kpad / 4 threads (4
 // consecutive k each, float4 loads of h) and sums the groups in LDS; phase 2 gives each
 // frequency kpad / 4 consecutive lanes (4 entries each), G frequencies at a time.
+// With `up` set the workgroup also takes its share of the display's first pass (the DFT
+// along v_y of z = conj(D), power-of-two Sy <= 1024): the zero-padded row holding only
+// its own frequencies, transformed in LDS, goes to up[y][vx][chunks[b].w] ([Sy][Sx][nslot],
+// so that the display's column pass reads each output row's inputs contiguously), and that
+// pass sums the nslot partials of each vx.
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 512;
 constexpr int kFusedFrames = 512;  // frames staged in LDS per round of phase 1
 static_assert(kFusedFrames <= kFusedThreads, "phase 1 stages one frame per thread");
+static_assert(kDisplayRowMax / 2 <= kFusedThreads, "one display twiddle per thread");
+static_assert(kDisplayRowMax <= (1 << 24), "twiddle arguments stay exact in float");
+static_assert(kDisplayRowMax * 3 / 2 <= kFusedThreads * 4, "a display row and its twiddles fit the group sums");
 
 __device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
   a0.x += c.x * h.x; a0.y += c.y * h.x; a0.z += c.x * h.y; a0.w += c.y * h.y;
@@ -790,7 +838,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                                                                  const int2* __restrict__ jv,
                                                                  const float2* __restrict__ w,
                                                                  float2* __restrict__ d, float2* __restrict__ z,
-                                                                 int max_chunk) {
+                                                                 int max_chunk, float2* __restrict__ up, int nslot,
+                                                                 int log2sy) {
   extern __shared__ float4 fsm[];
   const int q = kpad >> 2, G = kFusedThreads / q;
   const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
@@ -800,7 +849,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   int* lb = reinterpret_cast<int*>(lw + kFusedFrames);        // [kFusedFrames] their batch indices
   int* lj = lb + kFusedFrames;                                // [max_chunk] the chunk's frequencies
   int* lvy = lj + max_chunk;                                  // [max_chunk] their y-frequencies
-  const int4 ch = chunks[blockIdx.x];
+  // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
+  // share cache lines) run on one XCD, so partly written lines meet in one L2
+  const int4 ch = chunks[xcd_row(blockIdx.x, gridDim.x)];
   const int vx = ch.x, i0 = ch.y, cnt = ch.z;
   const bool px2 = (sx & (sx - 1)) == 0, py2 = (sy & (sy - 1)) == 0;
   const float invx = 1.0f / (float)sx, invy = 1.0f / (float)sy;
@@ -853,6 +904,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     lj[tid] = myjv.x;
     lvy[tid] = myjv.y;
   }
+  // display row (with up): the group sums are free now, so the row is cleared and its
+  // twiddles formed here; phase 2 drops each conj D into its bit-reversed slot
+  float2* lrow = reinterpret_cast<float2*>(lsum);  // [sy], then the twiddles [sy / 2]
+  float2* ltw = lrow + sy;
+  if (up) {
+    for (int m = tid; m < sy; m += kFusedThreads) lrow[m] = make_float2(0.f, 0.f);
+    if (tid < sy / 2) ltw[tid] = twiddle(tid, sy, 1.0f);
+  }
   __syncthreads();
 
   // phase 2: stream the chunk's frequencies, two per lane group per round with all their
@@ -883,12 +942,22 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
       const float2 na = make_float2(da.x + oa.x, da.y + oa.y);
       d[ja] = na;
       z[(size_t)vx * sy + vya] = make_float2(na.x, -na.y);
+      if (up) lrow[log2sy ? (int)(__brev((unsigned)vya) >> (32 - log2sy)) : 0] = make_float2(na.x, -na.y);
       if (two) {
         const float2 nb = make_float2(db.x + ob.x, db.y + ob.y);
         d[jb] = nb;
         z[(size_t)vx * sy + vyb] = make_float2(nb.x, -nb.y);
+        if (up) lrow[log2sy ? (int)(__brev((unsigned)vyb) >> (32 - log2sy)) : 0] = make_float2(nb.x, -nb.y);
       }
     }
+  }
+
+  if (up) {  // the chunk's partial row of the display's first pass
+    __syncthreads();
+    lds_fft<kFusedThreads>(lrow, ltw, sy, log2sy, tid);
+    const size_t ustride = (size_t)sx * nslot;
+    float2* dst = up + (size_t)vx * nslot + ch.w;
+    for (int m = tid; m < sy; m += kFusedThreads) dst[m * ustride] = lrow[m];
   }
 }
 
@@ -1209,18 +1278,23 @@ hipError_t launch_wiener(const float2* acc, const float2* w, int kpad, const int
 
 hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, const float2* e, const float2* d0,
                            float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc,
-                           hipStream_t st) {
+                           int nslot, int slot_stride, hipStream_t st) {
   int lg = -1;
   if ((len & (len - 1)) == 0) {
     lg = 0;
     while ((1 << lg) < len) ++lg;
   }
+  if (nslot < 1 || nslot > kMaxSlots || (nslot > 1 && lg < 0)) return hipErrorInvalidValue;
   const size_t lds = (size_t)len * sizeof(float2) + (lg >= 0 ? (size_t)(len / 2) * sizeof(float2) : 0);
   // grids of 64 Ki cells and more: rows per XCD in contiguous ranges (a column gather would
   // otherwise bring every cache line into all 8 L2s); smaller grids gain nothing from it
   const int xcd_map = (int64_t)rows * len >= 65536;
-  hipLaunchKernelGGL(k_dft_rows, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale, in_sr,
-                     in_sm, out_sr, out_sc, xcd_map);
+  if (nslot > 1)
+    hipLaunchKernelGGL(k_dft_rows<true>, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale,
+                       in_sr, in_sm, out_sr, out_sc, xcd_map, nslot, slot_stride);
+  else
+    hipLaunchKernelGGL(k_dft_rows<false>, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale,
+                       in_sr, in_sm, out_sr, out_sc, xcd_map, 1, 0);
   return hipGetLastError();
 }
 
@@ -1261,12 +1335,18 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
-                                hipStream_t st) {
+                                float2* up, int nslot, hipStream_t st) {
   if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
     return hipErrorInvalidValue;
+  int log2sy = 0;
+  if (up) {  // the partial rows need a power-of-two Sy whose row and twiddles fit the group-sum buffer
+    while ((1 << log2sy) < sy) ++log2sy;
+    if ((1 << log2sy) != sy || sy > kDisplayRowMax || nslot < 1 || nslot > kMaxSlots)
+      return hipErrorInvalidValue;
+  }
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
-                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk);
+                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk, up, nslot, log2sy);
   return hipGetLastError();
 }
 

@@ -95,3 +95,39 @@ def test_object_order_host_frames_and_float32():
     live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
     live.push(frames, pos)
     assert rel(got, live.snapshot()) <= 1e-5
+
+
+@pytest.mark.parametrize("radius,sy,sx,n,k,rows", [(8.0, 64, 64, 32, 64, 3), (8.0, 64, 32, 32, 36, 20),
+                                                   (8.0, 32, 128, 32, 64, 1), (4.0, 256, 16, 16, 20, 2)])
+def test_display_rows_left_by_the_update(radius, sy, sx, n, k, rows):
+    """Before a snapshot the object-order update also leaves the display's first pass (the
+    DFT along v_y) as one partial row per chunk of frequencies, and the column pass sums
+    them.  The image must match the two-pass display of the same D and the oracle, in
+    every case: 2 to 4 chunks per v_x, two row passes (20 rows), Sx > Sy, and a tall scan
+    whose 16 chunks per v_x exceed what the column pass sums (the two-pass display)."""
+    rng = np.random.default_rng(1000 + sy + sx + rows)
+    b = 200
+    ys = rng.choice(sy, size=rows, replace=False)
+    pos = np.stack([ys[rng.integers(0, rows, size=b)], rng.integers(0, sx, size=b)], axis=1).astype(np.int32)
+    frames = rng.poisson(15.0, size=(b, n, n)).astype(np.uint16)
+    dev = device(frames)
+    errs = []
+    with wdd.Plan(radius, sy, sx, n, n, k, max_batch=b, order=wdd.WDD_ORDER_OBJECT) as a, \
+            wdd.Plan(radius, sy, sx, n, n, k, max_batch=b, order=wdd.WDD_ORDER_OBJECT) as two:
+        for part in (slice(0, 120), slice(120, 200)):
+            got = a.push_snapshot(dev[part], pos[part])
+            two.push(dev[part], pos[part])
+            ref = two.snapshot()
+            errs.append(rel(got, ref))
+            assert np.array_equal(a.spectrum(), two.spectrum())
+        # a snapshot with no push in between reads the same partial rows
+        assert np.array_equal(a.snapshot(), got)
+        live = O.Live(O.make_plan(sy, sx, n, n, radius, k), "P")
+        live.push(frames, pos)
+        errs.append(rel(got, live.snapshot()))
+        # a plain push leaves them stale: both plans then take the two-pass display
+        a.push(dev[:7], pos[:7])
+        two.push(dev[:7], pos[:7])
+        assert np.array_equal(a.snapshot(), two.snapshot())
+    say(f"[order] display rows from the update, {sy}x{sx} scan, {rows} rows: vs two-pass, vs oracle {errs}")
+    assert max(errs[:2]) <= 1e-6 and errs[2] <= 1e-5
