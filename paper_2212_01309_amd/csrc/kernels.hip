@@ -849,6 +849,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   int* lb = reinterpret_cast<int*>(lw + kFusedFrames);        // [kFusedFrames] their batch indices
   int* lj = lb + kFusedFrames;                                // [max_chunk] the chunk's frequencies
   int* lvy = lj + max_chunk;                                  // [max_chunk] their y-frequencies
+  // the first staging block's frame indices and x positions depend on the kernel arguments
+  // only: their loads go out before anything waits for the chunk descriptor
+  int first_b = 0, first_x = 0;
+  if (tid < min(kFusedFrames, rs.r[0].z)) {
+    first_b = gload(order + rs.r[0].y + tid);
+    first_x = gload(xs + rs.r[0].y + tid);
+  }
   // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
   // share cache lines) run on one XCD, so partly written lines meet in one L2
   const int4 ch = chunks[xcd_row(blockIdx.x, gridDim.x)];
@@ -861,19 +868,26 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   int2 myjv = make_int2(0, 0);
   if (tid < cnt) myjv = gload(jv + i0 + tid);
 
-  // phase 1: T_r for this vx
+  // phase 1: T_r for this vx; the first block of frames is staged here, the others in the loop
+  if (tid < min(kFusedFrames, rs.r[0].z)) {
+    const int p = vx * first_x;
+    lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+    lb[tid] = first_b;
+  }
   const float4* h4 = reinterpret_cast<const float4*>(h);
   for (int r = 0; r < nrows; ++r) {
     const int4 row = rs.r[r];
     float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
     for (int f0 = 0; f0 < row.z; f0 += kFusedFrames) {
       const int n = min(kFusedFrames, row.z - f0);
-      __syncthreads();
-      if (tid < n) {
-        const int at = row.y + f0 + tid;
-        const int b = order[at], p = vx * xs[at];
-        lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
-        lb[tid] = b;
+      if (r != 0 || f0 != 0) {
+        __syncthreads();
+        if (tid < n) {
+          const int at = row.y + f0 + tid;
+          const int b = order[at], p = vx * xs[at];
+          lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+          lb[tid] = b;
+        }
       }
       __syncthreads();
       int i = grp;
