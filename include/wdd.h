@@ -46,6 +46,11 @@
 extern "C" {
 #endif
 
+/* A push call returns once its work is queued.  At most this many pushes of a plan are
+ * queued and not yet run: a push waits, if need be, until the one this many pushes
+ * earlier has been read. */
+#define WDD_MAX_PUSHES_IN_FLIGHT 64
+
 typedef enum {
   WDD_OK = 0,
   WDD_EINVAL = -1,   /* bad argument, size or option */
@@ -169,8 +174,8 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
  * and accumulation of the spectrum.
  *   frames  n x ny x nx values of the detector dtype; device memory if
  *           frames_on_device != 0 (must stay valid until the work completes:
- *           wdd_sync or the next wdd_snapshot), else host memory (copied before
- *           the call returns).
+ *           wdd_sync, a blocking snapshot, or WDD_MAX_PUSHES_IN_FLIGHT further
+ *           pushes), else host memory (copied before the call returns).
  *   pos_yx  host int32 [n][2] scan indices.
  * Batches whose frames lie on at most 16 scan rows are accumulated through the
  * Kronecker factorisation F = F_y (x) F_x (per-row x-DFT, then one pass over the

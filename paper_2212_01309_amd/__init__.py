@@ -7,6 +7,7 @@ pointers), host buffers as numpy arrays.  The library must have been built
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 from typing import Optional, Tuple
@@ -24,6 +25,7 @@ PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP1
 WDD_ORDER_SPECTRUM, WDD_ORDER_OBJECT = 0, 1
 WDD_BASIS_HERMITE_GAUSS, WDD_BASIS_FOURIER = 0, 1
 WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC = 0, 1, 2
+WDD_MAX_PUSHES_IN_FLIGHT = 64
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
 _STATUS_NAMES = {0: "WDD_OK", -1: "WDD_EINVAL", -2: "WDD_ENOMEM", -3: "WDD_ERANGE", -4: "WDD_EDEVICE",
@@ -248,6 +250,11 @@ class Plan:
         self._seen_ref = ctypes.byref(self._seen)
         self._addr_cache = {}
         self._pinned = None
+        # device tensors (frames, asynchronous outputs) of the latest calls: the plan's stream may
+        # still use them after the call returns (a temporary would go back to torch's allocator
+        # at once).  The library keeps at most WDD_MAX_PUSHES_IN_FLIGHT pushes queued, so holding
+        # that many covers every batch still in flight; sync() releases them.
+        self._held = collections.deque(maxlen=2 * WDD_MAX_PUSHES_IN_FLIGHT)
 
     # -- lifecycle ---------------------------------------------------------
     def close(self) -> None:
@@ -322,7 +329,8 @@ class Plan:
         _check(self._fn_push(self._h, ptr, pos, n, on_dev))
         if n:
             self._last_batch = n
-        del keep
+            if on_dev:
+                self._held.append(keep)
 
     def push_snapshot(self, frames, positions, out=None, wait: bool = True):
         """push() then snapshot() in one call (one pass over the spectrum when possible).
@@ -336,12 +344,15 @@ class Plan:
             kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
             _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, self._device_out(out), kind, self._seen_ref))
             res = out
+            if not wait:
+                self._held.append(out)
         else:
             res = self._host_out(out)
             _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, res.ctypes.data, 0, self._seen_ref))
         if n:
             self._last_batch = n
-        del keep
+            if on_dev and not wait:
+                self._held.append(keep)
         return res
 
     def _device_out(self, out) -> int:
@@ -358,6 +369,8 @@ class Plan:
         if out is not None and _is_device_tensor(out):
             kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
             _check(load_library().wdd_snapshot(self._h, self._device_out(out), kind, ctypes.byref(seen)))
+            if not wait:
+                self._held.append(out)
             return out
         host = self._host_out(out)
         _check(load_library().wdd_snapshot(self._h, host.ctypes.data, 0, ctypes.byref(seen)))
@@ -435,6 +448,7 @@ class Plan:
 
     def sync(self) -> None:
         _check(load_library().wdd_sync(self._h))
+        self._held.clear()
 
 
 class Server:

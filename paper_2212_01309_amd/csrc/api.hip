@@ -36,7 +36,13 @@
 
 namespace {
 
-constexpr int kRing = 4;         // pinned host staging slots for positions and frames
+// Pinned upload blocks (positions, row grouping, frame-address table) form a ring that the
+// projection kernel reads when it runs; a block is refilled only after the push that last
+// used it has been read.  Stream markers follow every mark_every-th push (an event per push
+// costs several microseconds of host time on a pipelined step).
+constexpr int kUploadSlots = WDD_MAX_PUSHES_IN_FLIGHT;  // most upload blocks in the ring
+constexpr size_t kUploadPinBudget = (size_t)8 << 20;    // pinned bytes the ring may take
+constexpr int kFrameSlots = 4;                          // pinned staging slots for host frames
 constexpr int kFactorRows = 16;  // batches touching at most this many scan rows use the row-factored update
 static_assert(kFactorRows <= wdd::kRowSetMax, "a row pass must fit the kernel-argument row set");
 constexpr int kMinChunk = 16, kMaxChunk = 512;  // kept frequencies per workgroup of the row-factored update
@@ -90,11 +96,16 @@ struct wdd_plan_impl {
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
-  char* pin_up[kRing] = {};
-  void* pin_frames[kRing] = {};
-  hipEvent_t ev[kRing] = {};
-  bool ev_live[kRing] = {};
-  int slot = 0;
+  int up_ring = 4, mark_every = 1;   // upload blocks in the ring; marker spacing in pushes
+  std::vector<char*> pin_up;         // [up_ring]
+  std::vector<hipEvent_t> marks;     // [up_ring / mark_every + 2]
+  std::vector<int64_t> mark_at;      // the push each marker follows (-1: none yet)
+  int64_t pushes = 0;                // pushes that carried frames
+  int64_t drained = -1;              // every push up to this one is known to have run
+  void* pin_frames[kFrameSlots] = {};
+  hipEvent_t fev[kFrameSlots] = {};
+  bool fev_live[kFrameSlots] = {};
+  int fslot = 0;
   float2* pin_out = nullptr;
   std::vector<void*> allocs;
 
@@ -197,10 +208,13 @@ void release(wdd_plan_s* p) {
   }
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
-  for (int i = 0; i < kRing; ++i) {
-    if (p->pin_up[i]) (void)hipHostFree(p->pin_up[i]);
+  for (char* b : p->pin_up)
+    if (b) (void)hipHostFree(b);
+  for (hipEvent_t e : p->marks)
+    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < kFrameSlots; ++i) {
     if (p->pin_frames[i]) (void)hipHostFree(p->pin_frames[i]);
-    if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    if (p->fev[i]) (void)hipEventDestroy(p->fev[i]);
   }
   if (p->pin_out) (void)hipHostFree(p->pin_out);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
@@ -409,10 +423,16 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
 
-  for (int i = 0; i < kRing; ++i) {
-    WDD_HIP(p, hipHostMalloc((void**)&p->pin_up[i], p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t),
-                             hipHostMallocDefault));
-    WDD_HIP(p, hipEventCreateWithFlags(&p->ev[i], hipEventDisableTiming));
+  {
+    const size_t slot_bytes = p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t);
+    p->up_ring = (int)std::max<size_t>(4, std::min<size_t>(kUploadSlots, kUploadPinBudget / slot_bytes));
+    p->mark_every = std::max(1, p->up_ring / 4);
+    p->pin_up.assign(p->up_ring, nullptr);
+    for (char*& b : p->pin_up) WDD_HIP(p, hipHostMalloc((void**)&b, slot_bytes, hipHostMallocDefault));
+    p->marks.assign(p->up_ring / p->mark_every + 2, nullptr);
+    p->mark_at.assign(p->marks.size(), -1);
+    for (hipEvent_t& e : p->marks) WDD_HIP(p, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t& e : p->fev) WDD_HIP(p, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   WDD_HIP(p, hipHostMalloc((void**)&p->pin_out, grid * sizeof(float2), hipHostMallocDefault));
   WDD_HIP(p, hipStreamSynchronize(p->stream));
@@ -521,8 +541,7 @@ namespace {
 // Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
 // reduction of the updated spectrum; *fused reports whether it did.
 wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device,
-                     bool fuse_wiener, bool* fused, bool drained_after = false,
-                     const uint64_t* frame_addrs = nullptr) {
+                     bool fuse_wiener, bool* fused, const uint64_t* frame_addrs = nullptr) {
   if (fused) *fused = false;
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
@@ -556,11 +575,20 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   const bool factored = passes || (int)p->host_rows.size() <= kFactorRows;
   const int nrows = factored ? (int)p->host_rows.size() : 0;
 
-  // reuse a pinned slot only after the copies that read it have run
-  const int s = p->slot;
-  p->slot = (p->slot + 1) % kRing;
-  if (p->ev_live[s]) WDD_HIP(p, hipEventSynchronize(p->ev[s]));
-  char* up = p->pin_up[s];
+  // the upload block of push i was last filled by push i - up_ring: wait, if that push may
+  // not have run yet, for the first stream marker at or after it
+  const int64_t push_no = p->pushes++;
+  char* up = p->pin_up[push_no % p->up_ring];
+  if (push_no >= p->up_ring && push_no - p->up_ring > p->drained) {
+    const int64_t last = push_no - p->up_ring;
+    const int64_t c = last + (p->mark_every - 1 - last % p->mark_every);
+    const size_t m = (size_t)(c / p->mark_every) % p->marks.size();
+    if (p->mark_at[m] == c)
+      WDD_HIP(p, hipEventSynchronize(p->marks[m]));
+    else
+      WDD_HIP(p, hipStreamSynchronize(p->stream));
+    p->drained = std::max(p->drained, c);
+  }
   std::memcpy(up, pos_yx, (size_t)n * sizeof(int2));
   size_t up_bytes = (size_t)n * sizeof(int2);
   if (factored) {
@@ -573,20 +601,25 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   }
   const void* fdev = frames;
   const uint64_t* ftab = nullptr;
+  int fs = -1;  // host-frame staging slot, if any
   if (frame_addrs) {  // frames scattered over device memory: the projection reads this pinned table
     uint64_t* tab = reinterpret_cast<uint64_t*>(up + p->upload_bytes);
     std::memcpy(tab, frame_addrs, (size_t)n * sizeof(uint64_t));
     ftab = tab;
   } else if (!frames_on_device) {
-    if (!p->pin_frames[s]) {
-      hipError_t e = hipHostMalloc(&p->pin_frames[s], (size_t)p->max_batch * p->frame_bytes, hipHostMallocDefault);
+    // host frames go through a pinned slot, refilled after the projection that read it
+    fs = p->fslot;
+    p->fslot = (p->fslot + 1) % kFrameSlots;
+    if (p->fev_live[fs]) WDD_HIP(p, hipEventSynchronize(p->fev[fs]));
+    if (!p->pin_frames[fs]) {
+      hipError_t e = hipHostMalloc(&p->pin_frames[fs], (size_t)p->max_batch * p->frame_bytes, hipHostMallocDefault);
       if (e != hipSuccess) {
-        p->pin_frames[s] = nullptr;
+        p->pin_frames[fs] = nullptr;
         return dev_fail(p, e, "hipHostMalloc");
       }
     }
-    std::memcpy(p->pin_frames[s], frames, (size_t)n * p->frame_bytes);
-    WDD_HIP(p, hipMemcpyAsync(p->frames, p->pin_frames[s], (size_t)n * p->frame_bytes, hipMemcpyHostToDevice,
+    std::memcpy(p->pin_frames[fs], frames, (size_t)n * p->frame_bytes);
+    WDD_HIP(p, hipMemcpyAsync(p->frames, p->pin_frames[fs], (size_t)n * p->frame_bytes, hipMemcpyHostToDevice,
                               p->stream));
     fdev = p->frames;
   }
@@ -610,13 +643,15 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
                                       p->kpad, p->h, up, p->upload, up_bytes, ftab, p->stream));
   }
   WDD_HIP(p, stage_end(p, end));
-  // slot s (pinned upload and frames) may be refilled once this point of the stream is reached;
-  // a caller that drains the stream before returning needs no marker
-  if (!drained_after) {
-    WDD_HIP(p, hipEventRecord(p->ev[s], p->stream));
-    p->ev_live[s] = true;
-  } else {
-    p->ev_live[s] = false;
+  // the pinned data of this push may be refilled once this point of the stream is reached
+  if (push_no % p->mark_every == p->mark_every - 1) {
+    const size_t m = (size_t)(push_no / p->mark_every) % p->marks.size();
+    WDD_HIP(p, hipEventRecord(p->marks[m], p->stream));
+    p->mark_at[m] = push_no;
+  }
+  if (fs >= 0) {
+    WDD_HIP(p, hipEventRecord(p->fev[fs], p->stream));
+    p->fev_live[fs] = true;
   }
   bool wiener_done = object;
   if (p->fourier) {
@@ -717,6 +752,7 @@ wdd_status snapshot_finish_impl(wdd_plan_s* p, float* out, int32_t out_on_device
     return WDD_OK;
   }
   WDD_HIP(p, hipStreamSynchronize(p->stream));
+  p->drained = p->pushes - 1;
   if (!out_on_device && reinterpret_cast<float2*>(out) != p->pin_out) std::memcpy(out, p->pin_out, grid * sizeof(float2));
   WDD_HIP(p, harvest(p));
   if (frames_seen) *frames_seen = p->frames_seen;
@@ -736,7 +772,7 @@ namespace wdd {
 
 wdd_status push_table(wdd_plan_t p, const uint64_t* frame_addrs, const int32_t* pos_yx, int32_t n, bool fuse_wiener,
                       bool* fused) {
-  return push_impl(p, nullptr, pos_yx, n, 1, fuse_wiener, fused, false, frame_addrs);
+  return push_impl(p, nullptr, pos_yx, n, 1, fuse_wiener, fused, frame_addrs);
 }
 
 wdd_status snapshot_enqueue(wdd_plan_t p, bool reduce) {
@@ -788,7 +824,7 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
   if (st != WDD_OK) return st;
   if ((st = check_out(out, out_on_device)) != WDD_OK) return st;
   bool fused = false;
-  st = push_impl(p, frames, pos_yx, n, frames_on_device, n > 0, &fused, /*drained_after=*/true);
+  st = push_impl(p, frames, pos_yx, n, frames_on_device, n > 0, &fused);
   if (st != WDD_OK) return st;
   return snapshot_impl(p, out, out_on_device, frames_seen, !fused);
 }
@@ -1029,6 +1065,7 @@ wdd_status wdd_sync(wdd_plan_t p) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
+  p->drained = p->pushes - 1;
   return WDD_OK;
 }
 

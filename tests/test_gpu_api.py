@@ -278,3 +278,46 @@ def test_profile_period_samples_one_push_in_n():
         with pytest.raises(wdd.WddError) as ei:
             plan.profile_period(0)
         assert ei.value.code == wdd.WDD_EINVAL
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_many_asynchronous_steps_keep_their_own_positions(order):
+    """More asynchronous push + snapshot steps than the library keeps in flight (the host
+    runs ahead of the GPU and must wait for pinned upload blocks to come free): each step
+    must still see its own positions, so the spectrum equals that of the same pushes made
+    one at a time, bit for bit."""
+    import torch
+    s, n, b, steps = 64, 32, 64, 3 * wdd.WDD_MAX_PUSHES_IN_FLIGHT
+    rng = np.random.default_rng(21 + order)
+    lin = rng.integers(0, s * s, size=b * steps)
+    pos = np.stack([lin // s, lin % s], axis=1).astype(np.int32)
+    dev = device(rng.poisson(30.0, size=(b * steps, n, n)).astype(np.uint16))
+    out = torch.empty((s, s), dtype=torch.complex64, device="cuda")
+    with wdd.Plan(8.0, s, s, n, n, 64, max_batch=b, order=order) as a, \
+            wdd.Plan(8.0, s, s, n, n, 64, max_batch=b, order=order) as one:
+        for i in range(steps):
+            a.push_snapshot(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b], out=out, wait=False)
+        for i in range(steps):
+            one.push(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+            one.sync()
+        a.sync()
+        if order == 0:  # A itself; D there is formed at a snapshot (in the update for a)
+            assert np.array_equal(a.accumulator(), one.accumulator())
+            one.snapshot()
+            assert rel(a.spectrum(), one.spectrum()) <= 1e-6
+        else:
+            assert np.array_equal(a.spectrum(), one.spectrum())
+        assert a.info().frames_seen == one.info().frames_seen == b * steps
+
+
+def test_temporary_device_frames_outlive_the_call():
+    """A device tensor made only for the call (freed when it returns) is held by the binding
+    until the plan's stream has read it, even while another plan allocates and pushes."""
+    frames, pos = _random_case(17, 8, 8, 16, 16, 10, wdd.WDD_F32)
+    for _ in range(3):
+        with wdd.Plan(4.0, 8, 8, 16, 16, 16, dtype=wdd.WDD_F32) as a, \
+                wdd.Plan(4.0, 8, 8, 16, 16, 16, dtype=wdd.WDD_F32) as b:
+            a.push(device(frames * 3), pos)
+            for _ in range(3):
+                b.push(device(frames), pos)
+            assert rel(b.accumulator(), a.accumulator()) <= 1e-6

@@ -88,3 +88,23 @@ def test_reduced_precision_needs_uint16_frames():
     with pytest.raises(wdd.WddError) as ei:
         wdd.Plan(8.0, 16, 16, 32, 32, 64, dtype=wdd.WDD_F32, precision="bf16")
     assert ei.value.code == wdd.WDD_EINVAL
+
+
+@pytest.mark.parametrize("ny,nx,dtype,mode", [(1024, 1024, wdd.WDD_U16, "fp32"), (1000, 1024, wdd.WDD_F32, "fp32"),
+                                              (520, 1024, wdd.WDD_U16, "fp16_hilo"), (256, 256, wdd.WDD_U16, "fp32")])
+def test_projection_of_large_detectors(ny, nx, dtype, mode):
+    """The projection's basis tables at the largest detectors: 1024 x 1024 leaves no room
+    in LDS for the bank-spreading row padding (unpadded tables), 1000 rows loop the waves
+    over 63 tiles with a partial last one, and 256 x 256 takes the padded tables."""
+    rng = np.random.default_rng(ny + nx)
+    n, k, radius = 3, 10, ny / 8.0
+    frames = (rng.poisson(30.0, size=(n, ny, nx)).astype(np.uint16) if dtype == wdd.WDD_U16
+              else rng.uniform(0.0, 4.0, size=(n, ny, nx)).astype(np.float32))
+    pos = np.array([[0, 1], [3, 2], [1, 3]], np.int32)
+    with wdd.Plan(radius, 4, 4, ny, nx, k, dtype=dtype, max_batch=n, precision=mode) as plan:
+        plan.push(device(frames), pos)
+        got = plan.projection()
+    oplan = O.make_plan(4, 4, ny, nx, radius, k)
+    err = rel(got, O.project(frames, oplan.phi))
+    say(f"[precision] projection {ny}x{nx} {mode}: {err:.2e}")
+    assert err <= (1e-6 if mode == "fp32" else BOUNDS[mode])

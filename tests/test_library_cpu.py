@@ -2,6 +2,7 @@
 declared symbol, the FP64 host tables agree with the oracle, and bad arguments
 are rejected."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -106,3 +107,14 @@ def test_fourier_plan_rejects_reduced_precision_before_touching_a_device():
     with pytest.raises(wdd.WddError) as ei:
         wdd.Plan(8.0, 16, 16, 32, 32, 1024, basis=wdd.WDD_BASIS_FOURIER, precision=wdd.WDD_BF16_HILO)
     assert ei.value.code == wdd.WDD_EINVAL
+
+
+def test_binding_constants_match_the_header():
+    """The binding's copy of the in-flight bound (it holds that many device tensors) and of
+    the enumerations must be the header's."""
+    import re
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "wdd.h")).read()
+    assert int(re.search(r"#define WDD_MAX_PUSHES_IN_FLIGHT (\d+)", text).group(1)) == wdd.WDD_MAX_PUSHES_IN_FLIGHT
+    for name in ("WDD_OUT_HOST", "WDD_OUT_DEVICE", "WDD_OUT_DEVICE_ASYNC", "WDD_ORDER_SPECTRUM", "WDD_ORDER_OBJECT",
+                 "WDD_BASIS_HERMITE_GAUSS", "WDD_BASIS_FOURIER"):
+        assert int(re.search(name + r" = (\d+)", text).group(1)) == getattr(wdd, name), name
