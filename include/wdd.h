@@ -296,6 +296,19 @@ wdd_status wdd_sync(wdd_plan_t p);
 /* Releases the plan (waits for its work first).  NULL is accepted. */
 wdd_status wdd_plan_destroy(wdd_plan_t p);
 
+/* Device memory for plans created after this call (tables, spectrum, grids, device
+ * staging; not pinned host buffers) comes from alloc(bytes, ctx) and goes back through
+ * release(ptr, ctx) when the plan is destroyed, after its stream has drained: a caller
+ * with its own pool (a framework's caching allocator) lends it to the library.
+ * alloc must return memory of the current device aligned to 256 bytes, or NULL; NULL
+ * makes the plan's creation fail with WDD_ENOMEM, unaligned memory is released again and
+ * WDD_EINVAL returned.  alloc = NULL restores hipMalloc / hipFree.  Process-wide and
+ * thread-safe; a plan keeps the allocator it was created with.  WDD_EINVAL if alloc is
+ * given without release. */
+typedef void* (*wdd_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*wdd_release_fn)(void* ptr, void* ctx);
+wdd_status wdd_set_allocator(wdd_alloc_fn alloc, wdd_release_fn release, void* ctx);
+
 /* ------------------------------------------------------------------------- */
 /* Serving: many concurrent acquisitions on one GPU.
  *

@@ -83,8 +83,12 @@ class ServerStats(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _SIGNATURES = {
     "wdd_last_error": (ctypes.c_char_p, []),
+    "wdd_set_allocator": (ctypes.c_int, [_ALLOC_FN, _RELEASE_FN, ctypes.c_void_p]),
     "wdd_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
     "wdd_tables_build": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
                                         ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(_P)]),
@@ -153,6 +157,42 @@ def load_library() -> ctypes.CDLL:
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+_allocator_refs = None  # the ctypes callbacks in use (kept alive while the library may call them)
+
+
+def set_allocator(alloc=None, release=None) -> None:
+    """Device memory for plans created from now on comes from alloc(nbytes) -> int device
+    address (0 if none) and goes back through release(address) (wdd_set_allocator); with
+    alloc None the library allocates with hipMalloc again.  Existing plans keep theirs."""
+    global _allocator_refs
+    if alloc is None:
+        _check(load_library().wdd_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None))
+        return
+    if release is None:
+        raise ValueError("an allocator needs a release function")
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:  # the library reports the failure as WDD_ENOMEM
+            return None
+
+    def _release(ptr, _ctx):
+        release(int(ptr))
+
+    refs = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+    _check(load_library().wdd_set_allocator(refs[0], refs[1], None))
+    # plans created with the previous callbacks release through them: keep every set alive
+    _allocator_refs = (refs, _allocator_refs)
+
+
+def use_torch_allocator() -> None:
+    """Plans created from now on take their device memory from torch's caching allocator
+    (one pool with the caller's tensors)."""
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n), torch.cuda.caching_allocator_delete)
 
 
 def _check(code: int) -> None:

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -108,6 +109,9 @@ struct wdd_plan_impl {
   int fslot = 0;
   float2* pin_out = nullptr;
   std::vector<void*> allocs;
+  wdd_alloc_fn alloc_fn = nullptr;  // the caller's device allocator when the plan was created
+  wdd_release_fn release_fn = nullptr;
+  void* alloc_ctx = nullptr;
 
   // stage timing (wdd_profile_*): events around launches, harvested when the stream is idle
   int32_t profile_mask = 0;  // bit i: time stage i (Stage enum)
@@ -145,6 +149,18 @@ template <typename T>
 wdd_status dalloc(wdd_plan_s* p, T** ptr, size_t count) {
   *ptr = nullptr;
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (p->alloc_fn) {
+    void* m = p->alloc_fn(bytes, p->alloc_ctx);
+    if (!m) return wdd::fail(WDD_ENOMEM, "the caller's allocator returned no memory for %zu bytes", bytes);
+    if (reinterpret_cast<uintptr_t>(m) % 256 != 0) {
+      p->release_fn(m, p->alloc_ctx);
+      return wdd::fail(WDD_EINVAL, "the caller's allocator returned memory not aligned to 256 bytes");
+    }
+    *ptr = static_cast<T*>(m);
+    p->allocs.push_back(m);
+    p->device_bytes += (int64_t)bytes;
+    return WDD_OK;
+  }
   hipError_t e = hipMalloc((void**)ptr, bytes);
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
     (void)hipGetLastError();
@@ -207,7 +223,12 @@ void release(wdd_plan_s* p) {
     p->ev_pool.push_back(x.e1);
   }
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  for (void* a : p->allocs) (void)hipFree(a);
+  for (void* a : p->allocs) {
+    if (p->release_fn)
+      p->release_fn(a, p->alloc_ctx);
+    else
+      (void)hipFree(a);
+  }
   for (char* b : p->pin_up)
     if (b) (void)hipHostFree(b);
   for (hipEvent_t e : p->marks)
@@ -485,11 +506,25 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
   return b;
 }
 
+// The process-wide device allocator that new plans take (wdd_set_allocator).
+std::mutex g_alloc_mu;
+wdd_alloc_fn g_alloc = nullptr;
+wdd_release_fn g_release = nullptr;
+void* g_alloc_ctx = nullptr;
+
+void current_allocator(wdd_alloc_fn* a, wdd_release_fn* r, void** ctx) {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  *a = g_alloc;
+  *r = g_release;
+  *ctx = g_alloc_ctx;
+}
+
 wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe, const wdd_scan* scan,
                                    const wdd_detector* det, const wdd_options& opts, void* hip_stream, wdd_plan_t* out) {
   *out = nullptr;
   wdd_plan_s* p = new (std::nothrow) wdd_plan_s();
   if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
+  current_allocator(&p->alloc_fn, &p->release_fn, &p->alloc_ctx);
   p->dtype = det->dtype;
   p->precision = opts.precision;
   p->order_mode = opts.order;
@@ -1058,6 +1093,15 @@ wdd_status wdd_reset(wdd_plan_t p) {
   p->up_valid = false;
   p->frames_seen = 0;
   p->last_batch = 0;
+  return WDD_OK;
+}
+
+wdd_status wdd_set_allocator(wdd_alloc_fn alloc, wdd_release_fn release, void* ctx) {
+  if (alloc && !release) return wdd::fail(WDD_EINVAL, "an allocator needs its release function");
+  std::lock_guard<std::mutex> lock(wdd::g_alloc_mu);
+  wdd::g_alloc = alloc;
+  wdd::g_release = alloc ? release : nullptr;
+  wdd::g_alloc_ctx = alloc ? ctx : nullptr;
   return WDD_OK;
 }
 

@@ -321,3 +321,37 @@ def test_temporary_device_frames_outlive_the_call():
             for _ in range(3):
                 b.push(device(frames), pos)
             assert rel(b.accumulator(), a.accumulator()) <= 1e-6
+
+
+def test_plans_take_device_memory_from_the_callers_allocator():
+    """wdd_set_allocator: a plan created under torch's caching allocator takes every device
+    buffer from it, gives each back when destroyed, and computes what a plan with its own
+    allocations does; an allocator that returns nothing makes creation fail cleanly."""
+    import torch
+    frames, pos = _random_case(23, 16, 16, 32, 32, 64, wdd.WDD_U16)
+    dev = device(frames)
+    live = {}
+
+    def alloc(n):
+        ptr = torch.cuda.caching_allocator_alloc(n)
+        live[ptr] = n
+        return ptr
+
+    def release(ptr):
+        del live[ptr]
+        torch.cuda.caching_allocator_delete(ptr)
+
+    try:
+        wdd.set_allocator(alloc, release)
+        with wdd.Plan(8.0, 16, 16, 32, 32, 64, order=wdd.WDD_ORDER_OBJECT) as lent:
+            assert len(live) > 5 and sum(live.values()) >= lent.info().device_bytes
+            got = lent.push_snapshot(dev, pos)
+        assert not live
+        wdd.set_allocator(lambda n: 0, lambda p: None)
+        with pytest.raises(wdd.WddError) as ei:
+            wdd.Plan(8.0, 16, 16, 32, 32, 64)
+        assert ei.value.code == wdd.WDD_ENOMEM
+    finally:
+        wdd.set_allocator(None)
+    with wdd.Plan(8.0, 16, 16, 32, 32, 64, order=wdd.WDD_ORDER_OBJECT) as own:
+        assert np.array_equal(own.push_snapshot(dev, pos), got)

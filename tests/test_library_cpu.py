@@ -118,3 +118,13 @@ def test_binding_constants_match_the_header():
     for name in ("WDD_OUT_HOST", "WDD_OUT_DEVICE", "WDD_OUT_DEVICE_ASYNC", "WDD_ORDER_SPECTRUM", "WDD_ORDER_OBJECT",
                  "WDD_BASIS_HERMITE_GAUSS", "WDD_BASIS_FOURIER"):
         assert int(re.search(name + r" = (\d+)", text).group(1)) == getattr(wdd, name), name
+
+
+def test_allocator_hook_arguments():
+    """wdd_set_allocator: an allocator without its release function is refused; setting and
+    clearing one needs no device."""
+    lib = wdd.load_library()
+    alloc = wdd._ALLOC_FN(lambda n, ctx: None)
+    assert lib.wdd_set_allocator(alloc, wdd._RELEASE_FN(), None) == wdd.WDD_EINVAL
+    assert lib.wdd_set_allocator(alloc, wdd._RELEASE_FN(lambda p, ctx: None), None) == wdd.WDD_OK
+    assert lib.wdd_set_allocator(wdd._ALLOC_FN(), wdd._RELEASE_FN(), None) == wdd.WDD_OK
