@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--profile-period", type=int, default=8,
                     help="time the dominant stage with HIP events on one step in every N of the timed region")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
+    ap.add_argument("--display", default="deferred", choices=["deferred", "async"],
+                    help="pipelined steps: each image written by the next push's first launch (deferred) or "
+                         "queued at once (async)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
     ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the single acquisition")
@@ -300,7 +303,7 @@ def main():
 
     def step(i, wait=False):
         fr, ps = batches[i % nb]
-        plan.push_snapshot(fr, ps, out=shown, wait=wait)
+        plan.push_snapshot(fr, ps, out=shown, wait=wait, defer=not wait and args.display == "deferred")
 
     for i in range(args.warmup):
         step(i)
@@ -372,7 +375,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
-                   "wiener_order": args.order, "basis": args.basis, "display": "hbm"},
+                   "wiener_order": args.order, "basis": args.basis,
+                   "display": "hbm" + (", each image written in the next push's projection launch"
+                                       if args.display == "deferred" else "")},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "steps": nlat},
         "host_display_fps": host_fps,

@@ -203,8 +203,19 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *   WDD_OUT_DEVICE_ASYNC  device memory (8-byte aligned); returns once the work is
  *                         enqueued on the plan's stream.  `out` (which must stay valid)
  *                         is complete after wdd_sync, or once the plan's stream passes
- *                         this point; frames_seen then counts the frames enqueued. */
-typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2 } wdd_out_kind;
+ *                         this point; frames_seen then counts the frames enqueued.
+ *   WDD_OUT_DEVICE_DEFERRED  as WDD_OUT_DEVICE_ASYNC, except that the image (of this
+ *                         point's spectrum) may be written by the plan's next push, in
+ *                         the same launch as that push's projection (one kernel boundary
+ *                         fewer per pipelined step), or else by the next call that waits
+ *                         for the plan's stream or changes its state (wdd_snapshot,
+ *                         wdd_sync, wdd_get_*, wdd_profile_read, checkpoints,
+ *                         wdd_update_probe, wdd_reset, wdd_plan_destroy).  `out` is
+ *                         complete after wdd_sync.  Where the display cannot wait (spectrum
+ *                         order, the Fourier basis, reduced precision, scans whose sides
+ *                         are not powers of two, detectors of more than 128 rows) it is
+ *                         queued at once, as WDD_OUT_DEVICE_ASYNC. */
+typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2, WDD_OUT_DEVICE_DEFERRED = 3 } wdd_out_kind;
 
 /* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
  * conjugation and normalisation (eq. extract).  Writes sy x sx complex values

@@ -24,7 +24,7 @@ PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP1
               "fp16": WDD_FP16}
 WDD_ORDER_SPECTRUM, WDD_ORDER_OBJECT = 0, 1
 WDD_BASIS_HERMITE_GAUSS, WDD_BASIS_FOURIER = 0, 1
-WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC = 0, 1, 2
+WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC, WDD_OUT_DEVICE_DEFERRED = 0, 1, 2, 3
 WDD_MAX_PUSHES_IN_FLIGHT = 64
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
@@ -372,16 +372,17 @@ class Plan:
             if on_dev:
                 self._held.append(keep)
 
-    def push_snapshot(self, frames, positions, out=None, wait: bool = True):
+    def push_snapshot(self, frames, positions, out=None, wait: bool = True, defer: bool = False):
         """push() then snapshot() in one call (one pass over the spectrum when possible).
         With a device `out` and wait=False the call returns once the work is enqueued; `out`
-        is complete after sync()."""
+        is complete after sync().  defer=True (with wait=False) lets the image be written by
+        the next push's first launch (WDD_OUT_DEVICE_DEFERRED)."""
         pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
         if out is not None and out is self._pinned:
             res = out
             _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, self._pinned_addr, 0, self._seen_ref))
         elif out is not None and _is_device_tensor(out):
-            kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
+            kind = WDD_OUT_DEVICE if wait else (WDD_OUT_DEVICE_DEFERRED if defer else WDD_OUT_DEVICE_ASYNC)
             _check(self._fn_push_snapshot(self._h, ptr, pos, n, on_dev, self._device_out(out), kind, self._seen_ref))
             res = out
             if not wait:

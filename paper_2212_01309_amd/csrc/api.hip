@@ -94,6 +94,7 @@ struct wdd_plan_impl {
   float2* up = nullptr;
   int32_t nslot = 1;
   bool up_valid = false;
+  float2* deferred_dst = nullptr;  // a display from `up` left to the next push (WDD_OUT_DEVICE_DEFERRED)
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
@@ -246,6 +247,31 @@ wdd_status check_usable(wdd_plan_s* p) {
   if (!p) return wdd::fail(WDD_EINVAL, "null plan");
   if (p->failed) return wdd::fail(WDD_ESTATE, "plan is unusable after an earlier device error");
   return WDD_OK;
+}
+
+// The display's column pass from the partial rows the object-order update left in `up`.
+wdd_status display_from_partials(wdd_plan_s* p, float2* dst) {
+  WDD_HIP(p, wdd::launch_dft_rows(p->up, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1,
+                                  p->sx * p->nslot, p->nslot, p->sx, 1, p->nslot, 1, p->stream));
+  return WDD_OK;
+}
+
+// A deferred display can ride in the next push's projection launch (the FP32 Hermite-Gauss
+// projection kernel); the partial rows exist only for power-of-two scan sides.  Detectors of
+// more than 128 rows keep it in its own launch: their 1024-thread projection workgroups
+// (one wave per 16 rows) would carry the display rows too, and the merged launch then took
+// longer than the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
+bool can_defer(const wdd_plan_s* p) {
+  return p->up_valid && !p->fourier && p->precision == WDD_FP32 && p->ny <= 128;
+}
+
+// Writes a display left to the next push now; every call that waits for the plan's stream
+// or changes its state goes through here first.
+wdd_status flush_deferred(wdd_plan_s* p) {
+  if (!p->deferred_dst) return WDD_OK;
+  float2* dst = p->deferred_dst;
+  p->deferred_dst = nullptr;
+  return display_from_partials(p, dst);
 }
 
 // Round to the nearest bf16 / fp16 (ties to even); returns the 16-bit pattern and the value.
@@ -664,12 +690,24 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   }
   p->profile_now = (p->profile_tick++ % p->profile_period) == 0;
   hipEvent_t end;
+  if (p->fourier || p->precision != WDD_FP32) {  // a deferred display rides only in the FP32 projection
+    if ((st = flush_deferred(p)) != WDD_OK) return st;
+  }
   WDD_HIP(p, stage_begin(p, kProject, &end));
   // the projection kernel also brings the pinned upload block (positions, grouping) to the device
   if (p->fourier) {
     WDD_HIP(p, wdd::launch_project_fourier(p->dtype, fdev, n, p->ny, p->nx, p->fy, p->fx,
                                            reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
                                            p->stream));
+  } else if (p->precision == WDD_FP32 && p->deferred_dst) {
+    // the previous step's display rides in this launch (it reads `up` and D before this
+    // push's update changes them)
+    float2* dst = p->deferred_dst;
+    p->deferred_dst = nullptr;
+    WDD_HIP(p, wdd::launch_project_display(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up,
+                                           p->upload, up_bytes, ftab, p->up, dst, p->sy, p->sx, p->ex, p->d,
+                                           (float)((double)p->sy * p->sx), p->sx * p->nslot, p->nslot, p->sx, 1,
+                                           p->nslot, 1, p->stream));
   } else if (p->precision == WDD_FP32) {
     WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
                                    up_bytes, ftab, p->stream));
@@ -752,6 +790,12 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
 // Queues the display step (optionally after the Wiener reduction) writing to `out`.
 wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_device, bool reduce) {
   hipEvent_t end;
+  wdd_status st = flush_deferred(p);
+  if (st != WDD_OK) return st;
+  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && can_defer(p)) {  // written by the next push's first launch
+    p->deferred_dst = reinterpret_cast<float2*>(out);
+    return WDD_OK;
+  }
   if (reduce && p->order_mode == WDD_ORDER_SPECTRUM) {  // object order keeps D current
     WDD_HIP(p, stage_begin(p, kWiener, &end));
     WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sy, p->stream));
@@ -767,8 +811,7 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   // the column pass sums each vx's partials as it reads them.
   const float s_total = (float)((double)p->sy * p->sx);
   if (p->up_valid) {
-    WDD_HIP(p, wdd::launch_dft_rows(p->up, dst, p->sy, p->sx, p->ex, p->d, s_total, 1, p->sx * p->nslot, p->nslot,
-                                    p->sx, 1, p->nslot, 1, p->stream));
+    if ((st = display_from_partials(p, dst)) != WDD_OK) return st;
   } else {
     WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, p->sy, 1, p->sy, 1, 1, 0,
                                     p->stream));
@@ -782,7 +825,7 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
 // Waits for the queued snapshot and copies it out of the pinned buffer if needed.
 wdd_status snapshot_finish_impl(wdd_plan_s* p, float* out, int32_t out_on_device, uint64_t* frames_seen) {
   const size_t grid = (size_t)p->sy * p->sx;
-  if (out_on_device == WDD_OUT_DEVICE_ASYNC) {
+  if (out_on_device == WDD_OUT_DEVICE_ASYNC || out_on_device == WDD_OUT_DEVICE_DEFERRED) {
     if (frames_seen) *frames_seen = p->frames_seen;
     return WDD_OK;
   }
@@ -839,7 +882,8 @@ wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int
 
 static wdd_status check_out(const float* out, int32_t out_on_device) {
   if (!out) return wdd::fail(WDD_EINVAL, "null output");
-  if (out_on_device != WDD_OUT_HOST && out_on_device != WDD_OUT_DEVICE && out_on_device != WDD_OUT_DEVICE_ASYNC)
+  if (out_on_device != WDD_OUT_HOST && out_on_device != WDD_OUT_DEVICE && out_on_device != WDD_OUT_DEVICE_ASYNC &&
+      out_on_device != WDD_OUT_DEVICE_DEFERRED)
     return wdd::fail(WDD_EINVAL, "out_on_device must be a wdd_out_kind");
   if (out_on_device && (reinterpret_cast<uintptr_t>(out) % 8) != 0)
     return wdd::fail(WDD_EINVAL, "device output must be 8-byte aligned");
@@ -883,6 +927,7 @@ wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out) {
 wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!d_out) return wdd::fail(WDD_EINVAL, "null output");
   return copy_rows(p, d_out, p->d, 1, (size_t)p->n_freq * sizeof(float2), (size_t)p->n_freq * sizeof(float2),
                    on_device);
@@ -891,6 +936,7 @@ wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device) {
 wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!a_out) return wdd::fail(WDD_EINVAL, "null output");
   if (!p->acc) return wdd::fail(WDD_ESTATE, "the object-order plan keeps no spectrum A");
   return copy_rows(p, a_out, p->acc, (size_t)p->n_freq, (size_t)p->k * sizeof(float2),
@@ -900,6 +946,7 @@ wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device) {
 wdd_status wdd_get_projection(wdd_plan_t p, float* h_out, int32_t on_device) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!h_out) return wdd::fail(WDD_EINVAL, "null output");
   if (p->last_batch == 0) return WDD_OK;
   const size_t esz = p->fourier ? sizeof(float2) : sizeof(float);
@@ -956,6 +1003,7 @@ wdd_status wdd_profile_period(wdd_plan_t p, int32_t period) {
 wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!out) return wdd::fail(WDD_EINVAL, "null output");
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   WDD_HIP(p, harvest(p));
@@ -990,6 +1038,7 @@ static wdd_status upload_wiener(wdd_plan_s* p, const wdd_tables_s& t) {
 wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!probe) return wdd::fail(WDD_EINVAL, "null probe");
   if (p->order_mode == WDD_ORDER_OBJECT)
     return wdd::fail(WDD_ESTATE, "object order applies the Wiener filter per frame; no spectrum to re-deconvolve");
@@ -1033,6 +1082,7 @@ wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes) {
 wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   size_t need = 0;
   wdd_checkpoint_size(p, &need);
   if (!host_buf || bytes < need) return wdd::fail(WDD_EINVAL, "checkpoint buffer needs %zu bytes", need);
@@ -1056,6 +1106,7 @@ wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes) {
 wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   size_t need = 0;
   wdd_checkpoint_size(p, &need);
   if (!host_buf || bytes < need) return wdd::fail(WDD_EINVAL, "checkpoint image needs %zu bytes", need);
@@ -1086,6 +1137,7 @@ wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes)
 wdd_status wdd_reset(wdd_plan_t p) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (p->acc)
     WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
@@ -1108,12 +1160,14 @@ wdd_status wdd_set_allocator(wdd_alloc_fn alloc, wdd_release_fn release, void* c
 wdd_status wdd_sync(wdd_plan_t p) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   WDD_HIP(p, hipStreamSynchronize(p->stream));
   p->drained = p->pushes - 1;
   return WDD_OK;
 }
 
 wdd_status wdd_plan_destroy(wdd_plan_t p) {
+  if (p && !p->failed) (void)flush_deferred(p);  // a display left to a next push that will not come
   release(p);
   return WDD_OK;
 }

@@ -20,6 +20,15 @@ hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, 
                           int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
                           hipStream_t st);
 
+// launch_project, and in the same launch the column pass of a display from partial rows
+// (launch_dft_rows with nslot partials, final scale): workgroups past the n projections
+// each write one of `rows` output rows.  Power-of-two len.
+hipError_t launch_project_display(int dtype, const void* frames, int n, int ny, int nx, const float* psi,
+                                  const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
+                                  size_t up_bytes, const uint64_t* fptr, const float2* din, float2* dout, int rows,
+                                  int len, const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
+                                  int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st);
+
 // Reduced-precision form of launch_project for uint16 frames (precision = WDD_BF16_HILO,
 // WDD_FP16_HILO, WDD_BF16 or WDD_FP16).  psix_lp: [2][16][nx] bf16/fp16 words, the hi and
 // lo parts of psi_x * 2^shift (columns >= L zero); psi_unscale = 2^-shift.  psi holds the

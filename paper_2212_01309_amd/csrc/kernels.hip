@@ -28,6 +28,8 @@ using wdd::kRowSetMax;
 using wdd::kDisplayRowMax;
 using wdd::kMaxSlots;
 
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -147,14 +149,14 @@ struct Chunk<float> {
 // One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
 // more tiles than waves).  A wave first issues the loads of up to 8 chunks of 32
 // pixels per row (256 columns), then runs their MFMAs, so the loads of a tile are in
-// flight together.
+// flight together.  Frame b of the batch; smem: [ny + nx][16] tables, [waves][256]
+// partial G, [kpad] coefficient map.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
-                                                  const float* __restrict__ psi, const int* __restrict__ kmap,
-                                                  int kpad, float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                                  uint32_t* __restrict__ up_dst, int up_words,
-                                                  const uint64_t* __restrict__ fptr) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void project_frame(const T* __restrict__ frames, int ny, int nx,
+                                              const float* __restrict__ psi, const int* __restrict__ kmap, int kpad,
+                                              float* __restrict__ h, const uint32_t* __restrict__ up_src,
+                                              uint32_t* __restrict__ up_dst, int up_words,
+                                              const uint64_t* __restrict__ fptr, float* smem, int b) {
   const int nw = blockDim.x >> 6;
   float* lpsy = smem;               // [ny][16]
   float* lpsx = smem + ny * 16;     // [nx][16]
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   int* lkmap = reinterpret_cast<int*>(lg + nw * 256);  // [kpad]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // frame b: contiguous after `frames`, or at the address listed in fptr[b] (pinned host table)
-  const T* f = fptr ? reinterpret_cast<const T*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
+  const T* f = fptr ? reinterpret_cast<const T*>(fptr[b]) : frames + (size_t)b * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
   // loads of this wave's first chunk group go out before anything else
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
   }
   // the batch's positions / grouping live in pinned host memory; block 0 brings them over
   UploadWords upw;
-  const bool uploader = blockIdx.x == 0;
+  const bool uploader = b == 0;
   if (uploader) upload_issue(upw, up_src, up_words, tid, blockDim.x);
   stage_copy<8>(smem, psi, (ny + nx) * 16, tid, blockDim.x);
   stage_copy<1>(lkmap, kmap, kpad, tid, blockDim.x);
@@ -230,9 +232,20 @@ __global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, 
     float sum = 0.f;
     if (idx >= 0)
       for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
-    h[(size_t)blockIdx.x * kpad + k] = sum;
+    h[(size_t)b * kpad + k] = sum;
   }
 }
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
+                                                  const float* __restrict__ psi, const int* __restrict__ kmap,
+                                                  int kpad, float* __restrict__ h, const uint32_t* __restrict__ up_src,
+                                                  uint32_t* __restrict__ up_dst, int up_words,
+                                                  const uint64_t* __restrict__ fptr) {
+  extern __shared__ float smem[];
+  project_frame<T>(frames, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_words, fptr, smem, (int)blockIdx.x);
+}
+
 
 // Reduced-precision projection of uint16 frames.  Stage 1 runs on
 // v_mfma_f32_16x16x32_{bf16,f16}: the 8 consecutive pixels a lane loads are exactly
@@ -522,14 +535,13 @@ __global__ __launch_bounds__(256) void k_wiener(const float2* __restrict__ acc, 
 }
 
 // In-place radix-2 decimation-in-time FFT of buf[0 .. len) (stored in bit-reversed order)
-// with the twiddles tw[m] = E[m], m < len / 2, in LDS; the NT threads of the workgroup take
+// with the twiddles tw[m] = E[m], m < len / 2, in LDS; the nt threads of the workgroup take
 // part, and every stage ends at a workgroup barrier.
-template <int NT>
-__device__ inline void lds_fft(float2* buf, const float2* tw, int len, int log2len, int tid) {
+__device__ inline void lds_fft(float2* buf, const float2* tw, int len, int log2len, int tid, int nt) {
   for (int s = 1; s <= log2len; ++s) {
     const int half = 1 << (s - 1);
     const int stride = len >> s;  // twiddle index step
-    for (int k = tid; k < len / 2; k += NT) {
+    for (int k = tid; k < len / 2; k += nt) {
       const int grp = k >> (s - 1), p = k & (half - 1);
       const int i0 = grp * (half << 1) + p, i1 = i0 + half;
       const float2 t = tw[p * stride];
@@ -552,6 +564,54 @@ __device__ inline void lds_fft(float2* buf, const float2* tw, int len, int log2l
 // nslot partials in[r * in_sr + m * in_sm + s * slot_stride], s < nslot <= kMaxSlots, added
 // in order of s.
 // ---------------------------------------------------------------------------
+// One output row r of the display's column pass from partial rows: power-of-two len,
+// value m the sum of in[r * in_sr + m * in_sm + s * slot_stride] over s < nslot (added in
+// order of s), then the DFT along m and scale = 1 / sqrt(s_total |D[0]|) (0 when D[0] = 0):
+// out[r * out_sr + c * out_sc].  The nt threads of the workgroup; lbuf: [len] data and
+// [len / 2] twiddles in LDS.
+__device__ __forceinline__ void display_row_partials(const float2* __restrict__ in, float2* __restrict__ out, int len,
+                                                     int log2len, const float2* __restrict__ e,
+                                                     const float2* __restrict__ d0, float s_total, int in_sr,
+                                                     int in_sm, int out_sr, int out_sc, int nslot, int slot_stride,
+                                                     int r, float2* lbuf, int tid, int nt) {
+  const float2* src = in + (size_t)r * in_sr;
+  float2* dst = out + (size_t)r * out_sr;
+  const float2 dd = d0[0];
+  const float mag = sqrtf(dd.x * dd.x + dd.y * dd.y);
+  const float scale = mag > 0.f ? 1.0f / sqrtf(s_total * mag) : 0.f;
+  float2* ltw = lbuf + len;
+  for (int base = 0; base < len; base += 2 * nt) {  // two values of m per thread: all loads first, then the sums
+    float2 v[2][kMaxSlots];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int m = base + u * nt + tid;
+#pragma unroll
+      for (int q = 0; q < kMaxSlots; ++q)
+        if (m < len && q < nslot) v[u][q] = gload(src + (size_t)m * in_sm + (size_t)q * slot_stride);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int m = base + u * nt + tid;
+      if (m >= len) continue;
+      float2 a = v[u][0];
+#pragma unroll
+      for (int q = 1; q < kMaxSlots; ++q)
+        if (q < nslot) {
+          a.x += v[u][q].x;
+          a.y += v[u][q].y;
+        }
+      lbuf[log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0] = a;
+    }
+  }
+  stage_copy<4>(ltw, e, len / 2, tid, nt);
+  __syncthreads();
+  lds_fft(lbuf, ltw, len, log2len, tid, nt);
+  for (int c = tid; c < len; c += nt) {
+    const float2 v = lbuf[c];
+    dst[(size_t)c * out_sc] = make_float2(v.x * scale, v.y * scale);
+  }
+}
+
 template <bool SLOTS>
 __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int len,
                                                   int log2len, const float2* __restrict__ e,
@@ -560,6 +620,11 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
                                                   int nslot, int slot_stride) {
   extern __shared__ float2 lbuf[];  // [len] data, then [len / 2] twiddles (power-of-two lengths)
   const int r = xcd_map ? xcd_row(blockIdx.x, gridDim.x) : (int)blockIdx.x, tid = threadIdx.x;
+  if (SLOTS) {  // final_scale is set on this (the column) pass
+    display_row_partials(in, out, len, log2len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot, slot_stride, r,
+                         lbuf, tid, 256);
+    return;
+  }
   const float2* src = in + (size_t)r * in_sr;
   float2* dst = out + (size_t)r * out_sr;
   float scale = 1.0f;
@@ -570,32 +635,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
   }
   if (log2len >= 0) {
     float2* ltw = lbuf + len;
-    if (SLOTS) {  // the partials of two values of m per thread: all loads first, then the sums in order
-      for (int base = 0; base < len; base += 2 * 256) {
-        float2 v[2][kMaxSlots];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int m = base + u * 256 + tid;
-#pragma unroll
-          for (int q = 0; q < kMaxSlots; ++q)
-            if (m < len && q < nslot) v[u][q] = gload(src + (size_t)m * in_sm + (size_t)q * slot_stride);
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int m = base + u * 256 + tid;
-          if (m >= len) continue;
-          float2 a = v[u][0];
-#pragma unroll
-          for (int q = 1; q < kMaxSlots; ++q)
-            if (q < nslot) {
-              a.x += v[u][q].x;
-              a.y += v[u][q].y;
-            }
-          lbuf[log2len ? (int)(__brev((unsigned)m) >> (32 - log2len)) : 0] = a;
-        }
-      }
-    }
-    for (int base = 0; !SLOTS && base < len; base += 8 * 256) {  // loads first, then the bit-reversed stores
+    for (int base = 0; base < len; base += 8 * 256) {  // loads first, then the bit-reversed stores
       float2 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -610,7 +650,7 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
     }
     stage_copy<4>(ltw, e, len / 2, tid, 256);
     __syncthreads();
-    lds_fft<256>(lbuf, ltw, len, log2len, tid);
+    lds_fft(lbuf, ltw, len, log2len, tid, 256);
     for (int c = tid; c < len; c += 256) {
       const float2 v = lbuf[c];
       dst[(size_t)c * out_sc] = make_float2(v.x * scale, v.y * scale);
@@ -631,6 +671,28 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
       dst[(size_t)c * out_sc] = make_float2(re * scale, im * scale);
     }
   }
+}
+
+// One launch for two independent jobs: workgroups b < nproj project frame b of a batch,
+// the others each write one output row (b - nproj) of the previous step's displayed image
+// from its partial rows (display_row_partials).  Saves a kernel boundary per step when
+// the display of a step is left to the next push.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_project_display(
+    const T* __restrict__ frames, int ny, int nx, const float* __restrict__ psi, const int* __restrict__ kmap, int kpad,
+    float* __restrict__ h, const uint32_t* __restrict__ up_src, uint32_t* __restrict__ up_dst, int up_words,
+    const uint64_t* __restrict__ fptr, int nproj, const float2* __restrict__ din, float2* __restrict__ dout, int len,
+    int log2len, const float2* __restrict__ e, const float2* __restrict__ d0, float s_total, int in_sr, int in_sm,
+    int out_sr, int out_sc, int nslot, int slot_stride) {
+  extern __shared__ float4 msm[];
+  const int b = (int)blockIdx.x;
+  if (b < nproj) {
+    project_frame<T>(frames, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_words, fptr, reinterpret_cast<float*>(msm),
+                     b);
+    return;
+  }
+  display_row_partials(din, dout, len, log2len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot, slot_stride,
+                       b - nproj, reinterpret_cast<float2*>(msm), (int)threadIdx.x, (int)blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -968,7 +1030,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
 
   if (up) {  // the chunk's partial row of the display's first pass
     __syncthreads();
-    lds_fft<kFusedThreads>(lrow, ltw, sy, log2sy, tid);
+    lds_fft(lrow, ltw, sy, log2sy, tid, kFusedThreads);
     const size_t ustride = (size_t)sx * nslot;
     float2* dst = up + (size_t)vx * nslot + ch.w;
     for (int m = tid; m < sy; m += kFusedThreads) dst[m * ustride] = lrow[m];
@@ -1244,6 +1306,50 @@ hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, 
   return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, st);
 }
 
+template <typename T>
+hipError_t launch_project_display_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
+                                    int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes,
+                                    const uint64_t* fptr, const float2* din, float2* dout, int rows, int len,
+                                    const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
+                                    int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st) {
+  int lg = 0;
+  while ((1 << lg) < len) ++lg;
+  if (n < 1 || rows < 1 || (1 << lg) != len || nslot < 1 || nslot > kMaxSlots) return hipErrorInvalidValue;
+  const int ntiles = (ny + 15) / 16;
+  const int threads = std::max(64 * std::min(ntiles, 16), 256);
+  const size_t lds_proj = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)(threads / 64) * 256 * sizeof(float) +
+                          (size_t)kpad * sizeof(int);
+  const size_t lds_disp = (size_t)len * sizeof(float2) + (size_t)(len / 2) * sizeof(float2);
+  const size_t lds = std::max(lds_proj, lds_disp);
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t err = hipFuncSetAttribute((const void*)k_project_display<T>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    if (err != hipSuccess) return err;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_project_display<T>, dim3(n + rows), dim3(threads), lds, st, static_cast<const T*>(frames), ny,
+                     nx, psi, kmap, kpad, h, static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst),
+                     (int)(up_bytes / 4), fptr, n, din, dout, len, lg, e, d0, s_total, in_sr, in_sm, out_sr, out_sc,
+                     nslot, slot_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_display(int dtype, const void* frames, int n, int ny, int nx, const float* psi,
+                                  const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
+                                  size_t up_bytes, const uint64_t* fptr, const float2* din, float2* dout, int rows,
+                                  int len, const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
+                                  int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st) {
+  if (dtype == WDD_U16)
+    return launch_project_display_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr,
+                                              din, dout, rows, len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc,
+                                              nslot, slot_stride, st);
+  return launch_project_display_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, din,
+                                         dout, rows, len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot,
+                                         slot_stride, st);
+}
+
 hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
                              const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
                              const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
@@ -1298,7 +1404,7 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
     lg = 0;
     while ((1 << lg) < len) ++lg;
   }
-  if (nslot < 1 || nslot > kMaxSlots || (nslot > 1 && lg < 0)) return hipErrorInvalidValue;
+  if (nslot < 1 || nslot > kMaxSlots || (nslot > 1 && (lg < 0 || !final_scale))) return hipErrorInvalidValue;
   const size_t lds = (size_t)len * sizeof(float2) + (lg >= 0 ? (size_t)(len / 2) * sizeof(float2) : 0);
   // grids of 64 Ki cells and more: rows per XCD in contiguous ranges (a column gather would
   // otherwise bring every cache line into all 8 L2s); smaller grids gain nothing from it

@@ -260,7 +260,7 @@ def test_asynchronous_device_snapshots_match_blocking_ones(order):
         with pytest.raises(ValueError):
             a.snapshot(out=bad, wait=False)
         lib = wdd.load_library()
-        assert lib.wdd_snapshot(a._h, outs[0].data_ptr(), 3, None) == wdd.WDD_EINVAL
+        assert lib.wdd_snapshot(a._h, outs[0].data_ptr(), 4, None) == wdd.WDD_EINVAL
 
 
 def test_profile_period_samples_one_push_in_n():
@@ -355,3 +355,42 @@ def test_plans_take_device_memory_from_the_callers_allocator():
         wdd.set_allocator(None)
     with wdd.Plan(8.0, 16, 16, 32, 32, 64, order=wdd.WDD_ORDER_OBJECT) as own:
         assert np.array_equal(own.push_snapshot(dev, pos), got)
+
+
+@pytest.mark.parametrize("order,s,precision", [(1, 32, "fp32"), (0, 32, "fp32"), (1, 24, "fp32"), (1, 32, "bf16_hilo")])
+def test_deferred_device_snapshots_match_asynchronous_ones(order, s, precision):
+    """WDD_OUT_DEVICE_DEFERRED: the image is written by the next push's first launch (object
+    order, power-of-two scan, FP32 projection) or queued at once otherwise; either way each
+    output holds the image of its own point, bit for bit the asynchronous one, and a call
+    that waits for the stream or changes the state (inspection, checkpoint, reset,
+    destroy) writes a pending image first."""
+    import torch
+    n, b, steps = 32, 64, 8
+    frames, pos = _random_case(31 + s + order, s, s, n, n, b * (steps + 4), wdd.WDD_U16)
+    dev = device(frames)
+    blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+    img = lambda: torch.empty((s, s), dtype=torch.complex64, device="cuda")
+    outs = {True: [img() for _ in range(steps + 4)], False: [img() for _ in range(steps + 4)]}
+    kw = dict(max_batch=b, order=order, precision=precision)
+    with wdd.Plan(8.0, s, s, n, n, 64, **kw) as a, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        for i in range(steps):
+            a.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
+            r.push_snapshot(*blk(i), out=outs[False][i], wait=False)
+        a.sync()
+        r.sync()
+        for i in range(steps):
+            assert torch.equal(outs[True][i], outs[False][i]), i
+        # a pending image is written before an inspection, a checkpoint and a reset
+        for i, settle in zip(range(steps, steps + 3), (lambda p: p.spectrum(), lambda p: p.checkpoint(),
+                                                        lambda p: p.reset())):
+            a.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
+            r.push_snapshot(*blk(i), out=outs[False][i], wait=False)
+            settle(a)
+            settle(r)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[True][i], outs[False][i]), i
+        i = steps + 3
+        a.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
+        r.push_snapshot(*blk(i), out=outs[False][i], wait=False)
+    torch.cuda.synchronize()  # both plans destroyed: the pending image was written first
+    assert torch.equal(outs[True][i], outs[False][i])

@@ -115,7 +115,8 @@ def test_binding_constants_match_the_header():
     import re
     text = open(os.path.join(os.path.dirname(__file__), "..", "include", "wdd.h")).read()
     assert int(re.search(r"#define WDD_MAX_PUSHES_IN_FLIGHT (\d+)", text).group(1)) == wdd.WDD_MAX_PUSHES_IN_FLIGHT
-    for name in ("WDD_OUT_HOST", "WDD_OUT_DEVICE", "WDD_OUT_DEVICE_ASYNC", "WDD_ORDER_SPECTRUM", "WDD_ORDER_OBJECT",
+    for name in ("WDD_OUT_HOST", "WDD_OUT_DEVICE", "WDD_OUT_DEVICE_ASYNC", "WDD_OUT_DEVICE_DEFERRED", "WDD_ORDER_SPECTRUM",
+                 "WDD_ORDER_OBJECT",
                  "WDD_BASIS_HERMITE_GAUSS", "WDD_BASIS_FOURIER"):
         assert int(re.search(name + r" = (\d+)", text).group(1)) == getattr(wdd, name), name
 
