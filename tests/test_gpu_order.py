@@ -12,25 +12,42 @@ from gpu_util import device, rel, say
 pytestmark = pytest.mark.gpu
 
 
-def test_object_order_full_raster():
+@pytest.fixture(scope="module")
+def medium_raster():
+    """The medium workload's full raster and the oracle's object-order result for it."""
     wl = synth.WORKLOADS["medium"]
     pos = synth.raster_positions(wl.sy, wl.sx)
     frames = wl.frames(pos)
-    dev = device(frames)
     amp = wl.aperture_amplitude()
-    with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, amplitude=amp, max_batch=wl.batch,
+    live = O.Live(O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=amp), "P")
+    live.push(frames, pos)
+    return wl, pos, frames, live.spectrum(), live.snapshot()
+
+
+@pytest.mark.parametrize("mode", ["blocking", "deferred"])
+def test_object_order_full_raster(medium_raster, mode):
+    """Every batch through push_snapshot: blocking host images, or (as the bench drives it)
+    device images each written by the next push's first launch."""
+    import torch
+    wl, pos, frames, d_ref, o_ref = medium_raster
+    dev = device(frames)
+    shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
+    with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, amplitude=wl.aperture_amplitude(), max_batch=wl.batch,
                   order=wdd.WDD_ORDER_OBJECT) as plan:
         for b in range(0, len(pos), wl.batch):
-            o = plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch])
+            if mode == "blocking":
+                o = plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch])
+            else:
+                plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch], out=shown, wait=False, defer=True)
+        plan.sync()
+        if mode == "deferred":
+            o = shown.cpu().numpy()
         d = plan.spectrum()
         with pytest.raises(wdd.WddError) as ei:
             plan.accumulator()
         assert ei.value.code == wdd.WDD_ESTATE
-    op = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=amp)
-    live = O.Live(op, "P")
-    live.push(frames, pos)
-    errs = (rel(d, live.spectrum()), rel(o, live.snapshot()))
-    say(f"[order] object, medium full raster: D/O {errs}")
+    errs = (rel(d, d_ref), rel(o, o_ref))
+    say(f"[order] object, medium full raster, {mode} images: D/O {errs}")
     assert max(errs) <= 1e-5
 
 
