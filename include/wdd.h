@@ -211,9 +211,9 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *                         for the plan's stream or changes its state (wdd_snapshot,
  *                         wdd_sync, wdd_get_*, wdd_profile_read, checkpoints,
  *                         wdd_update_probe, wdd_reset, wdd_plan_destroy).  `out` is
- *                         complete after wdd_sync.  Where the display cannot wait (spectrum
- *                         order, the Fourier basis, reduced precision, scans whose sides
- *                         are not powers of two, detectors of more than 128 rows) it is
+ *                         complete after wdd_sync.  Where the display's last pass cannot
+ *                         wait (the Fourier basis, reduced precision, scans whose Sx is
+ *                         not a power of two, detectors of more than 128 rows) it is
  *                         queued at once, as WDD_OUT_DEVICE_ASYNC. */
 typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2, WDD_OUT_DEVICE_DEFERRED = 3 } wdd_out_kind;
 

@@ -94,7 +94,11 @@ struct wdd_plan_impl {
   float2* up = nullptr;
   int32_t nslot = 1;
   bool up_valid = false;
-  float2* deferred_dst = nullptr;  // a display from `up` left to the next push (WDD_OUT_DEVICE_DEFERRED)
+  // a display's column pass left to the next push (WDD_OUT_DEVICE_DEFERRED): destination
+  // and source (the partial rows in `up`, or the first pass's grid `u`)
+  float2* deferred_dst = nullptr;
+  const float2* deferred_src = nullptr;
+  int32_t deferred_sr = 0, deferred_sm = 0, deferred_nslot = 1, deferred_slot_stride = 0;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
 
@@ -249,20 +253,31 @@ wdd_status check_usable(wdd_plan_s* p) {
   return WDD_OK;
 }
 
-// The display's column pass from the partial rows the object-order update left in `up`.
-wdd_status display_from_partials(wdd_plan_s* p, float2* dst) {
-  WDD_HIP(p, wdd::launch_dft_rows(p->up, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1,
-                                  p->sx * p->nslot, p->nslot, p->sx, 1, p->nslot, 1, p->stream));
+// Where the display's column pass reads: the partial rows the object-order update left in
+// `up` ([y][vx][slot]), or the grid `u` ([vx][y]) of the first pass.
+void column_source(const wdd_plan_s* p, const float2** src, int32_t* sr, int32_t* sm, int32_t* nslot,
+                   int32_t* slot_stride) {
+  if (p->up_valid) {
+    *src = p->up, *sr = p->sx * p->nslot, *sm = p->nslot, *nslot = p->nslot, *slot_stride = 1;
+  } else {
+    *src = p->u, *sr = 1, *sm = p->sy, *nslot = 1, *slot_stride = 0;
+  }
+}
+
+wdd_status column_pass(wdd_plan_s* p, const float2* src, int32_t sr, int32_t sm, int32_t nslot, int32_t slot_stride,
+                       float2* dst) {
+  WDD_HIP(p, wdd::launch_dft_rows(src, dst, p->sy, p->sx, p->ex, p->d, (float)((double)p->sy * p->sx), 1, sr, sm, p->sx,
+                                  1, nslot, slot_stride, p->stream));
   return WDD_OK;
 }
 
-// A deferred display can ride in the next push's projection launch (the FP32 Hermite-Gauss
-// projection kernel); the partial rows exist only for power-of-two scan sides.  Detectors of
-// more than 128 rows keep it in its own launch: their 1024-thread projection workgroups
-// (one wave per 16 rows) would carry the display rows too, and the merged launch then took
-// longer than the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
+// A deferred column pass can ride in the next push's projection launch (the FP32
+// Hermite-Gauss projection kernel, radix-2 rows: power-of-two Sx).  Detectors of more than
+// 128 rows keep it in its own launch: their 1024-thread projection workgroups (one wave per
+// 16 rows) would carry the display rows too, and the merged launch then took longer than
+// the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
 bool can_defer(const wdd_plan_s* p) {
-  return p->up_valid && !p->fourier && p->precision == WDD_FP32 && p->ny <= 128;
+  return !p->fourier && p->precision == WDD_FP32 && p->ny <= 128 && (p->sx & (p->sx - 1)) == 0;
 }
 
 // Writes a display left to the next push now; every call that waits for the plan's stream
@@ -271,7 +286,8 @@ wdd_status flush_deferred(wdd_plan_s* p) {
   if (!p->deferred_dst) return WDD_OK;
   float2* dst = p->deferred_dst;
   p->deferred_dst = nullptr;
-  return display_from_partials(p, dst);
+  return column_pass(p, p->deferred_src, p->deferred_sr, p->deferred_sm, p->deferred_nslot, p->deferred_slot_stride,
+                     dst);
 }
 
 // Round to the nearest bf16 / fp16 (ties to even); returns the 16-bit pattern and the value.
@@ -700,14 +716,14 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
                                            reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
                                            p->stream));
   } else if (p->precision == WDD_FP32 && p->deferred_dst) {
-    // the previous step's display rides in this launch (it reads `up` and D before this
-    // push's update changes them)
+    // the previous step's column pass rides in this launch (it reads its source and D before
+    // this push's update changes them)
     float2* dst = p->deferred_dst;
     p->deferred_dst = nullptr;
     WDD_HIP(p, wdd::launch_project_display(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up,
-                                           p->upload, up_bytes, ftab, p->up, dst, p->sy, p->sx, p->ex, p->d,
-                                           (float)((double)p->sy * p->sx), p->sx * p->nslot, p->nslot, p->sx, 1,
-                                           p->nslot, 1, p->stream));
+                                           p->upload, up_bytes, ftab, p->deferred_src, dst, p->sy, p->sx, p->ex, p->d,
+                                           (float)((double)p->sy * p->sx), p->deferred_sr, p->deferred_sm, p->sx, 1,
+                                           p->deferred_nslot, p->deferred_slot_stride, p->stream));
   } else if (p->precision == WDD_FP32) {
     WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
                                    up_bytes, ftab, p->stream));
@@ -792,10 +808,6 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   hipEvent_t end;
   wdd_status st = flush_deferred(p);
   if (st != WDD_OK) return st;
-  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && can_defer(p)) {  // written by the next push's first launch
-    p->deferred_dst = reinterpret_cast<float2*>(out);
-    return WDD_OK;
-  }
   if (reduce && p->order_mode == WDD_ORDER_SPECTRUM) {  // object order keeps D current
     WDD_HIP(p, stage_begin(p, kWiener, &end));
     WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sy, p->stream));
@@ -809,14 +821,19 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   // order), then the columns of u along vx, each workgroup writing one whole output row.
   // When the object-order update has left the first pass as partial rows (up, [y][vx][slot]),
   // the column pass sums each vx's partials as it reads them.
-  const float s_total = (float)((double)p->sy * p->sx);
-  if (p->up_valid) {
-    if ((st = display_from_partials(p, dst)) != WDD_OK) return st;
-  } else {
+  // With a deferred output the column pass is left to the next push's first launch.
+  if (!p->up_valid)
     WDD_HIP(p, wdd::launch_dft_rows(p->z, p->u, p->sx, p->sy, p->ey, p->d, 1.f, 0, p->sy, 1, p->sy, 1, 1, 0,
                                     p->stream));
-    WDD_HIP(p, wdd::launch_dft_rows(p->u, dst, p->sy, p->sx, p->ex, p->d, s_total, 1, 1, p->sy, p->sx, 1, 1, 0,
-                                    p->stream));
+  const float2* src;
+  int32_t sr, sm, nslot, slot_stride;
+  column_source(p, &src, &sr, &sm, &nslot, &slot_stride);
+  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && can_defer(p)) {
+    p->deferred_dst = dst;
+    p->deferred_src = src, p->deferred_sr = sr, p->deferred_sm = sm, p->deferred_nslot = nslot;
+    p->deferred_slot_stride = slot_stride;
+  } else if ((st = column_pass(p, src, sr, sm, nslot, slot_stride, dst)) != WDD_OK) {
+    return st;
   }
   WDD_HIP(p, stage_end(p, end));
   return WDD_OK;

@@ -357,13 +357,15 @@ def test_plans_take_device_memory_from_the_callers_allocator():
         assert np.array_equal(own.push_snapshot(dev, pos), got)
 
 
-@pytest.mark.parametrize("order,s,precision", [(1, 32, "fp32"), (0, 32, "fp32"), (1, 24, "fp32"), (1, 32, "bf16_hilo")])
+@pytest.mark.parametrize("order,s,precision", [(1, 32, "fp32"), (0, 32, "fp32"), (1, 24, "fp32"), (0, 24, "fp32"),
+                                                (1, 32, "bf16_hilo")])
 def test_deferred_device_snapshots_match_asynchronous_ones(order, s, precision):
-    """WDD_OUT_DEVICE_DEFERRED: the image is written by the next push's first launch (object
-    order, power-of-two scan, FP32 projection) or queued at once otherwise; either way each
-    output holds the image of its own point, bit for bit the asynchronous one, and a call
-    that waits for the stream or changes the state (inspection, checkpoint, reset,
-    destroy) writes a pending image first."""
+    """WDD_OUT_DEVICE_DEFERRED: the display's last pass is written by the next push's first
+    launch (FP32 projection, power-of-two Sx: from the partial rows in object order, from the
+    first pass's grid in spectrum order) or queued at once otherwise; either way each output
+    holds the image of its own point, bit for bit the asynchronous one, and a call that waits
+    for the stream or changes the state (inspection, checkpoint, reset, destroy) writes a
+    pending image first."""
     import torch
     n, b, steps = 32, 64, 8
     frames, pos = _random_case(31 + s + order, s, s, n, n, b * (steps + 4), wdd.WDD_U16)
