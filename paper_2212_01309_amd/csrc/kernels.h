@@ -78,6 +78,7 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
 // up[(y sx + vx) nslot + slot] = sum_{j of chunk c} conj(d[j]) E_sy(v_y(j) y) after the update:
 // the display's first pass split over the chunks.
 constexpr int kRowSetMax = 16;
+constexpr int kFusedThreads = 512;  // threads of a workgroup of the object-order update
 struct RowSet {
   int4 r[kRowSetMax];
 };

@@ -26,6 +26,7 @@ namespace {
 using wdd::RowSet;
 using wdd::kRowSetMax;
 using wdd::kDisplayRowMax;
+using wdd::kFusedThreads;
 using wdd::kMaxSlots;
 
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
@@ -852,7 +853,6 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
 // so that the display's column pass reads each output row's inputs contiguously), and that
 // pass sums the nslot partials of each vx.
 // ---------------------------------------------------------------------------
-constexpr int kFusedThreads = 512;
 constexpr int kFusedFrames = 512;  // frames staged in LDS per round of phase 1
 static_assert(kFusedFrames <= kFusedThreads, "phase 1 stages one frame per thread");
 static_assert(kDisplayRowMax / 2 <= kFusedThreads, "one display twiddle per thread");
