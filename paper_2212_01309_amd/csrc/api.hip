@@ -775,6 +775,8 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D;
     // before a snapshot the last pass also leaves the display's first pass in `up`
     const bool rows_for_display = fuse_wiener && p->up;
+    bool in_order = true;  // frames already grouped by row (a raster batch): no reordering
+    for (int32_t i = 0; i < n && in_order; ++i) in_order = ord[i] == i;
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
       float2* up_pass = rows_for_display && r0 + kFactorRows >= nrows ? p->up : nullptr;
@@ -784,7 +786,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
       WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
                                            p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->z, up_pass,
-                                           p->nslot, p->stream));
+                                           p->nslot, in_order, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
     p->up_valid = rows_for_display;

@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                                                                  const float2* __restrict__ w,
                                                                  float2* __restrict__ d, float2* __restrict__ z,
                                                                  int max_chunk, float2* __restrict__ up, int nslot,
-                                                                 int log2sy) {
+                                                                 int log2sy, int in_order) {
   extern __shared__ float4 fsm[];
   const int q = kpad >> 2, G = kFusedThreads / q;
   const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
@@ -931,18 +931,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   if (tid < cnt) myjv = gload(jv + i0 + tid);
 
   // phase 1: T_r for this vx; the first block of frames is staged here, the others in the loop
-  if (tid < min(kFusedFrames, rs.r[0].z)) {
-    const int p = vx * first_x;
-    lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
-    lb[tid] = first_b;
-  }
   const float4* h4 = reinterpret_cast<const float4*>(h);
+  const int n_first = min(kFusedFrames, rs.r[0].z);
+  // frames already in row order (order[i] = i): the projections of this lane group's first 8
+  // frames sit at known addresses, so their loads go out now, beside the index loads above,
+  // and their products are taken once the first block is staged
+  const bool pre = in_order && grp + 7 * G < n_first;
+  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+  {
+    float4 hv0[8];
+    if (pre) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) hv0[u] = h4[(size_t)(rs.r[0].y + grp + u * G) * q + kq];
+    }
+    if (tid < n_first) {
+      const int p = vx * first_x;
+      lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+      lb[tid] = first_b;
+    }
+    __syncthreads();
+    if (pre) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[grp + u * G], hv0[u]);
+    }
+  }
   for (int r = 0; r < nrows; ++r) {
     const int4 row = rs.r[r];
-    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
     for (int f0 = 0; f0 < row.z; f0 += kFusedFrames) {
       const int n = min(kFusedFrames, row.z - f0);
-      if (r != 0 || f0 != 0) {
+      const bool first = r == 0 && f0 == 0;
+      if (!first) {
         __syncthreads();
         if (tid < n) {
           const int at = row.y + f0 + tid;
@@ -950,9 +968,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
           lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
           lb[tid] = b;
         }
+        __syncthreads();
       }
-      __syncthreads();
-      int i = grp;
+      int i = grp + (first && pre ? 8 * G : 0);
       for (; i + 7 * G < n; i += 8 * G) {
         float4 hv[8];
 #pragma unroll
@@ -974,6 +992,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
       lt[(size_t)(r * q + kq) * 2 + 1] = a1;
     }
     __syncthreads();
+    a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    a1 = a0;
   }
 
   if (tid < cnt) {
@@ -1455,7 +1475,7 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
-                                float2* up, int nslot, hipStream_t st) {
+                                float2* up, int nslot, bool in_order, hipStream_t st) {
   if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
     return hipErrorInvalidValue;
   int log2sy = 0;
@@ -1466,7 +1486,7 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
   }
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
-                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk, up, nslot, log2sy);
+                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk, up, nslot, log2sy, in_order ? 1 : 0);
   return hipGetLastError();
 }
 
