@@ -376,8 +376,9 @@ def main():
         "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
                    "wiener_order": args.order, "basis": args.basis,
-                   "display": "hbm" + (", each image written in the next push's projection launch"
-                                       if args.display == "deferred" else "")},
+                   "display": "hbm" + (", each image's last pass deferred to the next push's projection launch "
+                                       "where the plan allows it (FP32 Hermite-Gauss projection, detector rows "
+                                       "<= 128, power-of-two scan width)" if args.display == "deferred" else "")},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "steps": nlat},
         "host_display_fps": host_fps,
