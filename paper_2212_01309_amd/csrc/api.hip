@@ -371,6 +371,9 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   const int64_t per_round = 2 * (4 * wdd::kFusedThreads / p->kpad);
   int64_t chunk = (p->n_freq + 383) / 384;
   if (chunk > 3 * per_round) chunk = (p->n_freq + 511) / 512;
+  // a whole number of rounds: one frequency past a multiple of 2 G would cost its chunk a
+  // further round trip to HBM for W, and the slowest chunks set the launch's duration
+  if (chunk > per_round) chunk -= chunk % per_round;
   p->max_chunk = (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(kMinChunk, chunk));
   std::vector<int4> chunks;
   for (int64_t i = 0; i < p->n_freq;) {
