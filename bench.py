@@ -263,8 +263,8 @@ def main():
         serving(args)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the method's multi-GPU "
-              f"sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (sharding the update "
+              f"over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
     import torch
 
