@@ -911,12 +911,23 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   int* lb = reinterpret_cast<int*>(lw + kFusedFrames);        // [kFusedFrames] their batch indices
   int* lj = lb + kFusedFrames;                                // [max_chunk] the chunk's frequencies
   int* lvy = lj + max_chunk;                                  // [max_chunk] their y-frequencies
-  // the first staging block's frame indices and x positions depend on the kernel arguments
-  // only: their loads go out before anything waits for the chunk descriptor
-  int first_b = 0, first_x = 0;
-  if (tid < min(kFusedFrames, rs.r[0].z)) {
-    first_b = gload(order + rs.r[0].y + tid);
-    first_x = gload(xs + rs.r[0].y + tid);
+  // Every load of the prologue is unconditional, its index clamped into range (a row holds at
+  // least one frame, a chunk at least one frequency): a load under a branch makes the compiler
+  // wait for all loads in flight wherever a later one is used, which would serialise the
+  // round trips this prologue overlaps.
+  // The first staging block's frame indices and x positions, and (frames already in row
+  // order, order[i] = i) the projections of this lane group's first 8 frames, depend on the
+  // kernel arguments only: their loads go out before anything waits for the chunk descriptor.
+  const float4* h4 = reinterpret_cast<const float4*>(h);
+  const int n_first = min(kFusedFrames, rs.r[0].z);
+  const int fi = rs.r[0].y + min(tid, n_first - 1);
+  const int first_b = gload(order + fi), first_x = gload(xs + fi);
+  const bool pre = in_order && grp + 7 * G < n_first;
+  float4 hv0[8];
+  {
+    const int f0 = rs.r[0].y + (pre ? grp : 0), fs = pre ? G : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) hv0[u] = gload(h4 + (size_t)(f0 + u * fs) * q + kq);
   }
   // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
   // share cache lines) run on one XCD, so partly written lines meet in one L2
@@ -927,33 +938,19 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
 
   // this thread's (j, v_y) of the chunk (cnt <= kFusedThreads): loaded now, stored to LDS
   // after phase 1, so that its round trip hides under phase 1's
-  int2 myjv = make_int2(0, 0);
-  if (tid < cnt) myjv = gload(jv + i0 + tid);
+  const int2 myjv = gload(jv + i0 + min(tid, cnt - 1));
 
   // phase 1: T_r for this vx; the first block of frames is staged here, the others in the loop
-  const float4* h4 = reinterpret_cast<const float4*>(h);
-  const int n_first = min(kFusedFrames, rs.r[0].z);
-  // frames already in row order (order[i] = i): the projections of this lane group's first 8
-  // frames sit at known addresses, so their loads go out now, beside the index loads above,
-  // and their products are taken once the first block is staged
-  const bool pre = in_order && grp + 7 * G < n_first;
   float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-  {
-    float4 hv0[8];
-    if (pre) {
+  if (tid < n_first) {
+    const int p = vx * first_x;
+    lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+    lb[tid] = first_b;
+  }
+  __syncthreads();
+  if (pre) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) hv0[u] = h4[(size_t)(rs.r[0].y + grp + u * G) * q + kq];
-    }
-    if (tid < n_first) {
-      const int p = vx * first_x;
-      lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
-      lb[tid] = first_b;
-    }
-    __syncthreads();
-    if (pre) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[grp + u * G], hv0[u]);
-    }
+    for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[grp + u * G], hv0[u]);
   }
   for (int r = 0; r < nrows; ++r) {
     const int4 row = rs.r[r];
@@ -1017,12 +1014,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     const int ja = lj[i], jb = two ? lj[i + G] : ja;
     const float4* wa = reinterpret_cast<const float4*>(w + (size_t)ja * kpad + 4 * kq);
     const float4* wb = reinterpret_cast<const float4*>(w + (size_t)jb * kpad + 4 * kq);
-    const float4 wa0 = wa[0], wa1 = wa[1], wb0 = wb[0], wb1 = wb[1];
-    float2 da = make_float2(0.f, 0.f), db = da;
-    if (kq == 0) {
-      da = d[ja];
-      db = d[jb];
-    }
+    const float4 wa0 = gload(wa), wa1 = gload(wa + 1), wb0 = gload(wb), wb1 = gload(wb + 1);
+    const float2 da = gload(d + ja), db = gload(d + jb);  // all lanes: no branch around a load
     const int vya = lvy[i], vyb = two ? lvy[i + G] : vya;
     float4 sa0, sa1, sb0, sb1;
     phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, sy, py2, invy);
