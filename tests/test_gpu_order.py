@@ -148,3 +148,27 @@ def test_display_rows_left_by_the_update(radius, sy, sx, n, k, rows):
         assert np.array_equal(a.snapshot(), two.snapshot())
     say(f"[order] display rows from the update, {sy}x{sx} scan, {rows} rows: vs two-pass, vs oracle {errs}")
     assert max(errs[:2]) <= 1e-6 and errs[2] <= 1e-5
+
+
+@pytest.mark.parametrize("sy,sx", [(1, 1), (2, 8), (4, 4), (8, 2), (16, 32)])
+def test_display_rows_on_short_scan_columns(sy, sx):
+    """Short scan columns (S_y = 1, 2, 4: fewer outputs than the workgroup's waves; 8 and 16:
+    several lanes per output) through push_snapshot in object order, whose update transforms
+    each chunk's display row itself, against the oracle's per-frame order."""
+    n, k, b = 16, 16, 3 * sy * sx
+    rng = np.random.default_rng(500 + sy * 64 + sx)
+    lin = rng.integers(0, sy * sx, size=b)
+    pos = np.stack([lin // sx, lin % sx], axis=1).astype(np.int32)
+    order = np.argsort(pos[:, 0], kind="stable")  # whole rows per push, at most 16 rows per pass
+    pos = np.ascontiguousarray(pos[order])
+    frames = rng.poisson(15.0, size=(b, n, n)).astype(np.uint16)
+    dev = device(frames)
+    half = b // 2
+    with wdd.Plan(4.0, sy, sx, n, n, k, max_batch=b, order=wdd.WDD_ORDER_OBJECT) as plan:
+        plan.push_snapshot(dev[:half], pos[:half])
+        got = plan.push_snapshot(dev[half:], pos[half:])
+    live = O.Live(O.make_plan(sy, sx, n, n, 4.0, k), "P")
+    live.push(frames, pos)
+    err = rel(got, live.snapshot())
+    say(f"[order] display rows, {sy}x{sx} scan: {err:.2e}")
+    assert err <= 1e-5
