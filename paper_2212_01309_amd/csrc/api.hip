@@ -798,7 +798,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     wiener_done = fuse_wiener;
     if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
     WDD_HIP(p, stage_begin(p, kRowDft, &end));
-    WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->pos, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
+    WDD_HIP(p, wdd::launch_row_dft(p->h, p->kpad, p->xs, p->order, p->rows, nrows, p->tx, p->sx, p->t, p->stream));
     WDD_HIP(p, stage_end(p, end));
     WDD_HIP(p, stage_begin(p, kAccumulate, &end));
     WDD_HIP(p, wdd::launch_row_update(p->acc, p->kpad, p->n_freq_pad, p->freqs, p->n_freq, p->t, p->sx, p->rows, nrows,

@@ -60,9 +60,10 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
                            int slot_stride, hipStream_t st);
 
 // Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
-// Tx[(vx x_b) mod sx] h[b][c]; then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
+// Tx[(vx x_b) mod sx] h[b][c] (order[i]: the batch's frame indices grouped by row, xs[i]: the
+// scan x of frame order[i]); then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
 // optionally followed by the Wiener reduction of launch_wiener in the same pass (z as there).
-hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
+hipError_t launch_row_dft(const float* h, int kpad, const int* xs, const int* order, const int4* rows, int nrows,
                           const float2* tx, int sx, float2* t, hipStream_t st);
 hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, int64_t n_freq,
                              const float2* t, int sx, const int4* rows, int nrows, const float2* ty, int sy,

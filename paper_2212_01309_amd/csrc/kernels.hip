@@ -713,7 +713,7 @@ __global__ __launch_bounds__(1024) void k_project_display(
 // quarter of the frames, and the four partial tiles are summed at the end.
 constexpr int kRowChunk = 256;
 
-__global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int2* __restrict__ pos,
+__global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int* __restrict__ xs,
                                                  const int* __restrict__ order, const int4* __restrict__ rows,
                                                  const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
   extern __shared__ float2 rsmem[];
@@ -734,17 +734,25 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
   for (int i0 = 0; i0 < row.z; i0 += kRowChunk) {
     const int cnt = min(kRowChunk, row.z - i0);
     __syncthreads();
-    if (tid < cnt) {
-      const int b = order[row.y + i0 + tid];
-      lb[tid] = b;
-      lx[tid] = pos[b].y;
+    if (tid < cnt) {  // the frame's index and scan x, both in row order: one round trip
+      lb[tid] = order[row.y + i0 + tid];
+      lx[tid] = xs[row.y + i0 + tid];
     }
     __syncthreads();
+    // the chunk's h columns: all of a thread's loads first (frame index clamped into the
+    // chunk, no branch around a load, so they are all in flight at once; past the chunk's
+    // end they re-read its last frame), then the stores
+    constexpr int kPer = kRowChunk * 16 / 256;
+    float hv[kPer];
 #pragma unroll
-    for (int j = 0; j < kRowChunk * 16 / 256; ++j) {
+    for (int j = 0; j < kPer; ++j) {
       const int i = tid + 256 * j;
-      const int f = i >> 4, c = i & 15;
-      lh[i] = (f < cnt) ? h[(size_t)lb[f] * kpad + c0 + c] : 0.f;
+      hv[j] = gload(h + (size_t)lb[min(i >> 4, cnt - 1)] * kpad + c0 + (i & 15));
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int i = tid + 256 * j;
+      lh[i] = (i >> 4) < cnt ? hv[j] : 0.f;
     }
     __syncthreads();
     // wave w takes frames [w * per, (w + 1) * per), 4 per MFMA (k-slot q <-> frame f0 + q)
@@ -1431,7 +1439,7 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
   return hipGetLastError();
 }
 
-hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* order, const int4* rows, int nrows,
+hipError_t launch_row_dft(const float* h, int kpad, const int* xs, const int* order, const int4* rows, int nrows,
                           const float2* tx, int sx, float2* t, hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
   static bool attr = false;
@@ -1442,7 +1450,7 @@ hipError_t launch_row_dft(const float* h, int kpad, const int2* pos, const int* 
   }
   const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
   dim3 grid((unsigned)((sx + 7) / 8), (unsigned)(kpad / 16), (unsigned)nrows);
-  hipLaunchKernelGGL(k_row_dft, grid, dim3(256), lds, st, h, kpad, pos, order, rows, tx, sx, t);
+  hipLaunchKernelGGL(k_row_dft, grid, dim3(256), lds, st, h, kpad, xs, order, rows, tx, sx, t);
   return hipGetLastError();
 }
 
