@@ -317,12 +317,9 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
   if (uploader) upload_finish(upw, up_dst, up_src, up_words, tid, blockDim.x);
   const int parts = HILO ? 2 : 1, total = parts * 16 * nx;
   for (int base = 0; base < total; base += 4 * (int)blockDim.x) {  // loads first, then the padded stores
-    uint16_t v[4];
+    uint16_t v[4];  // unconditional loads (index clamped), all in flight before the stores
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = base + u * blockDim.x + tid;
-      if (i < total) v[u] = gload(psix_lp + i);
-    }
+    for (int u = 0; u < 4; ++u) v[u] = gload(psix_lp + min(base + u * (int)blockDim.x + tid, total - 1));
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = base + u * blockDim.x + tid;
