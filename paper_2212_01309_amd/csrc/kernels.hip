@@ -869,14 +869,15 @@ __device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
   a1.x += c.x * h.z; a1.y += c.y * h.z; a1.z += c.x * h.w; a1.w += c.y * h.w;
 }
 
-// s = sum_r ph_r T_r over this lane's 4 entries (T_r from LDS)
+// s = sum_r ph_r T_r over this lane's 4 entries (T_r from LDS); ph0, the twiddle of row 0,
+// is given (formed once per frequency), the others are formed here
 __device__ inline void phase_sum(float4& s0, float4& s1, const float4* __restrict__ lt, int q, int kq, int nrows,
-                                 const RowSet& rs, int vy, int sy, bool py2, float invy) {
+                                 const RowSet& rs, int vy, int sy, bool py2, float invy, float2 ph0) {
   s0 = make_float4(0.f, 0.f, 0.f, 0.f);
   s1 = s0;
   for (int r = 0; r < nrows; ++r) {
     const int p = vy * rs.r[r].x;
-    const float2 ph = twiddle(py2 ? (p & (sy - 1)) : mod_small(p, sy, invy), sy, 1.0f);
+    const float2 ph = r == 0 ? ph0 : twiddle(py2 ? (p & (sy - 1)) : mod_small(p, sy, invy), sy, 1.0f);
     const float4 t0 = lt[(size_t)(r * q + kq) * 2], t1 = lt[(size_t)(r * q + kq) * 2 + 1];
     s0.x += ph.x * t0.x - ph.y * t0.y; s0.y += ph.x * t0.y + ph.y * t0.x;
     s0.z += ph.x * t0.z - ph.y * t0.w; s0.w += ph.x * t0.w + ph.y * t0.z;
@@ -916,6 +917,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   int* lb = reinterpret_cast<int*>(lw + kFusedFrames);        // [kFusedFrames] their batch indices
   int* lj = lb + kFusedFrames;                                // [max_chunk] the chunk's frequencies
   int* lvy = lj + max_chunk;                                  // [max_chunk] their y-frequencies
+  float2* lph = reinterpret_cast<float2*>(lvy + max_chunk);   // [max_chunk] their row-0 twiddles
   // Every load of the prologue is unconditional, its index clamped into range (a row holds at
   // least one frame, a chunk at least one frequency): a load under a branch makes the compiler
   // wait for all loads in flight wherever a later one is used, which would serialise the
@@ -1001,6 +1003,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   if (tid < cnt) {
     lj[tid] = myjv.x;
     lvy[tid] = myjv.y;
+    const int p = myjv.y * rs.r[0].x;
+    lph[tid] = twiddle(py2 ? (p & (sy - 1)) : mod_small(p, sy, invy), sy, 1.0f);
   }
   // display row (with up): the group sums are free now, so the row is cleared and its
   // twiddles formed here; phase 2 drops each conj D into its bit-reversed slot
@@ -1023,8 +1027,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     const float2 da = gload(d + ja), db = gload(d + jb);  // all lanes: no branch around a load
     const int vya = lvy[i], vyb = two ? lvy[i + G] : vya;
     float4 sa0, sa1, sb0, sb1;
-    phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, sy, py2, invy);
-    phase_sum(sb0, sb1, lt, q, kq, nrows, rs, vyb, sy, py2, invy);
+    phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, sy, py2, invy, lph[i]);
+    phase_sum(sb0, sb1, lt, q, kq, nrows, rs, vyb, sy, py2, invy, lph[two ? i + G : i]);
     float2 oa = cdot4(wa0, wa1, sa0, sa1), ob = cdot4(wb0, wb1, sb0, sb1);
     for (int off = q >> 1; off > 0; off >>= 1) {
       oa.x += __shfl_xor(oa.x, off, 64);
@@ -1467,7 +1471,7 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
 
 size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
   return (size_t)nrows * (kpad / 4) * 32 + (size_t)kFusedThreads * 32 + (size_t)kFusedFrames * 12 +
-         (size_t)max_chunk * 8;
+         (size_t)max_chunk * 16;
 }
 
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
