@@ -16,15 +16,15 @@
  *     (eq. extract; final step of the modified-WDD algorithm).
  *
  * Conventions (fixed readings of points the paper leaves open):
- *   - detector frames are fftshifted (zero frequency at (ny/2, nx/2)), row-major
- *     [ny][nx]; the aperture is centred there;
+ *   - detector frames are row-major [ny][nx]; the aperture sits at the probe's centre
+ *     (ny/2, nx/2 for fftshifted frames of a centred beam);
  *   - scan positions are 0-based integer raster indices (y, x) on an sy x sx grid
  *     with step `step_px` object pixels; repeated positions are summed;
  *   - scan frequencies are 0-based DFT indices; the scan DFT is unitary;
  *   - the K basis functions are psi_{n_y}(y) psi_{n_x}(x), n_y, n_x < L =
  *     ceil(sqrt(K)), ordered by (max(n_y, n_x), n_y + n_x, n_y); psi_n are
- *     L2-normalised Hermite functions at t = (i - n/2) / sigma, each sampled
- *     column normalised on the grid; sigma defaults to R / sqrt(2L - 1);
+ *     L2-normalised Hermite functions at t = (i - c) / sigma, c the aperture centre,
+ *     each sampled column normalised on the grid; sigma defaults to R / sqrt(2L - 1);
  *   - eps = eps_rel * max_{v,k} |Phi^T vec(Y_v)|^2;
  *   - only frequencies whose shifted aperture overlaps the unshifted one on a
  *     detector pixel are kept (Section 6.2); D is zero elsewhere.
@@ -70,10 +70,16 @@ typedef enum { WDD_U16 = 0, WDD_F32 = 1 } wdd_dtype;
 typedef enum { WDD_FP32 = 0, WDD_BF16_HILO = 1, WDD_FP16_HILO = 2, WDD_BF16 = 3, WDD_FP16 = 4 } wdd_precision;
 
 /* Fourier-space probe: amplitude * 1[|u| <= radius] * exp(-i defocus_edge_rad |u|^2 / radius^2),
- * u = detector pixel - (ny/2, nx/2).  Initial probe of the pre-computed Wiener
- * filter algorithm (initialisation step 1), generated from the aperture radius. */
+ * u = detector pixel - (center_y, center_x).  Initial probe of the pre-computed Wiener
+ * filter algorithm (initialisation step 1), generated from the aperture radius; its centre
+ * is where the unscattered beam meets the detector, (ny/2, nx/2) for fftshifted frames of a
+ * centred beam.  The Hermite-Gauss basis is centred there too (Section 5: the functions sit
+ * at the centre of the bright-field disc).  The kept-frequency test is exact when the centre
+ * is a multiple of 1/2 pixel and the detector shifts are dyadic (power-of-two sizes);
+ * otherwise pixels exactly on a rim are decided in FP64 rounding. */
 typedef struct {
   double radius_px;
+  double center_y, center_x;
   double defocus_edge_rad;
   double amplitude;
 } wdd_probe;
@@ -141,8 +147,9 @@ wdd_status wdd_default_options(wdd_options* opts);
  * with Y^B_v = Phi^T vec(Y_v), Y_v(q) = P(q) conj(P(q + q_v)).                  */
 
 /* Builds the tables.  K in [1, 256]; sy, sx in [1, 4096]; ny, nx in [1, 1024]
- * with nx a multiple of 8.  `opts` may be NULL (defaults).  WDD_EINVAL on bad
- * arguments, WDD_ENOMEM if the tables do not fit in host memory. */
+ * with nx a multiple of 8; the aperture must cover at least one detector pixel.  `opts`
+ * may be NULL (defaults).  WDD_EINVAL on bad arguments, WDD_ENOMEM if the tables do not
+ * fit in host memory. */
 wdd_status wdd_tables_build(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
                             int32_t K, const wdd_options* opts, wdd_tables_t* out);
 
@@ -164,14 +171,23 @@ wdd_status wdd_tables_free(wdd_tables_t t);
 /* ------------------------------------------------------------------------- */
 /* Live reconstruction on the current HIP device.                            */
 
-/* Creates a plan: builds the host tables, uploads them (FP32), zeroes the
- * spectrum.  `hip_stream` is the hipStream_t all work is ordered on; NULL makes
- * the plan create its own stream.  WDD_EINVAL / WDD_ENOMEM / WDD_EDEVICE. */
-wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
-                           int32_t K, const wdd_options* opts, void* hip_stream, wdd_plan_t* out);
+/* Creates a plan for one acquisition: the pre-computed Wiener filter algorithm (its
+ * initialisation from the aperture, the kept frequencies of Section 6.2, the reduced
+ * probe Wigner functions and W) built in FP64 on the host, uploaded to the device as FP32,
+ * and a zeroed accumulator.  The plan keeps its FP64 tables (wdd_plan_export).
+ *   probe, scan, det  acquisition settings (host structs, read during the call);
+ *   K                 reduced basis size (1..256, or ny nx with the Fourier basis);
+ *   opts              NULL for the defaults of wdd_default_options;
+ *   hip_stream        the hipStream_t all of the plan's work is ordered on; NULL makes the
+ *                     plan create its own (non-blocking) stream.
+ * WDD_EINVAL (bad settings), WDD_ENOMEM (host or device memory), WDD_EDEVICE. */
+wdd_status wdd_plan(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
+                    const wdd_options* opts, void* hip_stream, wdd_plan_t* out);
 
-/* Adds n frames (modified-WDD algorithm, loop body): projection, phase weighting
- * and accumulation of the spectrum.
+/* Adds n frames (Section 6.3, modified-WDD algorithm, the body of its loop over frames):
+ * projection onto the reduced basis (Section 5, operator H), weighting by the scan
+ * position's column of the unitary scan DFT (Section 6.1, eq. outer_prod) and accumulation
+ * into the spectrum A (or, in WDD_ORDER_OBJECT, the Wiener-filtered object spectrum D).
  *   frames  n x ny x nx values of the detector dtype; device memory if
  *           frames_on_device != 0 (must stay valid until the work completes:
  *           wdd_sync, a blocking snapshot, or WDD_MAX_PUSHES_IN_FLIGHT further
@@ -187,7 +203,9 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
 wdd_status wdd_push(wdd_plan_t p, const void* frames, const int32_t* pos_yx, int32_t n,
                     int32_t frames_on_device);
 
-/* wdd_push followed by wdd_snapshot, with the same arguments and results.  When the
+/* wdd_push followed by wdd_snapshot (Section 6.3, modified-WDD algorithm: the loop body
+ * and the final summation, inverse transform and conjugation), with the same arguments and
+ * results.  When the
  * batch uses the row-factored update (it touches at most 16 scan rows), the Wiener
  * reduction is done in the same pass over the spectrum.  In object order with power-of-two
  * scan sides (Sy <= 1024) the update also performs the first pass of the display's inverse
@@ -210,15 +228,17 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *                         fewer per pipelined step), or else by the next call that waits
  *                         for the plan's stream or changes its state (wdd_snapshot,
  *                         wdd_sync, wdd_get_*, wdd_profile_read, checkpoints,
- *                         wdd_update_probe, wdd_reset, wdd_plan_destroy).  `out` is
+ *                         wdd_update_probe, wdd_reset, wdd_destroy).  `out` is
  *                         complete after wdd_sync.  Where the display's last pass cannot
  *                         wait (the Fourier basis, reduced precision, scans whose Sx is
  *                         not a power of two, detectors of more than 128 rows) it is
  *                         queued at once, as WDD_OUT_DEVICE_ASYNC. */
 typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2, WDD_OUT_DEVICE_DEFERRED = 3 } wdd_out_kind;
 
-/* Takes a snapshot of all frames pushed so far: Wiener reduction, inverse DFT,
- * conjugation and normalisation (eq. extract).  Writes sy x sx complex values
+/* Takes a snapshot of all frames pushed so far (Section 6.3, modified-WDD algorithm, the
+ * steps after the loop; eq. extract): Wiener reduction D[v] = sum_k W[v,k] A[v,k], inverse
+ * unitary DFT over the scan, conjugation and normalisation by sqrt(|D[0]|).  Reflects
+ * exactly the frames pushed before the call.  Writes sy x sx complex values
  * (interleaved float, row-major [y][x]) to `out`, a wdd_out_kind place given by
  * out_on_device (any other value: WDD_EINVAL).
  * Object pixel mapping: out[y][x] is the object at scan position (y, x) shifted
@@ -227,13 +247,30 @@ wdd_status wdd_snapshot(wdd_plan_t p, float* out, int32_t out_on_device, uint64_
 
 /* The plan's pinned host buffer of sy x sx complex values that host snapshots are
  * written through.  Passing it as `out` (out_on_device = 0) skips the final host
- * copy.  Owned by the plan, valid until wdd_plan_destroy; each host snapshot
+ * copy.  Owned by the plan, valid until wdd_destroy; each host snapshot
  * overwrites it. */
 wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out);
 
-/* Inspection (blocking): the Wiener-reduced spectrum D on the kept frequencies,
- * n_freq complex values, as computed by the last wdd_snapshot. */
-wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device);
+/* Test hook (blocking): the Wiener-reduced spectrum D on the kept frequencies (eq. extract
+ * before the inverse transform; Section 6.3, modified-WDD algorithm, summation step),
+ * n_freq complex values in the order of wdd_plan_export's freqs, as computed by the last
+ * snapshot (in WDD_ORDER_OBJECT D is always current).  d_out: device memory if
+ * on_device != 0, else host memory. */
+wdd_status wdd_spectrum(wdd_plan_t p, float* d_out, int32_t on_device);
+
+/* Test hook: the FP64 tables the plan was built from and uploaded (pre-computed Wiener
+ * filter algorithm; Sections 5 and 6.2).  Any pointer may be NULL to skip it.
+ *   phi    double [ny nx][K] the reduced basis, Phi[y nx + x][k] = psi_{n_y(k)}[y] psi_{n_x(k)}[x]
+ *          (Hermite-Gauss), or [ny nx][K][2] (re, im) with the Fourier basis;
+ *   w      double [n_freq][K][2] the Wiener filter W;
+ *   freqs  int32  [n_freq][2] the kept frequencies (v_y, v_x), 0-based DFT indices sorted by
+ *          v_y then v_x, (0, 0) first: the rows of W, D and A.
+ * The device holds W rounded to FP32 (wdd_get_wiener) and the sampled psi rounded to FP32. */
+wdd_status wdd_plan_export(wdd_plan_t p, double* phi, double* w, int32_t* freqs);
+
+/* Inspection (blocking): the Wiener filter as the device holds it, n_freq x K complex
+ * float values (FP32 rounding of wdd_plan_export's w). */
+wdd_status wdd_get_wiener(wdd_plan_t p, float* w_out, int32_t on_device);
 
 /* Inspection (blocking): the accumulated spectrum A, n_freq x k complex values
  * (WDD_ESTATE in WDD_ORDER_OBJECT). */
@@ -283,7 +320,7 @@ wdd_status wdd_profile_period(wdd_plan_t p, int32_t period);
 wdd_status wdd_profile_read(wdd_plan_t p, wdd_profile* out);
 
 /* Re-deconvolution: replaces the Wiener filter by the one of `probe` (same aperture
- * radius; defocus and amplitude may change) and `eps_rel`, built in FP64 as at plan
+ * radius and centre; defocus and amplitude may change) and `eps_rel`, built in FP64 as at plan
  * creation.  The accumulated spectrum A is kept (it does not depend on the probe), so
  * the next snapshot deconvolves every frame seen so far with the new filter without
  * re-reading them (Section 10: probe update; Algorithm "pre-computed Wiener filter").
@@ -298,14 +335,17 @@ wdd_status wdd_checkpoint_size(wdd_plan_t p, size_t* bytes);
 wdd_status wdd_checkpoint_save(wdd_plan_t p, void* host_buf, size_t bytes);
 wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes);
 
-/* Zeroes the spectrum and the frame count (asynchronous). */
+/* Zeroes the spectrum and the frame count (asynchronous): a new acquisition on the same
+ * plan (Section 6.3, modified-WDD algorithm, the accumulator's initialisation). */
 wdd_status wdd_reset(wdd_plan_t p);
 
-/* Waits for all work queued on the plan stream. */
+/* Waits for all work queued on the plan stream; device frames and asynchronous outputs of
+ * earlier calls may be reused afterwards. */
 wdd_status wdd_sync(wdd_plan_t p);
 
-/* Releases the plan (waits for its work first).  NULL is accepted. */
-wdd_status wdd_plan_destroy(wdd_plan_t p);
+/* Releases the plan (waits for its work first) and all its device and host memory.  NULL
+ * is accepted. */
+wdd_status wdd_destroy(wdd_plan_t p);
 
 /* Device memory for plans created after this call (tables, spectrum, grids, device
  * staging; not pinned host buffers) comes from alloc(bytes, ctx) and goes back through
@@ -354,7 +394,7 @@ typedef struct {
 wdd_status wdd_server_default_options(wdd_server_options* opts);
 wdd_status wdd_server_create(const wdd_server_options* opts, wdd_server_t* out);
 
-/* Opens an acquisition (arguments as wdd_plan_create; max_batch is raised to the
+/* Opens an acquisition (arguments as wdd_plan; max_batch is raised to the
  * server's batch_frames).  WDD_EBUSY when it does not fit the budget now. */
 wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
                            int32_t K, const wdd_options* opts, int32_t* acq_id);

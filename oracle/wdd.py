@@ -10,9 +10,11 @@ below are used (each is a numbered reading in the design notes):
 
   R1  K counts 2D basis functions.  Pairs (n_y, n_x) are ordered by
       (max(n_y, n_x), n_y + n_x, n_y) and the first K are kept; L = ceil(sqrt(K)).
-  R2  Normalised Hermite functions, t = (i - N/2) / sigma, sigma = R / sqrt(2L - 1)
-      unless given; each sampled 1D column is L2-normalised on the grid.
-  R3  Aperture value a * 1[|u| <= R] * exp(-i phi_edge |u|^2 / R^2), u = q - N/2.
+  R2  Normalised Hermite functions, t = (i - c) / sigma with c the aperture centre,
+      sigma = R / sqrt(2L - 1) unless given; each sampled 1D column is L2-normalised
+      on the grid.
+  R3  Aperture value a * 1[|u| <= R] * exp(-i phi_edge |u|^2 / R^2), u = q - c, with the
+      aperture centre c in detector pixels; c = (N_y/2, N_x/2) unless given.
   R4  Y_v(q) = P(q - c) * conj(P(q - c + d_v)), d_v = v_signed * N / (S * step).
   R5  v is kept iff some detector pixel lies inside both discs (exact test).
   R6  eps_abs = eps_rel * max over kept v and k of |Y^B_v[k]|^2.
@@ -23,7 +25,8 @@ below are used (each is a numbered reading in the design notes):
   R10 D[v] = sum_k W[v,k] A[v,k]  (the q = 0 value of the object Wigner function).
   R11 O~ = conj(IDFT2_unitary(D)) / sqrt(|D[0]|), zero when D[0] = 0.
 
-Parity status: every function here is pinned by a test in tests/test_oracle_*.py.
+Parity status: every function here is pinned by a test in tests/test_oracle_*.py
+against a property fixed by the paper or by the mathematics (see each test module).
 """
 from __future__ import annotations
 
@@ -39,16 +42,23 @@ import numpy as np
 # ----------------------------------------------------------------------------
 
 
+def default_center(ny: int, nx: int) -> Tuple[float, float]:
+    """The detector's zero frequency for fftshifted frames, (ny//2, nx//2)."""
+    return float(ny // 2), float(nx // 2)
+
+
 def aperture(ny: int, nx: int, radius: float, amplitude: float = 1.0, defocus_edge: float = 0.0,
-             shift: Tuple[float, float] = (0.0, 0.0)) -> np.ndarray:
-    """Fourier-space probe P(q - c + shift) on the ny x nx detector grid, c = (ny//2, nx//2).
+             shift: Tuple[float, float] = (0.0, 0.0), center: Optional[Tuple[float, float]] = None) -> np.ndarray:
+    """Fourier-space probe P(q - c + shift) on the ny x nx detector grid, c the aperture
+    centre (default (ny//2, nx//2)).
 
     The initial probe is a circular aperture generated from its radius
     (pre-computed Wiener filter algorithm, initialisation step 1); `shift`
     evaluates it at q + q_v for the Wigner function (Section 2).
     """
-    uy = np.arange(ny, dtype=np.float64) - (ny // 2) + shift[0]
-    ux = np.arange(nx, dtype=np.float64) - (nx // 2) + shift[1]
+    cy, cx = default_center(ny, nx) if center is None else center
+    uy = np.arange(ny, dtype=np.float64) - cy + shift[0]
+    ux = np.arange(nx, dtype=np.float64) - cx + shift[1]
     r2 = uy[:, None] ** 2 + ux[None, :] ** 2
     inside = r2 <= radius * radius
     phase = np.exp(-1j * defocus_edge * r2 / (radius * radius))
@@ -74,26 +84,28 @@ def detector_shift(vy, vx, sy: int, sx: int, ny: int, nx: int, step: float = 1.0
 
 
 def probe_wigner(vy: int, vx: int, sy: int, sx: int, ny: int, nx: int, radius: float,
-                 amplitude: float = 1.0, defocus_edge: float = 0.0, step: float = 1.0) -> np.ndarray:
+                 amplitude: float = 1.0, defocus_edge: float = 0.0, step: float = 1.0,
+                 center: Optional[Tuple[float, float]] = None) -> np.ndarray:
     """Y_v(q) = P(q) conj(P(q + q_v)) on the detector grid (pre-computed Wiener filter algorithm)."""
     dy, dx = detector_shift(vy, vx, sy, sx, ny, nx, step)
-    p0 = aperture(ny, nx, radius, amplitude, defocus_edge)
-    pv = aperture(ny, nx, radius, amplitude, defocus_edge, shift=(float(dy), float(dx)))
+    p0 = aperture(ny, nx, radius, amplitude, defocus_edge, center=center)
+    pv = aperture(ny, nx, radius, amplitude, defocus_edge, shift=(float(dy), float(dx)), center=center)
     return p0 * np.conj(pv)
 
 
 def nonzero_frequencies(sy: int, sx: int, ny: int, nx: int, radius: float, step: float = 1.0,
-                        chunk: int = 4096) -> np.ndarray:
+                        chunk: int = 4096, center: Optional[Tuple[float, float]] = None) -> np.ndarray:
     """All (vy, vx) whose shifted aperture overlaps the unshifted one on at least one
     detector pixel (Section 6.2, omitting frequencies without intersection).
 
     Brute force over the aperture's pixels: a pixel u (relative to the centre) is in
     both discs iff |u|^2 <= R^2 and |u + d_v|^2 <= R^2.  All shifts are dyadic
-    rationals for power-of-two sizes, so the comparisons are exact in FP64.
-    Returned as int32 [n, 2], sorted by (vy, vx); (0, 0) is always first.
+    rationals for power-of-two sizes (and half-pixel centres), so the comparisons are
+    exact in FP64.  Returned as int32 [n, 2], sorted by (vy, vx); (0, 0) is always first.
     """
-    uy = np.arange(ny, dtype=np.float64) - (ny // 2)
-    ux = np.arange(nx, dtype=np.float64) - (nx // 2)
+    cy, cx = default_center(ny, nx) if center is None else center
+    uy = np.arange(ny, dtype=np.float64) - cy
+    ux = np.arange(nx, dtype=np.float64) - cx
     UY, UX = np.meshgrid(uy, ux, indexing="ij")
     inside = UY ** 2 + UX ** 2 <= radius * radius
     py, px = UY[inside], UX[inside]
@@ -148,24 +160,26 @@ def default_sigma(radius: float, k: int) -> float:
     return radius / math.sqrt(2 * basis_size_1d(k) - 1)
 
 
-def sampled_hermite(n: int, nmax: int, sigma: float) -> np.ndarray:
+def sampled_hermite(n: int, nmax: int, sigma: float, center: Optional[float] = None) -> np.ndarray:
     """psi_x in R^{n x nmax} (Section 5): Hermite functions sampled on the grid centred
-    at n//2, each column L2-normalised on the grid."""
-    t = (np.arange(n, dtype=np.float64) - (n // 2)) / sigma
+    at `center` (default n//2, the aperture centre), each column L2-normalised on the grid."""
+    c = float(n // 2) if center is None else float(center)
+    t = (np.arange(n, dtype=np.float64) - c) / sigma
     psi = hermite_functions(nmax, t).T.copy()             # [n, nmax]
     psi /= np.sqrt(np.sum(psi * psi, axis=0, keepdims=True))
     return psi
 
 
-def hg_basis(ny: int, nx: int, k: int, sigma: float) -> np.ndarray:
+def hg_basis(ny: int, nx: int, k: int, sigma: float, center: Optional[Tuple[float, float]] = None) -> np.ndarray:
     """Phi in R^{(ny*nx) x k}: Phi[y*nx + x, j] = psi_{n_y(j)}[y] * psi_{n_x(j)}[x].
 
     Phi^T vec(A) equals the reduction H(A) of Section 5 with its L x L entries
     re-listed in shell order (the transpose in H only relabels entries)."""
     pairs = basis_order(k)
     lsz = basis_size_1d(k)
-    py = sampled_hermite(ny, lsz, sigma)
-    px = sampled_hermite(nx, lsz, sigma)
+    cy, cx = default_center(ny, nx) if center is None else center
+    py = sampled_hermite(ny, lsz, sigma, cy)
+    px = sampled_hermite(nx, lsz, sigma, cx)
     phi = py[:, None, pairs[:, 0]] * px[None, :, pairs[:, 1]]   # [ny, nx, k]
     return phi.reshape(ny * nx, k)
 
@@ -202,6 +216,7 @@ class Plan:
     yb: np.ndarray           # complex [n_hat, k]: Phi^T vec(Y_v)
     eps_abs: float
     w: np.ndarray            # complex [n_hat, k]
+    center: Optional[Tuple[float, float]] = None   # aperture centre; None: (ny//2, nx//2)
 
     @property
     def k(self) -> int:
@@ -223,7 +238,8 @@ def reduce_hg(a: np.ndarray, psi_y: np.ndarray, psi_x: np.ndarray, pairs: np.nda
 def make_plan(sy: int, sx: int, ny: int, nx: int, radius: float, k: Optional[int] = None,
               amplitude: float = 1.0, defocus_edge: float = 0.0, step: float = 1.0,
               eps_rel: float = 0.01, sigma: Optional[float] = None, phi: Optional[np.ndarray] = None,
-              freqs: Optional[np.ndarray] = None, eps_abs: Optional[float] = None, chunk: int = 256) -> Plan:
+              freqs: Optional[np.ndarray] = None, eps_abs: Optional[float] = None, chunk: int = 256,
+              center: Optional[Tuple[float, float]] = None) -> Plan:
     """Frequencies with overlap, the reduced probe Wigner functions and the Wiener filter.
 
     For each kept v: Y_v (probe autocorrelation at q + q_v), its reduction
@@ -236,14 +252,15 @@ def make_plan(sy: int, sx: int, ny: int, nx: int, radius: float, k: Optional[int
     if hg:
         if sigma is None:
             sigma = default_sigma(radius, k)
-        phi = hg_basis(ny, nx, k, sigma)
+        phi = hg_basis(ny, nx, k, sigma, center)
         lsz = basis_size_1d(k)
-        psi_y, psi_x, pairs = sampled_hermite(ny, lsz, sigma), sampled_hermite(nx, lsz, sigma), basis_order(k)
+        cy, cx = default_center(ny, nx) if center is None else center
+        psi_y, psi_x, pairs = sampled_hermite(ny, lsz, sigma, cy), sampled_hermite(nx, lsz, sigma, cx), basis_order(k)
     if freqs is None:
-        freqs = nonzero_frequencies(sy, sx, ny, nx, radius, step)
+        freqs = nonzero_frequencies(sy, sx, ny, nx, radius, step, center=center)
     yb = np.empty((len(freqs), phi.shape[1]), dtype=np.complex128)
     for c0 in range(0, len(freqs), chunk):
-        ys = np.stack([probe_wigner(int(vy), int(vx), sy, sx, ny, nx, radius, amplitude, defocus_edge, step)
+        ys = np.stack([probe_wigner(int(vy), int(vx), sy, sx, ny, nx, radius, amplitude, defocus_edge, step, center)
                        for vy, vx in freqs[c0:c0 + chunk]])
         if hg:
             yb[c0:c0 + chunk] = reduce_hg(ys, psi_y, psi_x, pairs)
@@ -252,7 +269,7 @@ def make_plan(sy: int, sx: int, ny: int, nx: int, radius: float, k: Optional[int
     if eps_abs is None:
         eps_abs = eps_rel * float(np.max(np.abs(yb) ** 2))
     w = np.conj(yb) / (np.abs(yb) ** 2 + eps_abs)
-    return Plan(sy, sx, ny, nx, radius, amplitude, defocus_edge, step, eps_rel, freqs, phi, yb, eps_abs, w)
+    return Plan(sy, sx, ny, nx, radius, amplitude, defocus_edge, step, eps_rel, freqs, phi, yb, eps_abs, w, center)
 
 
 # ----------------------------------------------------------------------------

@@ -39,7 +39,14 @@ class WddError(RuntimeError):
 
 
 class Probe(ctypes.Structure):
-    _fields_ = [("radius_px", ctypes.c_double), ("defocus_edge_rad", ctypes.c_double), ("amplitude", ctypes.c_double)]
+    _fields_ = [("radius_px", ctypes.c_double), ("center_y", ctypes.c_double), ("center_x", ctypes.c_double),
+                ("defocus_edge_rad", ctypes.c_double), ("amplitude", ctypes.c_double)]
+
+
+def _probe(radius: float, ny: int, nx: int, center, defocus: float, amplitude: float) -> Probe:
+    """The aperture centre defaults to the detector's zero frequency (ny/2, nx/2)."""
+    cy, cx = (ny // 2, nx // 2) if center is None else center
+    return Probe(radius, float(cy), float(cx), defocus, amplitude)
 
 
 class Scan(ctypes.Structure):
@@ -95,14 +102,16 @@ _SIGNATURES = {
     "wdd_tables_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
     "wdd_tables_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "wdd_tables_free": (ctypes.c_int, [_P]),
-    "wdd_plan_create": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
-                                       ctypes.c_int32, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "wdd_plan": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
+                                ctypes.c_int32, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
     "wdd_push": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
     "wdd_snapshot": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "wdd_push_snapshot": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "wdd_snapshot_buffer": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_float))]),
-    "wdd_get_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_get_wiener": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "wdd_plan_export": (ctypes.c_int, [_P, _P, _P, _P]),
     "wdd_get_accumulator": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_get_projection": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "wdd_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
@@ -115,7 +124,7 @@ _SIGNATURES = {
     "wdd_checkpoint_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "wdd_reset": (ctypes.c_int, [_P]),
     "wdd_sync": (ctypes.c_int, [_P]),
-    "wdd_plan_destroy": (ctypes.c_int, [_P]),
+    "wdd_destroy": (ctypes.c_int, [_P]),
     "wdd_server_default_options": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
     "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
@@ -228,10 +237,11 @@ class Tables:
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, defocus: float = 0.0,
                  amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01, sigma: float = 0.0,
-                 dtype: int = WDD_U16, basis: int = WDD_BASIS_HERMITE_GAUSS):
+                 dtype: int = WDD_U16, basis: int = WDD_BASIS_HERMITE_GAUSS, center=None):
         lib = load_library()
         self._h = _P()
-        _check(lib.wdd_tables_build(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
+        _check(lib.wdd_tables_build(ctypes.byref(_probe(radius, ny, nx, center, defocus, amplitude)),
+                                    ctypes.byref(Scan(sy, sx, step)),
                                     ctypes.byref(Detector(ny, nx, dtype)), k,
                                     ctypes.byref(_options(eps_rel, sigma, 256, basis=basis)), ctypes.byref(self._h)))
         info = PlanInfo()
@@ -264,12 +274,12 @@ class Tables:
 
 
 class Plan:
-    """A live reconstruction on the current HIP device (wdd_plan_create ... wdd_plan_destroy)."""
+    """A live reconstruction on the current HIP device (wdd_plan ... wdd_destroy)."""
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
                  sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32,
-                 order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS):
+                 order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, center=None):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
@@ -277,10 +287,11 @@ class Plan:
             precision = PRECISIONS[precision]
         self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
         self.basis = basis
-        _check(lib.wdd_plan_create(ctypes.byref(Probe(radius, defocus, amplitude)), ctypes.byref(Scan(sy, sx, step)),
-                                   ctypes.byref(Detector(ny, nx, dtype)), k,
-                                   ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order, basis)),
-                                   _P(stream) if stream else None, ctypes.byref(self._h)))
+        self.center = (ny // 2, nx // 2) if center is None else tuple(center)
+        _check(lib.wdd_plan(ctypes.byref(_probe(radius, ny, nx, center, defocus, amplitude)),
+                            ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)), k,
+                            ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order, basis)),
+                            _P(stream) if stream else None, ctypes.byref(self._h)))
         info = self.info()
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
         self._last_batch = 0
@@ -299,7 +310,7 @@ class Plan:
     # -- lifecycle ---------------------------------------------------------
     def close(self) -> None:
         if self._h:
-            load_library().wdd_plan_destroy(self._h)
+            load_library().wdd_destroy(self._h)
             self._h = _P()
             self._pinned = None          # the pinned buffer is freed with the plan
             self._addr_cache = {}
@@ -439,8 +450,26 @@ class Plan:
     def spectrum(self) -> np.ndarray:
         """D on the kept frequencies from the last snapshot, complex64 [n_freq]."""
         d = np.empty(self.n_freq, np.complex64)
-        _check(load_library().wdd_get_spectrum(self._h, d.ctypes.data, 0))
+        _check(load_library().wdd_spectrum(self._h, d.ctypes.data, 0))
         return d
+
+    def export(self):
+        """The plan's own FP64 tables: (phi [ny*nx, k] float64 (complex128 with the Fourier
+        basis), w [n_freq, k] complex128, freqs [n_freq, 2] int32)."""
+        fourier = self.basis == WDD_BASIS_FOURIER
+        phi = np.zeros((self.ny * self.nx, self.k, 2) if fourier else (self.ny * self.nx, self.k))
+        w = np.zeros((self.n_freq, self.k, 2))
+        freqs = np.zeros((self.n_freq, 2), np.int32)
+        _check(load_library().wdd_plan_export(self._h, phi.ctypes.data, w.ctypes.data, freqs.ctypes.data))
+        if fourier:
+            phi = phi[..., 0] + 1j * phi[..., 1]
+        return phi, w[..., 0] + 1j * w[..., 1], freqs
+
+    def wiener(self) -> np.ndarray:
+        """W as the device holds it, complex64 [n_freq, k]."""
+        w = np.empty((self.n_freq, self.k), np.complex64)
+        _check(load_library().wdd_get_wiener(self._h, w.ctypes.data, 0))
+        return w
 
     def accumulator(self) -> np.ndarray:
         """A, complex64 [n_freq, k]."""
@@ -468,8 +497,9 @@ class Plan:
         return {f: getattr(pr, f) for f, _ in Profile._fields_}
 
     def update_probe(self, radius: float, defocus: float = 0.0, amplitude: float = 1.0, eps_rel: float = 0.01):
-        """New Wiener filter for the frames already accumulated (same aperture radius)."""
-        _check(load_library().wdd_update_probe(self._h, ctypes.byref(Probe(radius, defocus, amplitude)), eps_rel))
+        """New Wiener filter for the frames already accumulated (same aperture radius and centre)."""
+        _check(load_library().wdd_update_probe(
+            self._h, ctypes.byref(_probe(radius, self.ny, self.nx, self.center, defocus, amplitude)), eps_rel))
 
     def checkpoint(self) -> bytes:
         """Image of the live state (spectrum A and frame count)."""
@@ -507,12 +537,12 @@ class Server:
     def open(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
              defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
              sigma: float = 0.0, precision=WDD_FP32, order: int = WDD_ORDER_SPECTRUM,
-             basis: int = WDD_BASIS_HERMITE_GAUSS) -> Optional[int]:
+             basis: int = WDD_BASIS_HERMITE_GAUSS, center=None) -> Optional[int]:
         """Acquisition id, or None when it does not fit the memory budget now."""
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         aid = ctypes.c_int32()
-        code = load_library().wdd_server_open(self._h, ctypes.byref(Probe(radius, defocus, amplitude)),
+        code = load_library().wdd_server_open(self._h, ctypes.byref(_probe(radius, ny, nx, center, defocus, amplitude)),
                                               ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)),
                                               k, ctypes.byref(_options(eps_rel, sigma, 256, precision, order, basis)),
                                               ctypes.byref(aid))

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -71,6 +72,7 @@ struct wdd_plan_impl {
   wdd_scan scan = {};
   wdd_detector det = {};
   wdd_options opts = {};
+  std::shared_ptr<const wdd_tables_s> tables;  // the FP64 tables uploaded (wdd_plan_export)
   int32_t* kmap = nullptr;
   int2* freqs = nullptr;
   float2* w = nullptr;
@@ -572,11 +574,15 @@ void current_allocator(wdd_alloc_fn* a, wdd_release_fn* r, void** ctx) {
   *ctx = g_alloc_ctx;
 }
 
-wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe, const wdd_scan* scan,
-                                   const wdd_detector* det, const wdd_options& opts, void* hip_stream, wdd_plan_t* out) {
+wdd_status plan_create_from_tables(std::shared_ptr<const wdd_tables_s> tp, const wdd_probe* probe,
+                                   const wdd_scan* scan, const wdd_detector* det, const wdd_options& opts,
+                                   void* hip_stream, wdd_plan_t* out) {
   *out = nullptr;
+  if (!tp) return wdd::fail(WDD_EINVAL, "null tables");
+  const wdd_tables_s& t = *tp;
   wdd_plan_s* p = new (std::nothrow) wdd_plan_s();
   if (!p) return wdd::fail(WDD_ENOMEM, "out of host memory");
+  p->tables = tp;
   current_allocator(&p->alloc_fn, &p->release_fn, &p->alloc_ctx);
   p->dtype = det->dtype;
   p->precision = opts.precision;
@@ -604,8 +610,8 @@ wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe
 
 extern "C" {
 
-wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
-                           const wdd_options* opts_in, void* hip_stream, wdd_plan_t* out) {
+wdd_status wdd_plan(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
+                    const wdd_options* opts_in, void* hip_stream, wdd_plan_t* out) {
   if (!out) return wdd::fail(WDD_EINVAL, "null output handle");
   *out = nullptr;
   wdd_options opts;
@@ -613,9 +619,10 @@ wdd_status wdd_plan_create(const wdd_probe* probe, const wdd_scan* scan, const w
   if (opts_in) opts = *opts_in;
   wdd_status st0 = wdd::check_plan_options(det, opts);
   if (st0 != WDD_OK) return st0;
-  wdd_tables_s t;
+  std::shared_ptr<wdd_tables_s> t;
   try {
-    if ((st0 = wdd::build_tables(probe, scan, det, K, &opts, &t)) != WDD_OK) return st0;
+    t = std::make_shared<wdd_tables_s>();
+    if ((st0 = wdd::build_tables(probe, scan, det, K, &opts, t.get())) != WDD_OK) return st0;
   } catch (const std::bad_alloc&) {
     return wdd::fail(WDD_ENOMEM, "out of host memory");
   }
@@ -954,13 +961,52 @@ wdd_status wdd_snapshot_buffer(wdd_plan_t p, float** host_out) {
   return WDD_OK;
 }
 
-wdd_status wdd_get_spectrum(wdd_plan_t p, float* d_out, int32_t on_device) {
+wdd_status wdd_spectrum(wdd_plan_t p, float* d_out, int32_t on_device) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;
   if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (!d_out) return wdd::fail(WDD_EINVAL, "null output");
   return copy_rows(p, d_out, p->d, 1, (size_t)p->n_freq * sizeof(float2), (size_t)p->n_freq * sizeof(float2),
                    on_device);
+}
+
+wdd_status wdd_get_wiener(wdd_plan_t p, float* w_out, int32_t on_device) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
+  if (!w_out) return wdd::fail(WDD_EINVAL, "null output");
+  return copy_rows(p, w_out, p->w, (size_t)p->n_freq, (size_t)p->k * sizeof(float2),
+                   (size_t)p->kpad * sizeof(float2), on_device);
+}
+
+wdd_status wdd_plan_export(wdd_plan_t p, double* phi, double* w, int32_t* freqs) {
+  if (!p) return wdd::fail(WDD_EINVAL, "null plan");
+  const wdd_tables_s& t = *p->tables;
+  if (freqs) std::copy(t.freqs.begin(), t.freqs.end(), freqs);
+  if (w) std::copy(t.w.begin(), t.w.end(), w);
+  if (phi) {
+    const int64_t K = t.k;
+    if (t.basis == WDD_BASIS_FOURIER) {  // Phi[q][k] = exp(+2 pi i (q_y k_y / ny + q_x k_x / nx)) / (ny nx)
+      const double norm = 1.0 / ((double)t.ny * t.nx);
+      for (int64_t qy = 0; qy < t.ny; ++qy)
+        for (int64_t qx = 0; qx < t.nx; ++qx)
+          for (int64_t k = 0; k < K; ++k) {
+            const int64_t ky = k / t.nx, kx = k % t.nx;
+            const int64_t m = ((qy * ky) % t.ny) * t.nx + ((qx * kx) % t.nx) * t.ny;  // angle in units of 1/(ny nx)
+            const double a = 2.0 * M_PI * (double)(m % ((int64_t)t.ny * t.nx)) / ((double)t.ny * t.nx);
+            double* o = phi + 2 * ((qy * t.nx + qx) * K + k);
+            o[0] = std::cos(a) * norm;
+            o[1] = std::sin(a) * norm;
+          }
+    } else {
+      for (int64_t qy = 0; qy < t.ny; ++qy)
+        for (int64_t qx = 0; qx < t.nx; ++qx)
+          for (int64_t k = 0; k < K; ++k)
+            phi[(qy * t.nx + qx) * K + k] =
+                t.psi_y[(size_t)qy * t.l + t.pairs[2 * k]] * t.psi_x[(size_t)qx * t.l + t.pairs[2 * k + 1]];
+    }
+  }
+  return WDD_OK;
 }
 
 wdd_status wdd_get_accumulator(wdd_plan_t p, float* a_out, int32_t on_device) {
@@ -1072,22 +1118,25 @@ wdd_status wdd_update_probe(wdd_plan_t p, const wdd_probe* probe, double eps_rel
   if (!probe) return wdd::fail(WDD_EINVAL, "null probe");
   if (p->order_mode == WDD_ORDER_OBJECT)
     return wdd::fail(WDD_ESTATE, "object order applies the Wiener filter per frame; no spectrum to re-deconvolve");
-  if (probe->radius_px != p->probe.radius_px)
-    return wdd::fail(WDD_EINVAL, "the aperture radius fixes the kept frequencies and cannot change");
+  if (probe->radius_px != p->probe.radius_px || probe->center_y != p->probe.center_y ||
+      probe->center_x != p->probe.center_x)
+    return wdd::fail(WDD_EINVAL, "the aperture radius and centre fix the kept frequencies and cannot change");
   wdd_options o = p->opts;
   o.eps_rel = eps_rel;
   o.sigma_px = p->sigma;
-  wdd_tables_s t;
+  std::shared_ptr<wdd_tables_s> t;
   try {
-    if ((st = wdd::build_tables(probe, &p->scan, &p->det, p->k, &o, &t)) != WDD_OK) return st;
-    if (t.n_freq() != p->n_freq) return wdd::fail(WDD_EINVAL, "kept frequency set changed");
-    if ((st = upload_wiener(p, t)) != WDD_OK) return st;
+    t = std::make_shared<wdd_tables_s>();
+    if ((st = wdd::build_tables(probe, &p->scan, &p->det, p->k, &o, t.get())) != WDD_OK) return st;
+    if (t->n_freq() != p->n_freq) return wdd::fail(WDD_EINVAL, "kept frequency set changed");
+    if ((st = upload_wiener(p, *t)) != WDD_OK) return st;
   } catch (const std::bad_alloc&) {
     return wdd::fail(WDD_ENOMEM, "out of host memory");
   }
   p->probe = *probe;
   p->opts.eps_rel = eps_rel;
-  p->eps_abs = t.eps_abs;
+  p->eps_abs = t->eps_abs;
+  p->tables = t;
   return WDD_OK;
 }
 
@@ -1196,7 +1245,7 @@ wdd_status wdd_sync(wdd_plan_t p) {
   return WDD_OK;
 }
 
-wdd_status wdd_plan_destroy(wdd_plan_t p) {
+wdd_status wdd_destroy(wdd_plan_t p) {
   if (p && !p->failed) (void)flush_deferred(p);  // a display left to a next push that will not come
   release(p);
   return WDD_OK;

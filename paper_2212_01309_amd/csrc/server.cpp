@@ -49,8 +49,8 @@ struct Acq {
 // Host tables keyed by everything they depend on; acquisitions of a repeated geometry
 // skip the FP64 table build.
 struct TableKey {
-  double radius, defocus, amplitude, step, eps_rel, sigma;
-  int32_t sy, sx, ny, nx, dtype, k, precision;
+  double radius, center_y, center_x, defocus, amplitude, step, eps_rel, sigma;
+  int32_t sy, sx, ny, nx, dtype, k, precision, basis;
   bool operator<(const TableKey& o) const {
     return std::memcmp(this, &o, sizeof(TableKey)) < 0;
   }
@@ -149,6 +149,7 @@ wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_sca
   TableKey key;
   std::memset(&key, 0, sizeof(key));
   key.radius = probe->radius_px; key.defocus = probe->defocus_edge_rad; key.amplitude = probe->amplitude;
+  key.center_y = probe->center_y; key.center_x = probe->center_x; key.basis = opts.basis;
   key.step = scan->step_px; key.eps_rel = opts.eps_rel; key.sigma = opts.sigma_px;
   key.sy = scan->sy; key.sx = scan->sx; key.ny = det->ny; key.nx = det->nx; key.dtype = det->dtype; key.k = K;
   key.precision = opts.precision;
@@ -178,7 +179,7 @@ wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_sca
                      (long long)s->used, (long long)s->opts.hbm_budget_bytes);
   Acq* a = new (std::nothrow) Acq();
   if (!a) return wdd::fail(WDD_ENOMEM, "out of host memory");
-  st = wdd::plan_create_from_tables(t, probe, scan, det, opts, nullptr, &a->plan);
+  st = wdd::plan_create_from_tables(tp, probe, scan, det, opts, nullptr, &a->plan);
   if (st != WDD_OK) {
     delete a;
     return st;
@@ -283,7 +284,7 @@ wdd_status wdd_server_close(wdd_server_t s, int32_t acq) {
   Acq* a = nullptr;
   wdd_status st = find(s, acq, &a);
   if (st != WDD_OK) return st;
-  wdd_plan_destroy(a->plan);
+  wdd_destroy(a->plan);
   s->used -= a->bytes;
   s->acqs.erase(acq);
   delete a;
@@ -320,7 +321,7 @@ wdd_status wdd_server_get_stats(wdd_server_t s, wdd_server_stats* out) {
 wdd_status wdd_server_destroy(wdd_server_t s) {
   if (!s) return WDD_OK;
   for (auto& kv : s->acqs) {
-    wdd_plan_destroy(kv.second->plan);
+    wdd_destroy(kv.second->plan);
     delete kv.second;
   }
   delete s;

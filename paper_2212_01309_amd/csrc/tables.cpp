@@ -1,7 +1,7 @@
 // Host FP64 construction of the pre-computed quantities of live WDD:
 // the kept scan frequencies (Section 6.2), the sampled Hermite-Gauss basis
 // (Sections 4 and 5) and the Wiener filter of the pre-computed Wiener filter
-// algorithm.  Independent of the device; used by wdd_plan_create and exported
+// algorithm.  Independent of the device; used by wdd_plan and exported
 // through wdd_tables_* for inspection.
 #include <algorithm>
 #include <cmath>
@@ -22,52 +22,56 @@ using cd = std::complex<double>;
 // Signed frequency of a 0-based DFT index (indices >= S/2 are negative).
 inline int64_t signed_freq(int64_t v, int64_t s) { return (2 * v >= s) ? v - s : v; }
 
-// Largest integer w >= 0 with w*w <= x (x >= 0), exact for the small values used here.
-inline int64_t floor_sqrt(double x) {
-  int64_t w = (int64_t)std::floor(std::sqrt(x));
-  while ((double)(w + 1) * (double)(w + 1) <= x) ++w;
-  while (w > 0 && (double)w * (double)w > x) --w;
-  return w;
-}
-
 struct Geometry {
-  int32_t ny, nx, cy, cx;  // detector size and aperture centre (ny/2, nx/2)
-  double r, r2;            // aperture radius and its square
-  // Aperture rows u_y = q_y - c_y that hold any pixel, and per row the pixel range
-  // [lo, hi] of u_x (clipped to the detector).
-  int64_t uy_lo, uy_hi;
+  int32_t ny, nx;
+  double cy, cx;  // aperture centre in detector pixels
+  double r, r2;   // aperture radius and its square
+  // Detector rows q_y whose offset u_y = q_y - c_y is inside the aperture, and per row the
+  // detector columns [lo, hi] with (q_x - c_x)^2 <= R^2 - u_y^2 (empty rows: lo > hi).
+  int64_t qy_lo, qy_hi;
   std::vector<int64_t> row_lo, row_hi;
 
-  void init(int32_t ny_, int32_t nx_, double radius) {
-    ny = ny_; nx = nx_; cy = ny / 2; cx = nx / 2; r = radius; r2 = radius * radius;
-    const int64_t rf = (int64_t)std::floor(radius);
-    uy_lo = std::max<int64_t>(-cy, -rf);
-    uy_hi = std::min<int64_t>(ny - 1 - cy, rf);
-    row_lo.assign(uy_hi - uy_lo + 1, 1);
-    row_hi.assign(uy_hi - uy_lo + 1, 0);
-    for (int64_t uy = uy_lo; uy <= uy_hi; ++uy) {
-      const double rem = r2 - (double)uy * (double)uy;
+  void init(int32_t ny_, int32_t nx_, double radius, double cy_, double cx_) {
+    ny = ny_; nx = nx_; cy = cy_; cx = cx_; r = radius; r2 = radius * radius;
+    qy_lo = std::max<int64_t>(0, (int64_t)std::floor(cy - radius) - 1);
+    qy_hi = std::min<int64_t>(ny - 1, (int64_t)std::ceil(cy + radius) + 1);
+    if (qy_hi < qy_lo) qy_hi = qy_lo - 1;
+    row_lo.assign(std::max<int64_t>(0, qy_hi - qy_lo + 1), 1);
+    row_hi.assign(row_lo.size(), 0);
+    for (int64_t qy = qy_lo; qy <= qy_hi; ++qy) {
+      const double uy = (double)qy - cy;
+      const double rem = r2 - uy * uy;
       if (rem < 0) continue;
-      const int64_t w = floor_sqrt(rem);
-      row_lo[uy - uy_lo] = std::max<int64_t>(-w, -cx);
-      row_hi[uy - uy_lo] = std::min<int64_t>(w, nx - 1 - cx);
+      // the exact test decides the ends: (q_x - c_x)^2 <= rem
+      const double sr = std::sqrt(rem);
+      int64_t lo = (int64_t)std::ceil(cx - sr) - 1, hi = (int64_t)std::floor(cx + sr) + 1;
+      auto in = [&](int64_t q) { const double u = (double)q - cx; return u * u <= rem; };
+      while (lo <= hi && !in(lo)) ++lo;
+      while (hi >= lo && !in(hi)) --hi;
+      lo = std::max<int64_t>(lo, 0);
+      hi = std::min<int64_t>(hi, nx - 1);
+      row_lo[qy - qy_lo] = lo;
+      row_hi[qy - qy_lo] = hi;
     }
   }
 
-  // True iff some detector pixel u lies in the aperture and in the aperture shifted by -d,
-  // i.e. |u|^2 <= R^2 and |u + d|^2 <= R^2.  Per row the second condition is a convex
-  // function of u_x, so the integer nearest to -d_x (clamped to the row) decides.
+  // True iff some detector pixel q lies in the aperture and in the aperture shifted by -d,
+  // i.e. |q - c|^2 <= R^2 and |q - c + d|^2 <= R^2.  Per row the second condition is a
+  // convex function of q_x, so the column nearest to c_x - d_x (clamped to the row) decides.
   bool overlaps(double dy, double dx) const {
-    for (int64_t uy = uy_lo; uy <= uy_hi; ++uy) {
-      const int64_t lo = row_lo[uy - uy_lo], hi = row_hi[uy - uy_lo];
+    for (int64_t qy = qy_lo; qy <= qy_hi; ++qy) {
+      const int64_t lo = row_lo[qy - qy_lo], hi = row_hi[qy - qy_lo];
       if (lo > hi) continue;
-      const double ry = (double)uy + dy;
+      const double ry = ((double)qy - cy) + dy;
       const double rem = r2 - ry * ry;
       if (rem < 0) continue;
-      int64_t c = (int64_t)std::floor(-dx + 0.5);
+      int64_t c = (int64_t)std::floor(cx - dx + 0.5);
       c = std::min(std::max(c, lo), hi);
-      const double rx = (double)c + dx;
-      if (rx * rx <= rem) return true;
+      // both neighbours of the real minimiser are candidates when it falls between columns
+      for (int64_t q = std::max(lo, c - 1); q <= std::min(hi, c + 1); ++q) {
+        const double rx = ((double)q - cx) + dx;
+        if (rx * rx <= rem) return true;
+      }
     }
     return false;
   }
@@ -106,26 +110,26 @@ void fourier_wigner(wdd_tables_s* t, const Geometry& geo) {
       const double dy = (double)signed_freq(vy, t->sy) * ny / (t->sy * t->step);
       const double dx = (double)signed_freq(vx, t->sx) * nx / (t->sx * t->step);
       std::fill(part.begin(), part.end(), cd(0, 0));
-      for (int64_t uy = geo.uy_lo; uy <= geo.uy_hi; ++uy) {
-        const int64_t lo = geo.row_lo[uy - geo.uy_lo], hi = geo.row_hi[uy - geo.uy_lo];
+      for (int64_t qy = geo.qy_lo; qy <= geo.qy_hi; ++qy) {
+        const int64_t lo = geo.row_lo[qy - geo.qy_lo], hi = geo.row_hi[qy - geo.qy_lo];
         if (lo > hi) continue;
-        const double ry = (double)uy + dy;
+        const double uy = (double)qy - geo.cy;
+        const double ry = uy + dy;
         const double rem = r2 - ry * ry;
         if (rem < 0) continue;
-        const cd rowf = quad_phase((double)uy) * std::conj(quad_phase(ry));
+        const cd rowf = quad_phase(uy) * std::conj(quad_phase(ry));
         bool any = false;
         std::fill(row.begin(), row.end(), cd(0, 0));
-        for (int64_t ux = lo; ux <= hi; ++ux) {
-          const double rx = (double)ux + dx;
+        for (int64_t qx = lo; qx <= hi; ++qx) {
+          const double ux = (double)qx - geo.cx;
+          const double rx = ux + dx;
           if (rx * rx > rem) continue;
           // Y = P(u) conj(P(u + d)); |P| = amp inside both discs
-          const cd y = amp * amp * rowf * quad_phase((double)ux) * std::conj(quad_phase(rx));
-          const int64_t qx = ux + geo.cx;
+          const cd y = amp * amp * rowf * quad_phase(ux) * std::conj(quad_phase(rx));
           for (int32_t kx = 0; kx < nx; ++kx) row[kx] += y * ex[(qx * kx) % nx];
           any = true;
         }
         if (!any) continue;
-        const int64_t qy = uy + geo.cy;
         for (int32_t ky = 0; ky < ny; ++ky) {
           const cd e = ey[(qy * ky) % ny];
           cd* dst = &part[(size_t)ky * nx];
@@ -176,6 +180,8 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
   if (!std::isfinite(probe->amplitude) || probe->amplitude == 0.0)
     return fail(WDD_EINVAL, "probe amplitude must be finite and non-zero");
   if (!std::isfinite(probe->defocus_edge_rad)) return fail(WDD_EINVAL, "defocus must be finite");
+  if (!std::isfinite(probe->center_y) || !std::isfinite(probe->center_x))
+    return fail(WDD_EINVAL, "probe centre must be finite");
   if (scan->sy < 1 || scan->sx < 1 || scan->sy > 4096 || scan->sx > 4096)
     return fail(WDD_EINVAL, "scan size %d x %d outside [1, 4096]", scan->sy, scan->sx);
   if (!(scan->step_px > 0) || !std::isfinite(scan->step_px)) return fail(WDD_EINVAL, "scan step must be > 0");
@@ -202,6 +208,7 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
   if (fourier) L = 0;
   t->sy = scan->sy; t->sx = scan->sx; t->ny = det->ny; t->nx = det->nx; t->k = K; t->l = L;
   t->step = scan->step_px; t->radius = radius; t->amplitude = probe->amplitude;
+  t->cy = probe->center_y; t->cx = probe->center_x;
   t->defocus = probe->defocus_edge_rad; t->eps_rel = opts.eps_rel;
   t->sigma = fourier ? 0.0 : (opts.sigma_px > 0 ? opts.sigma_px : radius / std::sqrt(2.0 * L - 1.0));
   t->basis = opts.basis;
@@ -209,7 +216,7 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
   try {
     // --- kept frequencies -------------------------------------------------
     Geometry geo;
-    geo.init(t->ny, t->nx, radius);
+    geo.init(t->ny, t->nx, radius, t->cy, t->cx);
     const double reach = 2.0 * radius + 2.0;
     t->freqs.clear();
     for (int64_t vy = 0; vy < t->sy; ++vy) {
@@ -225,6 +232,10 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
       }
     }
 
+    if (t->freqs.empty())
+      return fail(WDD_EINVAL, "the aperture (radius %g at (%g, %g)) covers no pixel of the %d x %d detector", radius,
+                  t->cy, t->cx, t->ny, t->nx);
+
     if (fourier) {
       fourier_wigner(t, geo);
       wiener_from_reduced(t);
@@ -232,10 +243,10 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
     }
 
     // --- Hermite-Gauss basis ---------------------------------------------
-    auto sample = [&](int32_t n, std::vector<double>& psi) {
+    auto sample = [&](int32_t n, double c, std::vector<double>& psi) {
       psi.assign((size_t)n * L, 0.0);
       for (int32_t i = 0; i < n; ++i) {
-        const double x = (double)(i - n / 2) / t->sigma;
+        const double x = ((double)i - c) / t->sigma;
         double pm = 0.0, p = std::pow(M_PI, -0.25) * std::exp(-0.5 * x * x);
         psi[(size_t)i * L] = p;
         for (int32_t m = 0; m + 1 < L; ++m) {
@@ -252,8 +263,8 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
         for (int32_t i = 0; i < n; ++i) psi[(size_t)i * L + m] *= inv;
       }
     };
-    sample(t->ny, t->psi_y);
-    sample(t->nx, t->psi_x);
+    sample(t->ny, t->cy, t->psi_y);
+    sample(t->nx, t->cx, t->psi_x);
 
     std::vector<std::pair<int32_t, int32_t>> pr;
     for (int32_t a = 0; a < L; ++a)
@@ -275,12 +286,12 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
     const int64_t nf = t->n_freq();
     t->w.assign((size_t)nf * K * 2, 0.0);
     const double amp = t->amplitude, phi_e = t->defocus, r2 = radius * radius;
-    const int64_t rows = geo.uy_hi - geo.uy_lo + 1;
+    const int64_t rows = std::max<int64_t>(0, geo.qy_hi - geo.qy_lo + 1);
     // The aperture's quadratic phase is separable in (u_y, u_x).
     auto quad_phase = [&](double u) { return cd(std::cos(phi_e * u * u / r2), -std::sin(phi_e * u * u / r2)); };
     std::vector<cd> p0y(rows), p0x(t->nx);
-    for (int64_t uy = geo.uy_lo; uy <= geo.uy_hi; ++uy) p0y[uy - geo.uy_lo] = quad_phase((double)uy);
-    for (int32_t qx = 0; qx < t->nx; ++qx) p0x[qx] = quad_phase((double)(qx - geo.cx));
+    for (int64_t qy = geo.qy_lo; qy <= geo.qy_hi; ++qy) p0y[qy - geo.qy_lo] = quad_phase((double)qy - geo.cy);
+    for (int32_t qx = 0; qx < t->nx; ++qx) p0x[qx] = quad_phase((double)qx - geo.cx);
 
     auto work = [&](int64_t f0, int64_t f1) {
       std::vector<cd> py(rows), px(t->nx), tr(L), g((size_t)L * L);
@@ -288,26 +299,25 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
         const int64_t vy = t->freqs[2 * f], vx = t->freqs[2 * f + 1];
         const double dy = (double)signed_freq(vy, t->sy) * t->ny / (t->sy * t->step);
         const double dx = (double)signed_freq(vx, t->sx) * t->nx / (t->sx * t->step);
-        for (int64_t uy = geo.uy_lo; uy <= geo.uy_hi; ++uy) py[uy - geo.uy_lo] = quad_phase((double)uy + dy);
-        for (int32_t qx = 0; qx < t->nx; ++qx) px[qx] = quad_phase((double)(qx - geo.cx) + dx);
+        for (int64_t qy = geo.qy_lo; qy <= geo.qy_hi; ++qy) py[qy - geo.qy_lo] = quad_phase(((double)qy - geo.cy) + dy);
+        for (int32_t qx = 0; qx < t->nx; ++qx) px[qx] = quad_phase(((double)qx - geo.cx) + dx);
         std::fill(g.begin(), g.end(), cd(0, 0));
-        for (int64_t uy = geo.uy_lo; uy <= geo.uy_hi; ++uy) {
-          const int64_t lo = geo.row_lo[uy - geo.uy_lo], hi = geo.row_hi[uy - geo.uy_lo];
+        for (int64_t qy = geo.qy_lo; qy <= geo.qy_hi; ++qy) {
+          const int64_t lo = geo.row_lo[qy - geo.qy_lo], hi = geo.row_hi[qy - geo.qy_lo];
           if (lo > hi) continue;
-          const double ry = (double)uy + dy;
+          const double ry = ((double)qy - geo.cy) + dy;
           const double rem = r2 - ry * ry;
           if (rem < 0) continue;
-          // pixels of this row inside the shifted disc: |u_x + d_x|^2 <= rem
+          // columns of this row inside the shifted disc: (q_x - c_x + d_x)^2 <= rem
           const double sr = std::sqrt(rem);
-          int64_t a = std::max<int64_t>(lo, (int64_t)std::ceil(-dx - sr) - 1);
-          int64_t b = std::min<int64_t>(hi, (int64_t)std::floor(-dx + sr) + 1);
+          const int64_t a = std::max<int64_t>(lo, (int64_t)std::ceil(geo.cx - dx - sr) - 1);
+          const int64_t b = std::min<int64_t>(hi, (int64_t)std::floor(geo.cx - dx + sr) + 1);
           std::fill(tr.begin(), tr.end(), cd(0, 0));
           bool any = false;
-          const cd rowf = p0y[uy - geo.uy_lo] * std::conj(py[uy - geo.uy_lo]);
-          for (int64_t ux = a; ux <= b; ++ux) {
-            const double rx = (double)ux + dx;
+          const cd rowf = p0y[qy - geo.qy_lo] * std::conj(py[qy - geo.qy_lo]);
+          for (int64_t qx = a; qx <= b; ++qx) {
+            const double rx = ((double)qx - geo.cx) + dx;
             if (rx * rx > rem) continue;
-            const int64_t qx = ux + geo.cx;
             // Y = P(u) conj(P(u + d)); |P| = amp inside both discs
             const cd y = amp * amp * rowf * p0x[qx] * std::conj(px[qx]);
             const double* ps = &t->psi_x[(size_t)qx * L];
@@ -315,7 +325,7 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
             any = true;
           }
           if (!any) continue;
-          const double* ps = &t->psi_y[(size_t)(uy + geo.cy) * L];
+          const double* ps = &t->psi_y[(size_t)qy * L];
           for (int32_t a2 = 0; a2 < L; ++a2)
             for (int32_t m = 0; m < L; ++m) g[(size_t)a2 * L + m] += ps[a2] * tr[m];
         }

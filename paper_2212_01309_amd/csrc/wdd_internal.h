@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -10,6 +11,7 @@
 struct wdd_tables_s {
   int32_t sy = 0, sx = 0, ny = 0, nx = 0, k = 0, l = 0;
   double step = 1.0, radius = 0.0, amplitude = 1.0, defocus = 0.0;
+  double cy = 0.0, cx = 0.0;  // aperture centre in detector pixels
   double eps_rel = 0.01, sigma = 0.0, eps_abs = 0.0;
   int32_t basis = WDD_BASIS_HERMITE_GAUSS;
   std::vector<int32_t> freqs;  // [n_freq][2]  (v_y, v_x)
@@ -33,8 +35,10 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
 wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts);
 // Device bytes a plan of these tables allocates.
 int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_t dtype);
-wdd_status plan_create_from_tables(const wdd_tables_s& t, const wdd_probe* probe, const wdd_scan* scan,
-                                   const wdd_detector* det, const wdd_options& opts, void* hip_stream, wdd_plan_t* out);
+// The plan keeps `t` (shared, read-only) as the tables it exports.
+wdd_status plan_create_from_tables(std::shared_ptr<const wdd_tables_s> t, const wdd_probe* probe,
+                                   const wdd_scan* scan, const wdd_detector* det, const wdd_options& opts,
+                                   void* hip_stream, wdd_plan_t* out);
 // Queues a batch whose frames sit at the given device addresses (16-byte aligned).
 wdd_status push_table(wdd_plan_t p, const uint64_t* frame_addrs, const int32_t* pos_yx, int32_t n, bool fuse_wiener,
                       bool* fused);

@@ -22,18 +22,20 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(wdd._SIGNATURES)
 
 
-def _compare(radius, sy, sx, ny, nx, k, defocus=0.0, amplitude=1.0, step=1.0, sigma=None, eps_rel=0.01):
+def _compare(radius, sy, sx, ny, nx, k, defocus=0.0, amplitude=1.0, step=1.0, sigma=None, eps_rel=0.01,
+             center=None):
     t = wdd.Tables(radius, sy, sx, ny, nx, k, defocus=defocus, amplitude=amplitude, step=step,
-                   sigma=sigma or 0.0, eps_rel=eps_rel)
+                   sigma=sigma or 0.0, eps_rel=eps_rel, center=center)
     freqs, psy, psx, pairs, w = t.export()
     p = O.make_plan(sy, sx, ny, nx, radius, k, amplitude=amplitude, defocus_edge=defocus, step=step,
-                    sigma=sigma, eps_rel=eps_rel)
+                    sigma=sigma, eps_rel=eps_rel, center=center)
     assert np.array_equal(freqs, p.freqs)
     assert np.array_equal(pairs, O.basis_order(k))
     sig = sigma or O.default_sigma(radius, k)
     assert t.sigma == pytest.approx(sig, rel=1e-15)
-    assert np.max(np.abs(psy - O.sampled_hermite(ny, t.l, sig))) < 1e-13
-    assert np.max(np.abs(psx - O.sampled_hermite(nx, t.l, sig))) < 1e-13
+    cy, cx = O.default_center(ny, nx) if center is None else center
+    assert np.max(np.abs(psy - O.sampled_hermite(ny, t.l, sig, cy))) < 1e-13
+    assert np.max(np.abs(psx - O.sampled_hermite(nx, t.l, sig, cx))) < 1e-13
     assert t.eps_abs == pytest.approx(p.eps_abs, rel=1e-12)
     assert np.linalg.norm(w - p.w) <= 1e-12 * np.linalg.norm(p.w)
 
@@ -46,6 +48,9 @@ def _compare(radius, sy, sx, ny, nx, k, defocus=0.0, amplitude=1.0, step=1.0, si
     dict(radius=3.0, sy=30, sx=18, ny=12, nx=16, k=10, step=0.75),        # non-power-of-two shifts
     dict(radius=20.0, sy=16, sx=16, ny=32, nx=32, k=9),                   # aperture clipped by the detector
     dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=128, sigma=3.0, eps_rel=0.1),
+    dict(radius=8.0, sy=32, sx=32, ny=32, nx=32, k=64, center=(14.5, 17.0), defocus=0.6),   # off-centre probe
+    dict(radius=6.0, sy=16, sx=24, ny=24, nx=32, k=30, center=(10.0, 20.5), step=0.75),
+    dict(radius=9.0, sy=16, sx=16, ny=32, nx=32, k=16, center=(3.5, 29.0)),                # partly off the detector
 ])
 def test_host_tables_match_oracle(args):
     _compare(**args)
@@ -73,6 +78,13 @@ def test_tables_reject_bad_arguments(bad):
         wdd.Tables(args["radius"], args["sy"], args["sx"], args["ny"], args["nx"], args["k"], **extra)
     assert ei.value.code == wdd.WDD_EINVAL
     assert wdd.load_library().wdd_last_error()
+
+
+@pytest.mark.parametrize("center", [(-40.0, 16.0), (16.0, 100.0), (float("nan"), 16.0), (16.0, float("inf"))])
+def test_tables_reject_an_aperture_off_the_detector(center):
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Tables(8.0, 32, 32, 32, 32, 64, center=center)
+    assert ei.value.code == wdd.WDD_EINVAL
 
 
 def test_default_options():

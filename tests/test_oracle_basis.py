@@ -77,3 +77,25 @@ def test_grid_orthonormality_is_close():
     gram = phi.T @ phi
     assert np.allclose(np.diag(gram), 1.0, atol=1e-12)
     assert np.max(np.abs(gram - np.eye(256))) < 1e-6
+
+
+@pytest.mark.parametrize("radius,k", [(8.0, 64), (16.0, 256), (48.0, 128), (32.0, 64), (5.0, 7)])
+def test_default_sigma_puts_the_highest_turning_point_on_the_rim(radius, k):
+    """Reading R2: sigma is chosen so that the classical turning point of the highest 1D
+    order n = L - 1 lies on the aperture rim.  The turning point is found from the Hermite
+    differential equation psi'' = (t^2 - (2n + 1)) psi, i.e. where the second difference
+    of the sampled function changes from oscillating (psi''/psi < 0) to decaying, not from
+    the closed form in default_sigma."""
+    sigma = O.default_sigma(radius, k)
+    n = O.basis_size_1d(k) - 1
+    x = np.linspace(0.5 * radius, 1.5 * radius, 200001)      # detector pixels from the centre
+    h = x[1] - x[0]
+    psi = O.hermite_functions(n + 1, x / sigma)[n]
+    curv = (psi[2:] - 2 * psi[1:-1] + psi[:-2]) / (h * h) / psi[1:-1]   # psi''/psi in 1/px^2
+    xm = x[1:-1]
+    ok = np.abs(psi[1:-1]) > 1e-300
+    # outermost sign change of psi''/psi from negative to positive
+    s = np.sign(curv[ok])
+    idx = np.nonzero((s[:-1] < 0) & (s[1:] > 0))[0]
+    turn = xm[ok][idx[-1]]
+    assert abs(turn - radius) <= 2 * h + 1e-9 * radius

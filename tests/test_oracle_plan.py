@@ -131,3 +131,63 @@ def test_aperture_value_17_gives_the_same_reconstruction():
         out.append((d, ot))
     assert np.linalg.norm(out[0][0] - out[1][0]) <= 1e-12 * np.linalg.norm(out[0][0])
     assert np.linalg.norm(out[0][1] - out[1][1]) <= 1e-12 * np.linalg.norm(out[0][1])
+
+
+@pytest.mark.parametrize("s,n,radius", [(16, 32, 4.0), (32, 32, 6.0), (16, 16, 3.5)])
+def test_scan_step_enters_as_a_finer_frequency_grid(s, n, radius):
+    """Section 6.2: a scan frequency is v / (S step) cycles per object pixel.  A raster of S
+    positions at step 2 and one of 2S positions at step 1 therefore sample the same
+    frequencies wherever both grids have them: the kept signed frequencies of (S, step 2)
+    are exactly those of (2S, step 1) with |v| < S/2, and the probe Wigner functions agree."""
+    def signed_set(sz, step):
+        got = O.nonzero_frequencies(sz, sz, n, n, radius, step)
+        vy = O.signed_index(got[:, 0], sz)
+        vx = O.signed_index(got[:, 1], sz)
+        return set(zip(vy.tolist(), vx.tolist()))
+    coarse = signed_set(s, 2.0)
+    fine = {(a, b) for a, b in signed_set(2 * s, 1.0) if -s / 2 <= a < s / 2 and -s / 2 <= b < s / 2}
+    assert coarse == fine
+    for a, b in sorted(coarse)[:: max(1, len(coarse) // 12)]:
+        y2 = O.probe_wigner(a % s, b % s, s, s, n, n, radius, defocus_edge=0.9, step=2.0)
+        y1 = O.probe_wigner(a % (2 * s), b % (2 * s), 2 * s, 2 * s, n, n, radius, defocus_edge=0.9, step=1.0)
+        assert np.max(np.abs(y2 - y1)) < 1e-15
+
+
+def test_aperture_centre_moves_the_whole_method_with_the_frames():
+    """Reading R3 with the aperture centre c as an acquisition setting: frames whose
+    diffraction disc sits at c + (dy, dx) on the detector, reconstructed with that centre,
+    give exactly the D of the same frames centred at c, because aperture, basis and kept
+    set all move with c (the detector is large enough that nothing reaches its edge)."""
+    wl = synth.Workload("c", 16, 16, 64, 8.0, 16, 16, 32, 12, 1.5, 0.3, None, seed=5)
+    pos = synth.raster_positions(wl.sy, wl.sx)
+    frames = wl.frames(pos)
+    amp = wl.aperture_amplitude()
+    base = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=amp, defocus_edge=0.8)
+    _, d0, _ = O.offline_reduced(base, frames, pos)
+    for dy, dx in [(-3, 5), (2, -4)]:
+        moved = np.roll(frames, (dy, dx), axis=(1, 2))
+        plan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.k, amplitude=amp, defocus_edge=0.8,
+                           center=(wl.n // 2 + dy, wl.n // 2 + dx))
+        assert np.array_equal(plan.freqs, base.freqs)
+        _, d1, _ = O.offline_reduced(plan, moved, pos)
+        assert np.linalg.norm(d1 - d0) <= 1e-12 * np.linalg.norm(d0)
+        # the unmoved centre on moved frames is a different reconstruction
+        _, dwrong, _ = O.offline_reduced(base, moved, pos)
+        assert np.linalg.norm(dwrong - d0) > 1e-3 * np.linalg.norm(d0)
+
+
+@pytest.mark.parametrize("center", [(15.5, 16.0), (16.5, 14.5), (13.0, 17.5)])
+def test_kept_frequencies_match_bruteforce_off_centre(center):
+    sy = sx = 16
+    n, radius = 32, 5.0
+    got = set(map(tuple, O.nonzero_frequencies(sy, sx, n, n, radius, center=center).tolist()))
+    kept = set()
+    for vy in range(sy):
+        for vx in range(sx):
+            dy = (vy - sy if 2 * vy >= sy else vy) * n / sy
+            dx = (vx - sx if 2 * vx >= sx else vx) * n / sx
+            if any((qy - center[0]) ** 2 + (qx - center[1]) ** 2 <= radius ** 2 and
+                   (qy - center[0] + dy) ** 2 + (qx - center[1] + dx) ** 2 <= radius ** 2
+                   for qy in range(n) for qx in range(n)):
+                kept.add((vy, vx))
+    assert got == kept
