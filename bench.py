@@ -1,10 +1,13 @@
 """Benchmark of the live WDD per-frame update on one MI355X.
 
-A step is one pass of the whole hot path over one batch of frames: decode and
-project the batch onto the reduced basis, phase-weight and accumulate it into
-the spectrum, Wiener-reduce, inverse DFT, and copy the displayed object to the
-host.  Frames are resident in HBM before the timed region starts.  Prints one
-JSON line (rank 0, one GPU).
+A step is one pass of the whole hot path over one batch of frames: decode and project
+the batch onto the reduced basis, phase-weight it and add it to the spectrum (with the
+Wiener filter applied per frame in the object order, the default, or at the snapshot in
+the spectrum order), inverse DFT and display.  Frames are resident in HBM before the
+timed region starts, and the displayed image is written to a buffer in HBM (steps
+pipeline on the plan's stream); the rate with every image brought to host memory is
+reported beside it.  The default workload is the largest single acquisition (512 x 512
+scan, 256 x 256 uint16 detector, K = 128).  Prints one JSON line (one GPU).
 """
 import argparse
 import json
@@ -28,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="medium")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--order", default="object", choices=["spectrum", "object"],
                     help="accumulate the spectrum A (Wiener filter at snapshot) or the object spectrum D "
                          "(Wiener filter per frame)")
@@ -37,24 +40,25 @@ def parse():
                          "conventional WDD; detectors up to 64x64)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16_hilo", "fp16_hilo", "bf16", "fp16"],
                     help="arithmetic of the projection's first stage (FP32 accumulation throughout)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle baseline (0: skip)")
-    ap.add_argument("--profile-period", type=int, default=8,
-                    help="time the dominant stage with HIP events on one step in every N of the timed region")
-    ap.add_argument("--no-profile", action="store_true", help="skip the per-stage HIP event timing")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle baseline (0: skip)")
+    ap.add_argument("--no-profile", action="store_true", help="skip the untimed per-stage HIP event pass")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (other Wiener order, snapshot cadence, precision, serving)")
     ap.add_argument("--display", default="deferred", choices=["deferred", "async"],
                     help="pipelined steps: each image written by the next push's first launch (deferred) or "
                          "queued at once (async)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
-    ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the single acquisition")
+    ap.add_argument("--serving", action="store_true", help="run the Poisson-paced serving mix instead")
     ap.add_argument("--serving-acquisitions", type=int, default=24)
     ap.add_argument("--serving-budget-mb", type=int, default=1024)
     ap.add_argument("--serving-precision", default="bf16_hilo")
     ap.add_argument("--serving-order", default="object", choices=["spectrum", "object"])
     ap.add_argument("--serving-saturate", action="store_true", help="submit frames as fast as possible")
     ap.add_argument("--serving-limit-s", type=float, default=150.0)
-    ap.add_argument("--pool-batches", type=int, default=128,
-                    help="distinct batches generated (steps cycle through them); the medium workload has 128")
+    ap.add_argument("--pool-batches", type=int, default=4,
+                    help="distinct batches generated (steps cycle through them; the work per step does not "
+                         "depend on the frame values)")
     return ap.parse_args()
 
 
@@ -66,98 +70,273 @@ def workload_label(wl, n_freq, k, fourier=False):
             f"batches of {wl.batch} in raster order, snapshot after every batch")
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the calibrated rocprofv3 counter passes recorded in
-    profiles/hbm_traffic.md, or None when that record is missing or the kernel source has
-    changed since the counters were taken."""
+def _kernels_sha():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
     src = os.path.join(ROOT, "paper_2212_01309_amd", "csrc", "kernels.hip")
-    if not os.path.exists(path):
-        return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for line in open(path):
-        if line.startswith("traffic:"):
-            f = dict(kv.split("=", 1) for kv in line.split()[1:])
-            if f.get("workload") == workload and f.get("kernel") == kernel and f.get("kernels_sha") == digest:
-                return float(f["bytes_per_launch"])
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def profile_record(kind, workload, kernel):
+    """A machine-readable line `<kind>: workload=.. kernel=.. ... kernels_sha=..` from the
+    rocprofv3 summaries under profiles/, valid only while kernels.hip is unchanged."""
+    digest = _kernels_sha()
+    pdir = os.path.join(ROOT, "profiles")
+    for name in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        for line in open(os.path.join(pdir, name)):
+            if line.startswith(kind + ":"):
+                f = dict(kv.split("=", 1) for kv in line.split()[1:])
+                if f.get("workload") == workload and f.get("kernel") == kernel and f.get("kernels_sha") == digest:
+                    f["file"] = "profiles/" + name
+                    return f
     return None
 
 
-def roofline(wl, n_freq, k, dom, us, factored, fused, order="spectrum", fourier=False):
-    """Roofline entry of stage `dom` (mean launch time `us`), from its algorithmic work."""
-    if dom == "accumulate" and fourier:
-        # one workgroup per kept frequency streams its W row (object order) or its A row
-        # (read and write; W too when the Wiener reduction is fused)
-        nbytes = (8.0 if order == "object" else (24.0 if fused else 16.0)) * n_freq * k
-        kernel = "k_update_c<%d>" % (0 if order == "object" else (2 if fused else 1))
-        bound = "hbm"
-    elif dom == "accumulate" and order == "object":
-        # object order: stream W once per row pass (D, the frames' projections and the
-        # twiddles are a few hundred kB)
-        nbytes, kernel, bound = 8.0 * n_freq * k, "k_row_fused_obj", "hbm"
-    elif dom == "accumulate" and factored:
-        # row-factored update: read and write A, read W when the Wiener reduction is fused
-        nbytes = (24.0 if fused else 16.0) * n_freq * k
-        kernel, bound = "k_row_update" + ("<true>" if fused else "<false>"), "hbm"
-    elif dom == "accumulate":
-        flops = 4.0 * n_freq * k * wl.batch            # complex phase x real coefficient per (v, k, frame)
-        ach = flops / (us * 1e-6) / 1e12
-        return {"kernel": "k_accumulate", "bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "avg_us": us}
-    elif dom == "wiener":
-        nbytes, kernel, bound = 16.0 * n_freq * k, "k_wiener", "hbm"
-    elif dom == "project":
-        nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
-        kernel, bound = "k_project", "hbm"
+def roofline(wl, n_freq, k, order, fourier, precision, event_us):
+    """Roofline entry of the accumulation kernel (the method's O(S^2 L^2) term and the
+    largest kernel of every workload's kernel trace): algorithmic bytes per launch over the
+    kernel's average duration from the rocprofv3 kernel trace recorded under profiles/ for
+    this kernel source, with the live HIP-event mean from the untimed stage pass beside it
+    (events include the launch's dispatch latency)."""
+    if fourier:
+        nbytes = (8.0 if order == "object" else 24.0) * n_freq * k
+        kernel = "k_update_c<%d>" % (0 if order == "object" else 2)
+    elif order == "object":
+        # stream W once per row pass (D, the projections and the twiddles are a few hundred kB)
+        nbytes, kernel = 8.0 * n_freq * k, "k_row_fused_obj"
     else:
-        nbytes = 3 * 8.0 * wl.sy * wl.sx
-        kernel, bound = "k_dft_rows (x2)", "hbm"
+        # read and write A, read W (the Wiener reduction fused in before a snapshot)
+        nbytes, kernel = 24.0 * n_freq * k, "k_row_update<true>"
+    trace = profile_record("kernel_trace", wl.name, kernel)
+    if trace is not None:
+        us, source = float(trace["avg_us"]), f"rocprofv3 kernel trace, {trace['file']}"
+    else:
+        us, source = event_us, "HIP events (untimed stage pass; no kernel trace recorded for this kernel source)"
     ach = nbytes / (us * 1e-6) / 1e9
-    return {"kernel": kernel, "bound": bound, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(wl.name, kernel), "avg_us": us,
+    traffic = profile_record("traffic", wl.name, kernel)
+    return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": float(traffic["bytes_per_launch"]) if traffic else None,
+            "avg_us": us, "avg_us_source": source, "hip_event_us": event_us, "algorithmic_bytes": nbytes,
+            "algorithmic_bytes_rule": ("8 * n_freq * K (W read once)" if order == "object"
+                                       else "24 * n_freq * K (A read and written, W read)")}
+
+
+def projection_roofline(wl, k):
+    """The projection kernel against HBM: frame bytes + h written per launch, over the
+    kernel-trace average recorded for this source (None without one)."""
+    kernel = "k_project<unsigned short>" if wl.dose else "k_project<float>"
+    trace = profile_record("kernel_trace", wl.name, kernel)
+    if trace is None:
+        return None
+    nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
+    us = float(trace["avg_us"])
+    return {"kernel": kernel, "bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": nbytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, "avg_us": us,
             "algorithmic_bytes": nbytes}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, frames, pos, seconds, fourier=False):
-    """The FP64 oracle's live path (same step: push one batch, then snapshot) on the host cores."""
+    """The FP64 oracle's live path on the host cores, for the same step (push one batch,
+    then snapshot).  The oracle's per-step work is linear in the number of kept frequencies
+    except for the projection and the display's inverse FFT, so on workloads with many
+    frequencies its plan is built on a random sample of them and the frequency-dependent
+    part scaled by n_freq / sample: each part is timed with the oracle's own functions."""
     import oracle.wdd as O
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        threads = None
+    cores = len(os.sched_getaffinity(0))
+    all_f = O.nonzero_frequencies(wl.sy, wl.sx, wl.n, wl.n, wl.radius, wl.step)
+    n_freq = len(all_f)
+    sample = min(n_freq, 2048)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(n_freq, size=sample, replace=False)) if sample < n_freq else np.arange(n_freq)
     t0 = time.perf_counter()
     plan = O.make_plan(wl.sy, wl.sx, wl.n, wl.n, wl.radius, None if fourier else wl.k,
                        amplitude=wl.aperture_amplitude(), defocus_edge=wl.defocus_edge, step=wl.step,
-                       phi=O.fourier_basis(wl.n, wl.n) if fourier else None)
+                       phi=O.fourier_basis(wl.n, wl.n) if fourier else None, freqs=all_f[pick])
     plan_s = time.perf_counter() - t0
+    scale = n_freq / sample
+    nb = len(pos) // wl.batch
 
-    def run(budget):
+    def one_run(budget):
         live = O.Live(plan, "N")
-        done = 0
-        t0 = time.perf_counter()
+        t_proj = t_push = t_extract = t_snap = 0.0
+        steps = 0
+        t_start = time.perf_counter()
         while True:
-            b = (done * wl.batch) % len(pos)
-            live.push(frames[b:b + wl.batch], pos[b:b + wl.batch])
-            live.snapshot()
-            done += 1
-            el = time.perf_counter() - t0
-            if el >= budget or done * wl.batch >= len(pos):
-                return done, el
+            b = (steps % nb) * wl.batch
+            fr, ps = frames[b:b + wl.batch], pos[b:b + wl.batch]
+            t = time.perf_counter()
+            O.project(fr, plan.phi)
+            t_proj += time.perf_counter() - t
+            t = time.perf_counter()
+            live.push(fr, ps)                      # projection + phases + accumulation
+            t_push += time.perf_counter() - t
+            t = time.perf_counter()
+            live.spectrum()                        # the Wiener reduction
+            t_extract += time.perf_counter() - t
+            t = time.perf_counter()
+            live.snapshot()                        # reduction + scatter + inverse FFT + normalisation
+            t_snap += time.perf_counter() - t
+            steps += 1
+            if time.perf_counter() - t_start >= budget:
+                break
+        # full-size step: projection + scaled accumulation + scaled reduction + display
+        step_s = (t_proj + (t_push - t_proj) * scale + t_extract * scale + (t_snap - t_extract)) / steps
+        return wl.batch / step_s, steps
 
-    done, el = run(seconds)
-    out = {"value": done * wl.batch / el, "unit": "frames/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{done} steps of {wl.batch} frames (push + snapshot each) of the same workload, FP64 NumPy, "
-                     f"{el:.1f} s; plan build {plan_s:.1f} s excluded"}
-    try:  # the same on one thread, a third of the time budget
+    runs = [one_run(seconds / 3) for _ in range(3)]
+    vals = sorted(r[0] for r in runs)
+    out = {"value": vals[1], "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": (f"median of 3 runs of ~{seconds / 3:.0f} s ({', '.join(str(r[1]) for r in runs)} steps of "
+                      f"{wl.batch} frames: push, then snapshot) on the same workload, FP64 NumPy; plan on "
+                      f"{sample} of {n_freq} kept frequencies, frequency-dependent time scaled by "
+                      f"{scale:.2f}; plan build {plan_s:.1f} s excluded"),
+           "runs": vals, "blas_threads": threads, "cpu_model": cpu_model()}
+    try:  # the same on one thread, one short run
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
-            d1, e1 = run(seconds / 3)
-        out["value_1_thread"] = d1 * wl.batch / e1
+            out["value_1_thread"] = one_run(seconds / 6)[0]
     except ImportError:
         pass
     return out
+
+
+def make_plan(wdd, wl, order, precision="fp32", fourier=False, max_batch=None):
+    return wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.n * wl.n if fourier else wl.k,
+                    dtype=wdd.WDD_U16 if wl.dose else wdd.WDD_F32, defocus=wl.defocus_edge,
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=max_batch or wl.batch,
+                    precision=precision,
+                    order=wdd.WDD_ORDER_OBJECT if order == "object" else wdd.WDD_ORDER_SPECTRUM,
+                    basis=wdd.WDD_BASIS_FOURIER if fourier else wdd.WDD_BASIS_HERMITE_GAUSS)
+
+
+def run_steps(plan, batches, shown, first, count, defer, snapshot_every=1):
+    """`count` pipelined steps from step number `first`; returns the host time spent issuing."""
+    nb = len(batches)
+    issue = 0.0
+    for i in range(first, first + count):
+        fr, ps = batches[i % nb]
+        t = time.perf_counter()
+        if (i + 1) % snapshot_every == 0:
+            plan.push_snapshot(fr, ps, out=shown, wait=False, defer=defer)
+        else:
+            plan.push(fr, ps)
+        issue += time.perf_counter() - t
+    return issue
+
+
+def timed(torch, plan, batches, shown, warmup, steps, defer, snapshot_every=1):
+    run_steps(plan, batches, shown, 0, warmup, defer, snapshot_every)
+    plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    issue = run_steps(plan, batches, shown, warmup, steps, defer, snapshot_every)
+    plan.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, issue
+
+
+DEVICE_FRAME_BYTES = 1 << 30   # frames held in HBM for the timed steps: 4x the 256 MB last-level cache
+
+
+def load_batches(torch, wl, pool_batches):
+    """Frames of `pool_batches` batches generated on the host, copied into HBM as many times
+    as it takes to fill DEVICE_FRAME_BYTES (at most the whole acquisition), so that steps read
+    frames from HBM rather than from the last-level cache; a step's positions walk the whole
+    raster."""
+    import synth
+    total = (wl.sy * wl.sx) // wl.batch
+    nb = max(1, min(pool_batches, total))
+    pos_all = synth.raster_positions(wl.sy, wl.sx)
+    pos = pos_all[:nb * wl.batch]
+    t0 = time.perf_counter()
+    frames = wl.frames(pos)
+    gen_s = time.perf_counter() - t0
+    host = frames.view(np.int16) if frames.dtype == np.uint16 else frames
+    pool = torch.from_numpy(host).to("cuda")
+    batch_bytes = host[:wl.batch].nbytes
+    ndev = max(nb, min(total, -(-DEVICE_FRAME_BYTES // batch_bytes)))
+    reps = -(-ndev // nb)
+    dev = pool.repeat((reps,) + (1,) * (pool.dim() - 1))[:ndev * wl.batch].contiguous()
+    del pool
+    torch.cuda.synchronize()
+    batches = [(dev[(i % ndev) * wl.batch:((i % ndev) + 1) * wl.batch], pos_all[i * wl.batch:(i + 1) * wl.batch])
+               for i in range(total)]
+    return frames, pos, batches, gen_s
+
+
+def precision_lines(torch, wdd, synth, steps, warmup):
+    """The reduced-precision projections beside FP32 on the precision workload (256 x 256
+    scan, 128 x 128 uint16 detector with a defocused probe, K = 64), same steps."""
+    wl = synth.WORKLOADS["defocus"]
+    _, _, batches, _ = load_batches(torch, wl, 4)
+    shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
+    out = {"workload": "defocus: 256x256 scan, 128x128 uint16 detector (1e3 e/frame, pi rad defocus at the rim), "
+                       "K=64, 51167 kept frequencies, object order, batches of 256, snapshot after every batch",
+           "steps": steps}
+    for prec in ("fp32", "bf16_hilo", "fp16_hilo"):
+        with make_plan(wdd, wl, "object", prec) as plan:
+            el, _ = timed(torch, plan, batches, shown, warmup, steps, True)
+        out[prec] = {"frames_per_s": steps * wl.batch / el, "us_per_step": el / steps * 1e6}
+    return out
+
+
+def serving_line(torch, wdd, synth, limit_s=20.0):
+    """A short serving mix beside the single acquisition: 8 acquisitions of different scan
+    and detector sizes, every frame available at the start (saturated), BF16 hi+lo
+    projection, object order, 1 GiB budget; aggregate frames/s and submit-to-snapshot
+    latency."""
+    rng = np.random.default_rng(7)
+    pools = {}
+    for n in (64, 128, 256):
+        radius = n / 4 if n <= 128 else 48.0
+        wl = synth.Workload(f"pool{n}", 32, 32, n, radius, 64, 256, 2 * n, 30, (1.0, 3.0), (0.2, 0.5), 5e3, seed=n)
+        fr = wl.frames(synth.raster_positions(8, 32))               # 256 frames per detector size
+        pools[n] = torch.from_numpy(fr.view(np.int16)).to("cuda")
+    torch.cuda.synchronize()
+    geoms = [(64, 64), (128, 64), (128, 128), (256, 128), (128, 256), (256, 64), (64, 256), (256, 256)]
+    srv = wdd.Server(hbm_budget_bytes=1 << 30, snapshot_interval_us=1000.0, batch_frames=512)
+    todo = []
+    for s, n in geoms:
+        aid = srv.open(n / 4 if n <= 128 else 48.0, s, s, n, n, 64 if n <= 128 else 128, precision="bf16_hilo",
+                       order=wdd.WDD_ORDER_OBJECT)
+        todo.append(dict(id=aid, s=s, n=n, sent=0, total=s * s, pos=synth.raster_positions(s, s)))
+    t0 = time.perf_counter()
+    while todo and time.perf_counter() - t0 < limit_s:
+        for a in list(todo):
+            if a["id"] is None:
+                todo.remove(a)
+                continue
+            nb = int(rng.integers(1, 513))
+            nb = min(nb, a["total"] - a["sent"], 256 - a["sent"] % 256)
+            srv.submit(a["id"], pools[a["n"]][a["sent"] % 256:a["sent"] % 256 + nb], a["pos"][a["sent"]:a["sent"] + nb])
+            a["sent"] += nb
+            if a["sent"] >= a["total"]:
+                srv.snapshot(a["id"])
+                srv.close(a["id"])
+                todo.remove(a)
+        srv.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.destroy()
+    return {"workload": "8 acquisitions, scans 64^2..256^2, detectors 64^2..256^2, all frames available at t=0, "
+                        "deliveries of 1-512 frames, bf16 hi+lo projection, object order, snapshot every >= 1 ms",
+            "frames_per_s": st["frames"] / wall, "frames": st["frames"], "wall_s": wall,
+            "latency_ms": {"p50": st["latency_p50_us"] / 1e3, "p99": st["latency_p99_us"] / 1e3}}
 
 
 def serving(args):
@@ -256,16 +435,13 @@ def serving(args):
 
 def main():
     args = parse()
-    if args.serving:
-        if args.gpus != 1:
-            print("bench.py measures one GPU only", file=sys.stderr)
-            sys.exit(2)
-        serving(args)
-        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (sharding the update "
               f"over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args)
+        return
     import torch
 
     if args.copy_calibration:
@@ -281,90 +457,64 @@ def main():
     import synth
 
     wl = synth.WORKLOADS[args.workload]
-    pos = synth.raster_positions(wl.sy, wl.sx)[:args.pool_batches * wl.batch]
-    t0 = time.perf_counter()
-    frames = wl.frames(pos)
-    gen_s = time.perf_counter() - t0
-    host = frames.view(np.int16) if frames.dtype == np.uint16 else frames
-    dev = torch.from_numpy(host).to("cuda")
-    torch.cuda.synchronize()
-    dtype = wdd.WDD_U16 if frames.dtype == np.uint16 else wdd.WDD_F32
     fourier = args.basis == "fourier"
-    plan = wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.n * wl.n if fourier else wl.k, dtype=dtype,
-                    defocus=wl.defocus_edge, amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=wl.batch,
-                    precision=args.precision,
-                    order=wdd.WDD_ORDER_OBJECT if args.order == "object" else wdd.WDD_ORDER_SPECTRUM,
-                    basis=wdd.WDD_BASIS_FOURIER if fourier else wdd.WDD_BASIS_HERMITE_GAUSS)
-    nb = len(pos) // wl.batch
-    batches = [(dev[i * wl.batch:(i + 1) * wl.batch], pos[i * wl.batch:(i + 1) * wl.batch]) for i in range(nb)]
-
-    # the displayed image stays in HBM (as the frames do); steps pipeline on the plan's stream
+    frames, pos, batches, gen_s = load_batches(torch, wl, args.pool_batches)
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
+    defer = args.display == "deferred"
+    plan = make_plan(wdd, wl, args.order, args.precision, fourier)
+    n_freq, k = plan.n_freq, plan.k
 
-    def step(i, wait=False):
-        fr, ps = batches[i % nb]
-        plan.push_snapshot(fr, ps, out=shown, wait=wait, defer=not wait and args.display == "deferred")
-
-    for i in range(args.warmup):
-        step(i)
-    stage_bits = {"project": wdd.STAGE_PROJECT, "rowdft": wdd.STAGE_ROWDFT, "accumulate": wdd.STAGE_ACCUMULATE,
-                  "wiener": wdd.STAGE_WIENER, "display": wdd.STAGE_DISPLAY}
     stages = None
     if not args.no_profile:
-        # untimed pass over every stage to find the dominant one; the timed region then brackets
-        # only that stage with events (each timed launch costs two event records)
+        # untimed pass over every stage with HIP events on the plan stream (each timed launch
+        # costs two event records, so none are recorded in the timed region)
         plan.profile_enable(wdd.STAGE_ALL)
-        for i in range(min(args.warmup, 100) or 20):
-            step(i)
+        run_steps(plan, batches, shown, 0, max(20, min(args.warmup, 100)), defer)
         pre = plan.profile_read()
-        stages = {s: (pre[f"{s}_ms"] / pre[f"{s}_launches"] * 1e3 if pre[f"{s}_launches"] else 0.0)
-                  for s in stage_bits}
-        # the roofline entry is the accumulation kernel (the method's O(S^2 L^2) loop, the largest
-        # kernel in the rocprofv3 summaries); the others are reported per launch beside it
-        per_kernel = {s: stages[s] / (2.0 if s == "display" else 1.0) for s in stages}
-        dominant = "accumulate"
-        factored, fused = pre["factored_launches"] > 0, pre["wiener_launches"] == 0
-        # events on one step in every `period` of the timed region (each timed launch costs two
-        # event records, about 6 us of a 30 us step)
-        plan.profile_period(args.profile_period)
-        plan.profile_enable(stage_bits[dominant])
-    plan.sync()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    plan.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    prof = plan.profile_read() if not args.no_profile else None
-    if not args.no_profile:
         plan.profile_enable(0)
-        plan.profile_period(1)
-    # untimed: latency of one step (push to image complete in HBM), and the rate when every
-    # image is also brought to the host through the plan's pinned buffer (PCIe included)
-    nlat = min(args.steps, 500)
+        stages = {s: (pre[f"{s}_ms"] / pre[f"{s}_launches"] * 1e3 if pre[f"{s}_launches"] else 0.0)
+                  for s in ("project", "rowdft", "accumulate", "wiener", "display")}
+
+    elapsed, issue = timed(torch, plan, batches, shown, args.warmup, args.steps, defer)
+
+    # untimed: latency from a push's call to its image ready in host memory (blocking push +
+    # snapshot into the plan's pinned buffer), the rate with every image brought to the host,
+    # and frames streamed from host memory instead (staged through pinned memory over PCIe)
+    nlat = max(100, min(args.steps, 500))
+    pinned = plan.snapshot_buffer()
     lat = np.empty(nlat)
     for i in range(nlat):
+        fr, ps = batches[i % len(batches)]
         t = time.perf_counter()
-        step(i, wait=True)
-        lat[i] = time.perf_counter() - t
-    pinned = plan.snapshot_buffer()
-    t = time.perf_counter()
-    for i in range(nlat):
-        fr, ps = batches[i % nb]
         plan.push_snapshot(fr, ps, out=pinned)
-    host_fps = nlat * wl.batch / (time.perf_counter() - t)
-    # frames streamed from host memory instead (the library stages them through pinned
-    # memory and copies them over PCIe), display kept in HBM
+        lat[i] = time.perf_counter() - t
+    host_fps = nlat * wl.batch / lat.sum()
+    nb = len(frames) // wl.batch
     host_frames = [frames[i * wl.batch:(i + 1) * wl.batch] for i in range(nb)]
     plan.sync()
     t = time.perf_counter()
     for i in range(nlat):
-        plan.push_snapshot(host_frames[i % nb], batches[i % nb][1], out=shown, wait=False)
+        plan.push_snapshot(host_frames[i % nb], batches[i % len(batches)][1], out=shown, wait=False)
     plan.sync()
     host_frames_fps = nlat * wl.batch / (time.perf_counter() - t)
-    n_freq, k = plan.n_freq, plan.k
+    extras = {}
+    if not args.no_extras and wl.snapshot_every:
+        # the configuration's own snapshot cadence (every snapshot_every frames)
+        every = max(1, wl.snapshot_every // wl.batch)
+        el, _ = timed(torch, plan, batches, shown, args.warmup, max(args.steps, 2 * every), defer, every)
+        steps_c = max(args.steps, 2 * every)
+        extras["snapshot_every_%d_frames" % wl.snapshot_every] = {
+            "frames_per_s": steps_c * wl.batch / el, "us_per_batch": el / steps_c * 1e6, "steps": steps_c}
     plan.close()
+
+    if not args.no_extras and not fourier:
+        other = "spectrum" if args.order == "object" else "object"
+        with make_plan(wdd, wl, other, args.precision) as p2:
+            el, _ = timed(torch, p2, batches, shown, args.warmup, args.steps, defer)
+        extras[f"{other}_order"] = {"frames_per_s": args.steps * wl.batch / el, "us_per_step": el / args.steps * 1e6,
+                                    "note": ("A resident in HBM, Wiener filter at each snapshot (the sufficient "
+                                             "statistic kept)" if other == "spectrum" else
+                                             "Wiener filter per frame, D accumulated")}
 
     fps = args.steps * wl.batch / elapsed
     out = {
@@ -378,18 +528,23 @@ def main():
                    "wiener_order": args.order, "basis": args.basis,
                    "display": "hbm" + (", each image's last pass deferred to the next push's projection launch "
                                        "where the plan allows it (FP32 Hermite-Gauss projection, detector rows "
-                                       "<= 128, power-of-two scan width)" if args.display == "deferred" else "")},
+                                       "<= 128, power-of-two scan width)" if defer else "")},
+        "host_issue_us_per_step": issue / args.steps * 1e6,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
-                       "steps": nlat},
+                       "samples": nlat, "definition": "wdd_push_snapshot call to the image complete in host memory"},
         "host_display_fps": host_fps,
         "host_frames_fps": host_frames_fps,
     }
-    if prof is not None:
-        # the dominant stage's mean launch time over the timed region replaces the pre-pass value
-        stages[dominant] = prof[f"{dominant}_ms"] / max(prof[f"{dominant}_launches"], 1) * 1e3
-        out["stages_us"] = stages
-        out["largest_kernel_stage"] = max(per_kernel, key=per_kernel.get)
-        out["roofline"] = roofline(wl, n_freq, k, dominant, stages[dominant], factored, fused, args.order, fourier)
+    if stages is not None:
+        out["stages_us_hip_events"] = stages
+        out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"])
+        proj = None if fourier or args.precision != "fp32" else projection_roofline(wl, k)
+        if proj is not None:
+            out["roofline_projection"] = proj
+    out.update(extras)
+    if not args.no_extras and args.workload == "large" and not fourier:
+        out["precision_variants"] = precision_lines(torch, wdd, synth, max(args.steps, 500), args.warmup)
+        out["serving"] = serving_line(torch, wdd, synth)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(wl, frames, pos, args.cpu_seconds, fourier)
     out["generation_s"] = gen_s

@@ -347,6 +347,20 @@ wdd_status wdd_sync(wdd_plan_t p);
  * is accepted. */
 wdd_status wdd_destroy(wdd_plan_t p);
 
+/* The display of a spectrum given on the whole scan grid (eq. extract; the final step of
+ * the modified-WDD algorithm, Section 6.3): out = conj(IDFT2_unitary(D)) / sqrt(|D[0, 0]|),
+ * all zeros when D[0, 0] = 0.
+ *   spectrum  device, sy x sx complex values (interleaved float, row-major [v_y][v_x], 0-based
+ *             DFT indices; zero outside the kept frequencies), 8-byte aligned; read only;
+ *   out       device, sy x sx complex values [y][x], 8-byte aligned; may not overlap spectrum;
+ *   hip_stream  the hipStream_t the work is queued on (NULL: the null stream).
+ * 1 <= sy, sx <= 4096.  Asynchronous: returns once the work is queued; out is complete when
+ * the stream reaches this point.  The scratch (two sy x sx grids and the twiddles) is taken
+ * with hipMallocAsync and returned with hipFreeAsync on the same stream.  Stateless: calls on
+ * different streams are independent.  WDD_EINVAL (sizes, null or misaligned pointers),
+ * WDD_ENOMEM, WDD_EDEVICE. */
+wdd_status wdd_display(const float* spectrum, int32_t sy, int32_t sx, float* out, void* hip_stream);
+
 /* Device memory for plans created after this call (tables, spectrum, grids, device
  * staging; not pinned host buffers) comes from alloc(bytes, ctx) and goes back through
  * release(ptr, ctx) when the plan is destroyed, after its stream has drained: a caller

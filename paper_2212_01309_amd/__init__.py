@@ -125,6 +125,7 @@ _SIGNATURES = {
     "wdd_reset": (ctypes.c_int, [_P]),
     "wdd_sync": (ctypes.c_int, [_P]),
     "wdd_destroy": (ctypes.c_int, [_P]),
+    "wdd_display": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "wdd_server_default_options": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
     "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
@@ -602,6 +603,26 @@ class Server:
             self.destroy()
         except Exception:
             pass
+
+
+def display(spectrum, out=None, stream: Optional[int] = None):
+    """O~ = conj(IDFT2_unitary(D)) / sqrt(|D[0, 0]|) of a spectrum grid D [sy, sx] (complex64
+    torch GPU tensor) into `out` (a new complex64 GPU tensor if None), queued on `stream`
+    (a hipStream_t; None: torch's current stream) (wdd_display)."""
+    import torch
+    if not (_is_device_tensor(spectrum) and spectrum.dtype == torch.complex64 and spectrum.dim() == 2
+            and spectrum.is_contiguous()):
+        raise ValueError("spectrum must be a contiguous 2-D complex64 GPU tensor")
+    sy, sx = spectrum.shape
+    if out is None:
+        out = torch.empty_like(spectrum)
+    elif not (_is_device_tensor(out) and out.dtype == torch.complex64 and tuple(out.shape) == (sy, sx)
+              and out.is_contiguous()):
+        raise ValueError("out must be a contiguous complex64 GPU tensor of the spectrum's shape")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(load_library().wdd_display(spectrum.data_ptr(), sy, sx, out.data_ptr(), _P(stream) if stream else None))
+    return out
 
 
 def header_symbols(header: Optional[str] = None) -> Tuple[str, ...]:

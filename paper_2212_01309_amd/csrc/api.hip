@@ -103,6 +103,7 @@ struct wdd_plan_impl {
   int32_t deferred_sr = 0, deferred_sm = 0, deferred_nslot = 1, deferred_slot_stride = 0;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
+  float2* dlo = nullptr;  // object order: the rounding remainder of D (D = d + dlo, compensated sum)
 
   int up_ring = 4, mark_every = 1;   // upload blocks in the ring; marker spacing in pushes
   std::vector<char*> pin_up;         // [up_ring]
@@ -273,13 +274,13 @@ wdd_status column_pass(wdd_plan_s* p, const float2* src, int32_t sr, int32_t sm,
   return WDD_OK;
 }
 
-// A deferred column pass can ride in the next push's projection launch (the FP32
-// Hermite-Gauss projection kernel, radix-2 rows: power-of-two Sx).  Detectors of more than
-// 128 rows keep it in its own launch: their 1024-thread projection workgroups (one wave per
-// 16 rows) would carry the display rows too, and the merged launch then took longer than
-// the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
+// A deferred column pass can ride in the next push's projection launch (the Hermite-Gauss
+// projection kernels, any arithmetic; radix-2 rows: power-of-two Sx).  Detectors of more
+// than 128 rows keep it in its own launch: their 1024-thread projection workgroups (one wave
+// per 16 rows) would carry the display rows too, and the merged launch then took longer
+// than the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
 bool can_defer(const wdd_plan_s* p) {
-  return !p->fourier && p->precision == WDD_FP32 && p->ny <= 128 && (p->sx & (p->sx - 1)) == 0;
+  return !p->fourier && p->ny <= 128 && (p->sx & (p->sx - 1)) == 0;
 }
 
 // Writes a display left to the next push now; every call that waits for the plan's stream
@@ -458,6 +459,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     p->frames = fr;
   }
   ALLOC(p->d, (size_t)p->n_freq_pad);
+  if (p->order_mode == WDD_ORDER_OBJECT) ALLOC(p->dlo, (size_t)p->n_freq_pad);
   ALLOC(p->z, grid);
   ALLOC(p->u, grid);
 #undef ALLOC
@@ -497,6 +499,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   // slots that no chunk owns stay zero for the plan's life
   if (p->up) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->up), (size_t)t.sx * p->nslot * t.sy * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
+  if (p->dlo) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
 
   {
@@ -557,6 +560,7 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
     const int64_t nchunks_max = t.n_freq() / kMinChunk + t.sx + 1;  // upper bound of the chunk count
     b += a(t.n_freq() * 8) + a(nchunks_max * 16);
   }
+  if (opts.order == WDD_ORDER_OBJECT) b += a(nfp * 8);  // D's rounding remainder
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
 }
@@ -724,30 +728,55 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   }
   p->profile_now = (p->profile_tick++ % p->profile_period) == 0;
   hipEvent_t end;
-  if (p->fourier || p->precision != WDD_FP32) {  // a deferred display rides only in the FP32 projection
+  if (p->fourier) {  // a deferred display rides only in the Hermite-Gauss projection
     if ((st = flush_deferred(p)) != WDD_OK) return st;
   }
   WDD_HIP(p, stage_begin(p, kProject, &end));
-  // the projection kernel also brings the pinned upload block (positions, grouping) to the device
+  // the projection launch also brings the pinned upload block (positions, grouping) to the device
   if (p->fourier) {
     WDD_HIP(p, wdd::launch_project_fourier(p->dtype, fdev, n, p->ny, p->nx, p->fy, p->fx,
                                            reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
                                            p->stream));
-  } else if (p->precision == WDD_FP32 && p->deferred_dst) {
-    // the previous step's column pass rides in this launch (it reads its source and D before
-    // this push's update changes them)
-    float2* dst = p->deferred_dst;
-    p->deferred_dst = nullptr;
-    WDD_HIP(p, wdd::launch_project_display(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up,
-                                           p->upload, up_bytes, ftab, p->deferred_src, dst, p->sy, p->sx, p->ex, p->d,
-                                           (float)((double)p->sy * p->sx), p->deferred_sr, p->deferred_sm, p->sx, 1,
-                                           p->deferred_nslot, p->deferred_slot_stride, p->stream));
-  } else if (p->precision == WDD_FP32) {
-    WDD_HIP(p, wdd::launch_project(p->dtype, fdev, n, p->ny, p->nx, p->psi, p->kmap, p->kpad, p->h, up, p->upload,
-                                   up_bytes, ftab, p->stream));
   } else {
-    WDD_HIP(p, wdd::launch_project_lp(p->precision, fdev, n, p->ny, p->nx, p->psi, p->psix_lp, p->psi_unscale, p->kmap,
-                                      p->kpad, p->h, up, p->upload, up_bytes, ftab, p->stream));
+    wdd::ProjectLaunch pl;
+    pl.dtype = p->dtype;
+    pl.precision = p->precision;
+    pl.frames = fdev;
+    pl.n = n;
+    pl.ny = p->ny;
+    pl.nx = p->nx;
+    pl.psi = p->psi;
+    pl.psix_lp = p->psix_lp;
+    pl.psi_unscale = p->psi_unscale;
+    pl.kmap = p->kmap;
+    pl.kpad = p->kpad;
+    pl.h = p->h;
+    pl.up_src = up;
+    pl.up_dst = p->upload;
+    pl.up_bytes = up_bytes;
+    pl.fptr = ftab;
+    if (p->deferred_dst) {
+      // the previous step's column pass rides in this launch (it reads its source and D
+      // before this push's update changes them)
+      wdd::DisplayColumns dc;
+      dc.din = p->deferred_src;
+      dc.dout = p->deferred_dst;
+      dc.rows = p->sy;
+      dc.len = p->sx;
+      dc.e = p->ex;
+      dc.d0 = p->d;
+      dc.s_total = (float)((double)p->sy * p->sx);
+      dc.in_sr = p->deferred_sr;
+      dc.in_sm = p->deferred_sm;
+      dc.out_sr = p->sx;
+      dc.out_sc = 1;
+      dc.nslot = p->deferred_nslot;
+      dc.slot_stride = p->deferred_slot_stride;
+      p->deferred_dst = nullptr;
+      WDD_HIP(p, wdd::launch_project_display(pl, dc, p->stream));
+    } else {
+      WDD_HIP(p, wdd::launch_project(pl, p->stream));
+    }
   }
   WDD_HIP(p, stage_end(p, end));
   // the pinned data of this push may be refilled once this point of the stream is reached
@@ -778,7 +807,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       WDD_HIP(p, stage_end(p, end));
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
       WDD_HIP(p, wdd::launch_update_c(mode, p->t, p->kpad, rs, nr, p->ty, p->sy, p->sx, p->freqs, p->n_freq, p->w,
-                                      p->acc, p->d, p->z, p->stream));
+                                      p->acc, p->d, p->dlo, p->z, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
   } else if (object) {
@@ -795,7 +824,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       wdd::RowSet rs;
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
       WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
-                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->z, up_pass,
+                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z, up_pass,
                                            p->nslot, in_order, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
@@ -1202,8 +1231,10 @@ wdd_status wdd_checkpoint_load(wdd_plan_t p, const void* host_buf, size_t bytes)
     WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
     WDD_HIP(p, hipMemcpy2DAsync(p->acc, (size_t)p->kpad * sizeof(float2), src, (size_t)p->k * sizeof(float2),
                                 (size_t)p->k * sizeof(float2), (size_t)p->n_freq, hipMemcpyHostToDevice, p->stream));
-  } else {
+  } else {  // D itself (d is the FP32 value nearest the compensated sum; the remainder restarts at zero)
     WDD_HIP(p, hipMemcpyAsync(p->d, src, (size_t)p->n_freq * sizeof(float2), hipMemcpyHostToDevice, p->stream));
+    if (p->dlo)
+      WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
     WDD_HIP(p, wdd::launch_scatter_conj(p->d, p->freqs, p->n_freq, p->z, p->sy, p->stream));
   }
   p->up_valid = false;
@@ -1220,10 +1251,68 @@ wdd_status wdd_reset(wdd_plan_t p) {
   if (p->acc)
     WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->acc), (size_t)p->n_freq_pad * p->kpad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
+  if (p->dlo) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), (size_t)p->sy * p->sx * 2, p->stream));
   p->up_valid = false;
   p->frames_seen = 0;
   p->last_batch = 0;
+  return WDD_OK;
+}
+
+}  // extern "C"
+
+namespace wdd {
+
+wdd_status check_display_args(const float* spectrum, int32_t sy, int32_t sx, const float* out) {
+  if (!spectrum || !out) return fail(WDD_EINVAL, "null spectrum or output");
+  if (sy < 1 || sx < 1 || sy > kDisplayMaxSide || sx > kDisplayMaxSide)
+    return fail(WDD_EINVAL, "grid %d x %d outside [1, %d]", sy, sx, kDisplayMaxSide);
+  if ((reinterpret_cast<uintptr_t>(spectrum) % 8) != 0 || (reinterpret_cast<uintptr_t>(out) % 8) != 0)
+    return fail(WDD_EINVAL, "spectrum and output must be 8-byte aligned device memory");
+  return WDD_OK;
+}
+
+// The display of a spectrum grid through the scratch `scr` (display_scratch_floats(sy, sx)
+// floats): z = conj(d) transposed, rows of z along v_y into u, then the columns of u along v_x
+// written as whole output rows, scaled by 1 / sqrt(sy sx |d[0]|) (eq. extract).  Nothing in
+// the scratch needs to start at zero: every value is written before it is read.
+wdd_status display_grid(const float* spectrum, int32_t sy, int32_t sx, float* out, float* scratch, void* stream) {
+  const hipStream_t st = (hipStream_t)stream;
+  const float2* d = reinterpret_cast<const float2*>(spectrum);
+  const size_t cells = (size_t)sy * sx;
+  float2* z = reinterpret_cast<float2*>(scratch);
+  float2* u = z + cells;
+  float2* ey = u + cells;
+  float2* ex = ey + sy;
+  hipError_t e = launch_display_prep(d, sy, sx, z, ey, ex, st);
+  if (e == hipSuccess) e = launch_dft_rows(z, u, sx, sy, ey, d, 1.f, 0, sy, 1, sy, 1, 1, 0, st);
+  if (e == hipSuccess)
+    e = launch_dft_rows(u, reinterpret_cast<float2*>(out), sy, sx, ex, d, (float)((double)sy * sx), 1, 1, sy, sx, 1, 1,
+                        0, st);
+  if (e != hipSuccess) return fail(WDD_EDEVICE, "display launch: %s", hipGetErrorString(e));
+  return WDD_OK;
+}
+
+}  // namespace wdd
+
+extern "C" {
+
+wdd_status wdd_display(const float* spectrum, int32_t sy, int32_t sx, float* out, void* hip_stream) {
+  wdd_status st = wdd::check_display_args(spectrum, sy, sx, out);
+  if (st != WDD_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t bytes = wdd::display_scratch_floats(sy, sx) * sizeof(float);
+  float* scr = nullptr;
+  hipError_t e = hipMallocAsync((void**)&scr, bytes, s);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return wdd::fail(WDD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  if (e != hipSuccess) return wdd::fail(WDD_EDEVICE, "hipMallocAsync: %s", hipGetErrorString(e));
+  st = wdd::display_grid(spectrum, sy, sx, out, scr, hip_stream);
+  const hipError_t ef = hipFreeAsync(scr, s);
+  if (st != WDD_OK) return st;
+  if (ef != hipSuccess) return wdd::fail(WDD_EDEVICE, "hipFreeAsync: %s", hipGetErrorString(ef));
   return WDD_OK;
 }
 

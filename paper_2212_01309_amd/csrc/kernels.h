@@ -11,31 +11,44 @@
 
 namespace wdd {
 
-// h[b][k] = sum_q Phi[q][k] frames[b][q] for b < n.  psi: [ny][16] then [nx][16]
-// (columns >= L zero); kmap[k] = 16 n_y(k) + n_x(k), or -1 for padding columns.
-// Also copies up_bytes (a multiple of 4) from up_src (pinned host memory) to up_dst.  With fptr
-// (pinned host table of n device addresses) frame b is read from fptr[b], else from
-// frames + b * ny * nx.
-hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
-                          hipStream_t st);
+// Projection of a batch: h[b][k] = sum_q Phi[q][k] frames[b][q] for b < n.  psi: [ny][16]
+// then [nx][16] FP32 (columns >= L zero); kmap[k] = 16 n_y(k) + n_x(k), or -1 for padding
+// columns.  precision (a wdd_precision): WDD_FP32, or a reduced one for uint16 frames with
+// psix_lp = [2][16][nx] bf16/fp16 words, the hi and lo parts of psi_x * 2^shift, and
+// psi_unscale = 2^-shift.  With up_src (pinned host memory) the launch also copies up_bytes
+// (a multiple of 4) from it to up_dst, in a workgroup of its own.  With fptr (pinned host
+// table of n device addresses) frame b is read from fptr[b], else from frames + b ny nx.
+struct ProjectLaunch {
+  int dtype, precision;
+  const void* frames;
+  int n, ny, nx;
+  const float* psi;
+  const uint16_t* psix_lp;
+  float psi_unscale;
+  const int* kmap;
+  int kpad;
+  float* h;
+  const void* up_src;
+  void* up_dst;
+  size_t up_bytes;
+  const uint64_t* fptr;
+};
+hipError_t launch_project(const ProjectLaunch& pl, hipStream_t st);
 
-// launch_project, and in the same launch the column pass of a display from partial rows
-// (launch_dft_rows with nslot partials, final scale): workgroups past the n projections
-// each write one of `rows` output rows.  Power-of-two len.
-hipError_t launch_project_display(int dtype, const void* frames, int n, int ny, int nx, const float* psi,
-                                  const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
-                                  size_t up_bytes, const uint64_t* fptr, const float2* din, float2* dout, int rows,
-                                  int len, const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
-                                  int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st);
-
-// Reduced-precision form of launch_project for uint16 frames (precision = WDD_BF16_HILO,
-// WDD_FP16_HILO, WDD_BF16 or WDD_FP16).  psix_lp: [2][16][nx] bf16/fp16 words, the hi and
-// lo parts of psi_x * 2^shift (columns >= L zero); psi_unscale = 2^-shift.  psi holds the
-// FP32 psi_y in its first ny * 16 entries.
-hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
-                             const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
-                             const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr, hipStream_t st);
+// The column pass of a display from partial rows (launch_dft_rows with nslot partials and
+// the final scale): `rows` output rows of power-of-two length len.
+struct DisplayColumns {
+  const float2* din;
+  float2* dout;
+  int rows, len;
+  const float2* e;
+  const float2* d0;
+  float s_total;
+  int in_sr, in_sm, out_sr, out_sc, nslot, slot_stride;
+};
+// launch_project and, in the same launch, that column pass: workgroups past the projections
+// (and the upload copy) each write one output row.  n >= 1.
+hipError_t launch_project_display(const ProjectLaunch& pl, const DisplayColumns& dc, hipStream_t st);
 
 // Columns (in blocks of 32) per accumulation workgroup for a padded basis size.
 int accumulate_col_blocks(int kpad);
@@ -70,7 +83,8 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
                              const float2* w, float2* d, float2* z, bool fuse_wiener, hipStream_t st);
 
 // Object-order row-factored update with the per-row x-DFT fused in (one workgroup per chunk
-// of kept frequencies sharing an x-frequency): d[j] += sum_r E_sy(v_y(j) y_r) sum_c w[j][c]
+// of kept frequencies sharing an x-frequency; D held as the compensated pair d + dlo, d the
+// FP32 value nearest the sum): d[j] += sum_r E_sy(v_y(j) y_r) sum_c w[j][c]
 // T_r[v_x(j)][c] with T_r[vx][c] = sum_{frames b of row r} tscale E_sx(vx x_b) h[b][c],
 // E_s(m) = exp(-2 pi i m / s); z as in launch_wiener.  rows.r[r] = (y_r, first index into
 // order and xs, frame count, 0) for r < nrows <= kRowSetMax; xs[i] is the scan x of frame
@@ -87,7 +101,7 @@ struct RowSet {
 };
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
-                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
+                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
                                 float2* up, int nslot, bool in_order, hipStream_t st);
 
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
@@ -103,10 +117,14 @@ hipError_t launch_row_dft_c(const float2* h, int kpad, const int* order, const i
                             const float2* tx, int sx, float2* t, hipStream_t st);
 hipError_t launch_update_c(int mode, const float2* t, int kpad, const RowSet& rows, int nrows, const float2* ty, int sy,
                            int sx, const int2* freqs, int64_t n_freq, const float2* w, float2* acc, float2* d,
-                           float2* z, hipStream_t st);
+                           float2* dlo, float2* z, hipStream_t st);
 
 // z[v_x(j)][v_y(j)] = conj(d[j]) for j < n_freq.
 hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st);
+
+// z[vx][vy] = conj(d[vy][vx]) for the sy x sx grid d; ey, ex = exp(-2 pi i m / s) for m < s
+// (FP64 arguments, FP32 values): the inputs of the two display passes (launch_dft_rows).
+hipError_t launch_display_prep(const float2* d, int sy, int sx, float2* z, float2* ey, float2* ex, hipStream_t st);
 
 hipError_t launch_zero(float* p, size_t n, hipStream_t st);
 

@@ -31,6 +31,16 @@ using wdd::kMaxSlots;
 
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 
+// Opts a kernel into the whole LDS once: a function-local static per kernel, whose
+// initialisation C++ makes thread-safe (plans on several host threads may launch at once).
+template <typename K>
+hipError_t allow_full_lds(K* kernel) {
+  static const hipError_t e =
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kLdsBytes);
+  return e;
+}
+
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -63,30 +73,6 @@ __device__ inline int2 gload(const int2* p) {
   return make_int2(v.x, v.y);
 }
 #undef WDD_GLOBAL
-
-// The batch's upload block (pinned host memory, read by workgroup 0 of the projection): the
-// loads of the first 4 * nthreads words are issued by upload_issue, before the tables are
-// staged, and their stores (and the rest of a long block) done by upload_finish, so the
-// PCIe round trip overlaps the other loads.
-struct UploadWords {
-  uint32_t v[4];
-};
-__device__ inline void upload_issue(UploadWords& u, const uint32_t* src, int n, int tid, int nthreads) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int i = k * nthreads + tid;
-    if (i < n) u.v[k] = gload(src + i);
-  }
-}
-__device__ inline void upload_finish(const UploadWords& u, uint32_t* dst, const uint32_t* src, int n, int tid,
-                                     int nthreads) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int i = k * nthreads + tid;
-    if (i < n) dst[i] = u.v[k];
-  }
-  for (int i = 4 * nthreads + tid; i < n; i += nthreads) dst[i] = gload(src + i);
-}
 
 // dst[i] = src[i] for i < n by `nthreads` threads, U loads in flight per thread before any
 // store (a plain strided copy loop waits for each load in turn).
@@ -147,28 +133,86 @@ struct Chunk<float> {
   }
 };
 
+// The batch's upload block (positions, row grouping) lives in pinned host memory; one extra
+// workgroup of the projection launch copies it to the device, so that no frame's workgroup
+// waits for the PCIe round trip (loads complete in issue order).
+__device__ inline void upload_block(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int n, int tid,
+                                    int nthreads) {
+  stage_copy<4>(dst, src, n, tid, nthreads);
+}
+
+// Table staging of the projection: psi ([ny][16] psi_y then [nx][16] psi_x, FP32) goes to
+// LDS as psi_y [ny][16] and psi_x transposed, [16][nxp] (nxp = nx + 4: a lane's 8 basis
+// values of a chunk are two 16-byte reads, and the 16 rows start in different banks), kmap to
+// [kpad].  The first 8 psi values and 4 kmap values of every thread are loaded by
+// table_issue before the frame loads go out and stored by table_finish after them, so the
+// barrier that follows waits for the tables only, not for the frame.
+struct TableRegs {
+  float v[8];
+  int k[4];
+};
+__device__ inline void table_issue(TableRegs& r, const float* __restrict__ psi, int ntab,
+                                   const int* __restrict__ kmap, int kpad, int tid, int nt) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) r.v[u] = gload(psi + min(u * nt + tid, ntab - 1));
+#pragma unroll
+  for (int u = 0; u < 4; ++u) r.k[u] = gload(kmap + min(u * nt + tid, kpad - 1));
+}
+__device__ inline void table_store(float* __restrict__ lpsy, float* __restrict__ lpsxt, int ny, int nxp, int i,
+                                   float v) {
+  if (i < ny * 16) {
+    lpsy[i] = v;
+  } else {
+    const int j = i - ny * 16;
+    lpsxt[(j & 15) * nxp + (j >> 4)] = v;
+  }
+}
+__device__ inline void table_finish(const TableRegs& r, const float* __restrict__ psi, int ntab,
+                                    const int* __restrict__ kmap, int kpad, float* __restrict__ lpsy,
+                                    float* __restrict__ lpsxt, int* __restrict__ lkmap, int ny, int nxp, int tid,
+                                    int nt) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u * nt + tid;
+    if (i < ntab) table_store(lpsy, lpsxt, ny, nxp, i, r.v[u]);
+  }
+  for (int i = 8 * nt + tid; i < ntab; i += nt) table_store(lpsy, lpsxt, ny, nxp, i, gload(psi + i));
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = u * nt + tid;
+    if (i < kpad) lkmap[i] = r.k[u];
+  }
+  for (int i = 4 * nt + tid; i < kpad; i += nt) lkmap[i] = gload(kmap + i);
+}
+
+// LDS floats of a projection workgroup: psi_y, transposed psi_x, per-wave G, kmap.
+__host__ __device__ inline size_t project_lds_floats(int ny, int nx, int nw, int kpad) {
+  return (size_t)ny * 16 + (size_t)16 * (nx + 4) + (size_t)nw * 256 + (size_t)kpad;
+}
+
 // One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
-// more tiles than waves).  A wave first issues the loads of up to 8 chunks of 32
-// pixels per row (256 columns), then runs their MFMAs, so the loads of a tile are in
-// flight together.  Frame b of the batch; smem: [ny + nx][16] tables, [waves][256]
-// partial G, [kpad] coefficient map.
+// more tiles than waves).  A wave issues the loads of up to 8 chunks of 32 pixels per row
+// (256 columns) right after the table loads, and runs a chunk's MFMAs as soon as that
+// chunk has arrived.  Frame b of the batch; smem: project_lds_floats(ny, nx, nw, kpad).
 template <typename T>
 __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int ny, int nx,
                                               const float* __restrict__ psi, const int* __restrict__ kmap, int kpad,
-                                              float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                              uint32_t* __restrict__ up_dst, int up_words,
-                                              const uint64_t* __restrict__ fptr, float* smem, int b) {
-  const int nw = blockDim.x >> 6;
-  float* lpsy = smem;               // [ny][16]
-  float* lpsx = smem + ny * 16;     // [nx][16]
-  float* lg = lpsx + nx * 16;       // [nw][256]
+                                              float* __restrict__ h, const uint64_t* __restrict__ fptr, float* smem,
+                                              int b) {
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
+  const int nxp = nx + 4;
+  float* lpsy = smem;                    // [ny][16]
+  float* lpsxt = smem + ny * 16;         // [16][nxp]
+  float* lg = lpsxt + 16 * nxp;          // [nw][256]
   int* lkmap = reinterpret_cast<int*>(lg + nw * 256);  // [kpad]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // frame b: contiguous after `frames`, or at the address listed in fptr[b] (pinned host table)
   const T* f = fptr ? reinterpret_cast<const T*>(fptr[b]) : frames + (size_t)b * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
-  // loads of this wave's first chunk group go out before anything else
+  const int ntab = (ny + nx) * 16;
+  TableRegs tr;
+  table_issue(tr, psi, ntab, kmap, kpad, tid, nt);
   Chunk<T> ch[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -176,16 +220,11 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
     if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
     else ch[c].zero();
   }
-  // the batch's positions / grouping live in pinned host memory; block 0 brings them over
-  UploadWords upw;
-  const bool uploader = b == 0;
-  if (uploader) upload_issue(upw, up_src, up_words, tid, blockDim.x);
-  stage_copy<8>(smem, psi, (ny + nx) * 16, tid, blockDim.x);
-  stage_copy<1>(lkmap, kmap, kpad, tid, blockDim.x);
-  if (uploader) upload_finish(upw, up_dst, up_src, up_words, tid, blockDim.x);
+  table_finish(tr, psi, ntab, kmap, kpad, lpsy, lpsxt, lkmap, ny, nxp, tid, nt);
   __syncthreads();
 
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
+  const float* brow = lpsxt + r16 * nxp;
   for (int t = wave; t < ntiles; t += nw) {
     const int y = t * 16 + r16;
     floatx4 tacc = {0.f, 0.f, 0.f, 0.f};
@@ -199,22 +238,26 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
         }
       }
       const int nch = min(8, (nx - xg + 31) >> 5);  // chunks of 32 columns inside the frame
-      // per chunk: its 8 basis values first (LDS), then 8 MFMAs alternating between two
-      // accumulators, so neither the LDS reads nor one MFMA chain serialise the loop
+      // per chunk: its 8 basis values (two 16-byte LDS reads), then 8 MFMAs alternating
+      // between two accumulators, so that one MFMA chain does not serialise the loop
       floatx4 tacc2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         if (c >= nch) break;
         const int xs = xg + 32 * c + 8 * q;
-        const int xb = (xs < nx) ? xs : 0;
-        float bv[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = (xs < nx) ? lpsx[(xb + j) * 16 + r16] : 0.f;
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-          tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j), bv[j], tacc, 0, 0, 0);
-          tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(j + 1), bv[j + 1], tacc2, 0, 0, 0);
+        float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0;
+        if (xs < nx) {
+          b0 = *reinterpret_cast<const float4*>(brow + xs);
+          b1 = *reinterpret_cast<const float4*>(brow + xs + 4);
         }
+        tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(0), b0.x, tacc, 0, 0, 0);
+        tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(1), b0.y, tacc2, 0, 0, 0);
+        tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(2), b0.z, tacc, 0, 0, 0);
+        tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(3), b0.w, tacc2, 0, 0, 0);
+        tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(4), b1.x, tacc, 0, 0, 0);
+        tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(5), b1.y, tacc2, 0, 0, 0);
+        tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(6), b1.z, tacc, 0, 0, 0);
+        tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(7), b1.w, tacc2, 0, 0, 0);
       }
       tacc += tacc2;
     }
@@ -228,7 +271,7 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
 #pragma unroll
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
-  for (int k = tid; k < kpad; k += blockDim.x) {
+  for (int k = tid; k < kpad; k += nt) {
     const int idx = lkmap[k];
     float sum = 0.f;
     if (idx >= 0)
@@ -236,17 +279,6 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
     h[(size_t)b * kpad + k] = sum;
   }
 }
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_project(const T* __restrict__ frames, int ny, int nx,
-                                                  const float* __restrict__ psi, const int* __restrict__ kmap,
-                                                  int kpad, float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                                  uint32_t* __restrict__ up_dst, int up_words,
-                                                  const uint64_t* __restrict__ fptr) {
-  extern __shared__ float smem[];
-  project_frame<T>(frames, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_words, fptr, smem, (int)blockIdx.x);
-}
-
 
 // Reduced-precision projection of uint16 frames.  Stage 1 runs on
 // v_mfma_f32_16x16x32_{bf16,f16}: the 8 consecutive pixels a lane loads are exactly
@@ -280,28 +312,47 @@ struct LpTraits<false> {
   }
 };
 
+// LDS bytes of a reduced-precision projection workgroup: psi_y (FP32), per-wave G, kmap, and
+// the 16-bit psi_x parts [2][16][nx + 8].
+__host__ __device__ inline size_t project_lp_lds_bytes(int ny, int nx, int nw, int kpad) {
+  return ((size_t)ny * 16 + (size_t)nw * 256 + (size_t)kpad) * 4 + (size_t)2 * 16 * (nx + 8) * 2;
+}
+
+// Frame b of a batch of uint16 frames with the reduced-precision stage 1 (see above).  The
+// tables (psi_y, the 16-bit psi_x parts as 32-bit words, kmap) are loaded before the frame
+// and stored after its loads have been issued, as in project_frame.
 template <bool BF, bool HILO>
-__global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict__ frames, int ny, int nx,
-                                                     const float* __restrict__ psi, const uint16_t* __restrict__ psix_lp,
-                                                     float psi_unscale, const int* __restrict__ kmap, int kpad,
-                                                     float* __restrict__ h, const uint32_t* __restrict__ up_src,
-                                                     uint32_t* __restrict__ up_dst, int up_words,
-                                                     const uint64_t* __restrict__ fptr) {
+__device__ __forceinline__ void project_frame_lp(const uint16_t* __restrict__ frames, int ny, int nx,
+                                                 const float* __restrict__ psi,
+                                                 const uint16_t* __restrict__ psix_lp, float psi_unscale,
+                                                 const int* __restrict__ kmap, int kpad, float* __restrict__ h,
+                                                 const uint64_t* __restrict__ fptr, float* smem, int b) {
   typedef LpTraits<BF> Tr;
   typedef typename Tr::vec V;
   typedef typename Tr::elem E;
   constexpr int S = Tr::kShift;
-  extern __shared__ float smem[];
-  const int nw = blockDim.x >> 6;
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
   const int nxp = nx + 8;                                              // padded row of the 16-bit basis
   float* lpsy = smem;                                                  // [ny][16] FP32
   float* lg = lpsy + ny * 16;                                          // [nw][256]
   int* lkmap = reinterpret_cast<int*>(lg + nw * 256);                  // [kpad]
   uint16_t* lpx = reinterpret_cast<uint16_t*>(lkmap + kpad);           // [2][16][nxp]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[blockIdx.x]) : frames + (size_t)blockIdx.x * ny * nx;
+  const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[b]) : frames + (size_t)b * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
+  // table loads first (index clamped, no branch), then the frame's
+  const int nsy = ny * 16, half = nx >> 1, nwords = (HILO ? 2 : 1) * 16 * half;
+  const uint32_t* px32 = reinterpret_cast<const uint32_t*>(psix_lp);
+  float vy[8];
+  uint32_t vx[8];
+  int vk[4];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vy[u] = gload(psi + min(u * nt + tid, nsy - 1));
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vx[u] = gload(px32 + min(u * nt + tid, nwords - 1));
+#pragma unroll
+  for (int u = 0; u < 4; ++u) vk[u] = gload(kmap + min(u * nt + tid, kpad - 1));
   Chunk<uint16_t> ch[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -309,26 +360,22 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
     if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
     else ch[c].zero();
   }
-  UploadWords upw;
-  const bool uploader = blockIdx.x == 0;
-  if (uploader) upload_issue(upw, up_src, up_words, tid, blockDim.x);
-  stage_copy<4>(lpsy, psi, ny * 16, tid, blockDim.x);
-  stage_copy<1>(lkmap, kmap, kpad, tid, blockDim.x);
-  if (uploader) upload_finish(upw, up_dst, up_src, up_words, tid, blockDim.x);
-  const int parts = HILO ? 2 : 1, total = parts * 16 * nx;
-  for (int base = 0; base < total; base += 4 * (int)blockDim.x) {  // loads first, then the padded stores
-    uint16_t v[4];  // unconditional loads (index clamped), all in flight before the stores
+  uint32_t* lpx32 = reinterpret_cast<uint32_t*>(lpx);
+  const int hp = nxp >> 1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = gload(psix_lp + min(base + u * (int)blockDim.x + tid, total - 1));
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = base + u * blockDim.x + tid;
-      if (i < total) {
-        const int row = i / nx, x = i - row * nx;
-        lpx[row * nxp + x] = v[u];
-      }
-    }
+  for (int u = 0; u < 8; ++u) {
+    const int i = u * nt + tid;
+    if (i < nsy) lpsy[i] = vy[u];
+    if (i < nwords) lpx32[(i / half) * hp + i % half] = vx[u];
   }
+  for (int i = 8 * nt + tid; i < nsy; i += nt) lpsy[i] = gload(psi + i);
+  for (int i = 8 * nt + tid; i < nwords; i += nt) lpx32[(i / half) * hp + i % half] = gload(px32 + i);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = u * nt + tid;
+    if (i < kpad) lkmap[i] = vk[u];
+  }
+  for (int i = 4 * nt + tid; i < kpad; i += nt) lkmap[i] = gload(kmap + i);
   __syncthreads();
 
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
@@ -386,13 +433,53 @@ __global__ __launch_bounds__(1024) void k_project_lp(const uint16_t* __restrict_
 #pragma unroll
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
-  for (int k = tid; k < kpad; k += blockDim.x) {
+  for (int k = tid; k < kpad; k += nt) {
     const int idx = lkmap[k];
     float sum = 0.f;
     if (idx >= 0)
       for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
-    h[(size_t)blockIdx.x * kpad + k] = sum;
+    h[(size_t)b * kpad + k] = sum;
   }
+}
+
+// Arguments of a projection launch (passed by value).
+struct ProjArgs {
+  const void* frames;
+  int n, ny, nx;
+  const float* psi;
+  const uint16_t* psix_lp;  // reduced precision: [2][16][nx] 16-bit parts of psi_x
+  float psi_unscale;
+  const int* kmap;
+  int kpad;
+  float* h;
+  const uint32_t* up_src;  // upload block (pinned host memory) and its device copy
+  uint32_t* up_dst;
+  int up_words;
+  const uint64_t* fptr;  // per-frame addresses (pinned host table) or null
+};
+
+// Frame b with the arithmetic PREC (a wdd_precision; reduced precisions need uint16 frames).
+template <typename T, int PREC>
+__device__ __forceinline__ void project_any(const ProjArgs& a, float* smem, int b) {
+  if constexpr (PREC == WDD_FP32) {
+    project_frame<T>(static_cast<const T*>(a.frames), a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b);
+  } else {
+    constexpr bool bf = PREC == WDD_BF16_HILO || PREC == WDD_BF16;
+    constexpr bool hilo = PREC == WDD_BF16_HILO || PREC == WDD_FP16_HILO;
+    project_frame_lp<bf, hilo>(static_cast<const uint16_t*>(a.frames), a.ny, a.nx, a.psi, a.psix_lp, a.psi_unscale,
+                               a.kmap, a.kpad, a.h, a.fptr, smem, b);
+  }
+}
+
+// Workgroups b < n project frame b; with an upload block, workgroup n copies it.
+template <typename T, int PREC>
+__global__ __launch_bounds__(1024) void k_project(ProjArgs a) {
+  extern __shared__ float4 psm[];
+  if ((int)blockIdx.x == a.n) {
+    upload_block(a.up_src, a.up_dst, a.up_words, (int)threadIdx.x, (int)blockDim.x);
+    return;
+  }
+  project_any<T, PREC>(a, reinterpret_cast<float*>(psm), (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -671,26 +758,37 @@ __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in,
   }
 }
 
-// One launch for two independent jobs: workgroups b < nproj project frame b of a batch,
-// the others each write one output row (b - nproj) of the previous step's displayed image
-// from its partial rows (display_row_partials).  Saves a kernel boundary per step when
-// the display of a step is left to the next push.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_project_display(
-    const T* __restrict__ frames, int ny, int nx, const float* __restrict__ psi, const int* __restrict__ kmap, int kpad,
-    float* __restrict__ h, const uint32_t* __restrict__ up_src, uint32_t* __restrict__ up_dst, int up_words,
-    const uint64_t* __restrict__ fptr, int nproj, const float2* __restrict__ din, float2* __restrict__ dout, int len,
-    int log2len, const float2* __restrict__ e, const float2* __restrict__ d0, float s_total, int in_sr, int in_sm,
-    int out_sr, int out_sc, int nslot, int slot_stride) {
+// The column pass of a display from partial rows (display_row_partials), as launch arguments.
+struct DispArgs {
+  const float2* din;
+  float2* dout;
+  int len, log2len;
+  const float2* e;
+  const float2* d0;
+  float s_total;
+  int in_sr, in_sm, out_sr, out_sc, nslot, slot_stride;
+};
+
+// One launch for independent jobs: workgroups b < n project frame b of a batch, workgroup n
+// copies the upload block (when there is one), and the rest each write one output row of
+// the previous step's displayed image from its partial rows (display_row_partials).  Saves
+// a kernel boundary per step when the display of a step is left to the next push.
+template <typename T, int PREC>
+__global__ __launch_bounds__(1024) void k_project_display(ProjArgs a, DispArgs d) {
   extern __shared__ float4 msm[];
   const int b = (int)blockIdx.x;
-  if (b < nproj) {
-    project_frame<T>(frames, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_words, fptr, reinterpret_cast<float*>(msm),
-                     b);
+  if (b < a.n) {
+    project_any<T, PREC>(a, reinterpret_cast<float*>(msm), b);
     return;
   }
-  display_row_partials(din, dout, len, log2len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot, slot_stride,
-                       b - nproj, reinterpret_cast<float2*>(msm), (int)threadIdx.x, (int)blockDim.x);
+  const int up = a.up_words > 0 ? 1 : 0;
+  if (up && b == a.n) {
+    upload_block(a.up_src, a.up_dst, a.up_words, (int)threadIdx.x, (int)blockDim.x);
+    return;
+  }
+  display_row_partials(d.din, d.dout, d.len, d.log2len, d.e, d.d0, d.s_total, d.in_sr, d.in_sm, d.out_sr, d.out_sc,
+                       d.nslot, d.slot_stride, b - a.n - up, reinterpret_cast<float2*>(msm), (int)threadIdx.x,
+                       (int)blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,6 +992,25 @@ __device__ inline float2 cdot4(const float4 w0, const float4 w1, const float4 v0
   return make_float2(re, im);
 }
 
+// (hi, lo) += c with the rounding error kept: hi stays the FP32 value nearest the running sum
+// hi + lo, lo the remainder (Knuth's two-sum, then a fast renormalisation; additions only,
+// so no contraction into fused multiply-adds can change them).  Used for the object
+// spectrum D, which sums one contribution per push: without it the rounding of each of the
+// thousands of additions adds up to several 1e-6 of the signal beside the zero frequency.
+__device__ inline void two_sum_add(float& hi, float& lo, float c) {
+  const float s = hi + c;
+  const float bb = s - hi;
+  const float err = (hi - (s - bb)) + (c - bb);
+  const float t = lo + err;
+  const float h2 = s + t;
+  lo = t - (h2 - s);
+  hi = h2;
+}
+__device__ inline void two_sum_add2(float2& hi, float2& lo, float2 c) {
+  two_sum_add(hi.x, lo.x, c.x);
+  two_sum_add(hi.y, lo.y, c.y);
+}
+
 __device__ inline void add4(float4& a, const float4 b) {
   a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
 }
@@ -905,7 +1022,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                                                                  const int4* __restrict__ chunks,
                                                                  const int2* __restrict__ jv,
                                                                  const float2* __restrict__ w,
-                                                                 float2* __restrict__ d, float2* __restrict__ z,
+                                                                 float2* __restrict__ d, float2* __restrict__ dlo,
+                                                                 float2* __restrict__ z,
                                                                  int max_chunk, float2* __restrict__ up, int nslot,
                                                                  int log2sy, int in_order) {
   extern __shared__ float4 fsm[];
@@ -1024,7 +1142,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     const float4* wa = reinterpret_cast<const float4*>(w + (size_t)ja * kpad + 4 * kq);
     const float4* wb = reinterpret_cast<const float4*>(w + (size_t)jb * kpad + 4 * kq);
     const float4 wa0 = gload(wa), wa1 = gload(wa + 1), wb0 = gload(wb), wb1 = gload(wb + 1);
-    const float2 da = gload(d + ja), db = gload(d + jb);  // all lanes: no branch around a load
+    // all lanes load D: no branch around a load
+    const float2 da = gload(d + ja), db = gload(d + jb), la = gload(dlo + ja), lb = gload(dlo + jb);
     const int vya = lvy[i], vyb = two ? lvy[i + G] : vya;
     float4 sa0, sa1, sb0, sb1;
     phase_sum(sa0, sa1, lt, q, kq, nrows, rs, vya, sy, py2, invy, lph[i]);
@@ -1037,13 +1156,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
       ob.y += __shfl_xor(ob.y, off, 64);
     }
     if (kq == 0) {
-      const float2 na = make_float2(da.x + oa.x, da.y + oa.y);
+      float2 na = da, nla = la;
+      two_sum_add2(na, nla, oa);
       d[ja] = na;
+      dlo[ja] = nla;
       z[(size_t)vx * sy + vya] = make_float2(na.x, -na.y);
       if (up) lrow[log2sy ? (int)(__brev((unsigned)vya) >> (32 - log2sy)) : 0] = make_float2(na.x, -na.y);
       if (two) {
-        const float2 nb = make_float2(db.x + ob.x, db.y + ob.y);
+        float2 nb = db, nlb = lb;
+        two_sum_add2(nb, nlb, ob);
         d[jb] = nb;
+        dlo[jb] = nlb;
         z[(size_t)vx * sy + vyb] = make_float2(nb.x, -nb.y);
         if (up) lrow[log2sy ? (int)(__brev((unsigned)vyb) >> (32 - log2sy)) : 0] = make_float2(nb.x, -nb.y);
       }
@@ -1186,7 +1309,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_update_c(const float2* __restrict__ t, int kpad, RowSet rs, int nrows,
                                                   const float2* __restrict__ ty, int sy, int sx,
                                                   const int2* __restrict__ freqs, const float2* __restrict__ w,
-                                                  float2* __restrict__ acc, float2* __restrict__ d,
+                                                  float2* __restrict__ acc, float2* __restrict__ d, float2* __restrict__ dlo,
                                                   float2* __restrict__ z) {
   __shared__ float2 lph[kRowSetMax];
   __shared__ float lre[4], lim[4];
@@ -1234,9 +1357,11 @@ __global__ __launch_bounds__(256) void k_update_c(const float2* __restrict__ t, 
     re = (lre[0] + lre[1]) + (lre[2] + lre[3]);
     im = (lim[0] + lim[1]) + (lim[2] + lim[3]);
     float2 nd = make_float2(re, im);
-    if (MODE == 0) {
-      const float2 old = d[j];
-      nd = make_float2(old.x + re, old.y + im);
+    if (MODE == 0) {  // compensated: the object spectrum sums one contribution per push
+      float2 lo = dlo[j];
+      nd = d[j];
+      two_sum_add2(nd, lo, make_float2(re, im));
+      dlo[j] = lo;
     }
     d[j] = nd;
     z[(size_t)v.y * sy + v.x] = make_float2(nd.x, -nd.y);
@@ -1253,62 +1378,44 @@ __global__ void k_scatter_conj(const float2* __restrict__ d, const int2* __restr
   z[(size_t)v.y * sy + v.x] = make_float2(x.x, -x.y);
 }
 
+// Standalone display from a caller's spectrum grid d [sy][sx] (row-major, complex): the
+// display's input z[vx][vy] = conj(d[vy][vx]) (transposed, as the update leaves it), and the
+// forward twiddles ey[m] = exp(-2 pi i m / sy), ex[m] = exp(-2 pi i m / sx) evaluated in FP64
+// (the argument 2 m / s is reduced exactly there) and rounded to FP32.
+__global__ void k_display_prep(const float2* __restrict__ d, int sy, int sx, float2* __restrict__ z,
+                               float2* __restrict__ ey, float2* __restrict__ ex) {
+  const int64_t cells = (int64_t)sy * sx;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cells) {
+    const int vy = (int)(i / sx), vx = (int)(i - (int64_t)vy * sx);
+    const float2 v = d[i];
+    z[(int64_t)vx * sy + vy] = make_float2(v.x, -v.y);
+  }
+  if (i < sy) {
+    double sn, cs;
+    sincospi(2.0 * (double)i / (double)sy, &sn, &cs);
+    ey[i] = make_float2((float)cs, (float)-sn);
+  }
+  if (i < sx) {
+    double sn, cs;
+    sincospi(2.0 * (double)i / (double)sx, &sn, &cs);
+    ex[i] = make_float2((float)cs, (float)-sn);
+  }
+}
+
 __global__ void k_zero(float* __restrict__ p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t st = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += st) p[i] = 0.f;
 }
 
-template <typename T>
-hipError_t launch_project_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap, int kpad,
-                            float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
-                            hipStream_t st) {
-  const int ntiles = (ny + 15) / 16;
-  const int nw = ntiles < 16 ? ntiles : 16;
-  const size_t lds = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) +
-                     (size_t)kpad * sizeof(int);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_project<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(k_project<T>, dim3(n), dim3(64 * nw), lds, st, static_cast<const T*>(frames), ny, nx, psi, kmap,
-                     kpad, h, static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst),
-                     (int)(up_bytes / 4), fptr);
-  return hipGetLastError();
-}
-
-template <bool BF, bool HILO>
-hipError_t launch_project_lp_t(const void* frames, int n, int ny, int nx, const float* psi, const uint16_t* psix_lp,
-                               float psi_unscale, const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
-                               size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
-  const int ntiles = (ny + 15) / 16;
-  const int nw = ntiles < 16 ? ntiles : 16;
-  const size_t lds = (size_t)ny * 16 * sizeof(float) + (size_t)nw * 256 * sizeof(float) + (size_t)kpad * sizeof(int) +
-                     (size_t)2 * 16 * (nx + 8) * sizeof(uint16_t);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_project_lp<BF, HILO>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_project_lp<BF, HILO>), dim3(n), dim3(64 * nw), lds, st, static_cast<const uint16_t*>(frames),
-                     ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, static_cast<const uint32_t*>(up_src),
-                     static_cast<uint32_t*>(up_dst), (int)(up_bytes / 4), fptr);
-  return hipGetLastError();
-}
-
 template <int NCB>
 hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* freqs, const float* h,
                         const int2* pos, int n, const float2* ty, int sy, const float2* tx, int sx, hipStream_t st) {
   const size_t lds = (size_t)(sy + sx) * sizeof(float2) + 32 * sizeof(int2) + 32 * NCB * 32 * sizeof(float);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_accumulate<NCB>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  {
+    const hipError_t e = allow_full_lds(k_accumulate<NCB>);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   dim3 grid((unsigned)(n_freq_pad / 64), (unsigned)(kpad / (NCB * 32)));
   hipLaunchKernelGGL(k_accumulate<NCB>, grid, dim3(256), lds, st, acc, kpad, freqs, h, pos, n, ty, sy, tx, sx);
@@ -1319,77 +1426,96 @@ hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* f
 
 namespace wdd {
 
-hipError_t launch_project(int dtype, const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                          int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr,
-                          hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (dtype == WDD_U16)
-    return launch_project_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, st);
-  return launch_project_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, st);
+namespace {
+
+ProjArgs proj_args(const ProjectLaunch& pl) {
+  ProjArgs a;
+  a.frames = pl.frames;
+  a.n = pl.n;
+  a.ny = pl.ny;
+  a.nx = pl.nx;
+  a.psi = pl.psi;
+  a.psix_lp = pl.psix_lp;
+  a.psi_unscale = pl.psi_unscale;
+  a.kmap = pl.kmap;
+  a.kpad = pl.kpad;
+  a.h = pl.h;
+  a.up_src = static_cast<const uint32_t*>(pl.up_src);
+  a.up_dst = static_cast<uint32_t*>(pl.up_dst);
+  a.up_words = pl.up_src ? (int)(pl.up_bytes / 4) : 0;
+  a.fptr = pl.fptr;
+  return a;
 }
 
-template <typename T>
-hipError_t launch_project_display_t(const void* frames, int n, int ny, int nx, const float* psi, const int* kmap,
-                                    int kpad, float* h, const void* up_src, void* up_dst, size_t up_bytes,
-                                    const uint64_t* fptr, const float2* din, float2* dout, int rows, int len,
-                                    const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
-                                    int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st) {
-  int lg = 0;
-  while ((1 << lg) < len) ++lg;
-  if (n < 1 || rows < 1 || (1 << lg) != len || nslot < 1 || nslot > kMaxSlots) return hipErrorInvalidValue;
-  const int ntiles = (ny + 15) / 16;
-  const int threads = std::max(64 * std::min(ntiles, 16), 256);
-  const size_t lds_proj = (size_t)(ny + nx) * 16 * sizeof(float) + (size_t)(threads / 64) * 256 * sizeof(float) +
-                          (size_t)kpad * sizeof(int);
-  const size_t lds_disp = (size_t)len * sizeof(float2) + (size_t)(len / 2) * sizeof(float2);
-  const size_t lds = std::max(lds_proj, lds_disp);
-  if (lds > kLdsBytes) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t err = hipFuncSetAttribute((const void*)k_project_display<T>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-    if (err != hipSuccess) return err;
-    attr = true;
+// LDS bytes of a projection workgroup of nw waves.
+size_t project_lds(const ProjectLaunch& pl, int nw) {
+  return pl.precision == WDD_FP32 ? project_lds_floats(pl.ny, pl.nx, nw, pl.kpad) * sizeof(float)
+                                  : project_lp_lds_bytes(pl.ny, pl.nx, nw, pl.kpad);
+}
+
+template <typename T, int PREC>
+hipError_t launch_project_tp(const ProjectLaunch& pl, const DisplayColumns* dc, hipStream_t st) {
+  const int ntiles = (pl.ny + 15) / 16;
+  const int nw_proj = std::min(ntiles, 16);
+  const ProjArgs a = proj_args(pl);
+  const int up = a.up_words > 0 ? 1 : 0;
+  if (!dc) {
+    const size_t lds = project_lds(pl, nw_proj);
+    if (lds > kLdsBytes) return hipErrorInvalidValue;
+    hipError_t e = allow_full_lds(k_project<T, PREC>);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_project<T, PREC>), dim3(pl.n + up), dim3(64 * nw_proj), lds, st, a);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_project_display<T>, dim3(n + rows), dim3(threads), lds, st, static_cast<const T*>(frames), ny,
-                     nx, psi, kmap, kpad, h, static_cast<const uint32_t*>(up_src), static_cast<uint32_t*>(up_dst),
-                     (int)(up_bytes / 4), fptr, n, din, dout, len, lg, e, d0, s_total, in_sr, in_sm, out_sr, out_sc,
-                     nslot, slot_stride);
+  int lg = 0;
+  while ((1 << lg) < dc->len) ++lg;
+  if (dc->rows < 1 || (1 << lg) != dc->len || dc->nslot < 1 || dc->nslot > kMaxSlots) return hipErrorInvalidValue;
+  const int threads = std::max(64 * nw_proj, 256);
+  const size_t lds = std::max(project_lds(pl, threads / 64), (size_t)dc->len * sizeof(float2) * 3 / 2);
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  hipError_t e = allow_full_lds(k_project_display<T, PREC>);
+  if (e != hipSuccess) return e;
+  DispArgs d;
+  d.din = dc->din;
+  d.dout = dc->dout;
+  d.len = dc->len;
+  d.log2len = lg;
+  d.e = dc->e;
+  d.d0 = dc->d0;
+  d.s_total = dc->s_total;
+  d.in_sr = dc->in_sr;
+  d.in_sm = dc->in_sm;
+  d.out_sr = dc->out_sr;
+  d.out_sc = dc->out_sc;
+  d.nslot = dc->nslot;
+  d.slot_stride = dc->slot_stride;
+  hipLaunchKernelGGL((k_project_display<T, PREC>), dim3(pl.n + up + dc->rows), dim3(threads), lds, st, a, d);
   return hipGetLastError();
 }
 
-hipError_t launch_project_display(int dtype, const void* frames, int n, int ny, int nx, const float* psi,
-                                  const int* kmap, int kpad, float* h, const void* up_src, void* up_dst,
-                                  size_t up_bytes, const uint64_t* fptr, const float2* din, float2* dout, int rows,
-                                  int len, const float2* e, const float2* d0, float s_total, int in_sr, int in_sm,
-                                  int out_sr, int out_sc, int nslot, int slot_stride, hipStream_t st) {
-  if (dtype == WDD_U16)
-    return launch_project_display_t<uint16_t>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr,
-                                              din, dout, rows, len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc,
-                                              nslot, slot_stride, st);
-  return launch_project_display_t<float>(frames, n, ny, nx, psi, kmap, kpad, h, up_src, up_dst, up_bytes, fptr, din,
-                                         dout, rows, len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot,
-                                         slot_stride, st);
+hipError_t launch_project_any(const ProjectLaunch& pl, const DisplayColumns* dc, hipStream_t st) {
+  if (pl.n <= 0) return hipSuccess;
+  if (pl.dtype == WDD_F32) {
+    if (pl.precision != WDD_FP32) return hipErrorInvalidValue;
+    return launch_project_tp<float, WDD_FP32>(pl, dc, st);
+  }
+  switch (pl.precision) {
+    case WDD_FP32: return launch_project_tp<uint16_t, WDD_FP32>(pl, dc, st);
+    case WDD_BF16_HILO: return launch_project_tp<uint16_t, WDD_BF16_HILO>(pl, dc, st);
+    case WDD_FP16_HILO: return launch_project_tp<uint16_t, WDD_FP16_HILO>(pl, dc, st);
+    case WDD_BF16: return launch_project_tp<uint16_t, WDD_BF16>(pl, dc, st);
+    case WDD_FP16: return launch_project_tp<uint16_t, WDD_FP16>(pl, dc, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_project_lp(int precision, const void* frames, int n, int ny, int nx, const float* psi,
-                             const uint16_t* psix_lp, float psi_unscale, const int* kmap, int kpad, float* h,
-                             const void* up_src, void* up_dst, size_t up_bytes, const uint64_t* fptr, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  switch (precision) {
-    case WDD_BF16_HILO:
-      return launch_project_lp_t<true, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                             up_dst, up_bytes, fptr, st);
-    case WDD_FP16_HILO:
-      return launch_project_lp_t<false, true>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                              up_dst, up_bytes, fptr, st);
-    case WDD_BF16:
-      return launch_project_lp_t<true, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                              up_dst, up_bytes, fptr, st);
-    default:
-      return launch_project_lp_t<false, false>(frames, n, ny, nx, psi, psix_lp, psi_unscale, kmap, kpad, h, up_src,
-                                               up_dst, up_bytes, fptr, st);
-  }
+}  // namespace
+
+hipError_t launch_project(const ProjectLaunch& pl, hipStream_t st) { return launch_project_any(pl, nullptr, st); }
+
+hipError_t launch_project_display(const ProjectLaunch& pl, const DisplayColumns& dc, hipStream_t st) {
+  if (pl.n <= 0) return hipErrorInvalidValue;
+  return launch_project_any(pl, &dc, st);
 }
 
 int accumulate_col_blocks(int kpad) {
@@ -1443,11 +1569,9 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
 hipError_t launch_row_dft(const float* h, int kpad, const int* xs, const int* order, const int4* rows, int nrows,
                           const float2* tx, int sx, float2* t, hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_row_dft, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  {
+    const hipError_t e = allow_full_lds(k_row_dft);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
   dim3 grid((unsigned)((sx + 7) / 8), (unsigned)(kpad / 16), (unsigned)nrows);
@@ -1476,7 +1600,7 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
 
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
-                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* z,
+                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
                                 float2* up, int nslot, bool in_order, hipStream_t st) {
   if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
     return hipErrorInvalidValue;
@@ -1488,7 +1612,7 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
   }
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
-                     tscale, sx, sy, chunks, jv, w, d, z, max_chunk, up, nslot, log2sy, in_order ? 1 : 0);
+                     tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, in_order ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1524,15 +1648,15 @@ hipError_t launch_row_dft_c(const float2* h, int kpad, const int* order, const i
 
 hipError_t launch_update_c(int mode, const float2* t, int kpad, const RowSet& rows, int nrows, const float2* ty, int sy,
                            int sx, const int2* freqs, int64_t n_freq, const float2* w, float2* acc, float2* d,
-                           float2* z, hipStream_t st) {
+                           float2* dlo, float2* z, hipStream_t st) {
   if (nrows < 1 || nrows > kRowSetMax || n_freq < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_freq);
   if (mode == 0)
-    hipLaunchKernelGGL(k_update_c<0>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+    hipLaunchKernelGGL(k_update_c<0>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, dlo, z);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_update_c<1>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+    hipLaunchKernelGGL(k_update_c<1>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, dlo, z);
   else if (mode == 2)
-    hipLaunchKernelGGL(k_update_c<2>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, z);
+    hipLaunchKernelGGL(k_update_c<2>, grid, dim3(256), 0, st, t, kpad, rows, nrows, ty, sy, sx, freqs, w, acc, d, dlo, z);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1541,6 +1665,13 @@ hipError_t launch_update_c(int mode, const float2* t, int kpad, const RowSet& ro
 hipError_t launch_scatter_conj(const float2* d, const int2* freqs, int64_t n_freq, float2* z, int sy, hipStream_t st) {
   if (n_freq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_conj, dim3((unsigned)((n_freq + 255) / 256)), dim3(256), 0, st, d, freqs, n_freq, z, sy);
+  return hipGetLastError();
+}
+
+hipError_t launch_display_prep(const float2* d, int sy, int sx, float2* z, float2* ey, float2* ex, hipStream_t st) {
+  if (sy < 1 || sx < 1) return hipErrorInvalidValue;
+  const int64_t n = std::max<int64_t>((int64_t)sy * sx, std::max(sy, sx));
+  hipLaunchKernelGGL(k_display_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, sy, sx, z, ey, ex);
   return hipGetLastError();
 }
 

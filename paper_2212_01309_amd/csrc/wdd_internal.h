@@ -48,6 +48,16 @@ wdd_status snapshot_enqueue(wdd_plan_t p, bool reduce);
 wdd_status snapshot_finish(wdd_plan_t p, uint64_t* frames_seen);
 wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx);
 
+// The display of a spectrum grid (wdd_display): argument checks, the scratch it needs (in
+// floats: two sy x sx complex grids and the twiddles of both sides) and the launches, all
+// asynchronous on `stream`.
+constexpr int32_t kDisplayMaxSide = 4096;
+inline size_t display_scratch_floats(int32_t sy, int32_t sx) {
+  return ((size_t)2 * sy * sx + (size_t)sy + (size_t)sx) * 2;
+}
+wdd_status check_display_args(const float* spectrum, int32_t sy, int32_t sx, const float* out);
+wdd_status display_grid(const float* spectrum, int32_t sy, int32_t sx, float* out, float* scratch, void* stream);
+
 // Largest number of columns of psi held on the device per axis (L <= 16).
 constexpr int kMaxL = 16;
 

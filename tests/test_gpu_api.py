@@ -5,7 +5,7 @@ import pytest
 
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
-from gpu_util import device, rel, say
+from gpu_util import device, rel, rel_a, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_ragged_batches_and_odd_geometries(case):
         assert plan.info().frames_seen == n
     oplan, a, d, o = _oracle(case["radius"], case["sy"], case["sx"], case["ny"], case["nx"], case["k"], frames, pos,
                              defocus=case.get("defocus", 0.0), step=case.get("step", 1.0))
-    errs = (rel(got_a, a), rel(got_d, d), rel(got_o, o))
+    errs = (rel_a(got_a, a), rel_d(got_d, d), rel_img(got_o, o))
     say(f"[api] errors A/D/O {errs}")
     assert max(errs) <= TOL
 
@@ -151,7 +151,7 @@ def test_repeated_positions_are_summed():
         once.push(device(frames * 2), pos)
         twice.push(device(frames), pos)
         twice.push(device(frames), pos)
-        assert rel(twice.accumulator(), once.accumulator()) <= 1e-6
+        assert rel_a(twice.accumulator(), once.accumulator()) <= 1e-6
 
 
 def test_arrival_order_does_not_matter():
@@ -200,7 +200,7 @@ def test_row_factored_and_direct_updates_agree(rows):
         a, d = plan.accumulator(), plan.spectrum()
     assert prof["factored_launches"] == (1 if rows <= 16 else 0)
     ra, rd, ro = _oracle_all(8.0, s, n, k, frames, pos)
-    errs = (rel(a, ra), rel(d, rd), rel(o, ro))
+    errs = (rel_a(a, ra), rel_d(d, rd), rel_img(o, ro))
     say(f"[api] rows={rows}: A/D/O {errs}")
     assert max(errs) <= TOL
 
@@ -217,11 +217,11 @@ def test_push_snapshot_matches_push_then_snapshot():
             p1.push(dev[b:b + 32], pos[b:b + 32])
             o1 = p1.snapshot()
             o2 = p2.push_snapshot(dev[b:b + 32], pos[b:b + 32])
-            assert rel(o2, o1) <= 1e-6, b
-            assert rel(p2.spectrum(), p1.spectrum()) <= 1e-6
+            assert rel_img(o2, o1) <= 1e-6, b
+            assert rel_d(p2.spectrum(), p1.spectrum()) <= 1e-6
         assert np.array_equal(p1.accumulator(), p2.accumulator())
         o3 = p2.push_snapshot(dev[:0], pos[:0])     # n = 0: a plain snapshot
-        assert rel(o3, o1) <= 1e-6
+        assert rel_img(o3, o1) <= 1e-6
 
 
 def test_snapshot_into_the_plans_pinned_buffer():
@@ -304,7 +304,7 @@ def test_many_asynchronous_steps_keep_their_own_positions(order):
         if order == 0:  # A itself; D there is formed at a snapshot (in the update for a)
             assert np.array_equal(a.accumulator(), one.accumulator())
             one.snapshot()
-            assert rel(a.spectrum(), one.spectrum()) <= 1e-6
+            assert rel_d(a.spectrum(), one.spectrum()) <= 1e-6
         else:
             assert np.array_equal(a.spectrum(), one.spectrum())
         assert a.info().frames_seen == one.info().frames_seen == b * steps
@@ -320,7 +320,7 @@ def test_temporary_device_frames_outlive_the_call():
             a.push(device(frames * 3), pos)
             for _ in range(3):
                 b.push(device(frames), pos)
-            assert rel(b.accumulator(), a.accumulator()) <= 1e-6
+            assert rel_a(b.accumulator(), a.accumulator()) <= 1e-6
 
 
 def test_plans_take_device_memory_from_the_callers_allocator():

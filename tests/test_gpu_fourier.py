@@ -7,7 +7,7 @@ import pytest
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
 import synth
-from gpu_util import device, rel, say
+from gpu_util import device, rel, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +34,8 @@ def test_small_workload_is_conventional_wdd(order):
     frames4d = np.zeros((wl.sy, wl.sx, n, n))
     frames4d[pos[:, 0], pos[:, 1]] = frames
     d_conv, o_conv = O.offline_conventional(frames4d, wl.radius, amplitude=amp)
-    errs = dict(h=rel(h_last, h_ref), D=rel(d, live.spectrum()), O=rel(o, live.snapshot()),
-                O_conventional=rel(o, o_conv), D_conventional=rel(d, d_conv[op.freqs[:, 0], op.freqs[:, 1]]))
+    errs = dict(h=rel(h_last, h_ref), D=rel_d(d, live.spectrum()), O=rel_img(o, live.snapshot()),
+                O_conventional=rel_img(o, o_conv), D_conventional=rel_d(d, d_conv[op.freqs[:, 0], op.freqs[:, 1]]))
     say(f"[fourier] small workload, order {order}: {errs}")
     assert errs["h"] <= 1e-6
     assert max(errs["D"], errs["O"], errs["O_conventional"], errs["D_conventional"]) <= 1e-5
@@ -57,10 +57,10 @@ def test_rectangular_detector_scattered_batches(order):
             a.push(dev[i:i + 100], pos[i:i + 100])
             oa = a.snapshot()
             ob = b.push_snapshot(dev[i:i + 100], pos[i:i + 100])
-            assert rel(ob, oa) <= 1e-6
+            assert rel_img(ob, oa) <= 1e-6
     op = O.make_plan(sy, sx, ny, nx, r, defocus_edge=0.8, phi=O.fourier_basis(ny, nx))
     live = O.Live(op, "P")
     live.push(frames, pos)
-    err = rel(oa, live.snapshot())
+    err = rel_img(oa, live.snapshot())
     say(f"[fourier] 16x8 detector, 300 scattered frames, order {order}: {err:.2e}")
     assert err <= 1e-5

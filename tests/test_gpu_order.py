@@ -7,7 +7,7 @@ import pytest
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
 import synth
-from gpu_util import device, rel, say
+from gpu_util import device, rel, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_object_order_full_raster(medium_raster, mode):
         with pytest.raises(wdd.WddError) as ei:
             plan.accumulator()
         assert ei.value.code == wdd.WDD_ESTATE
-    errs = (rel(d, d_ref), rel(o, o_ref))
+    errs = (rel_d(d, d_ref), rel_img(o, o_ref))
     say(f"[order] object, medium full raster, {mode} images: D/O {errs}")
     assert max(errs) <= 1e-5
 
@@ -73,12 +73,12 @@ def test_object_order_matches_spectrum_order(rows, k):
             assert not np.any(plan.snapshot())
             plan.restore(image)
             assert np.array_equal(plan.snapshot(), out[order][0])
-    e = (rel(out[1][1], out[0][1]), rel(out[1][0], out[0][0]))
+    e = (rel_d(out[1][1], out[0][1]), rel_img(out[1][0], out[0][0]))
     say(f"[order] rows={rows}: object vs spectrum D/O {e}")
     assert max(e) <= 1e-6
     live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
     live.push(frames, pos)
-    assert rel(out[1][0], live.snapshot()) <= 1e-5
+    assert rel_img(out[1][0], live.snapshot()) <= 1e-5
 
 
 def test_object_order_long_row():
@@ -91,7 +91,7 @@ def test_object_order_long_row():
         got = plan.push_snapshot(device(frames), pos)
     live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
     live.push(frames, pos)
-    err = rel(got, live.snapshot())
+    err = rel_img(got, live.snapshot())
     say(f"[order] one row of {b} frames: {err:.2e}")
     assert err <= 1e-5
 
@@ -111,7 +111,7 @@ def test_object_order_host_frames_and_float32():
         assert ei.value.code == wdd.WDD_ESTATE
     live = O.Live(O.make_plan(s, s, n, n, 8.0, k), "P")
     live.push(frames, pos)
-    assert rel(got, live.snapshot()) <= 1e-5
+    assert rel_img(got, live.snapshot()) <= 1e-5
 
 
 @pytest.mark.parametrize("radius,sy,sx,n,k,rows", [(8.0, 64, 64, 32, 64, 3), (8.0, 64, 32, 32, 36, 20),
@@ -135,13 +135,13 @@ def test_display_rows_left_by_the_update(radius, sy, sx, n, k, rows):
             got = a.push_snapshot(dev[part], pos[part])
             two.push(dev[part], pos[part])
             ref = two.snapshot()
-            errs.append(rel(got, ref))
+            errs.append(rel_img(got, ref))
             assert np.array_equal(a.spectrum(), two.spectrum())
         # a snapshot with no push in between reads the same partial rows
         assert np.array_equal(a.snapshot(), got)
         live = O.Live(O.make_plan(sy, sx, n, n, radius, k), "P")
         live.push(frames, pos)
-        errs.append(rel(got, live.snapshot()))
+        errs.append(rel_img(got, live.snapshot()))
         # a plain push leaves them stale: both plans then take the two-pass display
         a.push(dev[:7], pos[:7])
         two.push(dev[:7], pos[:7])
@@ -169,6 +169,6 @@ def test_display_rows_on_short_scan_columns(sy, sx):
         got = plan.push_snapshot(dev[half:], pos[half:])
     live = O.Live(O.make_plan(sy, sx, n, n, 4.0, k), "P")
     live.push(frames, pos)
-    err = rel(got, live.snapshot())
+    err = rel_img(got, live.snapshot())
     say(f"[order] display rows, {sy}x{sx} scan: {err:.2e}")
     assert err <= 1e-5

@@ -7,7 +7,7 @@ import pytest
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
 import synth
-from gpu_util import device, golden_workload, rel, say
+from gpu_util import device, golden_workload, rel, rel_a, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_full_raster_every_result(name):
                         defocus_edge=wl.defocus_edge, step=wl.step)
     a, d, o = O.offline_reduced(oplan, frames, pos)
     h_last = O.project(frames[-wl.batch:], oplan.phi)
-    errs = dict(h=rel(got_h, h_last), A=rel(got_a, a), D=rel(got_d, d), O=rel(got_o, o))
+    errs = dict(h=rel(got_h, h_last), A=rel_a(got_a, a), D=rel_d(got_d, d), O=rel_img(got_o, o))
     say(f"[parity] {name}: {errs}")
     assert errs["h"] <= TOL_H
     assert errs["A"] <= TOL and errs["D"] <= TOL and errs["O"] <= TOL
@@ -83,14 +83,14 @@ def _sampled_case(name, n_frames, n_sample, seed, order=wdd.WDD_ORDER_SPECTRUM):
     h = O.project(frames, oplan.phi)
     a = O.scan_phase(oplan.freqs, pos, wl.sy, wl.sx) @ h
     d = O.extract(oplan, a)
-    errs = dict(h=rel(got_h, h[-wl.batch:]), D=rel(got_d[pick], d))
+    errs = dict(h=rel(got_h, h[-wl.batch:]), D=rel_d(got_d[pick], d))
     if not obj:
-        errs["A"] = rel(got_a[pick], a)
+        errs["A"] = rel_a(got_a[pick], a)
     else:
         grid = np.zeros((wl.sy, wl.sx), np.complex128)
         grid[all_f[:, 0], all_f[:, 1]] = got_d
         image = np.conj(np.fft.ifft2(grid, norm="ortho")) / np.sqrt(abs(grid[0, 0]))
-        errs["O vs IDFT of D"] = rel(got_o, image)
+        errs["O vs IDFT of D"] = rel_img(got_o, image)
     # the displayed object is the unitary inverse DFT of D (Parseval) normalised by |D[0]|
     pars = abs(np.sum(np.abs(got_o.astype(np.complex128)) ** 2) * abs(got_d[0]) /
                np.sum(np.abs(got_d.astype(np.complex128)) ** 2) - 1)

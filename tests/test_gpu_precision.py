@@ -7,13 +7,16 @@ import pytest
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
 import synth
-from gpu_util import device, golden_workload, rel, say
+from gpu_util import device, golden_workload, rel, rel_a, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
 # bound on the relative L2 error of h, A and D for each projection arithmetic:
 # basis rounding 2^-9 (bf16), 2^-12 (fp16), ~2^-17 (bf16 hi+lo), ~2^-22 (fp16 hi+lo)
 BOUNDS = {"fp32": 1e-5, "bf16_hilo": 3e-5, "fp16_hilo": 2e-6, "bf16": 6e-3, "fp16": 8e-4}
+# bound on the displayed image, whole and minus its mean (the signal beside the zero
+# frequency): the FP32 accumulation and display set a floor of the FP32 bar under every mode
+IMAGE_BOUNDS = {m: max(1e-5, b) for m, b in BOUNDS.items()}
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +49,7 @@ def test_projection_precision_against_oracle(defocus_case, mode):
             hs.append(plan.projection())
         plan.snapshot()
         got_a, got_d = plan.accumulator()[pick], plan.spectrum()[pick]
-    errs = dict(h=rel(np.concatenate(hs), h), A=rel(got_a, a), D=rel(got_d, d))
+    errs = dict(h=rel(np.concatenate(hs), h), A=rel_a(got_a, a), D=rel_d(got_d, d))
     say(f"[precision] {mode}: {errs}")
     assert max(errs.values()) <= BOUNDS[mode]
 
@@ -93,9 +96,9 @@ def test_reduced_precision_needs_uint16_frames():
 @pytest.mark.parametrize("ny,nx,dtype,mode", [(1024, 1024, wdd.WDD_U16, "fp32"), (1000, 1024, wdd.WDD_F32, "fp32"),
                                               (520, 1024, wdd.WDD_U16, "fp16_hilo"), (256, 256, wdd.WDD_U16, "fp32")])
 def test_projection_of_large_detectors(ny, nx, dtype, mode):
-    """The projection's basis tables at the largest detectors: 1024 x 1024 leaves no room
-    in LDS for the bank-spreading row padding (unpadded tables), 1000 rows loop the waves
-    over 63 tiles with a partial last one, and 256 x 256 takes the padded tables."""
+    """The projection's basis tables at the largest detectors: 1024 x 1024 (the tables take
+    most of the LDS), 1000 rows loop the waves over 63 tiles with a partial last one, 520 rows
+    with the 16-bit tables, and 256 x 256 (the large workload's detector)."""
     rng = np.random.default_rng(ny + nx)
     n, k, radius = 3, 10, ny / 8.0
     frames = (rng.poisson(30.0, size=(n, ny, nx)).astype(np.uint16) if dtype == wdd.WDD_U16
@@ -108,3 +111,32 @@ def test_projection_of_large_detectors(ny, nx, dtype, mode):
     err = rel(got, O.project(frames, oplan.phi))
     say(f"[precision] projection {ny}x{nx} {mode}: {err:.2e}")
     assert err <= (1e-6 if mode == "fp32" else BOUNDS[mode])
+
+
+@pytest.mark.parametrize("mode", ["bf16_hilo", "fp16_hilo"])
+def test_reduced_precision_with_the_deferred_display(mode):
+    """Object order with a reduced-precision projection, each image's column pass left to the
+    next push's projection launch (the merged launch) as the bench drives it: every image
+    equals the blocking push + snapshot image bit for bit, and the last one is within the
+    mode's bound of the FP64 oracle."""
+    import torch
+    s, n, k, b = 64, 64, 64, 256
+    rng = np.random.default_rng(88)
+    pos = np.stack([np.repeat(np.arange(s), s), np.tile(np.arange(s), s)], axis=1).astype(np.int32)
+    frames = rng.poisson(40.0, size=(s * s, n, n)).astype(np.uint16)
+    dev = device(frames)
+    shown = [torch.empty((s, s), dtype=torch.complex64, device="cuda") for _ in range(s * s // b)]
+    blocking = []
+    with wdd.Plan(16.0, s, s, n, n, k, max_batch=b, precision=mode, order=wdd.WDD_ORDER_OBJECT) as pa, \
+            wdd.Plan(16.0, s, s, n, n, k, max_batch=b, precision=mode, order=wdd.WDD_ORDER_OBJECT) as pb:
+        for i, b0 in enumerate(range(0, s * s, b)):
+            pa.push_snapshot(dev[b0:b0 + b], pos[b0:b0 + b], out=shown[i], wait=False, defer=True)
+            blocking.append(pb.push_snapshot(dev[b0:b0 + b], pos[b0:b0 + b]))
+        pa.sync()
+    for i in range(len(blocking)):
+        assert np.array_equal(shown[i].cpu().numpy(), blocking[i]), i
+    live = O.Live(O.make_plan(s, s, n, n, 16.0, k), "P")
+    live.push(frames, pos)
+    err = rel_img(blocking[-1], live.snapshot())
+    say(f"[precision] {mode} deferred display: vs oracle {err:.2e}")
+    assert err <= IMAGE_BOUNDS[mode]

@@ -1,12 +1,14 @@
 """Serving runtime: admission by device-memory budget, continuous batching of many
-acquisitions of different geometries, and results that are the same alone and in
-the mix (FP32, relative L2 <= 1e-6; batch boundaries differ, so not bitwise)."""
+acquisitions of different geometries, and results that are the same alone and in the mix
+within the FP32 bar (relative L2 <= 1e-5 on the image and on the image minus its mean;
+batch boundaries differ, so the accumulation's rounding differs and results are not
+bitwise equal)."""
 import numpy as np
 import pytest
 
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
-from gpu_util import device, rel, say
+from gpu_util import device, rel, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -43,13 +45,24 @@ def test_admission_by_memory_budget():
         assert c is not None and srv.stats()["open"] == 2
 
 
-@pytest.mark.parametrize("order", [wdd.WDD_ORDER_SPECTRUM, wdd.WDD_ORDER_OBJECT])
-def test_each_result_is_the_same_alone_and_in_the_mix(order):
+# relative L2 bound against the FP64 oracle for each projection arithmetic (as in the
+# precision tests: basis rounding ~2^-17 for bf16 hi+lo)
+ORACLE_BOUND = {"fp32": 1e-5, "bf16_hilo": 3e-5}
+
+
+@pytest.mark.parametrize("order,precision", [(wdd.WDD_ORDER_SPECTRUM, "fp32"), (wdd.WDD_ORDER_OBJECT, "fp32"),
+                                             (wdd.WDD_ORDER_OBJECT, "bf16_hilo"),
+                                             (wdd.WDD_ORDER_SPECTRUM, "bf16_hilo")])
+def test_each_result_is_the_same_alone_and_in_the_mix(order, precision):
+    """The serving mix pushes frames through a per-frame address table (frames from many
+    submitted buffers in one batch); with a reduced-precision projection that is the
+    bf16 kernel's address-table path.  Alone and in the mix the projections of a frame are
+    identical; only the accumulation's batch boundaries differ."""
     rng = np.random.default_rng(9)
     data = [_acquisition(i, *g) for i, g in enumerate(GEOMS)]
     devs = [device(f) for f, _ in data]
     with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=200.0, batch_frames=256) as srv:
-        ids = [srv.open(r, s, s, n, n, k, order=order) for (r, s, n, k) in GEOMS]
+        ids = [srv.open(r, s, s, n, n, k, order=order, precision=precision) for (r, s, n, k) in GEOMS]
         cursor = [0] * len(GEOMS)
         while any(c < len(d[1]) for c, d in zip(cursor, data)):
             for _ in range(3):
@@ -70,17 +83,50 @@ def test_each_result_is_the_same_alone_and_in_the_mix(order):
         f"{st['snapshots']} snapshots, latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
     for i, (r, s, n, k) in enumerate(GEOMS):
         frames, pos = data[i]
-        with wdd.Plan(r, s, s, n, n, k, max_batch=256, order=order) as plan:
+        with wdd.Plan(r, s, s, n, n, k, max_batch=256, order=order, precision=precision) as plan:
             for b in range(0, len(pos), 256):
                 plan.push(devs[i][b:b + 256], pos[b:b + 256])
             alone = plan.snapshot()
-        e = rel(mixed[i], alone)
-        say(f"[serving] order {order}, acquisition {i}: mix vs alone {e:.2e}")
-        assert e <= 1e-6
+        e = rel_img(mixed[i], alone)
+        say(f"[serving] order {order}, {precision}, acquisition {i}: mix vs alone {e:.2e}")
+        assert e <= 1e-5
     r, s, n, k = GEOMS[0]
     live = O.Live(O.make_plan(s, s, n, n, r, k), "N")
     live.push(*data[0])
-    assert rel(mixed[0], live.snapshot()) <= 1e-5
+    e = rel_img(mixed[0], live.snapshot())
+    say(f"[serving] order {order}, {precision}, acquisition 0 vs oracle {e:.2e}")
+    assert e <= ORACLE_BOUND[precision]
+
+
+def test_same_geometry_in_two_bases():
+    """A Hermite-Gauss and a Fourier-basis acquisition of one geometry (16 x 16 detector,
+    K = 256 = ny nx) open together: each must keep its own tables and match its own plan."""
+    r, s, n, k = 5.0, 16, 16, 256
+    rng = np.random.default_rng(21)
+    pos = synth_raster(s)
+    frames = rng.poisson(25.0, size=(len(pos), n, n)).astype(np.uint16)
+    dev = device(frames)
+    bases = (wdd.WDD_BASIS_HERMITE_GAUSS, wdd.WDD_BASIS_FOURIER)
+    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=0.0, batch_frames=64) as srv:
+        ids = [srv.open(r, s, s, n, n, k, basis=b) for b in bases]
+        for b0 in range(0, len(pos), 48):
+            for a in ids:
+                srv.submit(a, dev[b0:b0 + 48], pos[b0:b0 + 48])
+            srv.step()
+        mixed = [srv.snapshot(a) for a in ids]
+    for basis, got in zip(bases, mixed):
+        with wdd.Plan(r, s, s, n, n, k, basis=basis, max_batch=256) as plan:
+            plan.push(dev, pos)
+            alone = plan.snapshot()
+        e = rel_img(got, alone)
+        say(f"[serving] basis {basis}: mix vs alone {e:.2e}")
+        assert e <= 1e-5
+    assert rel_img(mixed[0], mixed[1]) > 1e-3   # the two bases give different reconstructions
+
+
+def synth_raster(s):
+    yy, xx = np.meshgrid(np.arange(s, dtype=np.int32), np.arange(s, dtype=np.int32), indexing="ij")
+    return np.stack([yy.ravel(), xx.ravel()], axis=1)
 
 
 def test_submit_rejects_positions_off_the_raster():

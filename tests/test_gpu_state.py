@@ -5,7 +5,7 @@ import pytest
 
 import oracle.wdd as O
 import paper_2212_01309_amd as wdd
-from gpu_util import device, rel, say
+from gpu_util import device, rel, rel_d, rel_img, say
 
 pytestmark = pytest.mark.gpu
 
@@ -36,10 +36,10 @@ def test_update_probe_redeconvolves_all_frames_seen():
     op = O.make_plan(s, s, n, n, radius, k, amplitude=2.0, defocus_edge=1.3, eps_rel=0.05)
     live = O.Live(op, "N")
     live.push(frames, pos)
-    errs = (rel(d2, live.spectrum()), rel(second, live.snapshot()))
+    errs = (rel_d(d2, live.spectrum()), rel_img(second, live.snapshot()))
     say(f"[state] update_probe D/O {errs}")
     assert max(errs) <= 1e-5
-    assert rel(third, first) <= 1e-6
+    assert rel_img(third, first) <= 1e-6
 
 
 def test_checkpoint_restore_continues_bitwise():
