@@ -361,6 +361,16 @@ wdd_status wdd_destroy(wdd_plan_t p);
  * WDD_ENOMEM, WDD_EDEVICE. */
 wdd_status wdd_display(const float* spectrum, int32_t sy, int32_t sx, float* out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): wdd_display with the same arguments and
+ * result, whose scratch is a fixed array in device memory that each GPU the library runs
+ * on holds until the process ends (16.8 MB), so the call allocates nothing.  sy sx <=
+ * 1 048 576 (e.g. 1024 x 1024) and sides <= 4096, else WDD_EINVAL.  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (different streams, or host
+ * threads) race and must be ordered by the caller; calls queued on one stream are ordered
+ * by it.  Nothing in the array needs to start at zero. */
+wdd_status wdd_display_noalloc(const float* spectrum, int32_t sy, int32_t sx, float* out, void* hip_stream);
+
 /* Device memory for plans created after this call (tables, spectrum, grids, device
  * staging; not pinned host buffers) comes from alloc(bytes, ctx) and goes back through
  * release(ptr, ctx) when the plan is destroyed, after its stream has drained: a caller

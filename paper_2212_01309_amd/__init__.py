@@ -126,6 +126,7 @@ _SIGNATURES = {
     "wdd_sync": (ctypes.c_int, [_P]),
     "wdd_destroy": (ctypes.c_int, [_P]),
     "wdd_display": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "wdd_display_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "wdd_server_default_options": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
     "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
