@@ -385,6 +385,53 @@ typedef void (*wdd_release_fn)(void* ptr, void* ctx);
 wdd_status wdd_set_allocator(wdd_alloc_fn alloc, wdd_release_fn release, void* ctx);
 
 /* ------------------------------------------------------------------------- */
+/* Field-of-view patches (Section 10, Discussion: a large field of view subdivided into
+ * patches that are reconstructed independently and then merged, so that the cost grows
+ * with the number of patches instead of with the square of the raster).  Reading of the
+ * paper: patches are Py x Px sub-rasters whose origins step by (Py - overlap_y,
+ * Px - overlap_x) from 0, the last one on each axis placed at S - P; every patch is a live
+ * WDD of its own raster (object order), a frame entering every patch that contains its
+ * position, at the local position; the merged image is the weighted mean of the patch images
+ * with separable trapezoid windows min(1, (i + 1) / (o + 1), (P - i) / (o + 1)), which
+ * de-weight each patch's edges (where its own scan DFT wraps around) wherever another patch
+ * covers them.  A single patch covering the raster is the plain plan's result. */
+typedef struct {
+  int32_t py, px;                /* patch size in scan positions, 1 <= p <= the raster's side */
+  int32_t overlap_y, overlap_x;  /* positions neighbouring patches share, 0 <= overlap < p */
+} wdd_patch_geometry;
+
+typedef struct wdd_patches_s* wdd_patches_t;
+
+/* Creates a patch set for the whole raster `scan` (arguments as wdd_plan; the Hermite-Gauss
+ * basis, object order; all patches share one set of tables built for the patch raster).
+ * WDD_EINVAL for a geometry that does not fit the raster. */
+wdd_status wdd_patches_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
+                              const wdd_patch_geometry* geo, const wdd_options* opts, void* hip_stream,
+                              wdd_patches_t* out);
+
+/* Adds n device frames (contiguous, 16-byte aligned; valid until the stream passes this
+ * point) at host positions pos_yx [n][2] of the whole raster: each frame is projected once
+ * and enters every patch that contains it.  Asynchronous.  WDD_ERANGE (nothing applied) for
+ * a position off the raster; WDD_EINVAL for n outside [0, max_batch]. */
+wdd_status wdd_patches_push(wdd_patches_t s, const void* frames, const int32_t* pos_yx, int32_t n);
+
+/* The merged image of all frames pushed so far, sy x sx complex (interleaved float) on the
+ * whole raster, into host memory (WDD_OUT_HOST, blocking) or device memory (WDD_OUT_DEVICE,
+ * blocking; WDD_OUT_DEVICE_ASYNC, queued).  Pixel (y, x) is the object at scan position
+ * (y, x) shifted by the probe centre, as for a plan. */
+wdd_status wdd_patches_snapshot(wdd_patches_t s, float* out, int32_t out_on_device, uint64_t* frames_seen);
+
+/* Patch grid, kept frequencies per patch and device memory held (any pointer may be NULL). */
+wdd_status wdd_patches_info(wdd_patches_t s, int32_t* npatch_y, int32_t* npatch_x, int64_t* n_freq,
+                            int64_t* device_bytes);
+
+/* Waits for all work queued by the patch set. */
+wdd_status wdd_patches_sync(wdd_patches_t s);
+
+/* Releases the patch set (waits for its work first).  NULL is accepted. */
+wdd_status wdd_patches_destroy(wdd_patches_t s);
+
+/* ------------------------------------------------------------------------- */
 /* Serving: many concurrent acquisitions on one GPU.
  *
  * Each acquisition is a plan (spectrum resident in HBM).  wdd_server_open admits an

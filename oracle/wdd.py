@@ -279,7 +279,7 @@ def make_plan(sy: int, sx: int, ny: int, nx: int, radius: float, k: Optional[int
 
 def project(frames: np.ndarray, phi: np.ndarray) -> np.ndarray:
     """h_s = Phi^T vec(I_s) for each frame (dimensionality reduction, Section 5)."""
-    x = np.asarray(frames, dtype=np.float64).reshape(len(frames), -1)
+    x = np.asarray(frames, dtype=np.float64).reshape(len(frames), phi.shape[0])  # (0 frames: an empty batch)
     return x @ phi
 
 
@@ -401,3 +401,70 @@ def frequency_fraction(theta: float, step: float, wavelength: float) -> float:
     """The paper's sufficient bound on the fraction of scan frequencies with overlap,
     sqrt(2) * step * sin(theta) / lambda (equation "low_correlation")."""
     return math.sqrt(2.0) * step * math.sin(theta) / wavelength
+
+
+# ----------------------------------------------------------------------------
+# Field-of-view patches (Section 10, Discussion: a large field of view subdivided into
+# patches reconstructed independently and merged).  The paper gives no patch geometry or
+# merge rule; the reading used here:
+#   * a patch is a Py x Px sub-raster; patch origins step by (Py - oy, Px - ox) from 0 and the
+#     last one on each axis sits at S - P, so patches stay inside the raster and cover it
+#     (oy, ox = overlap in scan positions);
+#   * every patch is a live WDD of its own over its Py x Px raster: a frame at scan position
+#     s enters every patch p that contains it, at the local position s - o_p;
+#   * the merged image is the weighted mean of the patch images over the patches covering a
+#     pixel, with the separable trapezoid window w(i) = min(1, (i + 1) / (o + 1),
+#     (P - i) / (o + 1)) per axis: the patch's own scan DFT treats it as periodic, so its
+#     edges carry wrap-around errors and are de-weighted where another patch covers them.
+# One patch covering the whole raster reproduces the full-scan result.
+# ----------------------------------------------------------------------------
+
+
+def patch_origins(s: int, p: int, overlap: int) -> np.ndarray:
+    """Origins of the patches of length p along an axis of s positions (0 <= overlap < p <= s)."""
+    if not (0 < p <= s and 0 <= overlap < p):
+        raise ValueError("need 0 < p <= s and 0 <= overlap < p")
+    step = p - overlap
+    out = list(range(0, s - p + 1, step))
+    if out[-1] != s - p:
+        out.append(s - p)
+    return np.array(out, dtype=np.int64)
+
+
+def patch_window(p: int, overlap: int) -> np.ndarray:
+    """The 1D merge weight over a patch of length p: 1 inside, linear ramps over the overlap."""
+    i = np.arange(p, dtype=np.float64)
+    return np.minimum(1.0, np.minimum((i + 1) / (overlap + 1), (p - i) / (overlap + 1)))
+
+
+def merge_patches(images: Sequence[np.ndarray], oy: np.ndarray, ox: np.ndarray, sy: int, sx: int,
+                  overlap_y: int, overlap_x: int) -> np.ndarray:
+    """Weighted mean of the patch images (listed row-major over the origin grid oy x ox) on
+    the sy x sx raster."""
+    py, px = images[0].shape
+    wy, wx = patch_window(py, overlap_y), patch_window(px, overlap_x)
+    num = np.zeros((sy, sx), dtype=np.complex128)
+    den = np.zeros((sy, sx), dtype=np.float64)
+    for idx, img in enumerate(images):
+        y0, x0 = oy[idx // len(ox)], ox[idx % len(ox)]
+        w = wy[:, None] * wx[None, :]
+        num[y0:y0 + py, x0:x0 + px] += w * img
+        den[y0:y0 + py, x0:x0 + px] += w
+    return num / den
+
+
+def patched_reconstruction(frames: np.ndarray, positions: np.ndarray, sy: int, sx: int, py: int, px: int,
+                           overlap_y: int, overlap_x: int, plan: Plan):
+    """Every patch reconstructed from the frames inside it (offline form of each patch's
+    live WDD, `plan` built for the Py x Px patch raster), then merged.  Returns (merged
+    image, patch images in origin order)."""
+    oy, ox = patch_origins(sy, py, overlap_y), patch_origins(sx, px, overlap_x)
+    images = []
+    for y0 in oy:
+        for x0 in ox:
+            inside = ((positions[:, 0] >= y0) & (positions[:, 0] < y0 + py) &
+                      (positions[:, 1] >= x0) & (positions[:, 1] < x0 + px))
+            local = positions[inside] - np.array([y0, x0])
+            _, _, img = offline_reduced(plan, frames[inside], local)
+            images.append(img)
+    return merge_patches(images, oy, ox, sy, sx, overlap_y, overlap_x), images

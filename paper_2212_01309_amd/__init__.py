@@ -76,6 +76,11 @@ class Profile(ctypes.Structure):
                 ("rowdft_ms", ctypes.c_double), ("rowdft_launches", ctypes.c_int64)]
 
 
+class PatchGeometry(ctypes.Structure):
+    _fields_ = [("py", ctypes.c_int32), ("px", ctypes.c_int32), ("overlap_y", ctypes.c_int32),
+                ("overlap_x", ctypes.c_int32)]
+
+
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("snapshot_interval_us", ctypes.c_double),
                 ("batch_frames", ctypes.c_int32)]
@@ -127,6 +132,15 @@ _SIGNATURES = {
     "wdd_destroy": (ctypes.c_int, [_P]),
     "wdd_display": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "wdd_display_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "wdd_patches_create": (ctypes.c_int, [ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
+                                          ctypes.c_int32, ctypes.POINTER(PatchGeometry), ctypes.POINTER(Options), _P,
+                                          ctypes.POINTER(_P)]),
+    "wdd_patches_push": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "wdd_patches_snapshot": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "wdd_patches_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "wdd_patches_sync": (ctypes.c_int, [_P]),
+    "wdd_patches_destroy": (ctypes.c_int, [_P]),
     "wdd_server_default_options": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
     "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
@@ -522,6 +536,77 @@ class Plan:
     def sync(self) -> None:
         _check(load_library().wdd_sync(self._h))
         self._held.clear()
+
+
+class Patches:
+    """A large field of view as independently reconstructed, merged patches (wdd_patches_*)."""
+
+    def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, py: int, px: int,
+                 overlap_y: int = 0, overlap_x: int = 0, *, dtype: int = WDD_U16, defocus: float = 0.0,
+                 amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01, sigma: float = 0.0,
+                 max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32, center=None):
+        lib = load_library()
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
+        self._np_dtype = np.uint16 if dtype == WDD_U16 else np.float32
+        self._h = _P()
+        _check(lib.wdd_patches_create(ctypes.byref(_probe(radius, ny, nx, center, defocus, amplitude)),
+                                      ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)), k,
+                                      ctypes.byref(PatchGeometry(py, px, overlap_y, overlap_x)),
+                                      ctypes.byref(_options(eps_rel, sigma, max_batch, precision, WDD_ORDER_OBJECT)),
+                                      _P(stream) if stream else None, ctypes.byref(self._h)))
+        self._held = collections.deque(maxlen=8)
+
+    def info(self) -> dict:
+        a, b, nf, dev = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().wdd_patches_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(nf),
+                                               ctypes.byref(dev)))
+        return {"npatch_y": a.value, "npatch_x": b.value, "n_freq": nf.value, "device_bytes": dev.value}
+
+    def push(self, frames, positions) -> None:
+        """frames: contiguous torch GPU tensor [n, ny, nx]; positions: host int32 [n, 2] on the whole raster."""
+        if not _is_device_tensor(frames) or not frames.is_contiguous():
+            raise ValueError("patch frames must be a contiguous GPU tensor")
+        pos = _host_array(positions, np.int32).reshape(-1, 2)
+        if frames.numel() != pos.shape[0] * self.ny * self.nx:
+            raise ValueError("frames and positions disagree in count or frame shape")
+        _check(load_library().wdd_patches_push(self._h, frames.data_ptr(), pos.ctypes.data, pos.shape[0]))
+        self._held.append(frames)
+
+    def snapshot(self, out=None, wait: bool = True):
+        """The merged image [sy, sx] complex64 (host array, or into a torch GPU tensor `out`)."""
+        seen = ctypes.c_uint64()
+        if out is not None and _is_device_tensor(out):
+            if out.numel() * out.element_size() != 8 * self.sy * self.sx or not out.is_contiguous():
+                raise ValueError("device output must be a contiguous tensor of sy*sx complex64 values")
+            kind = WDD_OUT_DEVICE if wait else WDD_OUT_DEVICE_ASYNC
+            _check(load_library().wdd_patches_snapshot(self._h, out.data_ptr(), kind, ctypes.byref(seen)))
+            return out
+        host = np.empty((self.sy, self.sx), np.complex64) if out is None else out
+        _check(load_library().wdd_patches_snapshot(self._h, host.ctypes.data, WDD_OUT_HOST, ctypes.byref(seen)))
+        return host
+
+    def sync(self) -> None:
+        _check(load_library().wdd_patches_sync(self._h))
+        self._held.clear()
+
+    def close(self) -> None:
+        if self._h:
+            load_library().wdd_patches_destroy(self._h)
+            self._h = _P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

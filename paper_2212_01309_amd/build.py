@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "libwdd.so")
-SOURCES = ["tables.cpp", "api.hip", "kernels.hip", "server.cpp", "noalloc.hip"]
+SOURCES = ["tables.cpp", "api.hip", "kernels.hip", "server.cpp", "noalloc.hip", "patches.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

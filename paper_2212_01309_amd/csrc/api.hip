@@ -33,112 +33,14 @@
 #include <new>
 #include <vector>
 
-#include "kernels.h"
-#include "wdd_internal.h"
+#include "plan.h"
 
-namespace {
-
-// Pinned upload blocks (positions, row grouping, frame-address table) form a ring that the
-// projection kernel reads when it runs; a block is refilled only after the push that last
-// used it has been read.  Stream markers follow every mark_every-th push (an event per push
-// costs several microseconds of host time on a pipelined step).
-constexpr int kUploadSlots = WDD_MAX_PUSHES_IN_FLIGHT;  // most upload blocks in the ring
-constexpr size_t kUploadPinBudget = (size_t)8 << 20;    // pinned bytes the ring may take
-constexpr int kFrameSlots = 4;                          // pinned staging slots for host frames
-constexpr int kFactorRows = 16;  // batches touching at most this many scan rows use the row-factored update
-static_assert(kFactorRows <= wdd::kRowSetMax, "a row pass must fit the kernel-argument row set");
-constexpr int kMinChunk = 16, kMaxChunk = 512;  // kept frequencies per workgroup of the row-factored update
-
-struct wdd_plan_impl {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  bool failed = false;
-  int32_t sy = 0, sx = 0, ny = 0, nx = 0, k = 0, kpad = 0, l = 0, dtype = 0, max_batch = 0;
-  int64_t n_freq = 0, n_freq_pad = 0;
-  double sigma = 0, eps_abs = 0;
-  uint64_t frames_seen = 0;
-  int32_t last_batch = 0;
-  int64_t device_bytes = 0;
-  size_t frame_bytes = 0;
-
-  float* psi = nullptr;
-  uint16_t* psix_lp = nullptr;  // [2][16][nx] bf16/fp16 hi and lo parts (reduced-precision projection)
-  float psi_unscale = 1.f;
-  int32_t precision = WDD_FP32;
-  int32_t order_mode = WDD_ORDER_SPECTRUM;
-  bool fourier = false;  // full Fourier basis: K = ny nx, complex projections
-  wdd_probe probe = {};
-  wdd_scan scan = {};
-  wdd_detector det = {};
-  wdd_options opts = {};
-  std::shared_ptr<const wdd_tables_s> tables;  // the FP64 tables uploaded (wdd_plan_export)
-  int32_t* kmap = nullptr;
-  int2* freqs = nullptr;
-  float2* w = nullptr;
-  float2* acc = nullptr;
-  float2 *ty = nullptr, *tx = nullptr, *ey = nullptr, *ex = nullptr;
-  float2 *fy = nullptr, *fx = nullptr;
-  float* h = nullptr;
-  char* upload = nullptr;  // pos, order, rows
-  int2* pos = nullptr;
-  int32_t* order = nullptr;
-  int32_t* xs = nullptr;
-  int4* rows = nullptr;
-  size_t upload_bytes = 0;
-  float2* t = nullptr;
-  int2* jv = nullptr;  // (j, v_y) of the kept frequencies grouped by v_x (object order)
-  float tscale = 1.f;  // 1 / sqrt(sy sx), the unitary scan DFT's factor
-  int4* chunks = nullptr;
-  int32_t nchunks = 0, max_chunk = 0;
-  // object order: the update also leaves the display's first pass as nslot partial rows per
-  // v_x in `up` (sx * nslot * sy values); up_valid while they match the current D
-  float2* up = nullptr;
-  int32_t nslot = 1;
-  bool up_valid = false;
-  // a display's column pass left to the next push (WDD_OUT_DEVICE_DEFERRED): destination
-  // and source (the partial rows in `up`, or the first pass's grid `u`)
-  float2* deferred_dst = nullptr;
-  const float2* deferred_src = nullptr;
-  int32_t deferred_sr = 0, deferred_sm = 0, deferred_nslot = 1, deferred_slot_stride = 0;
-  void* frames = nullptr;
-  float2 *d = nullptr, *z = nullptr, *u = nullptr;
-  float2* dlo = nullptr;  // object order: the rounding remainder of D (D = d + dlo, compensated sum)
-
-  int up_ring = 4, mark_every = 1;   // upload blocks in the ring; marker spacing in pushes
-  std::vector<char*> pin_up;         // [up_ring]
-  std::vector<hipEvent_t> marks;     // [up_ring / mark_every + 2]
-  std::vector<int64_t> mark_at;      // the push each marker follows (-1: none yet)
-  int64_t pushes = 0;                // pushes that carried frames
-  int64_t drained = -1;              // every push up to this one is known to have run
-  void* pin_frames[kFrameSlots] = {};
-  hipEvent_t fev[kFrameSlots] = {};
-  bool fev_live[kFrameSlots] = {};
-  int fslot = 0;
-  float2* pin_out = nullptr;
-  std::vector<void*> allocs;
-  wdd_alloc_fn alloc_fn = nullptr;  // the caller's device allocator when the plan was created
-  wdd_release_fn release_fn = nullptr;
-  void* alloc_ctx = nullptr;
-
-  // stage timing (wdd_profile_*): events around launches, harvested when the stream is idle
-  int32_t profile_mask = 0;  // bit i: time stage i (Stage enum)
-  int32_t profile_period = 1;  // time one push (and its snapshot) in every profile_period
-  int64_t profile_tick = 0;    // pushes since profiling was (re)configured
-  bool profile_now = true;     // the current push is sampled
-  std::vector<hipEvent_t> ev_pool;
-  struct Pending { int stage; hipEvent_t e0, e1; };
-  std::vector<Pending> pending;
-  double stage_ms[5] = {0, 0, 0, 0, 0};
-  int64_t stage_n[5] = {0, 0, 0, 0, 0};
-  int64_t factored_n = 0;  // timed accumulate launches that were row-factored
-  std::vector<int32_t> host_order;
-  std::vector<int4> host_rows;
-};
-
-}  // namespace
-
-struct wdd_plan_s : wdd_plan_impl {};
+using wdd::kFactorRows;
+using wdd::kFrameSlots;
+using wdd::kMaxChunk;
+using wdd::kMinChunk;
+using wdd::kUploadPinBudget;
+using wdd::kUploadSlots;
 
 namespace {
 
@@ -392,6 +294,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     i = e;
   }
   p->nchunks = (int32_t)chunks.size();
+  p->host_chunks = chunks;
   // partial display rows: power-of-two scan sides (the radix-2 passes), Sy up to the row the
   // update's workgroup transforms in LDS, at most kMaxSlots chunks per v_x
   const bool pow2 = (t.sy & (t.sy - 1)) == 0 && (t.sx & (t.sx - 1)) == 0;

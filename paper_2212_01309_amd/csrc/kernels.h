@@ -72,6 +72,18 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
                            float s_total, int final_scale, int in_sr, int in_sm, int out_sr, int out_sc, int nslot,
                            int slot_stride, hipStream_t st);
 
+// launch_dft_rows (no partials) over `blocks` grids of block_rows rows each, grid b's input,
+// output and D[0] in_block, out_block and d0_block values after grid 0's.
+hipError_t launch_dft_rows_blocks(const float2* in, float2* out, int blocks, int block_rows, int len, const float2* e,
+                                  const float2* d0, float s_total, int final_scale, int in_sr, int in_sm, int out_sr,
+                                  int out_sc, int64_t in_block, int64_t out_block, int64_t d0_block, hipStream_t st);
+
+// Field-of-view patches: out[y][x] = sum_p w img_p[y - oy][x - ox] / sum_p w over the patches
+// (row-major over the origin grid oy[npy] x ox[npx]) covering (y, x); img [npy npx][py][px];
+// w = trapezoid window of the y axis times the x axis's (1 inside, linear over the overlap).
+hipError_t launch_patch_merge(const float2* img, const int* oy, int npy, const int* ox, int npx, int py, int px,
+                              int overlap_y, int overlap_x, float2* out, int sy, int sx, hipStream_t st);
+
 // Row-factored accumulation (see kernels.hip): t[r][vx][c] = sum over the frames of row r of
 // Tx[(vx x_b) mod sx] h[b][c] (order[i]: the batch's frame indices grouped by row, xs[i]: the
 // scan x of frame order[i]); then acc[j][c] += sum_r Ty[(v_y(j) y_r) mod sy] t[r][v_x(j)][c],
@@ -99,6 +111,29 @@ constexpr int kFusedThreads = 512;  // threads of a workgroup of the object-orde
 struct RowSet {
   int4 r[kRowSetMax];
 };
+// One row pass of an object-order update, as launch_row_fused_obj takes it, for the grouped
+// launch: rows[r] as RowSet, the chunk list given per work item instead.
+struct ObjPass {
+  const float* h;
+  const int* order;
+  const int* xs;
+  const int2* jv;
+  const float2* w;
+  float2* d;
+  float2* dlo;
+  float2* z;
+  float2* up;
+  const int4* rows;  // [nrows] (y_r, first index into order and xs, frame count, 0), device memory
+  int kpad, nrows, sx, sy, max_chunk, nslot, log2sy, in_order;
+  float tscale;
+};
+// The row passes of several updates in one launch: workgroup b takes items[b] = (index into
+// passes, v_x, first jv index, count | slot << 16).  lds_bytes: the largest
+// row_fused_lds_bytes of the passes.  passes and items in device memory.
+hipError_t launch_row_fused_obj_group(const ObjPass* passes, const int4* items, int nitems, size_t lds_bytes,
+                                      hipStream_t st);
+size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
+
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,

@@ -112,6 +112,10 @@ struct Chunk<uint16_t> {
   uint4 v;
   __device__ inline void load(const uint16_t* p) { v = gload(reinterpret_cast<const uint4*>(p)); }
   __device__ inline void zero() { v = make_uint4(0u, 0u, 0u, 0u); }
+  // the loaded values where keep, else zero (a select on the values, after they arrive)
+  __device__ inline void keep_if(bool keep) {
+    v.x = keep ? v.x : 0u; v.y = keep ? v.y : 0u; v.z = keep ? v.z : 0u; v.w = keep ? v.w : 0u;
+  }
   __device__ inline float get(int j) const {
     const uint32_t w = (j < 2) ? v.x : (j < 4) ? v.y : (j < 6) ? v.z : v.w;
     return (float)((j & 1) ? (w >> 16) : (w & 0xffffu));
@@ -125,6 +129,10 @@ struct Chunk<float> {
     b = gload(reinterpret_cast<const float4*>(p + 4));
   }
   __device__ inline void zero() { a = b = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ inline void keep_if(bool keep) {
+    a.x = keep ? a.x : 0.f; a.y = keep ? a.y : 0.f; a.z = keep ? a.z : 0.f; a.w = keep ? a.w : 0.f;
+    b.x = keep ? b.x : 0.f; b.y = keep ? b.y : 0.f; b.z = keep ? b.z : 0.f; b.w = keep ? b.w : 0.f;
+  }
   __device__ inline float get(int j) const {
     switch (j) {
       case 0: return a.x; case 1: return a.y; case 2: return a.z; case 3: return a.w;
@@ -188,6 +196,101 @@ __device__ inline void table_finish(const TableRegs& r, const float* __restrict_
 // LDS floats of a projection workgroup: psi_y, transposed psi_x, per-wave G, kmap.
 __host__ __device__ inline size_t project_lds_floats(int ny, int nx, int nw, int kpad) {
   return (size_t)ny * 16 + (size_t)16 * (nx + 4) + (size_t)nw * 256 + (size_t)kpad;
+}
+
+// Straight-line form of project_frame for a frame whose tiles each have a wave of their own
+// (ntiles <= waves), NCH chunks of 32 columns per row (nx <= 32 NCH) and tables within the
+// first table_issue block.  Every load is unconditional (indices clamped into the frame and
+// the tables; lanes outside the frame get zero by a select after their load), so the wait
+// before chunk c's MFMAs counts exactly the NCH - 1 - c later loads: the MFMAs of early
+// chunks run while the later chunks are still arriving.  (Loads under a branch make the
+// compiler wait for every load in flight before the first use of any of them.)
+template <typename T, int NCH>
+__device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames, int ny, int nx,
+                                                   const float* __restrict__ psi, const int* __restrict__ kmap,
+                                                   int kpad, float* __restrict__ h, const uint64_t* __restrict__ fptr,
+                                                   float* smem, int b) {
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
+  const int nxp = nx + 4;
+  float* lpsy = smem;
+  float* lpsxt = smem + ny * 16;
+  float* lg = lpsxt + 16 * nxp;
+  int* lkmap = reinterpret_cast<int*>(lg + nw * 256);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T* f = fptr ? reinterpret_cast<const T*>(fptr[b]) : frames + (size_t)b * ny * nx;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int ntiles = (ny + 15) >> 4;
+  const int ntab = (ny + nx) * 16;
+  TableRegs tr;
+  table_issue(tr, psi, ntab, kmap, kpad, tid, nt);
+  const int y = wave * 16 + r16;
+  const bool row_ok = wave < ntiles && y < ny;
+  const T* rowp = f + (size_t)min(y, ny - 1) * nx;
+  Chunk<T> ch[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
+  // every lane stores (no store under a branch: the compiler would sink the table load into
+  // the branch, behind the frame loads); lanes past a table write to their own slot of the
+  // per-wave G area, which is written again after the MFMAs
+  float* spare = lg + tid;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u * nt + tid;
+    const int j = i - ny * 16;
+    float* dst = i >= ntab ? spare : (i < ny * 16 ? lpsy + i : lpsxt + (j & 15) * nxp + (j >> 4));
+    *dst = tr.v[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = u * nt + tid;
+    int* dst = i < kpad ? lkmap + i : reinterpret_cast<int*>(spare);
+    *dst = tr.k[u];
+  }
+  __syncthreads();
+
+  const float* brow = lpsxt + r16 * nxp;
+  floatx4 tacc = {0.f, 0.f, 0.f, 0.f}, tacc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int xs = 32 * c + 8 * q;
+    ch[c].keep_if(row_ok && xs < nx);
+    const int xb = min(xs, nx - 8);  // a valid table column; the zeroed pixels cancel it
+    const float4 b0 = *reinterpret_cast<const float4*>(brow + xb);
+    const float4 b1 = *reinterpret_cast<const float4*>(brow + xb + 4);
+    tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(0), b0.x, tacc, 0, 0, 0);
+    tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(1), b0.y, tacc2, 0, 0, 0);
+    tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(2), b0.z, tacc, 0, 0, 0);
+    tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(3), b0.w, tacc2, 0, 0, 0);
+    tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(4), b1.x, tacc, 0, 0, 0);
+    tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(5), b1.y, tacc2, 0, 0, 0);
+    tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(6), b1.z, tacc, 0, 0, 0);
+    tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(7), b1.w, tacc2, 0, 0, 0);
+  }
+  tacc += tacc2;
+  floatx4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int yy = wave * 16 + 4 * q + r;
+    const float av = (yy < ny) ? lpsy[min(yy, ny - 1) * 16 + r16] : 0.f;
+    g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, tacc[r], g, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
+  __syncthreads();
+  for (int k = tid; k < kpad; k += nt) {
+    const int idx = lkmap[k];
+    float sum = 0.f;
+    if (idx >= 0)
+      for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+    h[(size_t)b * kpad + k] = sum;
+  }
+}
+
+// Whether project_frame_tile applies: one tile per wave, at most 256 columns, tables within
+// the first block of table loads.
+__host__ __device__ inline bool project_tile_form(int ny, int nx, int nw, int kpad) {
+  const int ntiles = (ny + 15) / 16, nt = 64 * nw;
+  return ntiles <= nw && nx <= 256 && (ny + nx) * 16 <= 8 * nt && kpad <= 4 * nt;
 }
 
 // One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
@@ -442,6 +545,118 @@ __device__ __forceinline__ void project_frame_lp(const uint16_t* __restrict__ fr
   }
 }
 
+// Straight-line form of project_frame_lp under the conditions of project_tile_form (see
+// project_frame_tile): unconditional loads with clamped indices, lanes outside the frame
+// zeroed by a select, and table stores that every lane makes (out-of-range lanes into a
+// spare slot), so that chunk c's MFMAs wait only for chunk c.
+template <bool BF, bool HILO, int NCH>
+__device__ __forceinline__ void project_frame_lp_tile(const uint16_t* __restrict__ frames, int ny, int nx,
+                                                      const float* __restrict__ psi,
+                                                      const uint16_t* __restrict__ psix_lp, float psi_unscale,
+                                                      const int* __restrict__ kmap, int kpad, float* __restrict__ h,
+                                                      const uint64_t* __restrict__ fptr, float* smem, int b) {
+  typedef LpTraits<BF> Tr;
+  typedef typename Tr::vec V;
+  typedef typename Tr::elem E;
+  constexpr int S = Tr::kShift;
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
+  const int nxp = nx + 8;
+  float* lpsy = smem;
+  float* lg = lpsy + ny * 16;
+  int* lkmap = reinterpret_cast<int*>(lg + nw * 256);
+  uint16_t* lpx = reinterpret_cast<uint16_t*>(lkmap + kpad);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[b]) : frames + (size_t)b * ny * nx;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int ntiles = (ny + 15) >> 4;
+  const int nsy = ny * 16, half = nx >> 1, nwords = (HILO ? 2 : 1) * 16 * half;
+  const uint32_t* px32 = reinterpret_cast<const uint32_t*>(psix_lp);
+  float vy[8];
+  uint32_t vx[8];
+  int vk[4];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vy[u] = gload(psi + min(u * nt + tid, nsy - 1));
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vx[u] = gload(px32 + min(u * nt + tid, nwords - 1));
+#pragma unroll
+  for (int u = 0; u < 4; ++u) vk[u] = gload(kmap + min(u * nt + tid, kpad - 1));
+  const int y = wave * 16 + r16;
+  const bool row_ok = wave < ntiles && y < ny;
+  const uint16_t* rowp = f + (size_t)min(y, ny - 1) * nx;
+  Chunk<uint16_t> ch[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
+  uint32_t* lpx32 = reinterpret_cast<uint32_t*>(lpx);
+  const int hp = nxp >> 1;
+  float* spare = lg + tid;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u * nt + tid;
+    float* dy = i < nsy ? lpsy + i : spare;
+    *dy = vy[u];
+    uint32_t* dx = i < nwords ? lpx32 + (i / half) * hp + i % half : reinterpret_cast<uint32_t*>(spare);
+    *dx = vx[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = u * nt + tid;
+    int* dk = i < kpad ? lkmap + i : reinterpret_cast<int*>(spare);
+    *dk = vk[u];
+  }
+  __syncthreads();
+
+  floatx4 tlo = {0.f, 0.f, 0.f, 0.f}, thi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int xs = 32 * c + 8 * q;
+    ch[c].keep_if(row_ok && xs < nx);
+    const int xb = min(xs, nx - 8);
+    V alo, ahi;
+    uint32_t any_hi = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t v = (uint32_t)ch[c].get(j);
+      const uint32_t hi = v >> S;
+      any_hi |= hi;
+      alo[j] = (E)(float)(v & ((1u << S) - 1u));
+      ahi[j] = (E)(float)hi;
+    }
+    const V bhi = *reinterpret_cast<const V*>(lpx + r16 * nxp + xb);
+    tlo = Tr::mfma(alo, bhi, tlo);
+    if (HILO) tlo = Tr::mfma(alo, *reinterpret_cast<const V*>(lpx + (16 + r16) * nxp + xb), tlo);
+    if (__any(any_hi != 0u)) {
+      thi = Tr::mfma(ahi, bhi, thi);
+      if (HILO) thi = Tr::mfma(ahi, *reinterpret_cast<const V*>(lpx + (16 + r16) * nxp + xb), thi);
+    }
+  }
+  floatx4 tacc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tacc[r] = (tlo[r] + thi[r] * (float)(1 << S)) * psi_unscale;
+  floatx4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int yy = wave * 16 + 4 * q + r;
+    const float av = (yy < ny) ? lpsy[min(yy, ny - 1) * 16 + r16] : 0.f;
+    g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, tacc[r], g, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
+  __syncthreads();
+  for (int k = tid; k < kpad; k += nt) {
+    const int idx = lkmap[k];
+    float sum = 0.f;
+    if (idx >= 0)
+      for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+    h[(size_t)b * kpad + k] = sum;
+  }
+}
+
+// Whether project_frame_lp_tile applies (its 16-bit table within the first load block too).
+__host__ __device__ inline bool project_lp_tile_form(int ny, int nx, int nw, int kpad) {
+  const int ntiles = (ny + 15) / 16, nt = 64 * nw;
+  return ntiles <= nw && nx <= 256 && ny * 16 <= 8 * nt && 2 * 16 * (nx / 2) <= 8 * nt && kpad <= 4 * nt;
+}
+
 // Arguments of a projection launch (passed by value).
 struct ProjArgs {
   const void* frames;
@@ -462,12 +677,42 @@ struct ProjArgs {
 template <typename T, int PREC>
 __device__ __forceinline__ void project_any(const ProjArgs& a, float* smem, int b) {
   if constexpr (PREC == WDD_FP32) {
-    project_frame<T>(static_cast<const T*>(a.frames), a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b);
+    const T* fr = static_cast<const T*>(a.frames);
+    if (project_tile_form(a.ny, a.nx, (int)(blockDim.x >> 6), a.kpad)) {
+      switch ((a.nx + 31) >> 5) {  // chunks of 32 columns per row
+        case 1: project_frame_tile<T, 1>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 2: project_frame_tile<T, 2>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 3: project_frame_tile<T, 3>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 4: project_frame_tile<T, 4>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 5: project_frame_tile<T, 5>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 6: project_frame_tile<T, 6>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        case 7: project_frame_tile<T, 7>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+        default: project_frame_tile<T, 8>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+      }
+    }
+    project_frame<T>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b);
   } else {
     constexpr bool bf = PREC == WDD_BF16_HILO || PREC == WDD_BF16;
     constexpr bool hilo = PREC == WDD_BF16_HILO || PREC == WDD_FP16_HILO;
-    project_frame_lp<bf, hilo>(static_cast<const uint16_t*>(a.frames), a.ny, a.nx, a.psi, a.psix_lp, a.psi_unscale,
-                               a.kmap, a.kpad, a.h, a.fptr, smem, b);
+    const uint16_t* fr = static_cast<const uint16_t*>(a.frames);
+    if (project_lp_tile_form(a.ny, a.nx, (int)(blockDim.x >> 6), a.kpad)) {
+#define WDD_LP_TILE(N)                                                                                          \
+  project_frame_lp_tile<bf, hilo, N>(fr, a.ny, a.nx, a.psi, a.psix_lp, a.psi_unscale, a.kmap, a.kpad, a.h, a.fptr, \
+                                     smem, b);                                                                  \
+  return
+      switch ((a.nx + 31) >> 5) {
+        case 1: WDD_LP_TILE(1);
+        case 2: WDD_LP_TILE(2);
+        case 3: WDD_LP_TILE(3);
+        case 4: WDD_LP_TILE(4);
+        case 5: WDD_LP_TILE(5);
+        case 6: WDD_LP_TILE(6);
+        case 7: WDD_LP_TILE(7);
+        default: WDD_LP_TILE(8);
+      }
+#undef WDD_LP_TILE
+    }
+    project_frame_lp<bf, hilo>(fr, a.ny, a.nx, a.psi, a.psix_lp, a.psi_unscale, a.kmap, a.kpad, a.h, a.fptr, smem, b);
   }
 }
 
@@ -697,19 +942,27 @@ __device__ __forceinline__ void display_row_partials(const float2* __restrict__ 
   }
 }
 
+// Rows come in blocks of block_rows (several grids transformed in one launch, e.g. one per
+// field-of-view patch): row r is row r % block_rows of block r / block_rows, whose input,
+// output and D[0] are in_block, out_block and d0_block values further on.
 template <bool SLOTS>
 __global__ __launch_bounds__(256) void k_dft_rows(const float2* __restrict__ in, float2* __restrict__ out, int len,
                                                   int log2len, const float2* __restrict__ e,
                                                   const float2* __restrict__ d0, float s_total, int final_scale,
                                                   int in_sr, int in_sm, int out_sr, int out_sc, int xcd_map,
-                                                  int nslot, int slot_stride) {
+                                                  int nslot, int slot_stride, int block_rows, int64_t in_block,
+                                                  int64_t out_block, int64_t d0_block) {
   extern __shared__ float2 lbuf[];  // [len] data, then [len / 2] twiddles (power-of-two lengths)
-  const int r = xcd_map ? xcd_row(blockIdx.x, gridDim.x) : (int)blockIdx.x, tid = threadIdx.x;
+  const int rg = xcd_map ? xcd_row(blockIdx.x, gridDim.x) : (int)blockIdx.x, tid = threadIdx.x;
   if (SLOTS) {  // final_scale is set on this (the column) pass
-    display_row_partials(in, out, len, log2len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot, slot_stride, r,
+    display_row_partials(in, out, len, log2len, e, d0, s_total, in_sr, in_sm, out_sr, out_sc, nslot, slot_stride, rg,
                          lbuf, tid, 256);
     return;
   }
+  const int blk = rg / block_rows, r = rg - blk * block_rows;
+  in += blk * in_block;
+  out += blk * out_block;
+  d0 += blk * d0_block;
   const float2* src = in + (size_t)r * in_sr;
   float2* dst = out + (size_t)r * out_sr;
   float scale = 1.0f;
@@ -969,8 +1222,9 @@ __device__ inline void cmac4(float4& a0, float4& a1, float2 c, const float4 h) {
 
 // s = sum_r ph_r T_r over this lane's 4 entries (T_r from LDS); ph0, the twiddle of row 0,
 // is given (formed once per frequency), the others are formed here
+template <typename Rows>
 __device__ inline void phase_sum(float4& s0, float4& s1, const float4* __restrict__ lt, int q, int kq, int nrows,
-                                 const RowSet& rs, int vy, int sy, bool py2, float invy, float2 ph0) {
+                                 const Rows& rs, int vy, int sy, bool py2, float invy, float2 ph0) {
   s0 = make_float4(0.f, 0.f, 0.f, 0.f);
   s1 = s0;
   for (int r = 0; r < nrows; ++r) {
@@ -1015,18 +1269,14 @@ __device__ inline void add4(float4& a, const float4 b) {
   a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
 }
 
-__global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __restrict__ h, int kpad,
-                                                                 const int* __restrict__ order,
-                                                                 const int* __restrict__ xs, RowSet rs, int nrows,
-                                                                 float tscale, int sx, int sy,
-                                                                 const int4* __restrict__ chunks,
-                                                                 const int2* __restrict__ jv,
-                                                                 const float2* __restrict__ w,
-                                                                 float2* __restrict__ d, float2* __restrict__ dlo,
-                                                                 float2* __restrict__ z,
-                                                                 int max_chunk, float2* __restrict__ up, int nslot,
-                                                                 int log2sy, int in_order) {
-  extern __shared__ float4 fsm[];
+template <typename Rows>
+__device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, int kpad, const int* __restrict__ order,
+                                                   const int* __restrict__ xs, const Rows& rs, int nrows,
+                                                   float tscale, int sx, int sy, const int4 ch,
+                                                   const int2* __restrict__ jv, const float2* __restrict__ w,
+                                                   float2* __restrict__ d, float2* __restrict__ dlo,
+                                                   float2* __restrict__ z, int max_chunk, float2* __restrict__ up,
+                                                   int nslot, int log2sy, int in_order, float4* fsm) {
   const int q = kpad >> 2, G = kFusedThreads / q;
   const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
   float4* lt = fsm;                                           // [nrows][q][2]: T_r, 4 complex per float4 pair
@@ -1050,13 +1300,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
   const bool pre = in_order && grp + 7 * G < n_first;
   float4 hv0[8];
   {
-    const int f0 = rs.r[0].y + (pre ? grp : 0), fs = pre ? G : 0;
+    // (not in order: frame 0, always a valid row of h, stands in; these loads go unused)
+    const int f0 = pre ? rs.r[0].y + grp : 0, fs = pre ? G : 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) hv0[u] = gload(h4 + (size_t)(f0 + u * fs) * q + kq);
   }
-  // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
-  // share cache lines) run on one XCD, so partly written lines meet in one L2
-  const int4 ch = chunks[xcd_row(blockIdx.x, gridDim.x)];
   const int vx = ch.x, i0 = ch.y, cnt = ch.z;
   const bool px2 = (sx & (sx - 1)) == 0, py2 = (sy & (sy - 1)) == 0;
   const float invx = 1.0f / (float)sx, invy = 1.0f / (float)sy;
@@ -1180,6 +1428,41 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
     float2* dst = up + (size_t)vx * nslot + ch.w;
     for (int m = tid; m < sy; m += kFusedThreads) dst[m * ustride] = lrow[m];
   }
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __restrict__ h, int kpad,
+                                                                 const int* __restrict__ order,
+                                                                 const int* __restrict__ xs, RowSet rs, int nrows,
+                                                                 float tscale, int sx, int sy,
+                                                                 const int4* __restrict__ chunks,
+                                                                 const int2* __restrict__ jv,
+                                                                 const float2* __restrict__ w,
+                                                                 float2* __restrict__ d, float2* __restrict__ dlo,
+                                                                 float2* __restrict__ z,
+                                                                 int max_chunk, float2* __restrict__ up, int nslot,
+                                                                 int log2sy, int in_order) {
+  extern __shared__ float4 fsm[];
+  // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
+  // share cache lines) run on one XCD, so partly written lines meet in one L2
+  const int4 ch = chunks[xcd_row(blockIdx.x, gridDim.x)];
+  row_fused_obj_body(h, kpad, order, xs, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
+                     in_order, fsm);
+}
+
+// Row passes of several object-order updates in one launch: workgroup b takes work item
+// items[b] = (pass, v_x, first jv index, count | slot << 16) of the pass descriptors
+// (each a row pass of one plan's frames: its own D, tables, rows and frame lists).
+struct GlobalRows {
+  const int4* r;
+};
+__global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj_group(const wdd::ObjPass* __restrict__ passes,
+                                                                       const int4* __restrict__ items) {
+  extern __shared__ float4 fsm[];
+  const int4 it = items[blockIdx.x];
+  const wdd::ObjPass& p = passes[it.x];
+  const int4 ch = make_int4(it.y, it.z, it.w & 0xffff, it.w >> 16);
+  row_fused_obj_body(p.h, p.kpad, p.order, p.xs, GlobalRows{p.rows}, p.nrows, p.tscale, p.sx, p.sy, ch, p.jv, p.w,
+                     p.d, p.dlo, p.z, p.max_chunk, p.up, p.nslot, p.log2sy, p.in_order, fsm);
 }
 
 
@@ -1559,10 +1842,68 @@ hipError_t launch_dft_rows(const float2* in, float2* out, int rows, int len, con
   const int xcd_map = (int64_t)rows * len >= 65536;
   if (nslot > 1)
     hipLaunchKernelGGL(k_dft_rows<true>, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale,
-                       in_sr, in_sm, out_sr, out_sc, xcd_map, nslot, slot_stride);
+                       in_sr, in_sm, out_sr, out_sc, xcd_map, nslot, slot_stride, rows, (int64_t)0, (int64_t)0,
+                       (int64_t)0);
   else
     hipLaunchKernelGGL(k_dft_rows<false>, dim3(rows), dim3(256), lds, st, in, out, len, lg, e, d0, s_total, final_scale,
-                       in_sr, in_sm, out_sr, out_sc, xcd_map, 1, 0);
+                       in_sr, in_sm, out_sr, out_sc, xcd_map, 1, 0, rows, (int64_t)0, (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_rows_blocks(const float2* in, float2* out, int blocks, int block_rows, int len, const float2* e,
+                                  const float2* d0, float s_total, int final_scale, int in_sr, int in_sm, int out_sr,
+                                  int out_sc, int64_t in_block, int64_t out_block, int64_t d0_block, hipStream_t st) {
+  int lg = -1;
+  if ((len & (len - 1)) == 0) {
+    lg = 0;
+    while ((1 << lg) < len) ++lg;
+  }
+  if (blocks < 1 || block_rows < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)len * sizeof(float2) + (lg >= 0 ? (size_t)(len / 2) * sizeof(float2) : 0);
+  hipLaunchKernelGGL(k_dft_rows<false>, dim3((unsigned)(blocks * block_rows)), dim3(256), lds, st, in, out, len, lg, e,
+                     d0, s_total, final_scale, in_sr, in_sm, out_sr, out_sc, 0, 1, 0, block_rows, in_block, out_block,
+                     d0_block);
+  return hipGetLastError();
+}
+
+// The field-of-view patch merge: out[y][x] = sum_p w_p img_p[y - oy_p][x - ox_p] / sum_p w_p over
+// the patches covering (y, x), w_p the product of the trapezoid windows of the two axes, patches
+// taken in origin order (deterministic).
+__device__ inline float patch_weight(int i, int p, int overlap) {
+  const float o1 = (float)(overlap + 1);
+  return fminf(1.0f, fminf((float)(i + 1) / o1, (float)(p - i) / o1));
+}
+__global__ __launch_bounds__(256) void k_patch_merge(const float2* __restrict__ img, const int* __restrict__ oy,
+                                                     int npy, const int* __restrict__ ox, int npx, int py, int px,
+                                                     int overlap_y, int overlap_x, float2* __restrict__ out, int sy,
+                                                     int sx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)sy * sx) return;
+  const int y = (int)(i / sx), x = (int)(i - (int64_t)y * sx);
+  float re = 0.f, im = 0.f, den = 0.f;
+  for (int a = 0; a < npy; ++a) {
+    const int ly = y - oy[a];
+    if (ly < 0 || ly >= py) continue;
+    const float wy = patch_weight(ly, py, overlap_y);
+    for (int b = 0; b < npx; ++b) {
+      const int lx = x - ox[b];
+      if (lx < 0 || lx >= px) continue;
+      const float w = wy * patch_weight(lx, px, overlap_x);
+      const float2 v = img[((size_t)(a * npx + b) * py + ly) * px + lx];
+      re += w * v.x;
+      im += w * v.y;
+      den += w;
+    }
+  }
+  out[i] = den > 0.f ? make_float2(re / den, im / den) : make_float2(0.f, 0.f);
+}
+
+hipError_t launch_patch_merge(const float2* img, const int* oy, int npy, const int* ox, int npx, int py, int px,
+                              int overlap_y, int overlap_x, float2* out, int sy, int sx, hipStream_t st) {
+  const int64_t n = (int64_t)sy * sx;
+  if (n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_patch_merge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, img, oy, npy, ox, npx, py, px,
+                     overlap_y, overlap_x, out, sy, sx);
   return hipGetLastError();
 }
 
@@ -1613,6 +1954,16 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
   const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
                      tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, in_order ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_fused_obj_group(const ObjPass* passes, const int4* items, int nitems, size_t lds_bytes,
+                                      hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+  if (lds_bytes > kLdsBytes) return hipErrorInvalidValue;
+  const hipError_t e = allow_full_lds(k_row_fused_obj_group);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_fused_obj_group, dim3((unsigned)nitems), dim3(kFusedThreads), lds_bytes, st, passes, items);
   return hipGetLastError();
 }
 
