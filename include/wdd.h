@@ -224,15 +224,16 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *                         this point; frames_seen then counts the frames enqueued.
  *   WDD_OUT_DEVICE_DEFERRED  as WDD_OUT_DEVICE_ASYNC, except that the image (of this
  *                         point's spectrum) may be written by the plan's next push, in
- *                         the same launch as that push's projection (one kernel boundary
- *                         fewer per pipelined step), or else by the next call that waits
- *                         for the plan's stream or changes its state (wdd_snapshot,
- *                         wdd_sync, wdd_get_*, wdd_profile_read, checkpoints,
- *                         wdd_update_probe, wdd_reset, wdd_destroy).  `out` is
- *                         complete after wdd_sync.  Where the display's last pass cannot
- *                         wait (the Fourier basis, reduced precision, scans whose Sx is
- *                         not a power of two, detectors of more than 128 rows) it is
- *                         queued at once, as WDD_OUT_DEVICE_ASYNC. */
+ *                         one of that push's launches (its projection; for detectors of
+ *                         more than 128 rows in object order, its first update: one
+ *                         kernel boundary fewer per pipelined step), or else by the next
+ *                         call that waits for the plan's stream or changes its state
+ *                         (wdd_snapshot, wdd_sync, wdd_get_*, wdd_profile_read,
+ *                         checkpoints, wdd_update_probe, wdd_reset, wdd_destroy).  `out`
+ *                         is complete after wdd_sync.  Where the display's last pass
+ *                         cannot wait (the Fourier basis, scans whose Sx is not a power
+ *                         of two, detectors of more than 128 rows in spectrum order) it
+ *                         is queued at once, as WDD_OUT_DEVICE_ASYNC. */
 typedef enum { WDD_OUT_HOST = 0, WDD_OUT_DEVICE = 1, WDD_OUT_DEVICE_ASYNC = 2, WDD_OUT_DEVICE_DEFERRED = 3 } wdd_out_kind;
 
 /* Takes a snapshot of all frames pushed so far (Section 6.3, modified-WDD algorithm, the

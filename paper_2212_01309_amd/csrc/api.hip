@@ -178,19 +178,25 @@ wdd_status column_pass(wdd_plan_s* p, const float2* src, int32_t sr, int32_t sm,
 
 // A deferred column pass can ride in the next push's projection launch (the Hermite-Gauss
 // projection kernels, any arithmetic; radix-2 rows: power-of-two Sx).  Detectors of more
-// than 128 rows keep it in its own launch: their 1024-thread projection workgroups (one wave
-// per 16 rows) would carry the display rows too, and the merged launch then took longer
-// than the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).
+// than 128 rows do not put it there: their 1024-thread projection workgroups (one wave per
+// 16 rows) would carry the display rows too, and the merged launch then took longer than
+// the two (22 us against 15.5 + 5.4 us for a 512 x 512 scan, 256 x 256 frames).  In object
+// order it rides in the next push's first update launch instead (512-thread workgroups),
+// reading partial rows and D[0] kept from the previous push (can_defer_to_update).
 bool can_defer(const wdd_plan_s* p) {
   return !p->fourier && p->ny <= 128 && (p->sx & (p->sx - 1)) == 0;
 }
 
+bool can_defer_to_update(const wdd_plan_s* p) { return p->up_valid && p->up_alt && p->d0w; }
+
 // Writes a display left to the next push now; every call that waits for the plan's stream
-// or changes its state goes through here first.
+// or changes its state goes through here first (D has not changed since the display was
+// queued, so p->d gives its D[0]).
 wdd_status flush_deferred(wdd_plan_s* p) {
   if (!p->deferred_dst) return WDD_OK;
   float2* dst = p->deferred_dst;
   p->deferred_dst = nullptr;
+  p->deferred_in_update = false;
   return column_pass(p, p->deferred_src, p->deferred_sr, p->deferred_sm, p->deferred_nslot, p->deferred_slot_stride,
                      dst);
 }
@@ -356,6 +362,11 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     ALLOC(p->chunks, chunks.size());
   }
   if (partial_rows) ALLOC(p->up, (size_t)t.sx * p->nslot * t.sy);
+  if (partial_rows && t.ny > 128) {  // see can_defer
+    ALLOC(p->up_alt, (size_t)t.sx * p->nslot * t.sy);
+    ALLOC(p->d0w, 2);
+    p->d0w_alt = p->d0w + 1;
+  }
   {
     char* fr = nullptr;
     if ((st = dalloc(p, &fr, (size_t)p->max_batch * p->frame_bytes)) != WDD_OK) return st;
@@ -401,6 +412,8 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->z), grid * 2, p->stream));
   // slots that no chunk owns stay zero for the plan's life
   if (p->up) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->up), (size_t)t.sx * p->nslot * t.sy * 2, p->stream));
+  if (p->up_alt)
+    WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->up_alt), (size_t)t.sx * p->nslot * t.sy * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   if (p->dlo) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
@@ -631,7 +644,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   }
   p->profile_now = (p->profile_tick++ % p->profile_period) == 0;
   hipEvent_t end;
-  if (p->fourier) {  // a deferred display rides only in the Hermite-Gauss projection
+  if (p->fourier || (p->deferred_in_update && !object)) {  // see can_defer
     if ((st = flush_deferred(p)) != WDD_OK) return st;
   }
   WDD_HIP(p, stage_begin(p, kProject, &end));
@@ -658,7 +671,7 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     pl.up_dst = p->upload;
     pl.up_bytes = up_bytes;
     pl.fptr = ftab;
-    if (p->deferred_dst) {
+    if (p->deferred_dst && !p->deferred_in_update) {
       // the previous step's column pass rides in this launch (it reads its source and D
       // before this push's update changes them)
       wdd::DisplayColumns dc;
@@ -719,16 +732,42 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     const bool rows_for_display = fuse_wiener && p->up;
     bool in_order = true;  // frames already grouped by row (a raster batch): no reordering
     for (int32_t i = 0; i < n && in_order; ++i) in_order = ord[i] == i;
+    if (rows_for_display && p->up_alt) {  // keep the previous push's rows for a display still to come
+      std::swap(p->up, p->up_alt);
+      std::swap(p->d0w, p->d0w_alt);
+    }
     for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
       const int nr = std::min(kFactorRows, nrows - r0);
-      float2* up_pass = rows_for_display && r0 + kFactorRows >= nrows ? p->up : nullptr;
+      const bool last = r0 + kFactorRows >= nrows;
+      float2* up_pass = rows_for_display && last ? p->up : nullptr;
+      float2* d0out = up_pass && p->up_alt ? p->d0w : nullptr;
+      // the previous step's column pass, left to this launch (reads what that push kept)
+      wdd::DisplayColumns dc;
+      const bool carry = r0 == 0 && p->deferred_dst && p->deferred_in_update;
+      if (carry) {
+        dc.din = p->deferred_src;
+        dc.dout = p->deferred_dst;
+        dc.rows = p->sy;
+        dc.len = p->sx;
+        dc.e = p->ex;
+        dc.d0 = p->deferred_d0;
+        dc.s_total = (float)((double)p->sy * p->sx);
+        dc.in_sr = p->deferred_sr;
+        dc.in_sm = p->deferred_sm;
+        dc.out_sr = p->sx;
+        dc.out_sc = 1;
+        dc.nslot = p->deferred_nslot;
+        dc.slot_stride = p->deferred_slot_stride;
+        p->deferred_dst = nullptr;
+        p->deferred_in_update = false;
+      }
       if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
       WDD_HIP(p, stage_begin(p, kAccumulate, &end));
       wdd::RowSet rs;
       for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
       WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
                                            p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z, up_pass,
-                                           p->nslot, in_order, p->stream));
+                                           p->nslot, in_order, d0out, carry ? &dc : nullptr, p->stream));
       WDD_HIP(p, stage_end(p, end));
     }
     p->up_valid = rows_for_display;
@@ -780,10 +819,12 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   const float2* src;
   int32_t sr, sm, nslot, slot_stride;
   column_source(p, &src, &sr, &sm, &nslot, &slot_stride);
-  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && can_defer(p)) {
+  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && (can_defer(p) || can_defer_to_update(p))) {
     p->deferred_dst = dst;
     p->deferred_src = src, p->deferred_sr = sr, p->deferred_sm = sm, p->deferred_nslot = nslot;
     p->deferred_slot_stride = slot_stride;
+    p->deferred_in_update = !can_defer(p);
+    p->deferred_d0 = p->deferred_in_update ? p->d0w : p->d;
   } else if ((st = column_pass(p, src, sr, sm, nslot, slot_stride, dst)) != WDD_OK) {
     return st;
   }

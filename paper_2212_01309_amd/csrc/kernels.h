@@ -103,7 +103,11 @@ hipError_t launch_row_update(float2* acc, int kpad, int64_t n_freq_pad, const in
 // order[i].  chunks[c] = (vx, first index into jv, count <= max_chunk <= 512, slot < nslot);
 // jv[i] = (j, v_y(j)).  With up set (power-of-two sy <= kDisplayRowMax, nslot <= kMaxSlots),
 // up[(y sx + vx) nslot + slot] = sum_{j of chunk c} conj(d[j]) E_sy(v_y(j) y) after the update:
-// the display's first pass split over the chunks.  in_order: order[i] = i for the frames of
+// the display's first pass split over the chunks; with d0out set, the launch also stores the
+// updated D[0] there (the normalisation of that display, read by a later launch).  With dc,
+// workgroups past the chunks write the rows of an earlier image from its partial rows (the
+// column pass of launch_project_display), which must not be the `up` this launch writes.
+// in_order: order[i] = i for the frames of
 // the pass (row order already), which lets the kernel load their projections before the
 // indices arrive.
 constexpr int kRowSetMax = 16;
@@ -137,7 +141,8 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
-                                float2* up, int nslot, bool in_order, hipStream_t st);
+                                float2* up, int nslot, bool in_order, float2* d0out, const DisplayColumns* dc,
+                                hipStream_t st);
 
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
 // = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,

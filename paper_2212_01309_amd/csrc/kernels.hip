@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -1276,7 +1277,8 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
                                                    const int2* __restrict__ jv, const float2* __restrict__ w,
                                                    float2* __restrict__ d, float2* __restrict__ dlo,
                                                    float2* __restrict__ z, int max_chunk, float2* __restrict__ up,
-                                                   int nslot, int log2sy, int in_order, float4* fsm) {
+                                                   int nslot, int log2sy, int in_order, float2* __restrict__ d0out,
+                                                   float4* fsm) {
   const int q = kpad >> 2, G = kFusedThreads / q;
   const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
   float4* lt = fsm;                                           // [nrows][q][2]: T_r, 4 complex per float4 pair
@@ -1408,6 +1410,7 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
       two_sum_add2(na, nla, oa);
       d[ja] = na;
       dlo[ja] = nla;
+      if (d0out && ja == 0) d0out[0] = na;  // D[0] as of this pass, for a display read later
       z[(size_t)vx * sy + vya] = make_float2(na.x, -na.y);
       if (up) lrow[log2sy ? (int)(__brev((unsigned)vya) >> (32 - log2sy)) : 0] = make_float2(na.x, -na.y);
       if (two) {
@@ -1415,6 +1418,7 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
         two_sum_add2(nb, nlb, ob);
         d[jb] = nb;
         dlo[jb] = nlb;
+        if (d0out && jb == 0) d0out[0] = nb;
         z[(size_t)vx * sy + vyb] = make_float2(nb.x, -nb.y);
         if (up) lrow[log2sy ? (int)(__brev((unsigned)vyb) >> (32 - log2sy)) : 0] = make_float2(nb.x, -nb.y);
       }
@@ -1440,13 +1444,21 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                                                                  float2* __restrict__ d, float2* __restrict__ dlo,
                                                                  float2* __restrict__ z,
                                                                  int max_chunk, float2* __restrict__ up, int nslot,
-                                                                 int log2sy, int in_order) {
+                                                                 int log2sy, int in_order, float2* __restrict__ d0out,
+                                                                 int nchunks, DispArgs disp) {
   extern __shared__ float4 fsm[];
+  const int b = (int)blockIdx.x;
+  if (b >= nchunks) {  // a row of the previous step's image, left to this launch (see launch_row_fused_obj)
+    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
+                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nchunks,
+                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+    return;
+  }
   // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
   // share cache lines) run on one XCD, so partly written lines meet in one L2
-  const int4 ch = chunks[xcd_row(blockIdx.x, gridDim.x)];
+  const int4 ch = chunks[xcd_row(b, nchunks)];
   row_fused_obj_body(h, kpad, order, xs, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
-                     in_order, fsm);
+                     in_order, d0out, fsm);
 }
 
 // Row passes of several object-order updates in one launch: workgroup b takes work item
@@ -1462,7 +1474,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj_group(const wdd
   const wdd::ObjPass& p = passes[it.x];
   const int4 ch = make_int4(it.y, it.z, it.w & 0xffff, it.w >> 16);
   row_fused_obj_body(p.h, p.kpad, p.order, p.xs, GlobalRows{p.rows}, p.nrows, p.tscale, p.sx, p.sy, ch, p.jv, p.w,
-                     p.d, p.dlo, p.z, p.max_chunk, p.up, p.nslot, p.log2sy, p.in_order, fsm);
+                     p.d, p.dlo, p.z, p.max_chunk, p.up, p.nslot, p.log2sy, p.in_order, nullptr, fsm);
 }
 
 
@@ -1942,7 +1954,8 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
-                                float2* up, int nslot, bool in_order, hipStream_t st) {
+                                float2* up, int nslot, bool in_order, float2* d0out, const DisplayColumns* dc,
+                                hipStream_t st) {
   if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
     return hipErrorInvalidValue;
   int log2sy = 0;
@@ -1951,9 +1964,36 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
     if ((1 << log2sy) != sy || sy > kDisplayRowMax || nslot < 1 || nslot > kMaxSlots)
       return hipErrorInvalidValue;
   }
-  const size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
-  hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks), dim3(kFusedThreads), lds, st, h, kpad, order, xs, rows, nrows,
-                     tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, in_order ? 1 : 0);
+  size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
+  DispArgs da;
+  std::memset(&da, 0, sizeof(da));
+  int rows_disp = 0;
+  if (dc) {
+    int lg = 0;
+    while ((1 << lg) < dc->len) ++lg;
+    if (dc->rows < 1 || (1 << lg) != dc->len || dc->nslot < 1 || dc->nslot > kMaxSlots) return hipErrorInvalidValue;
+    da.din = dc->din;
+    da.dout = dc->dout;
+    da.len = dc->len;
+    da.log2len = lg;
+    da.e = dc->e;
+    da.d0 = dc->d0;
+    da.s_total = dc->s_total;
+    da.in_sr = dc->in_sr;
+    da.in_sm = dc->in_sm;
+    da.out_sr = dc->out_sr;
+    da.out_sc = dc->out_sc;
+    da.nslot = dc->nslot;
+    da.slot_stride = dc->slot_stride;
+    rows_disp = dc->rows;
+    lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
+  }
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  const hipError_t e = allow_full_lds(k_row_fused_obj);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks + rows_disp), dim3(kFusedThreads), lds, st, h, kpad, order, xs,
+                     rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
+                     in_order ? 1 : 0, d0out, nchunks, da);
   return hipGetLastError();
 }
 

@@ -70,6 +70,14 @@ struct wdd_plan_impl {
   float2* up = nullptr;
   int32_t nslot = 1;
   bool up_valid = false;
+  // detectors of more than 128 rows: a deferred column pass rides in the next push's first
+  // update launch, which reads the partial rows and D[0] of the previous push while writing
+  // new ones.  So they are double-buffered: up / up_alt swap on every push that writes
+  // partial rows, d0w (a copy of D[0] that the last pass of such a push stores) with them.
+  float2* up_alt = nullptr;
+  float2 *d0w = nullptr, *d0w_alt = nullptr;
+  bool deferred_in_update = false;  // the pending column pass goes with the update, not the projection
+  const float2* deferred_d0 = nullptr;
   // a display's column pass left to the next push (WDD_OUT_DEVICE_DEFERRED): destination
   // and source (the partial rows in `up`, or the first pass's grid `u`)
   float2* deferred_dst = nullptr;

@@ -357,22 +357,26 @@ def test_plans_take_device_memory_from_the_callers_allocator():
         assert np.array_equal(own.push_snapshot(dev, pos), got)
 
 
-@pytest.mark.parametrize("order,s,precision", [(1, 32, "fp32"), (0, 32, "fp32"), (1, 24, "fp32"), (0, 24, "fp32"),
-                                                (1, 32, "bf16_hilo")])
-def test_deferred_device_snapshots_match_asynchronous_ones(order, s, precision):
+@pytest.mark.parametrize("order,s,precision,n", [(1, 32, "fp32", 32), (0, 32, "fp32", 32), (1, 24, "fp32", 32),
+                                                  (0, 24, "fp32", 32), (1, 32, "bf16_hilo", 32),
+                                                  (1, 32, "fp32", 160), (0, 32, "fp32", 160),
+                                                  (1, 32, "bf16_hilo", 160)])
+def test_deferred_device_snapshots_match_asynchronous_ones(order, s, precision, n):
     """WDD_OUT_DEVICE_DEFERRED: the display's last pass is written by the next push's first
-    launch (FP32 projection, power-of-two Sx: from the partial rows in object order, from the
-    first pass's grid in spectrum order) or queued at once otherwise; either way each output
-    holds the image of its own point, bit for bit the asynchronous one, and a call that waits
-    for the stream or changes the state (inspection, checkpoint, reset, destroy) writes a
-    pending image first."""
+    launch (power-of-two Sx: from the partial rows in object order, from the first pass's
+    grid in spectrum order; with a 160-row detector in object order, by the first update
+    launch, from the previous push's copy of the partial rows and D[0], while a 64-frame
+    batch over about 28 scan rows takes two update passes) or queued at once otherwise;
+    either way each output holds the image of its own point, bit for bit the asynchronous
+    one, and a plain push, or a call that waits for the stream or changes the state
+    (inspection, checkpoint, reset, destroy), writes a pending image first."""
     import torch
-    n, b, steps = 32, 64, 8
-    frames, pos = _random_case(31 + s + order, s, s, n, n, b * (steps + 4), wdd.WDD_U16)
+    b, steps = 64, 8
+    frames, pos = _random_case(31 + s + order, s, s, n, n, b * (steps + 5), wdd.WDD_U16)
     dev = device(frames)
     blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
     img = lambda: torch.empty((s, s), dtype=torch.complex64, device="cuda")
-    outs = {True: [img() for _ in range(steps + 4)], False: [img() for _ in range(steps + 4)]}
+    outs = {True: [img() for _ in range(steps + 5)], False: [img() for _ in range(steps + 5)]}
     kw = dict(max_batch=b, order=order, precision=precision)
     with wdd.Plan(8.0, s, s, n, n, 64, **kw) as a, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
         for i in range(steps):
@@ -382,16 +386,17 @@ def test_deferred_device_snapshots_match_asynchronous_ones(order, s, precision):
         r.sync()
         for i in range(steps):
             assert torch.equal(outs[True][i], outs[False][i]), i
-        # a pending image is written before an inspection, a checkpoint and a reset
-        for i, settle in zip(range(steps, steps + 3), (lambda p: p.spectrum(), lambda p: p.checkpoint(),
-                                                        lambda p: p.reset())):
+        # a pending image is written by a plain push, and before an inspection, a checkpoint
+        # and a reset
+        for i, settle in zip(range(steps, steps + 4), (lambda p: p.push(*blk(0)), lambda p: p.spectrum(),
+                                                        lambda p: p.checkpoint(), lambda p: p.reset())):
             a.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
             r.push_snapshot(*blk(i), out=outs[False][i], wait=False)
             settle(a)
             settle(r)
             torch.cuda.synchronize()
             assert torch.equal(outs[True][i], outs[False][i]), i
-        i = steps + 3
+        i = steps + 4
         a.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
         r.push_snapshot(*blk(i), out=outs[False][i], wait=False)
     torch.cuda.synchronize()  # both plans destroyed: the pending image was written first
