@@ -211,9 +211,11 @@ wdd_status wdd_patches_push(wdd_patches_t s, const void* frames, const int32_t* 
       }
     }
     std::sort(s->touched.begin(), s->touched.end());
-    // row passes (at most kRowSetMax rows each) of every touched patch
+    // row passes (at most kRowSetMax rows each) of every touched patch.  Passes of one patch
+    // add to the same D, so they go to separate launches: launch k takes the k-th pass of
+    // every patch that has one (passes sorted by k, then patch).
     struct Pass {
-      int32_t patch, row0, nrows, e0;
+      int32_t patch, row0, nrows, k;
     };
     std::vector<Pass> passes;
     std::vector<int4> rows;
@@ -227,10 +229,11 @@ wdd_status wdd_patches_push(wdd_patches_t s, const void* frames, const int32_t* 
           rows.push_back(make_int4(v[i].ly, (int32_t)(nent + i), 0, 0));
         rows.back().z += 1;
       }
-      for (int32_t r = r0; r < (int32_t)rows.size(); r += wdd::kRowSetMax)
-        passes.push_back({p, r, std::min<int32_t>(wdd::kRowSetMax, (int32_t)rows.size() - r), 0});
+      for (int32_t r = r0, k = 0; r < (int32_t)rows.size(); r += wdd::kRowSetMax, ++k)
+        passes.push_back({p, r, std::min<int32_t>(wdd::kRowSetMax, (int32_t)rows.size() - r), k});
       nent += v.size();
     }
+    std::stable_sort(passes.begin(), passes.end(), [](const Pass& a, const Pass& b) { return a.k < b.k; });
     const size_t nchunk = m->host_chunks.size();
     const size_t nitems = passes.size() * nchunk;
     const size_t off_items = align16(passes.size() * sizeof(wdd::ObjPass));
@@ -332,9 +335,14 @@ wdd_status wdd_patches_push(wdd_patches_t s, const void* frames, const int32_t* 
     PATCH_HIP(hipEventRecord(s->blk_ev[slot], m->stream));
     s->blk_live[slot] = true;
     const size_t lds = wdd::row_fused_lds_bytes(m->kpad, max_rows, m->max_chunk);
-    PATCH_HIP(wdd::launch_row_fused_obj_group(reinterpret_cast<const wdd::ObjPass*>(db),
-                                              reinterpret_cast<const int4*>(db + off_items), (int)nitems, lds,
-                                              m->stream));
+    for (size_t i0 = 0; i0 < passes.size();) {  // one launch per pass index k
+      size_t i1 = i0;
+      while (i1 < passes.size() && passes[i1].k == passes[i0].k) ++i1;
+      PATCH_HIP(wdd::launch_row_fused_obj_group(reinterpret_cast<const wdd::ObjPass*>(db),
+                                                reinterpret_cast<const int4*>(db + off_items) + i0 * nchunk,
+                                                (int)((i1 - i0) * nchunk), lds, m->stream));
+      i0 = i1;
+    }
   } catch (const std::bad_alloc&) {
     return wdd::fail(WDD_ENOMEM, "out of host memory");
   }

@@ -24,6 +24,7 @@ def _case(s_y, s_x, n, radius, k, seed):
     (48, 40, 16, 20, 4, 0, 100, True),      # scattered positions, no overlap in x
     (40, 40, 24, 17, 6, 5, 64, False),      # non-power-of-two patch sides (direct DFT display)
     (32, 32, 32, 32, 0, 0, 96, False),      # one patch: the plain plan
+    (64, 64, 48, 40, 32, 16, 256, True),    # scattered: up to 48 scan rows of a patch in one push (3 passes)
 ])
 def test_patches_against_the_oracle(sy, sx, py, px, oy, ox, batch, scatter):
     n, radius, k = 32, 8.0, 36
