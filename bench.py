@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serving-precision", default="bf16_hilo")
     ap.add_argument("--serving-order", default="object", choices=["spectrum", "object"])
     ap.add_argument("--serving-saturate", action="store_true", help="submit frames as fast as possible")
+    ap.add_argument("--serving-mode", default="grouped", choices=["streams", "grouped", "graph"],
+                    help="server launch mode: per-acquisition streams, grouped rounds, grouped rounds from a HIP graph")
     ap.add_argument("--serving-limit-s", type=float, default=150.0)
     ap.add_argument("--pool-batches", type=int, default=4,
                     help="distinct batches generated (steps cycle through them; the work per step does not "
@@ -295,10 +297,10 @@ def precision_lines(torch, wdd, synth, steps, warmup):
 
 
 def serving_line(torch, wdd, synth, limit_s=20.0):
-    """A short serving mix beside the single acquisition: 8 acquisitions of different scan
-    and detector sizes, every frame available at the start (saturated), BF16 hi+lo
-    projection, object order, 1 GiB budget; aggregate frames/s and submit-to-snapshot
-    latency."""
+    """A short serving mix beside the single acquisition, under each launch mode of the
+    server: 8 acquisitions of different scan and detector sizes, every frame available at
+    the start (saturated), BF16 hi+lo projection, object order, 1 GiB budget; aggregate
+    frames/s and submit-to-snapshot latency."""
     rng = np.random.default_rng(7)
     pools = {}
     for n in (64, 128, 256):
@@ -307,13 +309,26 @@ def serving_line(torch, wdd, synth, limit_s=20.0):
         fr = wl.frames(synth.raster_positions(8, 32))               # 256 frames per detector size
         pools[n] = torch.from_numpy(fr.view(np.int16)).to("cuda")
     torch.cuda.synchronize()
+    out = {"workload": "8 acquisitions, scans 64^2..256^2, detectors 64^2..256^2, all frames available at t=0, "
+                       "deliveries of 1-512 frames, bf16 hi+lo projection, object order, snapshot every >= 1 ms; "
+                       "plans made before the timed region, one untimed pass first"}
+    serving_mode(torch, wdd, synth, pools, np.random.default_rng(7), "grouped", limit_s)  # warm-up
+    for mode in ("streams", "grouped", "graph"):
+        out[mode] = serving_mode(torch, wdd, synth, pools, np.random.default_rng(7), mode, limit_s)
+    return out
+
+
+def serving_mode(torch, wdd, synth, pools, rng, mode, limit_s):
     geoms = [(64, 64), (128, 64), (128, 128), (256, 128), (128, 256), (256, 64), (64, 256), (256, 256)]
-    srv = wdd.Server(hbm_budget_bytes=1 << 30, snapshot_interval_us=1000.0, batch_frames=512)
+    srv = wdd.Server(hbm_budget_bytes=1 << 30, snapshot_interval_us=1000.0, batch_frames=512, launch_mode=mode)
     todo = []
     for s, n in geoms:
         aid = srv.open(n / 4 if n <= 128 else 48.0, s, s, n, n, 64 if n <= 128 else 128, precision="bf16_hilo",
                        order=wdd.WDD_ORDER_OBJECT)
         todo.append(dict(id=aid, s=s, n=n, sent=0, total=s * s, pos=synth.raster_positions(s, s)))
+    for a in todo:
+        if a["id"] is not None:
+            srv.wait_open(a["id"])
     t0 = time.perf_counter()
     while todo and time.perf_counter() - t0 < limit_s:
         for a in list(todo):
@@ -322,20 +337,22 @@ def serving_line(torch, wdd, synth, limit_s=20.0):
                 continue
             nb = int(rng.integers(1, 513))
             nb = min(nb, a["total"] - a["sent"], 256 - a["sent"] % 256)
-            srv.submit(a["id"], pools[a["n"]][a["sent"] % 256:a["sent"] % 256 + nb], a["pos"][a["sent"]:a["sent"] + nb])
-            a["sent"] += nb
-            if a["sent"] >= a["total"]:
+            if nb > 0:
+                srv.submit(a["id"], pools[a["n"]][a["sent"] % 256:a["sent"] % 256 + nb],
+                           a["pos"][a["sent"]:a["sent"] + nb])
+                a["sent"] += nb
+        srv.step()
+        for a in list(todo):  # the last snapshot once the server has pushed all of its frames
+            if a["id"] is not None and a["sent"] >= a["total"] and srv.state(a["id"]) == (True, 0):
                 srv.snapshot(a["id"])
                 srv.close(a["id"])
                 todo.remove(a)
-        srv.step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.destroy()
-    return {"workload": "8 acquisitions, scans 64^2..256^2, detectors 64^2..256^2, all frames available at t=0, "
-                        "deliveries of 1-512 frames, bf16 hi+lo projection, object order, snapshot every >= 1 ms",
-            "frames_per_s": st["frames"] / wall, "frames": st["frames"], "wall_s": wall,
+    return {"frames_per_s": st["frames"] / wall, "frames": st["frames"], "wall_s": wall,
+            "grouped_rounds": st["group_rounds"], "graph_replays": st["graph_replays"],
             "latency_ms": {"p50": st["latency_p50_us"] / 1e3, "p99": st["latency_p99_us"] / 1e3}}
 
 
@@ -368,7 +385,8 @@ def serving(args):
                          radius=n / 4 if n <= 128 else 48.0, rate=float(rng.uniform(1e4, 5e4)),
                          dose=float(rng.uniform(1e3, 1e4)), total=s * s, sent=0, id=None, t_start=None,
                          next_chunk=int(rng.integers(1, 513)), pos=synth.raster_positions(s, s)))
-    srv = wdd.Server(hbm_budget_bytes=args.serving_budget_mb << 20, snapshot_interval_us=1000.0, batch_frames=512)
+    srv = wdd.Server(hbm_budget_bytes=args.serving_budget_mb << 20, snapshot_interval_us=1000.0, batch_frames=512,
+                     launch_mode=args.serving_mode)
     waiting, active, done = list(acqs), [], []
     deferred = 0
     t0 = time.perf_counter()
@@ -396,13 +414,14 @@ def serving(args):
                 srv.submit(a["id"], pool[off:off + nb], a["pos"][a["sent"]:a["sent"] + nb])
                 a["sent"] += nb
                 a["next_chunk"] = int(rng.integers(1, 513))
-            if a["sent"] >= a["total"]:
+        srv.step()
+        for a in list(active):  # the last snapshot once the server has pushed all of its frames
+            if a["sent"] >= a["total"] and srv.state(a["id"]) == (True, 0):
                 srv.snapshot(a["id"])
                 srv.close(a["id"])
                 a["t_end"] = time.perf_counter() - t0
                 active.remove(a)
                 done.append(a)
-        srv.step()
         if time.perf_counter() - last_print > 5.0:
             st = srv.stats()
             print(f"[serving] t={t:.1f}s open={st['open']} done={len(done)} frames={st['frames']} "
@@ -423,10 +442,11 @@ def serving(args):
                                f"64^2..256^2, {'all frames available at t=0' if args.serving_saturate else '10k-50k frames/s each'}, "
                                f"deliveries of 1-512 frames, HBM budget {args.serving_budget_mb} MiB, "
                                f"snapshot every >= 1 ms per acquisition",
-                   "wiener_order": args.serving_order,
+                   "wiener_order": args.serving_order, "launch_mode": args.serving_mode,
                    "acquisitions_done": len(done), "deferred_admissions": deferred,
                    "offered_frames_per_s_sum_of_rates": offered},
         "frames": st["frames"], "wall_s": wall, "batches": st["batches"], "snapshots": st["snapshots"],
+        "grouped_rounds": st["group_rounds"], "graph_replays": st["graph_replays"],
         "latency_ms": {"p50": st["latency_p50_us"] / 1e3, "p99": st["latency_p99_us"] / 1e3,
                        "max": st["latency_max_us"] / 1e3},
     }
@@ -526,9 +546,9 @@ def main():
         "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
                    "wiener_order": args.order, "basis": args.basis,
-                   "display": "hbm" + (", each image's last pass deferred to the next push's projection launch "
-                                       "where the plan allows it (FP32 Hermite-Gauss projection, detector rows "
-                                       "<= 128, power-of-two scan width)" if defer else "")},
+                   "display": "hbm" + (", each image's last pass deferred to the next push's first launch "
+                                       "(its projection for detectors of <= 128 rows, else its first update; "
+                                       "Hermite-Gauss basis, power-of-two scan width)" if defer else "")},
         "host_issue_us_per_step": issue / args.steps * 1e6,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "samples": nlat, "definition": "wdd_push_snapshot call to the image complete in host memory"},

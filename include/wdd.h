@@ -433,43 +433,61 @@ wdd_status wdd_patches_sync(wdd_patches_t s);
 wdd_status wdd_patches_destroy(wdd_patches_t s);
 
 /* ------------------------------------------------------------------------- */
-/* Serving: many concurrent acquisitions on one GPU.
+/* Serving: many concurrent acquisitions on one GPU (the live update of Section 6.3 run
+ * for several acquisitions at once; each keeps its own spectrum, Section 6.1).
  *
  * Each acquisition is a plan (spectrum resident in HBM).  wdd_server_open admits an
  * acquisition if the device memory of all open plans stays within the budget and
- * returns WDD_EBUSY otherwise (the caller retries after another closes).  Frames are
- * submitted as device memory and queued; wdd_server_step takes every queued frame of
- * every acquisition (continuous batching), queues the updates of different
- * acquisitions on their own streams so they overlap on the device, and snapshots the
- * acquisitions whose last snapshot is older than the snapshot interval, fusing the
- * Wiener reduction into the last update where possible.  The time from submit to the
- * snapshot that contains a frame is recorded per frame.  A server is used by one
- * host thread at a time. */
+ * returns WDD_EBUSY otherwise (the caller retries after another closes); the plan itself
+ * (FP64 tables, allocations, upload of W) is then made on a worker thread, and frames
+ * submitted meanwhile wait in the queue.  Frames are submitted as device memory and
+ * queued; wdd_server_step takes every queued frame of every ready acquisition (continuous
+ * batching) and snapshots the acquisitions whose last snapshot is older than the snapshot
+ * interval.  With WDD_SERVE_GROUPED (the default) object-order Hermite-Gauss acquisitions
+ * are pushed together in rounds: one projection launch for up to one batch of each (per
+ * frame type and arithmetic) and one update launch per row pass over all their spectra;
+ * WDD_SERVE_GRAPH captures a round as a HIP graph and replays it with updated arguments.
+ * Other acquisitions, and all of them under WDD_SERVE_STREAMS, are pushed through their
+ * plans on their own streams so that their work overlaps on the device, with the Wiener
+ * reduction fused into the last update where possible.  The time from submit to the
+ * snapshot that contains a frame is recorded per frame.  A server is used by one host
+ * thread at a time. */
 
 typedef struct wdd_server_s* wdd_server_t;
+
+typedef enum { WDD_SERVE_STREAMS = 0, WDD_SERVE_GROUPED = 1, WDD_SERVE_GRAPH = 2 } wdd_serve_mode;
 
 typedef struct {
   int64_t hbm_budget_bytes;     /* admission limit on the plans' device memory; <= 0: none.  Default 1 GiB */
   double snapshot_interval_us;  /* least time between snapshots of one acquisition.  Default 1000 */
   int32_t batch_frames;         /* largest batch pushed at once.  Default 256 */
+  int32_t launch_mode;          /* a wdd_serve_mode.  Default WDD_SERVE_GROUPED */
 } wdd_server_options;
 
 typedef struct {
   uint64_t frames, batches, snapshots, steps;
-  int32_t open;                 /* acquisitions open */
+  int32_t open;                 /* acquisitions open (including those still being made) */
   int64_t device_bytes;         /* device memory of the open plans */
   int64_t pending_frames;       /* submitted, not yet pushed */
   int64_t latency_samples;      /* frames that reached a snapshot */
   double latency_p50_us, latency_p99_us, latency_max_us;  /* submit -> snapshot ready */
+  int32_t opening;              /* acquisitions whose plan is still being made */
+  uint64_t group_rounds;        /* grouped rounds queued */
+  uint64_t graph_replays;       /* rounds replayed from the instantiated graph (WDD_SERVE_GRAPH) */
 } wdd_server_stats;
 
 wdd_status wdd_server_default_options(wdd_server_options* opts);
 wdd_status wdd_server_create(const wdd_server_options* opts, wdd_server_t* out);
 
-/* Opens an acquisition (arguments as wdd_plan; max_batch is raised to the
- * server's batch_frames).  WDD_EBUSY when it does not fit the budget now. */
+/* Opens an acquisition (arguments as wdd_plan; max_batch is raised to the server's
+ * batch_frames).  Argument errors and WDD_EBUSY (it does not fit the budget now) are
+ * returned here; the plan is made on a worker thread, and an error there is returned by
+ * the acquisition's next wdd_server_submit or wdd_server_snapshot. */
 wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
                            int32_t K, const wdd_options* opts, int32_t* acq_id);
+
+/* Waits until the acquisition's plan has been made; returns the error of a failed opening. */
+wdd_status wdd_server_wait_open(wdd_server_t s, int32_t acq);
 
 /* Queues n device-resident frames (contiguous, 16-byte aligned; they must stay valid
  * until a later wdd_server_step or wdd_server_snapshot has pushed them) with host
@@ -483,11 +501,16 @@ wdd_status wdd_server_step(wdd_server_t s, int32_t* frames_processed);
  * memory `out` (sy x sx complex, interleaved float).  Blocking. */
 wdd_status wdd_server_snapshot(wdd_server_t s, int32_t acq, float* out, uint64_t* frames_seen);
 
+/* Whether the acquisition's plan is ready (made) and how many submitted frames wait to be
+ * pushed (either pointer may be NULL). */
+wdd_status wdd_server_acq_state(wdd_server_t s, int32_t acq, int32_t* ready, int64_t* pending_frames);
+
 /* Scan size of an open acquisition. */
 wdd_status wdd_server_acq_shape(wdd_server_t s, int32_t acq, int32_t* sy, int32_t* sx);
 
-/* Closes an acquisition and returns its device memory to the budget (queued frames
- * that were not pushed are dropped). */
+/* Closes an acquisition (queued frames that were not pushed are dropped).  Its plan is
+ * freed on a worker thread; the memory returns to the budget when that is done, and an
+ * open that would not fit otherwise waits for it. */
 wdd_status wdd_server_close(wdd_server_t s, int32_t acq);
 
 wdd_status wdd_server_get_stats(wdd_server_t s, wdd_server_stats* out);

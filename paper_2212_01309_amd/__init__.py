@@ -25,6 +25,8 @@ PRECISIONS = {"fp32": WDD_FP32, "bf16_hilo": WDD_BF16_HILO, "fp16_hilo": WDD_FP1
 WDD_ORDER_SPECTRUM, WDD_ORDER_OBJECT = 0, 1
 WDD_BASIS_HERMITE_GAUSS, WDD_BASIS_FOURIER = 0, 1
 WDD_OUT_HOST, WDD_OUT_DEVICE, WDD_OUT_DEVICE_ASYNC, WDD_OUT_DEVICE_DEFERRED = 0, 1, 2, 3
+WDD_SERVE_STREAMS, WDD_SERVE_GROUPED, WDD_SERVE_GRAPH = 0, 1, 2
+SERVE_MODES = {"streams": WDD_SERVE_STREAMS, "grouped": WDD_SERVE_GROUPED, "graph": WDD_SERVE_GRAPH}
 WDD_MAX_PUSHES_IN_FLIGHT = 64
 STAGE_PROJECT, STAGE_ACCUMULATE, STAGE_WIENER, STAGE_DISPLAY, STAGE_ROWDFT, STAGE_ALL = 1, 2, 4, 8, 16, 31
 
@@ -83,7 +85,7 @@ class PatchGeometry(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("snapshot_interval_us", ctypes.c_double),
-                ("batch_frames", ctypes.c_int32)]
+                ("batch_frames", ctypes.c_int32), ("launch_mode", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -91,7 +93,8 @@ class ServerStats(ctypes.Structure):
                 ("steps", ctypes.c_uint64), ("open", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("pending_frames", ctypes.c_int64), ("latency_samples", ctypes.c_int64),
                 ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
-                ("latency_max_us", ctypes.c_double)]
+                ("latency_max_us", ctypes.c_double), ("opening", ctypes.c_int32),
+                ("group_rounds", ctypes.c_uint64), ("graph_replays", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -145,11 +148,14 @@ _SIGNATURES = {
     "wdd_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
     "wdd_server_open": (ctypes.c_int, [_P, ctypes.POINTER(Probe), ctypes.POINTER(Scan), ctypes.POINTER(Detector),
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32)]),
+    "wdd_server_wait_open": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wdd_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "wdd_server_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "wdd_server_snapshot": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_uint64)]),
     "wdd_server_acq_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
+    "wdd_server_acq_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int64)]),
     "wdd_server_close": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wdd_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
     "wdd_server_destroy": (ctypes.c_int, [_P]),
@@ -612,11 +618,16 @@ class Patches:
 class Server:
     """Many concurrent acquisitions with continuous batching (wdd_server_*)."""
 
-    def __init__(self, hbm_budget_bytes: int = 1 << 30, snapshot_interval_us: float = 1000.0, batch_frames: int = 256):
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, snapshot_interval_us: float = 1000.0, batch_frames: int = 256,
+                 launch_mode=None):
+        """launch_mode: a WDD_SERVE_* value or "streams" / "grouped" / "graph" (None: the
+        library's default)."""
         lib = load_library()
         o = ServerOptions()
         _check(lib.wdd_server_default_options(ctypes.byref(o)))
         o.hbm_budget_bytes, o.snapshot_interval_us, o.batch_frames = hbm_budget_bytes, snapshot_interval_us, batch_frames
+        if launch_mode is not None:
+            o.launch_mode = SERVE_MODES[launch_mode] if isinstance(launch_mode, str) else launch_mode
         self._h = _P()
         _check(lib.wdd_server_create(ctypes.byref(o), ctypes.byref(self._h)))
         self._keep = {}
@@ -638,6 +649,16 @@ class Server:
         _check(code)
         self._keep[aid.value] = []
         return aid.value
+
+    def state(self, acq: int) -> Tuple[bool, int]:
+        """(plan ready, submitted frames not yet pushed)."""
+        r, n = ctypes.c_int32(), ctypes.c_int64()
+        _check(load_library().wdd_server_acq_state(self._h, acq, ctypes.byref(r), ctypes.byref(n)))
+        return bool(r.value), n.value
+
+    def wait_open(self, acq: int) -> None:
+        """Waits until the acquisition's plan (made on a worker thread) is ready."""
+        _check(load_library().wdd_server_wait_open(self._h, acq))
 
     def submit(self, acq: int, frames, positions) -> None:
         """frames: contiguous torch GPU tensor [n, ny, nx]; kept referenced until pushed."""

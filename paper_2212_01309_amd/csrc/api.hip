@@ -139,8 +139,7 @@ void release(wdd_plan_s* p) {
     else
       (void)hipFree(a);
   }
-  for (char* b : p->pin_up)
-    if (b) (void)hipHostFree(b);
+  if (p->pin_ring) (void)hipHostFree(p->pin_ring);
   for (hipEvent_t e : p->marks)
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < kFrameSlots; ++i) {
@@ -422,8 +421,11 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     const size_t slot_bytes = p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t);
     p->up_ring = (int)std::max<size_t>(4, std::min<size_t>(kUploadSlots, kUploadPinBudget / slot_bytes));
     p->mark_every = std::max(1, p->up_ring / 4);
+    // one pinned allocation for the whole ring (pinned allocations and frees are slow)
+    const size_t stride = (slot_bytes + 255) / 256 * 256;
+    WDD_HIP(p, hipHostMalloc((void**)&p->pin_ring, stride * p->up_ring, hipHostMallocDefault));
     p->pin_up.assign(p->up_ring, nullptr);
-    for (char*& b : p->pin_up) WDD_HIP(p, hipHostMalloc((void**)&b, slot_bytes, hipHostMallocDefault));
+    for (int i = 0; i < p->up_ring; ++i) p->pin_up[i] = p->pin_ring + stride * i;
     p->marks.assign(p->up_ring / p->mark_every + 2, nullptr);
     p->mark_at.assign(p->marks.size(), -1);
     for (hipEvent_t& e : p->marks) WDD_HIP(p, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -477,6 +479,13 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
     b += a(t.n_freq() * 8) + a(nchunks_max * 16);
   }
   if (opts.order == WDD_ORDER_OBJECT) b += a(nfp * 8);  // D's rounding remainder
+  const bool pow2 = (t.sy & (t.sy - 1)) == 0 && (t.sx & (t.sx - 1)) == 0;
+  if (opts.order == WDD_ORDER_OBJECT && !fourier && pow2 && t.sy <= wdd::kDisplayRowMax) {
+    // partial display rows (at most kMaxSlots per v_x), a second set and D[0] copies for
+    // detectors of more than 128 rows
+    const int64_t up = a(grid * wdd::kMaxSlots * 8);
+    b += t.ny > 128 ? 2 * up + a(16) : up;
+  }
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
 }
@@ -873,6 +882,19 @@ wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx) {
   if (!p || !sy || !sx) return wdd::fail(WDD_EINVAL, "null argument");
   *sy = p->sy;
   *sx = p->sx;
+  return WDD_OK;
+}
+
+wdd_status plan_set_stream(wdd_plan_t p, void* stream) {
+  wdd_status st = check_usable(p);
+  if (st != WDD_OK) return st;
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
+  WDD_HIP(p, hipStreamSynchronize(p->stream));
+  p->drained = p->pushes - 1;
+  WDD_HIP(p, harvest(p));
+  if (p->own_stream && p->stream) WDD_HIP(p, hipStreamDestroy(p->stream));
+  p->stream = static_cast<hipStream_t>(stream);
+  p->own_stream = false;
   return WDD_OK;
 }
 

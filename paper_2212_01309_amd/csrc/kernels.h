@@ -35,6 +35,17 @@ struct ProjectLaunch {
 };
 hipError_t launch_project(const ProjectLaunch& pl, hipStream_t st);
 
+// The projections of `count` (1..16) batches of different plans in one launch, all of one
+// frame type and arithmetic and without upload blocks (up_src null); members with n = 0 are
+// allowed.  Its last workgroups copy xbytes (a multiple of 4) from pinned host memory xsrc
+// to device memory xdst.
+constexpr int kProjectGroupMax = 16;
+hipError_t launch_project_group(const ProjectLaunch* pls, int count, const void* xsrc, void* xdst, size_t xbytes,
+                                hipStream_t st);
+// Sets the launch attributes of the grouped kernels (done by their first launch otherwise;
+// call it before capturing such launches into a graph).
+hipError_t prepare_group_kernels();
+
 // The column pass of a display from partial rows (launch_dft_rows with nslot partials and
 // the final scale): `rows` output rows of power-of-two length len.
 struct DisplayColumns {

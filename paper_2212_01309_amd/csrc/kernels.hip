@@ -34,10 +34,10 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 
 // Opts a kernel into the whole LDS once: a function-local static per kernel, whose
 // initialisation C++ makes thread-safe (plans on several host threads may launch at once).
-template <typename K>
-hipError_t allow_full_lds(K* kernel) {
+template <auto Kernel>
+hipError_t allow_full_lds() {
   static const hipError_t e =
-      hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+      hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kLdsBytes);
   return e;
 }
@@ -726,6 +726,38 @@ __global__ __launch_bounds__(1024) void k_project(ProjArgs a) {
     return;
   }
   project_any<T, PREC>(a, reinterpret_cast<float*>(psm), (int)blockIdx.x);
+}
+
+// The projections of several plans' batches in one launch (plans of one frame type and
+// arithmetic): member m projects launch workgroups [first[m], first[m + 1]) as its frames
+// 0, 1, ...  Workgroups past the frames bring a block of xwords words from pinned host
+// memory to the device, kGroupUploadWords words each (the descriptors of the updates that
+// follow).  Passed by value: the member table is read with scalar loads.
+constexpr int kProjGroupMax = 16;
+constexpr int kGroupUploadWords = 8192;
+struct ProjGroupArgs {
+  ProjArgs a[kProjGroupMax];
+  int first[kProjGroupMax + 1];
+  int members;
+  const uint32_t* xsrc;
+  uint32_t* xdst;
+  int xwords;
+};
+static_assert(sizeof(ProjGroupArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
+template <typename T, int PREC>
+__global__ __launch_bounds__(1024) void k_project_group(ProjGroupArgs g) {
+  extern __shared__ float4 gsm[];
+  const int b = (int)blockIdx.x, total = g.first[g.members];
+  if (b >= total) {
+    const int w0 = (b - total) * kGroupUploadWords;
+    upload_block(g.xsrc + w0, g.xdst + w0, min(kGroupUploadWords, g.xwords - w0), (int)threadIdx.x,
+                 (int)blockDim.x);
+    return;
+  }
+  int m = 0;
+  while (m + 1 < g.members && b >= g.first[m + 1]) ++m;
+  project_any<T, PREC>(g.a[m], reinterpret_cast<float*>(gsm), b - g.first[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1709,7 +1741,7 @@ hipError_t launch_acc_t(float2* acc, int kpad, int64_t n_freq_pad, const int2* f
                         const int2* pos, int n, const float2* ty, int sy, const float2* tx, int sx, hipStream_t st) {
   const size_t lds = (size_t)(sy + sx) * sizeof(float2) + 32 * sizeof(int2) + 32 * NCB * 32 * sizeof(float);
   {
-    const hipError_t e = allow_full_lds(k_accumulate<NCB>);
+    const hipError_t e = allow_full_lds<k_accumulate<NCB>>();
     if (e != hipSuccess) return e;
   }
   dim3 grid((unsigned)(n_freq_pad / 64), (unsigned)(kpad / (NCB * 32)));
@@ -1757,7 +1789,7 @@ hipError_t launch_project_tp(const ProjectLaunch& pl, const DisplayColumns* dc, 
   if (!dc) {
     const size_t lds = project_lds(pl, nw_proj);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
-    hipError_t e = allow_full_lds(k_project<T, PREC>);
+    hipError_t e = allow_full_lds<k_project<T, PREC>>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_project<T, PREC>), dim3(pl.n + up), dim3(64 * nw_proj), lds, st, a);
     return hipGetLastError();
@@ -1768,7 +1800,7 @@ hipError_t launch_project_tp(const ProjectLaunch& pl, const DisplayColumns* dc, 
   const int threads = std::max(64 * nw_proj, 256);
   const size_t lds = std::max(project_lds(pl, threads / 64), (size_t)dc->len * sizeof(float2) * 3 / 2);
   if (lds > kLdsBytes) return hipErrorInvalidValue;
-  hipError_t e = allow_full_lds(k_project_display<T, PREC>);
+  hipError_t e = allow_full_lds<k_project_display<T, PREC>>();
   if (e != hipSuccess) return e;
   DispArgs d;
   d.din = dc->din;
@@ -1785,6 +1817,32 @@ hipError_t launch_project_tp(const ProjectLaunch& pl, const DisplayColumns* dc, 
   d.nslot = dc->nslot;
   d.slot_stride = dc->slot_stride;
   hipLaunchKernelGGL((k_project_display<T, PREC>), dim3(pl.n + up + dc->rows), dim3(threads), lds, st, a, d);
+  return hipGetLastError();
+}
+
+template <typename T, int PREC>
+hipError_t launch_project_group_tp(const ProjectLaunch* pls, int count, const void* xsrc, void* xdst, size_t xbytes,
+                                   hipStream_t st) {
+  ProjGroupArgs g;
+  std::memset(&g, 0, sizeof(g));
+  int nw = 1;
+  for (int m = 0; m < count; ++m) nw = std::max(nw, std::min((pls[m].ny + 15) / 16, 16));
+  size_t lds = 0;
+  g.first[0] = 0;
+  for (int m = 0; m < count; ++m) {
+    g.a[m] = proj_args(pls[m]);
+    g.first[m + 1] = g.first[m] + pls[m].n;
+    lds = std::max(lds, project_lds(pls[m], nw));
+  }
+  g.members = count;
+  g.xsrc = static_cast<const uint32_t*>(xsrc);
+  g.xdst = static_cast<uint32_t*>(xdst);
+  g.xwords = (int)(xbytes / 4);
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  const hipError_t e = allow_full_lds<k_project_group<T, PREC>>();
+  if (e != hipSuccess) return e;
+  const int xgroups = (g.xwords + kGroupUploadWords - 1) / kGroupUploadWords;
+  hipLaunchKernelGGL((k_project_group<T, PREC>), dim3(g.first[count] + xgroups), dim3(64 * nw), lds, st, g);
   return hipGetLastError();
 }
 
@@ -1805,6 +1863,41 @@ hipError_t launch_project_any(const ProjectLaunch& pl, const DisplayColumns* dc,
 }
 
 }  // namespace
+
+hipError_t prepare_group_kernels() {
+  const hipError_t es[] = {allow_full_lds<k_project_group<float, WDD_FP32>>(),
+                           allow_full_lds<k_project_group<uint16_t, WDD_FP32>>(),
+                           allow_full_lds<k_project_group<uint16_t, WDD_BF16_HILO>>(),
+                           allow_full_lds<k_project_group<uint16_t, WDD_FP16_HILO>>(),
+                           allow_full_lds<k_project_group<uint16_t, WDD_BF16>>(),
+                           allow_full_lds<k_project_group<uint16_t, WDD_FP16>>(),
+                           allow_full_lds<k_row_fused_obj_group>()};
+  for (hipError_t e : es)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_project_group(const ProjectLaunch* pls, int count, const void* xsrc, void* xdst, size_t xbytes,
+                                hipStream_t st) {
+  if (count < 1 || count > kProjGroupMax || xbytes % 4 != 0 || (xbytes && (!xsrc || !xdst)) ||
+      xbytes / 4 > (size_t)INT32_MAX)
+    return hipErrorInvalidValue;
+  for (int m = 0; m < count; ++m)
+    if (pls[m].dtype != pls[0].dtype || pls[m].precision != pls[0].precision || pls[m].n < 0 || pls[m].up_src)
+      return hipErrorInvalidValue;
+  if (pls[0].dtype == WDD_F32) {
+    if (pls[0].precision != WDD_FP32) return hipErrorInvalidValue;
+    return launch_project_group_tp<float, WDD_FP32>(pls, count, xsrc, xdst, xbytes, st);
+  }
+  switch (pls[0].precision) {
+    case WDD_FP32: return launch_project_group_tp<uint16_t, WDD_FP32>(pls, count, xsrc, xdst, xbytes, st);
+    case WDD_BF16_HILO: return launch_project_group_tp<uint16_t, WDD_BF16_HILO>(pls, count, xsrc, xdst, xbytes, st);
+    case WDD_FP16_HILO: return launch_project_group_tp<uint16_t, WDD_FP16_HILO>(pls, count, xsrc, xdst, xbytes, st);
+    case WDD_BF16: return launch_project_group_tp<uint16_t, WDD_BF16>(pls, count, xsrc, xdst, xbytes, st);
+    case WDD_FP16: return launch_project_group_tp<uint16_t, WDD_FP16>(pls, count, xsrc, xdst, xbytes, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_project(const ProjectLaunch& pl, hipStream_t st) { return launch_project_any(pl, nullptr, st); }
 
@@ -1923,7 +2016,7 @@ hipError_t launch_row_dft(const float* h, int kpad, const int* xs, const int* or
                           const float2* tx, int sx, float2* t, hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
   {
-    const hipError_t e = allow_full_lds(k_row_dft);
+    const hipError_t e = allow_full_lds<k_row_dft>();
     if (e != hipSuccess) return e;
   }
   const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
@@ -1989,7 +2082,7 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
     lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
   }
   if (lds > kLdsBytes) return hipErrorInvalidValue;
-  const hipError_t e = allow_full_lds(k_row_fused_obj);
+  const hipError_t e = allow_full_lds<k_row_fused_obj>();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks + rows_disp), dim3(kFusedThreads), lds, st, h, kpad, order, xs,
                      rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
@@ -2001,7 +2094,7 @@ hipError_t launch_row_fused_obj_group(const ObjPass* passes, const int4* items, 
                                       hipStream_t st) {
   if (nitems < 1) return hipSuccess;
   if (lds_bytes > kLdsBytes) return hipErrorInvalidValue;
-  const hipError_t e = allow_full_lds(k_row_fused_obj_group);
+  const hipError_t e = allow_full_lds<k_row_fused_obj_group>();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_fused_obj_group, dim3((unsigned)nitems), dim3(kFusedThreads), lds_bytes, st, passes, items);
   return hipGetLastError();

@@ -88,7 +88,8 @@ struct wdd_plan_impl {
   float2* dlo = nullptr;  // object order: the rounding remainder of D (D = d + dlo, compensated sum)
 
   int up_ring = 4, mark_every = 1;   // upload blocks in the ring; marker spacing in pushes
-  std::vector<char*> pin_up;         // [up_ring]
+  char* pin_ring = nullptr;          // the ring's pinned memory
+  std::vector<char*> pin_up;         // [up_ring] blocks in pin_ring
   std::vector<hipEvent_t> marks;     // [up_ring / mark_every + 2]
   std::vector<int64_t> mark_at;      // the push each marker follows (-1: none yet)
   int64_t pushes = 0;                // pushes that carried frames

@@ -170,7 +170,7 @@ wdd_status fail(wdd_status code, const char* fmt, ...) {
 }
 
 wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
-                        int32_t K, const wdd_options* opts_in, wdd_tables_s* t) {
+                        int32_t K, const wdd_options* opts_in, wdd_tables_s* t, bool kept_only) {
   if (!probe || !scan || !det || !t) return fail(WDD_EINVAL, "null argument");
   wdd_options opts;
   wdd_default_options(&opts);
@@ -235,6 +235,7 @@ wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_
     if (t->freqs.empty())
       return fail(WDD_EINVAL, "the aperture (radius %g at (%g, %g)) covers no pixel of the %d x %d detector", radius,
                   t->cy, t->cx, t->ny, t->nx);
+    if (kept_only) return WDD_OK;
 
     if (fourier) {
       fourier_wigner(t, geo);

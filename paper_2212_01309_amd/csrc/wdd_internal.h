@@ -27,9 +27,10 @@ namespace wdd {
 // Thread-local error message handling.
 wdd_status fail(wdd_status code, const char* fmt, ...);
 
-// Host FP64 table construction (validated arguments).
+// Host FP64 table construction (validated arguments).  kept_only: stop after the kept
+// frequencies (no basis, no W: enough for plan_device_bytes, in a small part of the time).
 wdd_status build_tables(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,
-                        int32_t K, const wdd_options* opts, wdd_tables_s* t);
+                        int32_t K, const wdd_options* opts, wdd_tables_s* t, bool kept_only = false);
 
 // Plan operations used by the serving runtime (api.hip).
 wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts);
@@ -47,6 +48,9 @@ wdd_status push_table(wdd_plan_t p, const uint64_t* frame_addrs, const int32_t* 
 wdd_status snapshot_enqueue(wdd_plan_t p, bool reduce);
 wdd_status snapshot_finish(wdd_plan_t p, uint64_t* frames_seen);
 wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx);
+// Waits for the plan's work, then moves it to `stream` (the plan's own stream, if it had
+// one, is destroyed).
+wdd_status plan_set_stream(wdd_plan_t p, void* stream);
 
 // The display of a spectrum grid (wdd_display): argument checks, the scratch it needs (in
 // floats: two sy x sx complex grids and the twiddles of both sides) and the launches, all

@@ -2,7 +2,9 @@
 acquisitions of different geometries, and results that are the same alone and in the mix
 within the FP32 bar (relative L2 <= 1e-5 on the image and on the image minus its mean;
 batch boundaries differ, so the accumulation's rounding differs and results are not
-bitwise equal)."""
+bitwise equal), under each launch mode: per-acquisition streams, grouped rounds (one
+projection and one update launch per row pass for all object-order acquisitions) and
+grouped rounds replayed from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -50,18 +52,21 @@ def test_admission_by_memory_budget():
 ORACLE_BOUND = {"fp32": 1e-5, "bf16_hilo": 3e-5}
 
 
+@pytest.mark.parametrize("mode", ["streams", "grouped", "graph"])
 @pytest.mark.parametrize("order,precision", [(wdd.WDD_ORDER_SPECTRUM, "fp32"), (wdd.WDD_ORDER_OBJECT, "fp32"),
                                              (wdd.WDD_ORDER_OBJECT, "bf16_hilo"),
                                              (wdd.WDD_ORDER_SPECTRUM, "bf16_hilo")])
-def test_each_result_is_the_same_alone_and_in_the_mix(order, precision):
+def test_each_result_is_the_same_alone_and_in_the_mix(order, precision, mode):
     """The serving mix pushes frames through a per-frame address table (frames from many
     submitted buffers in one batch); with a reduced-precision projection that is the
-    bf16 kernel's address-table path.  Alone and in the mix the projections of a frame are
-    identical; only the accumulation's batch boundaries differ."""
+    bf16 kernel's address-table path, and in object order under the grouped modes the
+    grouped projection over all acquisitions (random submissions over up to 48 scan rows
+    give rounds of several row passes).  Alone and in the mix the projections of a frame
+    agree; only the accumulation's batch boundaries differ."""
     rng = np.random.default_rng(9)
     data = [_acquisition(i, *g) for i, g in enumerate(GEOMS)]
     devs = [device(f) for f, _ in data]
-    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=200.0, batch_frames=256) as srv:
+    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=200.0, batch_frames=256, launch_mode=mode) as srv:
         ids = [srv.open(r, s, s, n, n, k, order=order, precision=precision) for (r, s, n, k) in GEOMS]
         cursor = [0] * len(GEOMS)
         while any(c < len(d[1]) for c, d in zip(cursor, data)):
@@ -77,10 +82,13 @@ def test_each_result_is_the_same_alone_and_in_the_mix(order, precision):
         mixed = [srv.snapshot(a) for a in ids]
         st = srv.stats()
     total = sum(len(p) for _, p in data)
-    assert st["frames"] == total and st["latency_samples"] == total
+    assert st["frames"] == total and st["latency_samples"] == total and st["opening"] == 0
     assert 0 < st["latency_p50_us"] <= st["latency_p99_us"] <= st["latency_max_us"]
-    say(f"[serving] mix of {len(GEOMS)} acquisitions, {total} frames, {st['batches']} batches, "
-        f"{st['snapshots']} snapshots, latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
+    grouped = mode != "streams" and order == wdd.WDD_ORDER_OBJECT
+    assert (st["group_rounds"] > 0) == grouped
+    say(f"[serving] {mode}: mix of {len(GEOMS)} acquisitions, {total} frames, {st['batches']} batches, "
+        f"{st['group_rounds']} grouped rounds ({st['graph_replays']} graph replays), {st['snapshots']} snapshots, "
+        f"latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
     for i, (r, s, n, k) in enumerate(GEOMS):
         frames, pos = data[i]
         with wdd.Plan(r, s, s, n, n, k, max_batch=256, order=order, precision=precision) as plan:
@@ -88,7 +96,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(order, precision):
                 plan.push(devs[i][b:b + 256], pos[b:b + 256])
             alone = plan.snapshot()
         e = rel_img(mixed[i], alone)
-        say(f"[serving] order {order}, {precision}, acquisition {i}: mix vs alone {e:.2e}")
+        say(f"[serving] {mode}, order {order}, {precision}, acquisition {i}: mix vs alone {e:.2e}")
         assert e <= 1e-5
     r, s, n, k = GEOMS[0]
     live = O.Live(O.make_plan(s, s, n, n, r, k), "N")
@@ -137,3 +145,72 @@ def test_submit_rejects_positions_off_the_raster():
             srv.submit(a, fr, np.array([[0, 0], [1, 1], [16, 2], [3, 3]], np.int32))
         assert ei.value.code == wdd.WDD_ERANGE
         assert srv.stats()["pending_frames"] == 0
+
+
+@pytest.mark.parametrize("mode", ["grouped", "graph"])
+def test_grouped_rounds_over_mixed_acquisitions(mode):
+    """One server holding object-order acquisitions of two frame types and two arithmetics
+    (several grouped projection launches per round), a 160-row detector (one wave per 16
+    rows in the projection, partial display rows double-buffered), a spectrum-order one
+    (pushed through its plan beside the rounds) and a steady phase of equal rounds (the
+    graph is then replayed with updated arguments); each result against its own plan."""
+    import torch
+    cases = [  # (radius, scan, detector, K, dtype, precision, order)
+        (8.0, 32, 32, 64, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_OBJECT),
+        (8.0, 32, 32, 64, wdd.WDD_F32, "fp32", wdd.WDD_ORDER_OBJECT),
+        (6.0, 32, 32, 36, wdd.WDD_U16, "bf16_hilo", wdd.WDD_ORDER_OBJECT),
+        (20.0, 32, 160, 100, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_OBJECT),
+        (8.0, 32, 32, 64, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_SPECTRUM),
+    ]
+    rng = np.random.default_rng(77)
+    data = []
+    for r, s, n, k, dt, prec, order in cases:
+        pos = np.stack([np.repeat(np.arange(s), s), np.tile(np.arange(s), s)], axis=1).astype(np.int32)
+        fr = rng.poisson(20.0, size=(s * s, n, n))
+        fr = fr.astype(np.uint16) if dt == wdd.WDD_U16 else fr.astype(np.float32)
+        data.append((device(fr), pos))
+    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=0.0, batch_frames=64, launch_mode=mode) as srv:
+        ids = [srv.open(r, s, s, n, n, k, dtype=dt, precision=prec, order=order)
+               for r, s, n, k, dt, prec, order in cases]
+        for a in ids:
+            srv.wait_open(a)
+        for b in range(0, 32 * 32, 64):   # 16 equal rounds of 64 raster frames (two scan rows) each
+            for a, (dev, pos) in zip(ids, data):
+                srv.submit(a, dev[b:b + 64], pos[b:b + 64])
+            srv.step()
+        mixed = [srv.snapshot(a) for a in ids]
+        st = srv.stats()
+    say(f"[serving] {mode}, mixed classes: {st['group_rounds']} rounds, {st['graph_replays']} graph replays")
+    assert st["group_rounds"] == 16
+    if mode == "graph":
+        assert st["graph_replays"] >= 14
+    for (r, s, n, k, dt, prec, order), (dev, pos), got in zip(cases, data, mixed):
+        with wdd.Plan(r, s, s, n, n, k, dtype=dt, precision=prec, order=order, max_batch=64) as plan:
+            for b in range(0, len(pos), 64):
+                plan.push(dev[b:b + 64], pos[b:b + 64])
+            alone = plan.snapshot()
+        e = rel_img(got, alone)
+        say(f"[serving] {mode}, n={n} dtype={dt} {prec} order={order}: mix vs alone {e:.2e}")
+        assert e <= 1e-5
+
+
+def test_open_does_not_wait_for_the_tables():
+    """wdd_server_open returns once the acquisition is admitted; the plan is made on a worker
+    thread, frames submitted meanwhile wait, and a snapshot waits for the plan."""
+    r, s, n, k = 16.0, 64, 64, 128
+    rng = np.random.default_rng(3)
+    pos = np.stack([np.repeat(np.arange(s), s), np.tile(np.arange(s), s)], axis=1).astype(np.int32)[:512]
+    dev = device(rng.poisson(10.0, size=(512, n, n)).astype(np.uint16))
+    with wdd.Server(hbm_budget_bytes=0, snapshot_interval_us=1e9, batch_frames=256) as srv:
+        a = srv.open(r, s, s, n, n, k, order=wdd.WDD_ORDER_OBJECT)
+        st = srv.stats()
+        assert st["open"] == 1 and st["opening"] in (0, 1)
+        srv.submit(a, dev, pos)
+        srv.step()
+        got = srv.snapshot(a)
+        assert srv.stats()["opening"] == 0 and srv.stats()["frames"] == 512
+    with wdd.Plan(r, s, s, n, n, k, order=wdd.WDD_ORDER_OBJECT, max_batch=256) as plan:
+        plan.push(dev[:256], pos[:256])
+        plan.push(dev[256:], pos[256:])
+        alone = plan.snapshot()
+    assert rel_img(got, alone) <= 1e-5

@@ -129,7 +129,8 @@ def test_binding_constants_match_the_header():
     assert int(re.search(r"#define WDD_MAX_PUSHES_IN_FLIGHT (\d+)", text).group(1)) == wdd.WDD_MAX_PUSHES_IN_FLIGHT
     for name in ("WDD_OUT_HOST", "WDD_OUT_DEVICE", "WDD_OUT_DEVICE_ASYNC", "WDD_OUT_DEVICE_DEFERRED", "WDD_ORDER_SPECTRUM",
                  "WDD_ORDER_OBJECT",
-                 "WDD_BASIS_HERMITE_GAUSS", "WDD_BASIS_FOURIER"):
+                 "WDD_BASIS_HERMITE_GAUSS", "WDD_BASIS_FOURIER", "WDD_SERVE_STREAMS", "WDD_SERVE_GROUPED",
+                 "WDD_SERVE_GRAPH"):
         assert int(re.search(name + r" = (\d+)", text).group(1)) == getattr(wdd, name), name
 
 
