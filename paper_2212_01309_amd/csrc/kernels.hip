@@ -201,11 +201,11 @@ __host__ __device__ inline size_t project_lds_floats(int ny, int nx, int nw, int
 
 // Straight-line form of project_frame for a frame whose tiles each have a wave of their own
 // (ntiles <= waves), NCH chunks of 32 columns per row (nx <= 32 NCH) and tables within the
-// first table_issue block.  Every load is unconditional (indices clamped into the frame and
-// the tables; lanes outside the frame get zero by a select after their load), so the wait
-// before chunk c's MFMAs counts exactly the NCH - 1 - c later loads: the MFMAs of early
-// chunks run while the later chunks are still arriving.  (Loads under a branch make the
-// compiler wait for every load in flight before the first use of any of them.)
+// first table_issue block.  Every frame load is unconditional (indices clamped into the
+// frame; lanes outside the frame get zero by a select after their load), so the wait before
+// chunk c's MFMAs counts exactly the NCH - 1 - c later loads: the MFMAs of early chunks run
+// while the later chunks are still arriving.  (Loads under a branch make the compiler wait
+// for every load in flight before the first use of any of them.)
 template <typename T, int NCH>
 __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames, int ny, int nx,
                                                    const float* __restrict__ psi, const int* __restrict__ kmap,
@@ -227,12 +227,11 @@ __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames,
   const int y = wave * 16 + r16;
   const bool row_ok = wave < ntiles && y < ny;
   const T* rowp = f + (size_t)min(y, ny - 1) * nx;
-  Chunk<T> ch[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
-  // every lane stores (no store under a branch: the compiler would sink the table load into
-  // the branch, behind the frame loads); lanes past a table write to their own slot of the
-  // per-wave G area, which is written again after the MFMAs
+  // The tables reach LDS, and the workgroup synchronises, before any frame load is issued: a
+  // barrier after the frame loads would hold every wave's MFMAs until all waves had issued
+  // all their loads (issue stalls while the memory pipeline is full), so that no MFMA could
+  // overlap the frame's arrival.  Every lane stores (lanes past a table write to their own
+  // slot of the per-wave G area, which is written again after the MFMAs).
   float* spare = lg + tid;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -248,6 +247,9 @@ __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames,
     *dst = tr.k[u];
   }
   __syncthreads();
+  Chunk<T> ch[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
 
   const float* brow = lpsxt + r16 * nxp;
   floatx4 tacc = {0.f, 0.f, 0.f, 0.f}, tacc2 = {0.f, 0.f, 0.f, 0.f};
@@ -295,9 +297,9 @@ __host__ __device__ inline bool project_tile_form(int ny, int nx, int nw, int kp
 }
 
 // One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
-// more tiles than waves).  A wave issues the loads of up to 8 chunks of 32 pixels per row
-// (256 columns) right after the table loads, and runs a chunk's MFMAs as soon as that
-// chunk has arrived.  Frame b of the batch; smem: project_lds_floats(ny, nx, nw, kpad).
+// more tiles than waves).  Once the tables are in LDS, a wave issues the loads of up to 8
+// chunks of 32 pixels per row (256 columns) and runs a chunk's MFMAs as soon as that chunk
+// has arrived.  Frame b of the batch; smem: project_lds_floats(ny, nx, nw, kpad).
 template <typename T>
 __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int ny, int nx,
                                               const float* __restrict__ psi, const int* __restrict__ kmap, int kpad,
@@ -317,15 +319,9 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
   const int ntab = (ny + nx) * 16;
   TableRegs tr;
   table_issue(tr, psi, ntab, kmap, kpad, tid, nt);
-  Chunk<T> ch[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int y = wave * 16 + r16, xs = 32 * c + 8 * q;
-    if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
-    else ch[c].zero();
-  }
   table_finish(tr, psi, ntab, kmap, kpad, lpsy, lpsxt, lkmap, ny, nxp, tid, nt);
-  __syncthreads();
+  __syncthreads();  // before the frame loads (see project_frame_tile)
+  Chunk<T> ch[8];
 
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
   const float* brow = lpsxt + r16 * nxp;
@@ -333,13 +329,11 @@ __device__ __forceinline__ void project_frame(const T* __restrict__ frames, int 
     const int y = t * 16 + r16;
     floatx4 tacc = {0.f, 0.f, 0.f, 0.f};
     for (int xg = 0; xg < nx; xg += 256) {
-      if (t != wave || xg != 0) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int xs = xg + 32 * c + 8 * q;
-          if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
-          else ch[c].zero();
-        }
+      for (int c = 0; c < 8; ++c) {
+        const int xs = xg + 32 * c + 8 * q;
+        if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+        else ch[c].zero();
       }
       const int nch = min(8, (nx - xg + 31) >> 5);  // chunks of 32 columns inside the frame
       // per chunk: its 8 basis values (two 16-byte LDS reads), then 8 MFMAs alternating
@@ -445,7 +439,8 @@ __device__ __forceinline__ void project_frame_lp(const uint16_t* __restrict__ fr
   const uint16_t* f = fptr ? reinterpret_cast<const uint16_t*>(fptr[b]) : frames + (size_t)b * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
-  // table loads first (index clamped, no branch), then the frame's
+  // tables to LDS (loads with clamped indices, no branch) and the barrier before the frame
+  // loads (see project_frame_tile)
   const int nsy = ny * 16, half = nx >> 1, nwords = (HILO ? 2 : 1) * 16 * half;
   const uint32_t* px32 = reinterpret_cast<const uint32_t*>(psix_lp);
   float vy[8];
@@ -458,12 +453,6 @@ __device__ __forceinline__ void project_frame_lp(const uint16_t* __restrict__ fr
 #pragma unroll
   for (int u = 0; u < 4; ++u) vk[u] = gload(kmap + min(u * nt + tid, kpad - 1));
   Chunk<uint16_t> ch[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int y = wave * 16 + r16, xs = 32 * c + 8 * q;
-    if (wave < ntiles && y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
-    else ch[c].zero();
-  }
   uint32_t* lpx32 = reinterpret_cast<uint32_t*>(lpx);
   const int hp = nxp >> 1;
 #pragma unroll
@@ -488,13 +477,11 @@ __device__ __forceinline__ void project_frame_lp(const uint16_t* __restrict__ fr
     const int y = t * 16 + r16;
     floatx4 tlo = {0.f, 0.f, 0.f, 0.f}, thi = {0.f, 0.f, 0.f, 0.f};
     for (int xg = 0; xg < nx; xg += 256) {
-      if (t != wave || xg != 0) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int xs = xg + 32 * c + 8 * q;
-          if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
-          else ch[c].zero();
-        }
+      for (int c = 0; c < 8; ++c) {
+        const int xs = xg + 32 * c + 8 * q;
+        if (y < ny && xs < nx) ch[c].load(f + (size_t)y * nx + xs);
+        else ch[c].zero();
       }
       const int nch = min(8, (nx - xg + 31) >> 5);
 #pragma unroll
@@ -584,9 +571,7 @@ __device__ __forceinline__ void project_frame_lp_tile(const uint16_t* __restrict
   const int y = wave * 16 + r16;
   const bool row_ok = wave < ntiles && y < ny;
   const uint16_t* rowp = f + (size_t)min(y, ny - 1) * nx;
-  Chunk<uint16_t> ch[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
+  // tables to LDS and the barrier before the frame loads (see project_frame_tile)
   uint32_t* lpx32 = reinterpret_cast<uint32_t*>(lpx);
   const int hp = nxp >> 1;
   float* spare = lg + tid;
@@ -605,6 +590,9 @@ __device__ __forceinline__ void project_frame_lp_tile(const uint16_t* __restrict
     *dk = vk[u];
   }
   __syncthreads();
+  Chunk<uint16_t> ch[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) ch[c].load(rowp + min(32 * c + 8 * q, nx - 8));
 
   floatx4 tlo = {0.f, 0.f, 0.f, 0.f}, thi = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
