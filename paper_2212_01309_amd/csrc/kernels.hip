@@ -200,8 +200,8 @@ __host__ __device__ inline size_t project_lds_floats(int ny, int nx, int nw, int
 }
 
 // Straight-line form of project_frame for a frame whose tiles each have a wave of their own
-// (ntiles <= waves), NCH chunks of 32 columns per row (nx <= 32 NCH) and tables within the
-// first table_issue block.  Every frame load is unconditional (indices clamped into the
+// (ntiles <= waves) and NCH chunks of 32 columns per row (nx <= 32 NCH), under the
+// conditions of project_tile_form.  Every frame load is unconditional (indices clamped into the
 // frame; lanes outside the frame get zero by a select after their load), so the wait before
 // chunk c's MFMAs counts exactly the NCH - 1 - c later loads: the MFMAs of early chunks run
 // while the later chunks are still arriving.  (Loads under a branch make the compiler wait
@@ -213,38 +213,38 @@ __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames,
                                                    float* smem, int b) {
   const int nw = blockDim.x >> 6, nt = blockDim.x;
   const int nxp = nx + 4;
-  float* lpsy = smem;
-  float* lpsxt = smem + ny * 16;
-  float* lg = lpsxt + 16 * nxp;
-  int* lkmap = reinterpret_cast<int*>(lg + nw * 256);
+  float* lpsxt = smem;                   // [16][nxp]: psi_x transposed
+  float* lg = lpsxt + 16 * nxp;          // [nw][256]: per-wave G
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T* f = fptr ? reinterpret_cast<const T*>(fptr[b]) : frames + (size_t)b * ny * nx;
   const int r16 = lane & 15, q = lane >> 4;
   const int ntiles = (ny + 15) >> 4;
-  const int ntab = (ny + nx) * 16;
-  TableRegs tr;
-  table_issue(tr, psi, ntab, kmap, kpad, tid, nt);
+  const int nsx = 16 * nx;
+  // Only psi_x goes through LDS (every wave reads all of it).  The 4 psi_y values of a lane's
+  // stage-2 rows and the kmap entries of its epilogue are loaded into registers here.
+  float vx[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vx[u] = gload(psi + (size_t)ny * 16 + min(u * nt + tid, nsx - 1));
+  float av[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) av[r] = gload(psi + (size_t)min(wave * 16 + 4 * q + r, ny - 1) * 16 + r16);
+  int km[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) km[u] = gload(kmap + min(u * nt + tid, kpad - 1));
   const int y = wave * 16 + r16;
   const bool row_ok = wave < ntiles && y < ny;
   const T* rowp = f + (size_t)min(y, ny - 1) * nx;
-  // The tables reach LDS, and the workgroup synchronises, before any frame load is issued: a
+  // The table reaches LDS, and the workgroup synchronises, before any frame load is issued: a
   // barrier after the frame loads would hold every wave's MFMAs until all waves had issued
   // all their loads (issue stalls while the memory pipeline is full), so that no MFMA could
-  // overlap the frame's arrival.  Every lane stores (lanes past a table write to their own
+  // overlap the frame's arrival.  Every lane stores (lanes past the table write to their own
   // slot of the per-wave G area, which is written again after the MFMAs).
   float* spare = lg + tid;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int i = u * nt + tid;
-    const int j = i - ny * 16;
-    float* dst = i >= ntab ? spare : (i < ny * 16 ? lpsy + i : lpsxt + (j & 15) * nxp + (j >> 4));
-    *dst = tr.v[u];
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = u * nt + tid;
-    int* dst = i < kpad ? lkmap + i : reinterpret_cast<int*>(spare);
-    *dst = tr.k[u];
+    float* dst = i < nsx ? lpsxt + (i & 15) * nxp + (i >> 4) : spare;
+    *dst = vx[u];
   }
   __syncthreads();
   Chunk<T> ch[NCH];
@@ -273,27 +273,30 @@ __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames,
   floatx4 g = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int yy = wave * 16 + 4 * q + r;
-    const float av = (yy < ny) ? lpsy[min(yy, ny - 1) * 16 + r16] : 0.f;
-    g = __builtin_amdgcn_mfma_f32_16x16x4f32(av, tacc[r], g, 0, 0, 0);
+    const float a = (wave * 16 + 4 * q + r < ny) ? av[r] : 0.f;
+    g = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tacc[r], g, 0, 0, 0);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
   __syncthreads();
-  for (int k = tid; k < kpad; k += nt) {
-    const int idx = lkmap[k];
-    float sum = 0.f;
-    if (idx >= 0)
-      for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
-    h[(size_t)b * kpad + k] = sum;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = u * nt + tid;
+    if (k < kpad) {
+      const int idx = km[u];
+      float sum = 0.f;
+      if (idx >= 0)
+        for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+      h[(size_t)b * kpad + k] = sum;
+    }
   }
 }
 
-// Whether project_frame_tile applies: one tile per wave, at most 256 columns, tables within
-// the first block of table loads.
+// Whether project_frame_tile applies: one tile per wave, at most 256 columns, psi_x within
+// 8 loads per thread, kmap within 4.
 __host__ __device__ inline bool project_tile_form(int ny, int nx, int nw, int kpad) {
   const int ntiles = (ny + 15) / 16, nt = 64 * nw;
-  return ntiles <= nw && nx <= 256 && (ny + nx) * 16 <= 8 * nt && kpad <= 4 * nt;
+  return ntiles <= nw && nx <= 256 && nx >= 8 && nx * 16 <= 8 * nt && kpad <= 4 * nt;
 }
 
 // One workgroup per frame, one wave per 16-row tile (waves loop when the frame has
