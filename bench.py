@@ -93,47 +93,56 @@ def profile_record(kind, workload, kernel):
     return None
 
 
-def roofline(wl, n_freq, k, order, fourier, precision, event_us):
+def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0.0):
     """Roofline entry of the accumulation kernel (the method's O(S^2 L^2) term and the
     largest kernel of every workload's kernel trace): algorithmic bytes per launch over the
     kernel's average duration from the rocprofv3 kernel trace recorded under profiles/ for
-    this kernel source, with the live HIP-event mean from the untimed stage pass beside it
-    (events include the launch's dispatch latency)."""
+    this kernel source (the launches of the timed steps), with the live HIP-event mean from
+    the untimed stage pass beside it (events include the launch's dispatch latency).
+    display_bytes: the previous image's column pass when it rides in this launch (partial
+    rows read, image written)."""
     if fourier:
         nbytes = (8.0 if order == "object" else 24.0) * n_freq * k
         kernel = "k_update_c<%d>" % (0 if order == "object" else 2)
+        rule = ("8" if order == "object" else "24") + " * n_freq * K"
     elif order == "object":
         # stream W once per row pass (D, the projections and the twiddles are a few hundred kB)
-        nbytes, kernel = 8.0 * n_freq * k, "k_row_fused_obj"
+        nbytes, kernel = 8.0 * n_freq * k + display_bytes, "k_row_fused_obj"
+        rule = "8 * n_freq * K (W read once)" + (" + 8 * Sy * Sx * (slots + 1) (the previous image's column "
+                                                 "pass in the same launch)" if display_bytes else "")
     else:
         # read and write A, read W (the Wiener reduction fused in before a snapshot)
         nbytes, kernel = 24.0 * n_freq * k, "k_row_update<true>"
-    trace = profile_record("kernel_trace", wl.name, kernel)
+        rule = "24 * n_freq * K (A read and written, W read)"
+    trace = profile_record("kernel_trace", wl.name + ("" if order == "object" else "_spectrum"), kernel)
     if trace is not None:
         us, source = float(trace["avg_us"]), f"rocprofv3 kernel trace, {trace['file']}"
     else:
         us, source = event_us, "HIP events (untimed stage pass; no kernel trace recorded for this kernel source)"
     ach = nbytes / (us * 1e-6) / 1e9
-    traffic = profile_record("traffic", wl.name, kernel)
+    traffic = profile_record("traffic", wl.name + ("" if order == "object" else "_spectrum"), kernel)
     return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": float(traffic["bytes_per_launch"]) if traffic else None,
             "avg_us": us, "avg_us_source": source, "hip_event_us": event_us, "algorithmic_bytes": nbytes,
-            "algorithmic_bytes_rule": ("8 * n_freq * K (W read once)" if order == "object"
-                                       else "24 * n_freq * K (A read and written, W read)")}
+            "algorithmic_bytes_rule": rule}
 
 
-def projection_roofline(wl, k):
-    """The projection kernel against HBM: frame bytes + h written per launch, over the
-    kernel-trace average recorded for this source (None without one)."""
-    kernel = "k_project<unsigned short>" if wl.dose else "k_project<float>"
-    trace = profile_record("kernel_trace", wl.name, kernel)
+def projection_roofline(wl, k, order, display_bytes=0.0):
+    """The projection kernel against HBM: frame bytes + h written per launch (+ the previous
+    image's column pass when it rides in the same launch), over the kernel-trace average
+    recorded for this source (None without one)."""
+    kernel = ("k_project_display" if display_bytes else "k_project") + (
+        "<unsignedshort,0>" if wl.dose else "<float,0>")  # as recorded: no spaces
+    trace = profile_record("kernel_trace", wl.name + ("" if order == "object" else "_spectrum"), kernel)
     if trace is None:
         return None
-    nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
+    nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch + display_bytes
     us = float(trace["avg_us"])
     return {"kernel": kernel, "bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": nbytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, "avg_us": us,
-            "algorithmic_bytes": nbytes}
+            "avg_us_source": f"rocprofv3 kernel trace, {trace['file']}", "algorithmic_bytes": nbytes,
+            "algorithmic_bytes_rule": "frames + 4 * K * batch (h)" + (
+                " + 8 * Sy * Sx * (slots + 1) (the previous image's column pass)" if display_bytes else "")}
 
 
 def cpu_model():
@@ -483,6 +492,7 @@ def main():
     defer = args.display == "deferred"
     plan = make_plan(wdd, wl, args.order, args.precision, fourier)
     n_freq, k = plan.n_freq, plan.k
+    plan_info = plan.info()
 
     stages = None
     if not args.no_profile:
@@ -557,8 +567,17 @@ def main():
     }
     if stages is not None:
         out["stages_us_hip_events"] = stages
-        out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"])
-        proj = None if fourier or args.precision != "fp32" else projection_roofline(wl, k)
+        # where the deferred column pass of each image rides (see the plan's can_defer rules)
+        info = plan_info
+        pow2x = (wl.sx & (wl.sx - 1)) == 0
+        slots = info.display_slots if args.order == "object" and info.display_slots else 1
+        disp = 8.0 * wl.sy * wl.sx * (slots + 1)
+        in_update = defer and not fourier and args.order == "object" and wl.n > 128 and info.display_slots > 0
+        in_proj = defer and not fourier and wl.n <= 128 and pow2x
+        out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"],
+                                   disp if in_update else 0.0)
+        proj = (None if fourier or args.precision != "fp32"
+                else projection_roofline(wl, k, args.order, disp if in_proj else 0.0))
         if proj is not None:
             out["roofline_projection"] = proj
     out.update(extras)

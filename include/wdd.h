@@ -128,6 +128,8 @@ typedef struct {
   double eps_abs;        /* absolute Wiener regularisation */
   uint64_t frames_seen;  /* frames pushed since the plan was made or reset */
   int64_t device_bytes;  /* device memory held by the plan */
+  int32_t update_chunks; /* object order: workgroups of a row pass (runs of kept frequencies of one v_x) */
+  int32_t display_slots; /* object order: partial display rows kept per v_x (0: the two-pass display) */
 } wdd_plan_info;
 
 typedef struct wdd_tables_s* wdd_tables_t;

@@ -67,7 +67,7 @@ class Options(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_freq", ctypes.c_int64), ("k", ctypes.c_int32), ("l", ctypes.c_int32),
                 ("sigma_px", ctypes.c_double), ("eps_abs", ctypes.c_double), ("frames_seen", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("update_chunks", ctypes.c_int32), ("display_slots", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

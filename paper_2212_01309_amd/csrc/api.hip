@@ -1034,6 +1034,8 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info) {
   info->eps_abs = p->eps_abs;
   info->frames_seen = p->frames_seen;
   info->device_bytes = p->device_bytes;
+  info->update_chunks = p->nchunks;
+  info->display_slots = p->up ? p->nslot : 0;
   return WDD_OK;
 }
 

@@ -52,7 +52,9 @@ def test_profile_records_are_used_only_for_the_source_they_were_measured_on(tmp_
 def test_roofline_entry_from_algorithmic_bytes(order, kernel, per, tmp_path, monkeypatch):
     source = b"x"
     sha = hashlib.sha256(source).hexdigest()[:16]
-    _tree(tmp_path, source, [f"kernel_trace: workload=medium kernel={kernel} avg_us=10.0 kernels_sha={sha}"])
+    # spectrum-order runs are recorded under "<workload>_spectrum"
+    label = "medium" if order == "object" else "medium_spectrum"
+    _tree(tmp_path, source, [f"kernel_trace: workload={label} kernel={kernel} avg_us=10.0 kernels_sha={sha}"])
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     wl = types.SimpleNamespace(name="medium", batch=128, n=64, dose=1e4, sy=128, sx=128)
     n_freq, k, ev = 12647, 256, 12.5
@@ -65,6 +67,9 @@ def test_roofline_entry_from_algorithmic_bytes(order, kernel, per, tmp_path, mon
     assert r["peak"] == 8000.0
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
     assert r["traffic"] is None
+    if order == "object":  # the previous image's column pass riding in the launch adds its bytes
+        r = bench.roofline(wl, n_freq, k, order, False, "fp32", ev, display_bytes=1e6)
+        assert r["algorithmic_bytes"] == per * n_freq * k + 1e6 and "column pass" in r["algorithmic_bytes_rule"]
     # without a trace record for this source the live HIP-event mean is used, and said so
     (tmp_path / "paper_2212_01309_amd" / "csrc" / "kernels.hip").write_bytes(b"y")
     r = bench.roofline(wl, n_freq, k, order, False, "fp32", ev)
