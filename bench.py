@@ -411,9 +411,15 @@ def serving(args):
                     a["deferred"] = True
                     deferred += 1
                 break                                              # admitted in arrival order once memory frees
-            a["id"], a["t_start"] = aid, t
+            a["id"], a["t_open"] = aid, t
             active.append(waiting.pop(0))
         for a in list(active):
+            if a["t_start"] is None:
+                # the scan starts streaming once the acquisition's plan is made (on the server's
+                # worker thread; the time from open to ready is reported separately)
+                if not srv.state(a["id"])[0]:
+                    continue
+                a["t_start"] = t
             due = a["total"] if args.serving_saturate else min(a["total"], int((t - a["t_start"]) * a["rate"]))
             while a["sent"] < a["total"] and a["sent"] + min(a["next_chunk"], a["total"] - a["sent"]) <= due:
                 nb = min(a["next_chunk"], a["total"] - a["sent"])
@@ -443,6 +449,7 @@ def serving(args):
     st = srv.stats()
     srv.destroy()
     offered = sum(a["rate"] for a in acqs)
+    ready_ms = [1e3 * (a["t_start"] - a["t_open"]) for a in acqs if a.get("t_start") is not None and "t_open" in a]
     out = {
         "metric": "serving mix: aggregate frames/s and frame-to-snapshot latency",
         "value": st["frames"] / wall, "unit": "frames/s", "n_gpus": 1, "higher_is_better": True,
@@ -452,6 +459,10 @@ def serving(args):
                                f"deliveries of 1-512 frames, HBM budget {args.serving_budget_mb} MiB, "
                                f"snapshot every >= 1 ms per acquisition",
                    "wiener_order": args.serving_order, "launch_mode": args.serving_mode,
+                   "open_to_ready_ms": {"p50": float(np.percentile(ready_ms, 50)) if ready_ms else None,
+                                        "max": float(max(ready_ms)) if ready_ms else None,
+                                        "definition": "wdd_server_open returned to the plan ready (tables, "
+                                                      "allocations and W upload on the server's worker thread)"},
                    "acquisitions_done": len(done), "deferred_admissions": deferred,
                    "offered_frames_per_s_sum_of_rates": offered},
         "frames": st["frames"], "wall_s": wall, "batches": st["batches"], "snapshots": st["snapshots"],
