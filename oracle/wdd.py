@@ -26,7 +26,11 @@ below are used (each is a numbered reading in the design notes):
   R11 O~ = conj(IDFT2_unitary(D)) / sqrt(|D[0]|), zero when D[0] = 0.
 
 Parity status: every function here is pinned by a test in tests/test_oracle_*.py
-against a property fixed by the paper or by the mathematics (see each test module).
+against a property fixed by the paper or by the mathematics (see each test module),
+except the shape of patch_window: the paper names no merge window for field-of-view
+patches, so its trapezoid is a choice of this reading (parity unpinned); the properties
+the merge relies on (weights normalised, merge linear and independent of patch order,
+one patch = the full scan) are pinned.
 """
 from __future__ import annotations
 
@@ -432,7 +436,8 @@ def patch_origins(s: int, p: int, overlap: int) -> np.ndarray:
 
 
 def patch_window(p: int, overlap: int) -> np.ndarray:
-    """The 1D merge weight over a patch of length p: 1 inside, linear ramps over the overlap."""
+    """The 1D merge weight over a patch of length p: 1 inside, linear ramps over the overlap.
+    Parity unpinned: the paper gives no window; this shape is the reading's choice."""
     i = np.arange(p, dtype=np.float64)
     return np.minimum(1.0, np.minimum((i + 1) / (overlap + 1), (p - i) / (overlap + 1)))
 
