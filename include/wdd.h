@@ -510,9 +510,10 @@ wdd_status wdd_server_acq_state(wdd_server_t s, int32_t acq, int32_t* ready, int
 /* Scan size of an open acquisition. */
 wdd_status wdd_server_acq_shape(wdd_server_t s, int32_t acq, int32_t* sy, int32_t* sx);
 
-/* Closes an acquisition (queued frames that were not pushed are dropped).  Its plan is
- * freed on a worker thread; the memory returns to the budget when that is done, and an
- * open that would not fit otherwise waits for it. */
+/* Closes an acquisition (queued frames that were not pushed are dropped).  Returns once
+ * no queued work reads its frames any more; its plan is then freed on a worker thread, the
+ * memory returns to the budget when that is done, and an open that would not fit
+ * otherwise waits for it. */
 wdd_status wdd_server_close(wdd_server_t s, int32_t acq);
 
 wdd_status wdd_server_get_stats(wdd_server_t s, wdd_server_stats* out);

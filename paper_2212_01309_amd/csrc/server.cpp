@@ -838,6 +838,12 @@ wdd_status wdd_server_close(wdd_server_t s, int32_t acq) {
   auto it = s->acqs.find(acq);
   if (it == s->acqs.end()) return wdd::fail(WDD_EINVAL, "no open acquisition %d", acq);
   Acq* a = it->second;
+  // the caller may reuse the acquisition's frames once this returns: wait for the work that
+  // reads them (the frees, which wait for the whole device, go to the closer thread)
+  if (a->plan) {
+    const hipError_t e = hipStreamSynchronize(static_cast<wdd_plan_s*>(a->plan)->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+  }
   s->acqs.erase(it);
   bool listed = false;
   try {
