@@ -445,13 +445,14 @@ wdd_status wdd_patches_destroy(wdd_patches_t s);
  * submitted meanwhile wait in the queue.  Frames are submitted as device memory and
  * queued; wdd_server_step takes every queued frame of every ready acquisition (continuous
  * batching) and snapshots the acquisitions whose last snapshot is older than the snapshot
- * interval.  With WDD_SERVE_GROUPED (the default) object-order Hermite-Gauss acquisitions
- * are pushed together in rounds: one projection launch for up to one batch of each (per
- * frame type and arithmetic) and one update launch per row pass over all their spectra;
- * WDD_SERVE_GRAPH captures a round as a HIP graph and replays it with updated arguments.
- * Other acquisitions, and all of them under WDD_SERVE_STREAMS, are pushed through their
- * plans on their own streams so that their work overlaps on the device, with the Wiener
- * reduction fused into the last update where possible.  The time from submit to the
+ * interval.  With WDD_SERVE_GROUPED (the default) Hermite-Gauss acquisitions are pushed
+ * together in rounds: one projection launch for up to one batch of each (per frame type
+ * and arithmetic), then per row pass one update launch over all object-order spectra and
+ * one row-DFT and one A-update launch over all spectrum-order ones (the Wiener reduction
+ * fused into the last pass before a snapshot); WDD_SERVE_GRAPH captures a round as a HIP
+ * graph and replays it with updated arguments.  Fourier-basis acquisitions, and all of
+ * them under WDD_SERVE_STREAMS, are pushed through their plans on their own streams so
+ * that their work overlaps on the device.  The time from submit to the
  * snapshot that contains a frame is recorded per frame.  A server is used by one host
  * thread at a time. */
 

@@ -149,6 +149,35 @@ hipError_t launch_row_fused_obj_group(const ObjPass* passes, const int4* items, 
                                       hipStream_t st);
 size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk);
 
+// One spectrum-order row pass of a plan (at most kRowSetMax rows of one batch) for the
+// grouped launches: the row DFT T_r = Fx_r h_r, then A += sum_r Ty T_r (with fuse, D =
+// sum_k W A and z = conj D in the same pass).  All pointers are device memory.
+struct SpecPass {
+  const float* h;
+  const int* xs;
+  const int* order;
+  const int4* rows;
+  const float2* tx;
+  const float2* ty;
+  float2* t;
+  float2* acc;
+  const int2* freqs;
+  const float2* w;
+  float2* d;
+  float2* z;
+  int64_t n_freq;
+  int nrows, sx, sy, kpad, fuse;
+};
+size_t row_dft_lds_bytes(int sx);
+int row_dft_blocks(int sx, int kpad, int nrows);
+int row_update_blocks(int64_t n_freq_pad, int kpad);
+// Launch of the row DFTs (resp. updates) of npass passes; first[i] = the first workgroup of
+// pass i (running sum of row_dft_blocks, resp. row_update_blocks), nblocks the total; lds
+// the largest row_dft_lds_bytes.  passes and first in device memory.
+hipError_t launch_row_dft_group(const SpecPass* passes, const int* first, int npass, int nblocks, size_t lds,
+                                hipStream_t st);
+hipError_t launch_row_update_group(const SpecPass* passes, const int* first, int npass, int nblocks, hipStream_t st);
+
 hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
                                 int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
                                 int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,

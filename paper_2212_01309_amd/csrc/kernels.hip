@@ -1085,20 +1085,20 @@ __global__ __launch_bounds__(1024) void k_project_display(ProjArgs a, DispArgs d
 // quarter of the frames, and the four partial tiles are summed at the end.
 constexpr int kRowChunk = 256;
 
-__global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int* __restrict__ xs,
-                                                 const int* __restrict__ order, const int4* __restrict__ rows,
-                                                 const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
-  extern __shared__ float2 rsmem[];
+__device__ __forceinline__ void row_dft_body(const float* __restrict__ h, int kpad, const int* __restrict__ xs,
+                                             const int* __restrict__ order, const int4* __restrict__ rows,
+                                             const float2* __restrict__ tx, int sx, float2* __restrict__ t, int bx,
+                                             int by, int bz, float2* rsmem) {
   float2* ltx = rsmem;                                   // [sx]
   int* lx = reinterpret_cast<int*>(ltx + sx);            // [kRowChunk]
   int* lb = lx + kRowChunk;                              // [kRowChunk]
   float* lh = reinterpret_cast<float*>(lb + kRowChunk);  // [kRowChunk][16]; reused for the final sum
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15, q = lane >> 4;
-  const int r = blockIdx.z;
+  const int r = bz;
   const int4 row = rows[r];
-  const int vx = blockIdx.x * 8 + (r16 >> 1);            // A-operand row r16 = 2 * (vx - vx0) + (re/im)
+  const int vx = bx * 8 + (r16 >> 1);                    // A-operand row r16 = 2 * (vx - vx0) + (re/im)
   const bool im = (r16 & 1) != 0;
-  const int c0 = blockIdx.y * 16;
+  const int c0 = by * 16;
   const bool p2 = (sx & (sx - 1)) == 0;
   const float inv = 1.0f / (float)sx;
   stage_copy<4>(ltx, tx, sx, tid, 256);
@@ -1157,24 +1157,31 @@ __global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, in
     // lane (q, r16) holds rows 4q .. 4q + 3 of column r16: vx = vx0 + 2q (+1), (re, im) pairs
 #pragma unroll
     for (int j = 0; j < 4; j += 2) {
-      const int v = blockIdx.x * 8 + 2 * q + (j >> 1);
+      const int v = bx * 8 + 2 * q + (j >> 1);
       if (v < sx) t[((size_t)r * sx + v) * kpad + c0 + r16] = make_float2(acc[j], acc[j + 1]);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_row_dft(const float* __restrict__ h, int kpad, const int* __restrict__ xs,
+                                                 const int* __restrict__ order, const int4* __restrict__ rows,
+                                                 const float2* __restrict__ tx, int sx, float2* __restrict__ t) {
+  extern __shared__ float2 rsmem[];
+  row_dft_body(h, kpad, xs, order, rows, tx, sx, t, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, rsmem);
 }
 
 // One group of G = kpad / 4 consecutive lanes per kept frequency; each lane owns 4
 // consecutive complex entries of A.  With FUSE the Wiener reduction of the new A (as
 // k_wiener) is done in the same pass.
 template <bool FUSE>
-__global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, int kpad, const int2* __restrict__ freqs,
-                                                    int64_t n_freq, const float2* __restrict__ t, int sx,
-                                                    const int4* __restrict__ rows, int nrows,
-                                                    const float2* __restrict__ ty, int sy,
-                                                    const float2* __restrict__ w, float2* __restrict__ d,
-                                                    float2* __restrict__ z) {
+__device__ __forceinline__ void row_update_body(float2* __restrict__ acc, int kpad, const int2* __restrict__ freqs,
+                                                int64_t n_freq, const float2* __restrict__ t, int sx,
+                                                const int4* __restrict__ rows, int nrows,
+                                                const float2* __restrict__ ty, int sy,
+                                                const float2* __restrict__ w, float2* __restrict__ d,
+                                                float2* __restrict__ z, int64_t block) {
   const int g = kpad >> 2;
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t gid = block * 256 + threadIdx.x;
   const int64_t j = gid / g;
   const int c = 4 * (int)(gid - j * g);
   const int2 v = freqs[j];
@@ -1214,6 +1221,55 @@ __global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, in
       z[(size_t)v.y * sy + v.x] = make_float2(re, -im);
     }
   }
+}
+
+template <bool FUSE>
+__global__ __launch_bounds__(256) void k_row_update(float2* __restrict__ acc, int kpad, const int2* __restrict__ freqs,
+                                                    int64_t n_freq, const float2* __restrict__ t, int sx,
+                                                    const int4* __restrict__ rows, int nrows,
+                                                    const float2* __restrict__ ty, int sy,
+                                                    const float2* __restrict__ w, float2* __restrict__ d,
+                                                    float2* __restrict__ z) {
+  row_update_body<FUSE>(acc, kpad, freqs, n_freq, t, sx, rows, nrows, ty, sy, w, d, z, (int64_t)blockIdx.x);
+}
+
+// Spectrum-order row passes of several plans in one launch each (serving rounds): the
+// passes' descriptors in device memory, their first workgroups in first[0 .. npass] (a
+// running sum of each pass's grid); workgroup b belongs to the pass i with first[i] <= b <
+// first[i + 1].
+__device__ inline int group_pass(const int* __restrict__ first, int npass, int b) {
+  int lo = 0, hi = npass - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_row_dft_group(const wdd::SpecPass* __restrict__ passes,
+                                                       const int* __restrict__ first, int npass) {
+  extern __shared__ float2 rsmem[];
+  const int b = (int)blockIdx.x;
+  const int i = group_pass(first, npass, b);
+  const wdd::SpecPass& p = passes[i];
+  const int local = b - first[i];
+  const int nbx = (p.sx + 7) / 8, nby = p.kpad / 16;
+  row_dft_body(p.h, p.kpad, p.xs, p.order, p.rows, p.tx, p.sx, p.t, local % nbx, (local / nbx) % nby,
+               local / (nbx * nby), rsmem);
+}
+
+__global__ __launch_bounds__(256) void k_row_update_group(const wdd::SpecPass* __restrict__ passes,
+                                                          const int* __restrict__ first, int npass) {
+  const int b = (int)blockIdx.x;
+  const int i = group_pass(first, npass, b);
+  const wdd::SpecPass& p = passes[i];
+  const int64_t local = b - first[i];
+  if (p.fuse)
+    row_update_body<true>(p.acc, p.kpad, p.freqs, p.n_freq, p.t, p.sx, p.rows, p.nrows, p.ty, p.sy, p.w, p.d, p.z,
+                          local);
+  else
+    row_update_body<false>(p.acc, p.kpad, p.freqs, p.n_freq, p.t, p.sx, p.rows, p.nrows, p.ty, p.sy, p.w, p.d, p.z,
+                           local);
 }
 
 // ---------------------------------------------------------------------------
@@ -1862,7 +1918,7 @@ hipError_t prepare_group_kernels() {
                            allow_full_lds<k_project_group<uint16_t, WDD_FP16_HILO>>(),
                            allow_full_lds<k_project_group<uint16_t, WDD_BF16>>(),
                            allow_full_lds<k_project_group<uint16_t, WDD_FP16>>(),
-                           allow_full_lds<k_row_fused_obj_group>()};
+                           allow_full_lds<k_row_fused_obj_group>(), allow_full_lds<k_row_dft_group>()};
   for (hipError_t e : es)
     if (e != hipSuccess) return e;
   return hipSuccess;
@@ -2013,6 +2069,28 @@ hipError_t launch_row_dft(const float* h, int kpad, const int* xs, const int* or
   const size_t lds = (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
   dim3 grid((unsigned)((sx + 7) / 8), (unsigned)(kpad / 16), (unsigned)nrows);
   hipLaunchKernelGGL(k_row_dft, grid, dim3(256), lds, st, h, kpad, xs, order, rows, tx, sx, t);
+  return hipGetLastError();
+}
+
+size_t row_dft_lds_bytes(int sx) {
+  return (size_t)sx * sizeof(float2) + 2 * kRowChunk * sizeof(int) + kRowChunk * 16 * sizeof(float);
+}
+int row_dft_blocks(int sx, int kpad, int nrows) { return ((sx + 7) / 8) * (kpad / 16) * nrows; }
+int row_update_blocks(int64_t n_freq_pad, int kpad) { return (int)((n_freq_pad * (kpad / 4) + 255) / 256); }
+
+hipError_t launch_row_dft_group(const SpecPass* passes, const int* first, int npass, int nblocks, size_t lds,
+                                hipStream_t st) {
+  if (npass < 1 || nblocks < 1) return hipSuccess;
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  const hipError_t e = allow_full_lds<k_row_dft_group>();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_dft_group, dim3((unsigned)nblocks), dim3(256), lds, st, passes, first, npass);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_update_group(const SpecPass* passes, const int* first, int npass, int nblocks, hipStream_t st) {
+  if (npass < 1 || nblocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_row_update_group, dim3((unsigned)nblocks), dim3(256), 0, st, passes, first, npass);
   return hipGetLastError();
 }
 

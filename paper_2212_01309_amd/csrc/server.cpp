@@ -7,16 +7,16 @@
 // as device addresses and queued per acquisition; every scheduling step takes whatever
 // frames have arrived (continuous batching) and snapshots the acquisitions that are due.
 //
-// Object-order Hermite-Gauss acquisitions (the live form of the modified-WDD algorithm,
-// D updated per frame) are pushed together: one round takes up to one batch of every such
-// acquisition, projects all of them in one launch (per frame type and arithmetic) and
-// updates all their spectra in one launch per row pass, whose work list covers every
-// (acquisition, row pass, chunk of kept frequencies).  That projection launch also brings
-// the round's descriptors (row passes, work list, frame order) to the device from pinned
-// host memory.  Optionally the round's launches are captured once as a HIP graph and
-// replayed with updated arguments.  Other acquisitions (spectrum order, Fourier basis)
-// are pushed through their plans on their own streams.  Every frame's submit-to-snapshot
-// latency is recorded.
+// Hermite-Gauss acquisitions are pushed together: one round takes up to one batch of every
+// such acquisition and projects all of them in one launch (per frame type and arithmetic);
+// per row pass, one launch updates every object-order spectrum (the live form of the
+// modified-WDD algorithm, D updated per frame; its work list covers every (acquisition,
+// row pass, chunk of kept frequencies)), and two launches (row DFTs, then A updates) every
+// spectrum-order one.  That projection launch also brings the round's descriptors to the
+// device from pinned host memory.  Optionally the round's launches are captured once as a
+// HIP graph and replayed with updated arguments.  Fourier-basis acquisitions are pushed
+// through their plans on their own streams.  Every frame's submit-to-snapshot latency is
+// recorded.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -56,6 +56,7 @@ struct Acq {
   std::deque<Pending> pending;
   std::vector<double> awaiting;  // submit times of frames pushed but not yet in a snapshot
   double last_snapshot = -1e300;
+  bool fused = false;  // grouped spectrum order: the last round reduced D (no Wiener launch needed)
   // a scheduled snapshot still running on the device (wdd_server_step does not wait for
   // it; a later call sees its event complete and records the latencies of its frames)
   hipEvent_t snap_ev = nullptr;
@@ -211,7 +212,9 @@ struct Member {
   Acq* a;
   wdd_plan_s* p;
   int32_t n;
-  bool display;             // leave the display's first pass in the plan's partial rows
+  bool spectrum;            // spectrum order (A resident): row DFT + A update per pass
+  bool display;             // a snapshot follows: object order leaves the display's first pass
+                            // in the partial rows, spectrum order fuses the Wiener reduction
   size_t first_frame;       // offset of its frames in the round's order / xs / address arrays
   size_t first_row;         // offset of its rows in the round's row array
   int32_t nrows;
@@ -224,11 +227,14 @@ struct Round {
   struct PassRef {
     int32_t member, k, row0, nrows;
   };
-  std::vector<PassRef> passes;   // sorted by k
+  std::vector<PassRef> passes;   // object-order passes, sorted by k
   std::vector<size_t> item0;     // first work item of each pass
+  std::vector<PassRef> spasses;  // spectrum-order passes, sorted by k
+  std::vector<int32_t> dft_first, upd_first;  // first workgroup of each within its k's launch
+  std::vector<int32_t> dft_total, upd_total;  // per k: workgroups of its launches
   char* hb = nullptr;            // pinned block
   char* db = nullptr;            // its device copy
-  size_t dev_bytes = 0, off_items = 0;
+  size_t dev_bytes = 0, off_items = 0, off_spass = 0, off_dft = 0, off_upd = 0;
   const uint64_t* ftab = nullptr;  // frame addresses (pinned)
   int slot = 0;
 };
@@ -261,21 +267,42 @@ wdd_status prepare_round(wdd_server_s* s, std::vector<Member>& ms, Round* rd) {
       }
       for (int32_t i = 0; i < m.n; ++i) addrs.push_back(q[i].addr);
       m.nrows = (int32_t)(rows.size() - m.first_row);
+      std::vector<Round::PassRef>& list = m.spectrum ? rd->spasses : rd->passes;
       for (int32_t r = 0, k = 0; r < m.nrows; r += wdd::kFactorRows, ++k)
-        rd->passes.push_back({mi, k, r, std::min<int32_t>(wdd::kFactorRows, m.nrows - r)});
+        list.push_back({mi, k, r, std::min<int32_t>(wdd::kFactorRows, m.nrows - r)});
     }
   } catch (const std::bad_alloc&) {
     return wdd::fail(WDD_ENOMEM, "out of host memory");
   }
+  auto by_k = [](const Round::PassRef& u, const Round::PassRef& v) { return u.k < v.k; };
   std::vector<Round::PassRef>& passes = rd->passes;
-  std::stable_sort(passes.begin(), passes.end(),
-                   [](const Round::PassRef& u, const Round::PassRef& v) { return u.k < v.k; });
+  std::stable_sort(passes.begin(), passes.end(), by_k);
+  std::vector<Round::PassRef>& spasses = rd->spasses;
+  std::stable_sort(spasses.begin(), spasses.end(), by_k);
   rd->item0.assign(passes.size() + 1, 0);
   for (size_t i = 0; i < passes.size(); ++i) rd->item0[i + 1] = rd->item0[i] + ms[passes[i].member].p->host_chunks.size();
   const size_t nitems = rd->item0.back();
-  // block: [passes][items][rows][order][xs] (copied to the device) then the frame addresses
+  // spectrum-order passes: workgroup offsets within the launch of their k
+  const int32_t kmax_s = spasses.empty() ? -1 : spasses.back().k;
+  rd->dft_first.assign(spasses.size(), 0);
+  rd->upd_first.assign(spasses.size(), 0);
+  rd->dft_total.assign((size_t)(kmax_s + 1), 0);
+  rd->upd_total.assign((size_t)(kmax_s + 1), 0);
+  for (size_t i = 0; i < spasses.size(); ++i) {
+    const wdd_plan_s* p = ms[spasses[i].member].p;
+    const int32_t k = spasses[i].k;
+    rd->dft_first[i] = rd->dft_total[k];
+    rd->upd_first[i] = rd->upd_total[k];
+    rd->dft_total[k] += wdd::row_dft_blocks(p->sx, p->kpad, spasses[i].nrows);
+    rd->upd_total[k] += wdd::row_update_blocks(p->n_freq_pad, p->kpad);
+  }
+  // block: [passes][items][spectrum passes][their first workgroups (row DFT, update)][rows]
+  // [order][xs] (copied to the device) then the frame addresses
   const size_t off_items = align16(passes.size() * sizeof(wdd::ObjPass));
-  const size_t off_rows = off_items + align16(nitems * sizeof(int4));
+  const size_t off_spass = off_items + align16(nitems * sizeof(int4));
+  const size_t off_dft = off_spass + align16(spasses.size() * sizeof(wdd::SpecPass));
+  const size_t off_upd = off_dft + align16(spasses.size() * sizeof(int32_t));
+  const size_t off_rows = off_upd + align16(spasses.size() * sizeof(int32_t));
   const size_t off_order = off_rows + align16(rows.size() * sizeof(int4));
   const size_t off_xs = off_order + align16(order.size() * sizeof(int32_t));
   const size_t dev_bytes = off_xs + align16(xs.size() * sizeof(int32_t));
@@ -350,6 +377,40 @@ wdd_status prepare_round(wdd_server_s* s, std::vector<Member>& ms, Round* rd) {
       items[rd->item0[i] + c] = make_int4((int32_t)i, ch.x, ch.y, ch.z | (ch.w << 16));
     }
   }
+  std::vector<int32_t> last_spass(ms.size(), 0);
+  for (const Round::PassRef& pr : spasses) last_spass[pr.member] = std::max(last_spass[pr.member], pr.k);
+  wdd::SpecPass* sp = reinterpret_cast<wdd::SpecPass*>(hb + off_spass);
+  for (size_t i = 0; i < spasses.size(); ++i) {
+    const Round::PassRef& pr = spasses[i];
+    const Member& m = ms[pr.member];
+    wdd_plan_s* p = m.p;
+    wdd::SpecPass o;
+    std::memset(&o, 0, sizeof(o));
+    o.h = p->h;
+    o.xs = reinterpret_cast<const int*>(db + off_xs) + m.first_frame;
+    o.order = reinterpret_cast<const int*>(db + off_order) + m.first_frame;
+    o.rows = reinterpret_cast<const int4*>(db + off_rows) + m.first_row + pr.row0;
+    o.tx = p->tx;
+    o.ty = p->ty;
+    o.t = p->t;
+    o.acc = p->acc;
+    o.freqs = p->freqs;
+    o.w = p->w;
+    o.d = p->d;
+    o.z = p->z;
+    o.n_freq = p->n_freq;
+    o.nrows = pr.nrows;
+    o.sx = p->sx;
+    o.sy = p->sy;
+    o.kpad = p->kpad;
+    o.fuse = m.display && pr.k == last_spass[pr.member] ? 1 : 0;  // D current for the snapshot
+    sp[i] = o;
+  }
+  std::memcpy(hb + off_dft, rd->dft_first.data(), rd->dft_first.size() * sizeof(int32_t));
+  std::memcpy(hb + off_upd, rd->upd_first.data(), rd->upd_first.size() * sizeof(int32_t));
+  rd->off_spass = off_spass;
+  rd->off_dft = off_dft;
+  rd->off_upd = off_upd;
   rd->hb = hb;
   rd->db = db;
   rd->dev_bytes = dev_bytes;
@@ -408,6 +469,23 @@ wdd_status launch_round(wdd_server_s* s, const std::vector<Member>& ms, const Ro
                                                (int)(rd.item0[i1] - rd.item0[i0]), lds, s->stream));
     i0 = i1;
   }
+  // spectrum order: per pass index, the row DFTs of every such member, then their A updates
+  // (a member's passes share its T and A, so the launches order them)
+  const wdd::SpecPass* sp = reinterpret_cast<const wdd::SpecPass*>(rd.db + rd.off_spass);
+  const int32_t* dft_first = reinterpret_cast<const int32_t*>(rd.db + rd.off_dft);
+  const int32_t* upd_first = reinterpret_cast<const int32_t*>(rd.db + rd.off_upd);
+  for (size_t i0 = 0; i0 < rd.spasses.size();) {
+    const int32_t k = rd.spasses[i0].k;
+    size_t i1 = i0;
+    size_t lds = 0;
+    while (i1 < rd.spasses.size() && rd.spasses[i1].k == k) {
+      lds = std::max(lds, wdd::row_dft_lds_bytes(ms[rd.spasses[i1].member].p->sx));
+      ++i1;
+    }
+    SRV_HIP(s, wdd::launch_row_dft_group(sp + i0, dft_first + i0, (int)(i1 - i0), rd.dft_total[k], lds, s->stream));
+    SRV_HIP(s, wdd::launch_row_update_group(sp + i0, upd_first + i0, (int)(i1 - i0), rd.upd_total[k], s->stream));
+    i0 = i1;
+  }
   return WDD_OK;
 }
 
@@ -434,6 +512,7 @@ wdd_status drain_grouped(wdd_server_s* s, const std::vector<Acq*>& acqs, const s
       m.a = a;
       m.p = static_cast<wdd_plan_s*>(a->plan);
       m.n = (int32_t)std::min<size_t>(a->pending.size(), (size_t)a->batch);
+      m.spectrum = m.p->order_mode == WDD_ORDER_SPECTRUM;
       m.display = due[i] && (size_t)m.n == a->pending.size();
       if (m.p->failed) return wdd::fail(WDD_ESTATE, "acquisition %d is unusable after an earlier device error", a->id);
       ms.push_back(m);
@@ -492,11 +571,20 @@ wdd_status drain_grouped(wdd_server_s* s, const std::vector<Acq*>& acqs, const s
       p->frames_seen += (uint64_t)m.n;
       p->last_batch = m.n;
       p->up_valid = m.display && p->up;  // D changed: the partial rows are current only if written now
+      a->fused = m.spectrum && m.display;  // spectrum order: D reduced in the round's last pass
       a->frames_done += (uint64_t)m.n;
       s->frames += (uint64_t)m.n;
       s->batches += 1;
     }
   }
+}
+
+// Whether D is current for a snapshot: object order always; spectrum order when the last
+// push (plan path: `fused_push`) or round (grouped) carried the Wiener reduction.
+bool current_d(const Acq* a, bool fused_push) {
+  const wdd_plan_s* p = static_cast<const wdd_plan_s*>(a->plan);
+  if (p->order_mode == WDD_ORDER_OBJECT) return true;
+  return a->grouped ? a->fused : fused_push;
 }
 
 void record_snapshot(wdd_server_s* s, Acq* a) {
@@ -695,8 +783,7 @@ wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_sca
   a->frame_bytes = (size_t)det->ny * det->nx * (det->dtype == WDD_U16 ? 2 : 4);
   a->sy = scan->sy;
   a->sx = scan->sx;
-  a->grouped = s->opts.launch_mode != WDD_SERVE_STREAMS && opts.order == WDD_ORDER_OBJECT &&
-               opts.basis == WDD_BASIS_HERMITE_GAUSS;
+  a->grouped = s->opts.launch_mode != WDD_SERVE_STREAMS && opts.basis == WDD_BASIS_HERMITE_GAUSS;
   try {
     a->worker = std::thread(open_worker, s, a, key, tp, *probe, *scan, *det, K, opts);
   } catch (const std::system_error&) {
@@ -756,6 +843,7 @@ wdd_status wdd_server_step(wdd_server_t s, int32_t* frames_processed) {
     const bool had = !a->pending.empty();
     bool fused = false;
     if (a->grouped) {
+      a->fused = false;
       grouped.push_back(a);
       grouped_due.push_back(due);
     } else {
@@ -768,8 +856,9 @@ wdd_status wdd_server_step(wdd_server_t s, int32_t* frames_processed) {
   // the due snapshots are queued, not waited for
   for (auto& sp : snap) {
     Acq* a = sp.first;
-    // object order keeps D current: no reduction for the grouped acquisitions
-    if ((st = wdd::snapshot_enqueue(a->plan, !sp.second && !a->grouped)) != WDD_OK) return st;
+    // object order keeps D current; a grouped spectrum-order acquisition has D current if its
+    // last round reduced it
+    if ((st = wdd::snapshot_enqueue(a->plan, !current_d(a, sp.second))) != WDD_OK) return st;
     if (!a->snap_ev) SRV_HIP(s, hipEventCreateWithFlags(&a->snap_ev, hipEventDisableTiming));
     SRV_HIP(s, hipEventRecord(a->snap_ev, static_cast<wdd_plan_s*>(a->plan)->stream));
     a->inflight.swap(a->awaiting);
@@ -791,6 +880,7 @@ wdd_status wdd_server_snapshot(wdd_server_t s, int32_t acq, float* out, uint64_t
   bool fused = false;
   if (a->grouped) {
     // rounds over every ready grouped acquisition with frames waiting, until this one's are in
+    a->fused = false;
     std::vector<Acq*> acqs;
     std::vector<bool> due;
     for (auto& kv : s->acqs) {
@@ -803,7 +893,7 @@ wdd_status wdd_server_snapshot(wdd_server_t s, int32_t acq, float* out, uint64_t
   } else if ((st = drain_plan(s, a, true, &fused)) != WDD_OK) {
     return st;
   }
-  if ((st = wdd::snapshot_enqueue(a->plan, !fused && !a->grouped)) != WDD_OK) return st;
+  if ((st = wdd::snapshot_enqueue(a->plan, !current_d(a, fused))) != WDD_OK) return st;
   if ((st = wdd::snapshot_finish(a->plan, frames_seen)) != WDD_OK) return st;
   if (a->snap_inflight) complete_inflight(s, a, now_us());  // queued earlier on the same stream
   record_snapshot(s, a);

@@ -59,9 +59,9 @@ ORACLE_BOUND = {"fp32": 1e-5, "bf16_hilo": 3e-5}
 def test_each_result_is_the_same_alone_and_in_the_mix(order, precision, mode):
     """The serving mix pushes frames through a per-frame address table (frames from many
     submitted buffers in one batch); with a reduced-precision projection that is the
-    bf16 kernel's address-table path, and in object order under the grouped modes the
-    grouped projection over all acquisitions (random submissions over up to 48 scan rows
-    give rounds of several row passes).  Alone and in the mix the projections of a frame
+    bf16 kernel's address-table path, and under the grouped modes the grouped projection
+    and the grouped updates of either order over all acquisitions (random submissions over
+    up to 48 scan rows give rounds of several row passes).  Alone and in the mix the projections of a frame
     agree; only the accumulation's batch boundaries differ."""
     rng = np.random.default_rng(9)
     data = [_acquisition(i, *g) for i, g in enumerate(GEOMS)]
@@ -84,8 +84,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(order, precision, mode):
     total = sum(len(p) for _, p in data)
     assert st["frames"] == total and st["latency_samples"] == total and st["opening"] == 0
     assert 0 < st["latency_p50_us"] <= st["latency_p99_us"] <= st["latency_max_us"]
-    grouped = mode != "streams" and order == wdd.WDD_ORDER_OBJECT
-    assert (st["group_rounds"] > 0) == grouped
+    assert (st["group_rounds"] > 0) == (mode != "streams")
     say(f"[serving] {mode}: mix of {len(GEOMS)} acquisitions, {total} frames, {st['batches']} batches, "
         f"{st['group_rounds']} grouped rounds ({st['graph_replays']} graph replays), {st['snapshots']} snapshots, "
         f"latency p50 {st['latency_p50_us']:.0f} us p99 {st['latency_p99_us']:.0f} us")
@@ -149,11 +148,11 @@ def test_submit_rejects_positions_off_the_raster():
 
 @pytest.mark.parametrize("mode", ["grouped", "graph"])
 def test_grouped_rounds_over_mixed_acquisitions(mode):
-    """One server holding object-order acquisitions of two frame types and two arithmetics
-    (several grouped projection launches per round), a 160-row detector (one wave per 16
-    rows in the projection, partial display rows double-buffered), a spectrum-order one
-    (pushed through its plan beside the rounds) and a steady phase of equal rounds (the
-    graph is then replayed with updated arguments); each result against its own plan."""
+    """One server holding acquisitions of two frame types and two arithmetics (several
+    grouped projection launches per round), a 160-row detector (one wave per 16 rows in the
+    projection), object and spectrum order in the same rounds (grouped object-order updates,
+    grouped row DFTs and A updates), and a steady phase of equal rounds (the graph is then
+    replayed with updated arguments); each result against its own plan."""
     import torch
     cases = [  # (radius, scan, detector, K, dtype, precision, order)
         (8.0, 32, 32, 64, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_OBJECT),
@@ -161,6 +160,7 @@ def test_grouped_rounds_over_mixed_acquisitions(mode):
         (6.0, 32, 32, 36, wdd.WDD_U16, "bf16_hilo", wdd.WDD_ORDER_OBJECT),
         (20.0, 32, 160, 100, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_OBJECT),
         (8.0, 32, 32, 64, wdd.WDD_U16, "fp32", wdd.WDD_ORDER_SPECTRUM),
+        (6.0, 32, 64, 36, wdd.WDD_U16, "bf16_hilo", wdd.WDD_ORDER_SPECTRUM),
     ]
     rng = np.random.default_rng(77)
     data = []
