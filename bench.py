@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--display", default="deferred", choices=["deferred", "async"],
                     help="pipelined steps: each image written by the next push's first launch (deferred) or "
                          "queued at once (async)")
+    ap.add_argument("--pipeline", default="auto", choices=["auto", "on", "off"],
+                    help="pipelined pushes (each batch's update in the next push's launch, beside that push's "
+                         "projection); auto: on where the plan supports it (object order, FP32 projection of "
+                         "uint16 frames of <= 256 rows and 32..256 columns in multiples of 32)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
     ap.add_argument("--serving", action="store_true", help="run the Poisson-paced serving mix instead")
@@ -93,14 +97,15 @@ def profile_record(kind, workload, kernel):
     return None
 
 
-def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0.0):
+def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0.0, pipelined=False):
     """Roofline entry of the accumulation kernel (the method's O(S^2 L^2) term and the
     largest kernel of every workload's kernel trace): algorithmic bytes per launch over the
     kernel's average duration from the rocprofv3 kernel trace recorded under profiles/ for
     this kernel source (the launches of the timed steps), with the live HIP-event mean from
     the untimed stage pass beside it (events include the launch's dispatch latency).
     display_bytes: the previous image's column pass when it rides in this launch (partial
-    rows read, image written)."""
+    rows read, image written).  pipelined: the launch also projects the next batch (frames
+    read, h written): k_row_fused_obj_next."""
     if fourier:
         nbytes = (8.0 if order == "object" else 24.0) * n_freq * k
         kernel = "k_update_c<%d>" % (0 if order == "object" else 2)
@@ -110,6 +115,10 @@ def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0
         nbytes, kernel = 8.0 * n_freq * k + display_bytes, "k_row_fused_obj"
         rule = "8 * n_freq * K (W read once)" + (" + 8 * Sy * Sx * (slots + 1) (the previous image's column "
                                                  "pass in the same launch)" if display_bytes else "")
+        if pipelined:
+            nbytes += (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
+            kernel = "k_row_fused_obj_next<unsignedshort>"  # as recorded: no spaces
+            rule += " + frames + 4 * K * batch (the next batch's projection in the same launch)"
     else:
         # read and write A, read W (the Wiener reduction fused in before a snapshot)
         nbytes, kernel = 24.0 * n_freq * k, "k_row_update<true>"
@@ -225,13 +234,19 @@ def cpu_baseline(wl, frames, pos, seconds, fourier=False):
     return out
 
 
-def make_plan(wdd, wl, order, precision="fp32", fourier=False, max_batch=None):
+def pipeline_supported(wl, order, precision, fourier):
+    pow2 = (wl.sy & (wl.sy - 1)) == 0 and (wl.sx & (wl.sx - 1)) == 0
+    return (order == "object" and not fourier and precision == "fp32" and bool(wl.dose) and wl.n % 32 == 0
+            and 32 <= wl.n <= 256 and pow2 and wl.sy <= 1024)
+
+
+def make_plan(wdd, wl, order, precision="fp32", fourier=False, max_batch=None, pipeline=False):
     return wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.n * wl.n if fourier else wl.k,
                     dtype=wdd.WDD_U16 if wl.dose else wdd.WDD_F32, defocus=wl.defocus_edge,
                     amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=max_batch or wl.batch,
                     precision=precision,
                     order=wdd.WDD_ORDER_OBJECT if order == "object" else wdd.WDD_ORDER_SPECTRUM,
-                    basis=wdd.WDD_BASIS_FOURIER if fourier else wdd.WDD_BASIS_HERMITE_GAUSS)
+                    basis=wdd.WDD_BASIS_FOURIER if fourier else wdd.WDD_BASIS_HERMITE_GAUSS, pipeline=pipeline)
 
 
 def run_steps(plan, batches, shown, first, count, defer, snapshot_every=1):
@@ -501,7 +516,11 @@ def main():
     frames, pos, batches, gen_s = load_batches(torch, wl, args.pool_batches)
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
     defer = args.display == "deferred"
-    plan = make_plan(wdd, wl, args.order, args.precision, fourier)
+    can_pipe = pipeline_supported(wl, args.order, args.precision, fourier)
+    if args.pipeline == "on" and not can_pipe:
+        sys.exit("--pipeline on: this workload / order / precision has no pipelined form")
+    pipelined = args.pipeline == "on" or (args.pipeline == "auto" and can_pipe)
+    plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipelined)
     n_freq, k = plan.n_freq, plan.k
     plan_info = plan.info()
 
@@ -548,6 +567,13 @@ def main():
             "frames_per_s": steps_c * wl.batch / el, "us_per_batch": el / steps_c * 1e6, "steps": steps_c}
     plan.close()
 
+    if not args.no_extras and can_pipe:
+        # the same steps with the other push form (pipelined or not)
+        with make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=not pipelined) as p2:
+            el, _ = timed(torch, p2, batches, shown, args.warmup, args.steps, defer)
+        extras["unpipelined" if pipelined else "pipelined"] = {
+            "frames_per_s": args.steps * wl.batch / el, "us_per_step": el / args.steps * 1e6}
+
     if not args.no_extras and not fourier:
         other = "spectrum" if args.order == "object" else "object"
         with make_plan(wdd, wl, other, args.precision) as p2:
@@ -566,10 +592,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
-                   "wiener_order": args.order, "basis": args.basis,
-                   "display": "hbm" + (", each image's last pass deferred to the next push's first launch "
-                                       "(its projection for detectors of <= 128 rows, else its first update; "
-                                       "Hermite-Gauss basis, power-of-two scan width)" if defer else "")},
+                   "wiener_order": args.order, "basis": args.basis, "pipelined": pipelined,
+                   "display": "hbm" + ((", each batch's update in the next push's launch (with that push's "
+                                        "projection), each image's last pass in the launch after" if pipelined else
+                                        ", each image's last pass deferred to the next push's first launch "
+                                        "(its projection for detectors of <= 128 rows, else its first update; "
+                                        "Hermite-Gauss basis, power-of-two scan width)") if defer else "")},
         "host_issue_us_per_step": issue / args.steps * 1e6,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "samples": nlat, "definition": "wdd_push_snapshot call to the image complete in host memory"},
@@ -583,11 +611,13 @@ def main():
         pow2x = (wl.sx & (wl.sx - 1)) == 0
         slots = info.display_slots if args.order == "object" and info.display_slots else 1
         disp = 8.0 * wl.sy * wl.sx * (slots + 1)
-        in_update = defer and not fourier and args.order == "object" and wl.n > 128 and info.display_slots > 0
-        in_proj = defer and not fourier and wl.n <= 128 and pow2x
+        in_update = (defer and not fourier and args.order == "object" and (wl.n > 128 or pipelined)
+                     and info.display_slots > 0)
+        in_proj = defer and not fourier and wl.n <= 128 and pow2x and not pipelined
         out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"],
-                                   disp if in_update else 0.0)
-        proj = (None if fourier or args.precision != "fp32"
+                                   disp if in_update else 0.0, pipelined)
+        # (pipelined: the projection has no launch of its own in the timed steps)
+        proj = (None if fourier or args.precision != "fp32" or pipelined
                 else projection_roofline(wl, k, args.order, disp if in_proj else 0.0))
         if proj is not None:
             out["roofline_projection"] = proj

@@ -118,7 +118,23 @@ typedef struct {
   int32_t max_batch;  /* largest n accepted by wdd_push; default 256 */
   int32_t order;      /* wdd_order; default WDD_ORDER_SPECTRUM */
   int32_t basis;      /* wdd_basis; default WDD_BASIS_HERMITE_GAUSS */
+  int32_t pipeline;   /* 0 (default) or 1: pipelined pushes, see below */
 } wdd_options;
+
+/* Pipelined pushes (wdd_options.pipeline = 1).  The update of a batch (its accumulation into
+ * D, Section 6.3, modified-WDD algorithm, the loop body) is held back and runs in the next
+ * push's launch, beside that push's projection: the two are independent, and the
+ * projection's frame stream from HBM then overlaps the update's first phase.  Every call
+ * that waits for the plan's stream or reads or changes its state (wdd_snapshot, wdd_sync,
+ * wdd_spectrum, wdd_get_*, wdd_profile_read, checkpoints, wdd_reset, wdd_destroy) first runs
+ * a held update, so results are those of unpipelined pushes up to FP32 rounding (the
+ * projection sums its tiles in another order; a snapshot taken while a batch is held gets
+ * the display's first pass from that batch's update, as wdd_push_snapshot does, so push +
+ * snapshot then gives wdd_push_snapshot's image).  A WDD_OUT_DEVICE_DEFERRED snapshot after
+ * push i is written during push i + 2 (its update runs in push i + 1's launch, its display's
+ * last pass in push i + 2's), or by such a call.  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
+ * basis, FP32 precision, uint16 frames of at most 256 rows and 32..256 columns in multiples
+ * of 32, and power-of-two scan sides with Sy <= 1024; other plans: WDD_EINVAL. */
 
 typedef struct {
   int64_t n_freq;        /* number of kept scan frequencies */
@@ -130,6 +146,7 @@ typedef struct {
   int64_t device_bytes;  /* device memory held by the plan */
   int32_t update_chunks; /* object order: workgroups of a row pass (runs of kept frequencies of one v_x) */
   int32_t display_slots; /* object order: partial display rows kept per v_x (0: the two-pass display) */
+  int32_t pipelined;     /* pushes are pipelined (wdd_options.pipeline) */
 } wdd_plan_info;
 
 typedef struct wdd_tables_s* wdd_tables_t;
@@ -228,7 +245,8 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *                         point's spectrum) may be written by the plan's next push, in
  *                         one of that push's launches (its projection; for detectors of
  *                         more than 128 rows in object order, its first update: one
- *                         kernel boundary fewer per pipelined step), or else by the next
+ *                         kernel boundary fewer per pipelined step; with pipelined
+ *                         pushes, by the push after next), or else by the next
  *                         call that waits for the plan's stream or changes its state
  *                         (wdd_snapshot, wdd_sync, wdd_get_*, wdd_profile_read,
  *                         checkpoints, wdd_update_probe, wdd_reset, wdd_destroy).  `out`
@@ -406,7 +424,8 @@ typedef struct {
 typedef struct wdd_patches_s* wdd_patches_t;
 
 /* Creates a patch set for the whole raster `scan` (arguments as wdd_plan; the Hermite-Gauss
- * basis, object order; all patches share one set of tables built for the patch raster).
+ * basis, object order, pushes not pipelined; all patches share one set of tables built for
+ * the patch raster).
  * WDD_EINVAL for a geometry that does not fit the raster. */
 wdd_status wdd_patches_create(const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det, int32_t K,
                               const wdd_patch_geometry* geo, const wdd_options* opts, void* hip_stream,
@@ -483,7 +502,7 @@ wdd_status wdd_server_default_options(wdd_server_options* opts);
 wdd_status wdd_server_create(const wdd_server_options* opts, wdd_server_t* out);
 
 /* Opens an acquisition (arguments as wdd_plan; max_batch is raised to the server's
- * batch_frames).  Argument errors and WDD_EBUSY (it does not fit the budget now) are
+ * batch_frames; pipeline is ignored: the server orders the acquisitions' launches itself).  Argument errors and WDD_EBUSY (it does not fit the budget now) are
  * returned here; the plan is made on a worker thread, and an error there is returned by
  * the acquisition's next wdd_server_submit or wdd_server_snapshot. */
 wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_scan* scan, const wdd_detector* det,

@@ -61,13 +61,15 @@ class Detector(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eps_rel", ctypes.c_double), ("sigma_px", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("order", ctypes.c_int32), ("basis", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("order", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_freq", ctypes.c_int64), ("k", ctypes.c_int32), ("l", ctypes.c_int32),
                 ("sigma_px", ctypes.c_double), ("eps_abs", ctypes.c_double), ("frames_seen", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_int64), ("update_chunks", ctypes.c_int32), ("display_slots", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("update_chunks", ctypes.c_int32), ("display_slots", ctypes.c_int32),
+                ("pipelined", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -233,11 +235,12 @@ def _check(code: int) -> None:
 
 
 def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32,
-             order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS) -> Options:
+             order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, pipeline: bool = False) -> Options:
     o = Options()
     _check(load_library().wdd_default_options(ctypes.byref(o)))
     o.eps_rel, o.sigma_px, o.max_batch, o.precision, o.order = eps_rel, sigma_px, max_batch, precision, order
     o.basis = basis
+    o.pipeline = 1 if pipeline else 0
     return o
 
 
@@ -296,12 +299,15 @@ class Tables:
 
 
 class Plan:
-    """A live reconstruction on the current HIP device (wdd_plan ... wdd_destroy)."""
+    """A live reconstruction on the current HIP device (wdd_plan ... wdd_destroy).
+    pipeline=True (object order): each push's update runs in the next push's launch, beside
+    that push's projection (wdd_options.pipeline)."""
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
                  sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32,
-                 order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, center=None):
+                 order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, center=None,
+                 pipeline: bool = False):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype
@@ -312,7 +318,7 @@ class Plan:
         self.center = (ny // 2, nx // 2) if center is None else tuple(center)
         _check(lib.wdd_plan(ctypes.byref(_probe(radius, ny, nx, center, defocus, amplitude)),
                             ctypes.byref(Scan(sy, sx, step)), ctypes.byref(Detector(ny, nx, dtype)), k,
-                            ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order, basis)),
+                            ctypes.byref(_options(eps_rel, sigma, max_batch, precision, order, basis, pipeline)),
                             _P(stream) if stream else None, ctypes.byref(self._h)))
         info = self.info()
         self.n_freq, self.k, self.l = int(info.n_freq), int(info.k), int(info.l)
@@ -409,7 +415,8 @@ class Plan:
         """push() then snapshot() in one call (one pass over the spectrum when possible).
         With a device `out` and wait=False the call returns once the work is enqueued; `out`
         is complete after sync().  defer=True (with wait=False) lets the image be written by
-        the next push's first launch (WDD_OUT_DEVICE_DEFERRED)."""
+        the next push's first launch (WDD_OUT_DEVICE_DEFERRED; with pipeline=True, by the push
+        after next)."""
         pos, n, ptr, on_dev, keep = self._frames_arg(frames, positions)
         if out is not None and out is self._pinned:
             res = out

@@ -188,10 +188,17 @@ bool can_defer(const wdd_plan_s* p) {
 
 bool can_defer_to_update(const wdd_plan_s* p) { return p->up_valid && p->up_alt && p->d0w; }
 
-// Writes a display left to the next push now; every call that waits for the plan's stream
-// or changes its state goes through here first (D has not changed since the display was
-// queued, so p->d gives its D[0]).
+wdd_status run_held(wdd_plan_s* p, const wdd::ProjectLaunch* next, bool for_display);
+
+// Runs a held update (pipelined pushes) and writes a display left to the next push now;
+// every call that waits for the plan's stream or reads or changes its state goes through here
+// first (D has not changed since a display kept for the projection was queued, so p->d gives
+// its D[0]; one kept for the update reads its own copy of D[0]).
 wdd_status flush_deferred(wdd_plan_s* p) {
+  if (p->held.live) {
+    const wdd_status st = run_held(p, nullptr, false);
+    if (st != WDD_OK) return st;
+  }
   if (!p->deferred_dst) return WDD_OK;
   float2* dst = p->deferred_dst;
   p->deferred_dst = nullptr;
@@ -234,6 +241,14 @@ std::vector<float2> twiddles(int32_t n, double scale) {
 }  // namespace
 static wdd_status upload_wiener(wdd_plan_s* p, const wdd_tables_s& t);
 namespace {
+
+// pos, order, xs and rows: views of the device upload block `upload`
+void set_upload_views(wdd_plan_s* p) {
+  p->pos = reinterpret_cast<int2*>(p->upload);
+  p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
+  p->xs = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 12);
+  p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 16 + 15) / 16 * 16);
+}
 
 wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts, void* stream) {
   p->sy = t.sy; p->sx = t.sx; p->ny = t.ny; p->nx = t.nx; p->k = t.k; p->l = t.l;
@@ -351,17 +366,20 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   }
   p->upload_bytes = (size_t)p->max_batch * 16 + 16 + (size_t)p->max_batch * sizeof(int4);
   ALLOC(p->upload, p->upload_bytes);
-  p->pos = reinterpret_cast<int2*>(p->upload);
-  p->order = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 8);
-  p->xs = reinterpret_cast<int32_t*>(p->upload + (size_t)p->max_batch * 12);
-  p->rows = reinterpret_cast<int4*>(p->upload + ((size_t)p->max_batch * 16 + 15) / 16 * 16);
+  set_upload_views(p);
   if (p->order_mode == WDD_ORDER_SPECTRUM || p->fourier) ALLOC(p->t, (size_t)kFactorRows * t.sx * p->kpad);
   if (p->order_mode == WDD_ORDER_OBJECT && !p->fourier) {
     ALLOC(p->jv, jlist.size());
     ALLOC(p->chunks, chunks.size());
   }
+  if (p->pipeline && !partial_rows)
+    return wdd::fail(WDD_EINVAL, "pipelined pushes need power-of-two scan sides with Sy <= %d", wdd::kDisplayRowMax);
+  if (p->pipeline) {
+    ALLOC(p->h_alt, (size_t)p->max_batch * p->kpad);
+    ALLOC(p->upload_alt, p->upload_bytes);
+  }
   if (partial_rows) ALLOC(p->up, (size_t)t.sx * p->nslot * t.sy);
-  if (partial_rows && t.ny > 128) {  // see can_defer
+  if (partial_rows && (t.ny > 128 || p->pipeline)) {  // see can_defer
     ALLOC(p->up_alt, (size_t)t.sx * p->nslot * t.sy);
     ALLOC(p->d0w, 2);
     p->d0w_alt = p->d0w + 1;
@@ -416,6 +434,7 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->d), (size_t)p->n_freq_pad * 2, p->stream));
   if (p->dlo) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
+  if (p->h_alt) WDD_HIP(p, wdd::launch_zero(p->h_alt, (size_t)p->max_batch * p->kpad, p->stream));
 
   {
     const size_t slot_bytes = p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t);
@@ -457,6 +476,13 @@ wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) 
     return wdd::fail(WDD_EINVAL, "unknown basis %d", opts.basis);
   if (opts.basis == WDD_BASIS_FOURIER && opts.precision != WDD_FP32)
     return wdd::fail(WDD_EINVAL, "the Fourier basis runs in FP32 only");
+  if (opts.pipeline != 0 && opts.pipeline != 1) return wdd::fail(WDD_EINVAL, "pipeline must be 0 or 1");
+  if (opts.pipeline &&
+      (opts.order != WDD_ORDER_OBJECT || opts.basis != WDD_BASIS_HERMITE_GAUSS || !det ||
+       !wdd::row_fused_next_supported(det->dtype, opts.precision, det->ny, det->nx, 256)))
+    return wdd::fail(WDD_EINVAL,
+                     "pipelined pushes need object order, the Hermite-Gauss basis, FP32 precision and uint16 "
+                     "frames of at most 256 rows and 32..256 columns in multiples of 32");
   return WDD_OK;
 }
 
@@ -484,8 +510,9 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
     // partial display rows (at most kMaxSlots per v_x), a second set and D[0] copies for
     // detectors of more than 128 rows
     const int64_t up = a(grid * wdd::kMaxSlots * 8);
-    b += t.ny > 128 ? 2 * up + a(16) : up;
+    b += t.ny > 128 || opts.pipeline ? 2 * up + a(16) : up;
   }
+  if (opts.pipeline) b += a(mb * kpad * 4) + a(mb * 16 + 16 + mb * 16);  // h_alt, upload_alt
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
 }
@@ -517,6 +544,7 @@ wdd_status plan_create_from_tables(std::shared_ptr<const wdd_tables_s> tp, const
   p->precision = opts.precision;
   p->order_mode = opts.order;
   p->fourier = t.basis == WDD_BASIS_FOURIER;
+  p->pipeline = opts.pipeline != 0;
   p->probe = *probe;
   p->scan = *scan;
   p->det = *det;
@@ -561,6 +589,100 @@ wdd_status wdd_plan(const wdd_probe* probe, const wdd_scan* scan, const wdd_dete
 }  // extern "C"
 
 namespace {
+
+// After the launch that read this push's pinned data (its projection): the upload block may
+// be refilled once the stream passes this point, and so may the host-frame staging slot fs.
+wdd_status mark_push(wdd_plan_s* p, int64_t push_no, int fs) {
+  if (push_no % p->mark_every == p->mark_every - 1) {
+    const size_t m = (size_t)(push_no / p->mark_every) % p->marks.size();
+    WDD_HIP(p, hipEventRecord(p->marks[m], p->stream));
+    p->mark_at[m] = push_no;
+  }
+  if (fs >= 0) {
+    WDD_HIP(p, hipEventRecord(p->fev[fs], p->stream));
+    p->fev_live[fs] = true;
+  }
+  return WDD_OK;
+}
+
+// The object-order update of one batch (Section 6.3, modified-WDD algorithm, the loop body
+// with the Wiener filter applied per frame): passes of at most kFactorRows of its scan rows,
+// each adding to D, the x-DFT fused in.  With rows_for_display the last pass also leaves the
+// display's first pass in `up`.  A deferred column pass kept for the update rides in the
+// first launch, and so does `next`, the projection of the following batch (pipelined
+// pushes), when given.
+wdd_status object_update(wdd_plan_s* p, const int4* rows, int nrows, bool in_order, bool rows_for_display,
+                         const wdd::ProjectLaunch* next) {
+  hipEvent_t end;
+  if (rows_for_display && p->up_alt) {  // keep the previous push's rows for a display still to come
+    std::swap(p->up, p->up_alt);
+    std::swap(p->d0w, p->d0w_alt);
+  }
+  for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
+    const int nr = std::min(kFactorRows, nrows - r0);
+    const bool last = r0 + kFactorRows >= nrows;
+    float2* up_pass = rows_for_display && last ? p->up : nullptr;
+    float2* d0out = up_pass && p->up_alt ? p->d0w : nullptr;
+    // the previous step's column pass, left to this launch (reads what that push kept)
+    wdd::DisplayColumns dc;
+    const bool carry = r0 == 0 && p->deferred_dst && p->deferred_in_update;
+    if (carry) {
+      dc.din = p->deferred_src;
+      dc.dout = p->deferred_dst;
+      dc.rows = p->sy;
+      dc.len = p->sx;
+      dc.e = p->ex;
+      dc.d0 = p->deferred_d0;
+      dc.s_total = (float)((double)p->sy * p->sx);
+      dc.in_sr = p->deferred_sr;
+      dc.in_sm = p->deferred_sm;
+      dc.out_sr = p->sx;
+      dc.out_sc = 1;
+      dc.nslot = p->deferred_nslot;
+      dc.slot_stride = p->deferred_slot_stride;
+      p->deferred_dst = nullptr;
+      p->deferred_in_update = false;
+    }
+    if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
+    WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+    wdd::RowSet rs;
+    for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? rows[r0 + i] : make_int4(0, 0, 0, 0);
+    if (r0 == 0 && next)
+      WDD_HIP(p, wdd::launch_row_fused_obj_next(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
+                                                p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z,
+                                                up_pass, p->nslot, in_order, d0out, carry ? &dc : nullptr, *next,
+                                                p->stream));
+    else
+      WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
+                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z,
+                                           up_pass, p->nslot, in_order, d0out, carry ? &dc : nullptr, p->stream));
+    WDD_HIP(p, stage_end(p, end));
+  }
+  p->up_valid = rows_for_display;
+  return WDD_OK;
+}
+
+// Runs the held batch's update (pipelined pushes), with `next` in its first launch when
+// given.  It leaves the display's first pass in `up` when a deferred snapshot followed the
+// batch (whose column pass then waits for the next launch, as a deferred display kept for
+// the update) or when for_display asks for it.
+wdd_status run_held(wdd_plan_s* p, const wdd::ProjectLaunch* next, bool for_display) {
+  wdd_plan_s::Held& hd = p->held;
+  hd.live = false;
+  const bool rows = (hd.display || for_display) && p->up;
+  wdd_status st = object_update(p, hd.rows.data(), (int)hd.rows.size(), hd.in_order, rows, next);
+  if (st != WDD_OK) return st;
+  if (hd.display_dst) {
+    p->deferred_dst = hd.display_dst;
+    column_source(p, &p->deferred_src, &p->deferred_sr, &p->deferred_sm, &p->deferred_nslot,
+                  &p->deferred_slot_stride);
+    p->deferred_in_update = true;
+    p->deferred_d0 = p->d0w;
+    hd.display_dst = nullptr;
+  }
+  hd.display = false;
+  return WDD_OK;
+}
 
 // Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
 // reduction of the updated spectrum; *fused reports whether it did.
@@ -656,14 +778,10 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   if (p->fourier || (p->deferred_in_update && !object)) {  // see can_defer
     if ((st = flush_deferred(p)) != WDD_OK) return st;
   }
-  WDD_HIP(p, stage_begin(p, kProject, &end));
-  // the projection launch also brings the pinned upload block (positions, grouping) to the device
-  if (p->fourier) {
-    WDD_HIP(p, wdd::launch_project_fourier(p->dtype, fdev, n, p->ny, p->nx, p->fy, p->fx,
-                                           reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
-                                           p->stream));
-  } else {
-    wdd::ProjectLaunch pl;
+  bool in_order = true;  // frames already grouped by row (a raster batch): no reordering
+  for (int32_t i = 0; i < n && in_order; ++i) in_order = ord[i] == i;
+  wdd::ProjectLaunch pl;
+  if (!p->fourier) {
     pl.dtype = p->dtype;
     pl.precision = p->precision;
     pl.frames = fdev;
@@ -675,45 +793,66 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     pl.psi_unscale = p->psi_unscale;
     pl.kmap = p->kmap;
     pl.kpad = p->kpad;
-    pl.h = p->h;
+    pl.h = p->pipeline ? p->h_alt : p->h;
     pl.up_src = up;
-    pl.up_dst = p->upload;
+    pl.up_dst = p->pipeline ? p->upload_alt : p->upload;
     pl.up_bytes = up_bytes;
     pl.fptr = ftab;
-    if (p->deferred_dst && !p->deferred_in_update) {
-      // the previous step's column pass rides in this launch (it reads its source and D
-      // before this push's update changes them)
-      wdd::DisplayColumns dc;
-      dc.din = p->deferred_src;
-      dc.dout = p->deferred_dst;
-      dc.rows = p->sy;
-      dc.len = p->sx;
-      dc.e = p->ex;
-      dc.d0 = p->d;
-      dc.s_total = (float)((double)p->sy * p->sx);
-      dc.in_sr = p->deferred_sr;
-      dc.in_sm = p->deferred_sm;
-      dc.out_sr = p->sx;
-      dc.out_sc = 1;
-      dc.nslot = p->deferred_nslot;
-      dc.slot_stride = p->deferred_slot_stride;
-      p->deferred_dst = nullptr;
-      WDD_HIP(p, wdd::launch_project_display(pl, dc, p->stream));
+  }
+  if (p->pipeline) {
+    // the held batch's update, with this batch's projection in its first launch (or the
+    // projection alone when nothing is held); this batch's update is held in turn
+    if (p->held.live) {
+      if ((st = run_held(p, &pl, false)) != WDD_OK) return st;
     } else {
+      WDD_HIP(p, stage_begin(p, kProject, &end));
       WDD_HIP(p, wdd::launch_project(pl, p->stream));
+      WDD_HIP(p, stage_end(p, end));
     }
+    if ((st = mark_push(p, push_no, fs)) != WDD_OK) return st;
+    std::swap(p->h, p->h_alt);
+    std::swap(p->upload, p->upload_alt);
+    set_upload_views(p);
+    p->held.live = true;
+    p->held.in_order = in_order;
+    p->held.rows.assign(p->host_rows.begin(), p->host_rows.end());
+    p->held.display = false;
+    p->held.display_dst = nullptr;
+    if (fused) *fused = true;
+    p->frames_seen += (uint64_t)n;
+    p->last_batch = n;
+    return WDD_OK;
+  }
+  WDD_HIP(p, stage_begin(p, kProject, &end));
+  // the projection launch also brings the pinned upload block (positions, grouping) to the device
+  if (p->fourier) {
+    WDD_HIP(p, wdd::launch_project_fourier(p->dtype, fdev, n, p->ny, p->nx, p->fy, p->fx,
+                                           reinterpret_cast<float2*>(p->h), p->kpad, up, p->upload, up_bytes, ftab,
+                                           p->stream));
+  } else if (p->deferred_dst && !p->deferred_in_update) {
+    // the previous step's column pass rides in this launch (it reads its source and D
+    // before this push's update changes them)
+    wdd::DisplayColumns dc;
+    dc.din = p->deferred_src;
+    dc.dout = p->deferred_dst;
+    dc.rows = p->sy;
+    dc.len = p->sx;
+    dc.e = p->ex;
+    dc.d0 = p->d;
+    dc.s_total = (float)((double)p->sy * p->sx);
+    dc.in_sr = p->deferred_sr;
+    dc.in_sm = p->deferred_sm;
+    dc.out_sr = p->sx;
+    dc.out_sc = 1;
+    dc.nslot = p->deferred_nslot;
+    dc.slot_stride = p->deferred_slot_stride;
+    p->deferred_dst = nullptr;
+    WDD_HIP(p, wdd::launch_project_display(pl, dc, p->stream));
+  } else {
+    WDD_HIP(p, wdd::launch_project(pl, p->stream));
   }
   WDD_HIP(p, stage_end(p, end));
-  // the pinned data of this push may be refilled once this point of the stream is reached
-  if (push_no % p->mark_every == p->mark_every - 1) {
-    const size_t m = (size_t)(push_no / p->mark_every) % p->marks.size();
-    WDD_HIP(p, hipEventRecord(p->marks[m], p->stream));
-    p->mark_at[m] = push_no;
-  }
-  if (fs >= 0) {
-    WDD_HIP(p, hipEventRecord(p->fev[fs], p->stream));
-    p->fev_live[fs] = true;
-  }
+  if ((st = mark_push(p, push_no, fs)) != WDD_OK) return st;
   bool wiener_done = object;
   if (p->fourier) {
     // complex per-row x-DFTs, then one update per pass of at most kFactorRows rows; the
@@ -736,50 +875,9 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
       WDD_HIP(p, stage_end(p, end));
     }
   } else if (object) {
-    // x-DFT fused into the update, in passes of at most kFactorRows rows, each adding to D;
     // before a snapshot the last pass also leaves the display's first pass in `up`
-    const bool rows_for_display = fuse_wiener && p->up;
-    bool in_order = true;  // frames already grouped by row (a raster batch): no reordering
-    for (int32_t i = 0; i < n && in_order; ++i) in_order = ord[i] == i;
-    if (rows_for_display && p->up_alt) {  // keep the previous push's rows for a display still to come
-      std::swap(p->up, p->up_alt);
-      std::swap(p->d0w, p->d0w_alt);
-    }
-    for (int r0 = 0; r0 < nrows; r0 += kFactorRows) {
-      const int nr = std::min(kFactorRows, nrows - r0);
-      const bool last = r0 + kFactorRows >= nrows;
-      float2* up_pass = rows_for_display && last ? p->up : nullptr;
-      float2* d0out = up_pass && p->up_alt ? p->d0w : nullptr;
-      // the previous step's column pass, left to this launch (reads what that push kept)
-      wdd::DisplayColumns dc;
-      const bool carry = r0 == 0 && p->deferred_dst && p->deferred_in_update;
-      if (carry) {
-        dc.din = p->deferred_src;
-        dc.dout = p->deferred_dst;
-        dc.rows = p->sy;
-        dc.len = p->sx;
-        dc.e = p->ex;
-        dc.d0 = p->deferred_d0;
-        dc.s_total = (float)((double)p->sy * p->sx);
-        dc.in_sr = p->deferred_sr;
-        dc.in_sm = p->deferred_sm;
-        dc.out_sr = p->sx;
-        dc.out_sc = 1;
-        dc.nslot = p->deferred_nslot;
-        dc.slot_stride = p->deferred_slot_stride;
-        p->deferred_dst = nullptr;
-        p->deferred_in_update = false;
-      }
-      if ((p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
-      WDD_HIP(p, stage_begin(p, kAccumulate, &end));
-      wdd::RowSet rs;
-      for (int i = 0; i < wdd::kRowSetMax; ++i) rs.r[i] = i < nr ? p->host_rows[r0 + i] : make_int4(0, 0, 0, 0);
-      WDD_HIP(p, wdd::launch_row_fused_obj(p->h, p->kpad, p->order, p->xs, rs, nr, p->tscale, p->sx, p->sy,
-                                           p->chunks, p->nchunks, p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z, up_pass,
-                                           p->nslot, in_order, d0out, carry ? &dc : nullptr, p->stream));
-      WDD_HIP(p, stage_end(p, end));
-    }
-    p->up_valid = rows_for_display;
+    if ((st = object_update(p, p->host_rows.data(), nrows, in_order, fuse_wiener && p->up, nullptr)) != WDD_OK)
+      return st;
   } else if (factored) {
     // per-row x-DFTs, then one pass over A (with the Wiener reduction when asked)
     wiener_done = fuse_wiener;
@@ -806,8 +904,17 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
 // Queues the display step (optionally after the Wiener reduction) writing to `out`.
 wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_device, bool reduce) {
   hipEvent_t end;
-  wdd_status st = flush_deferred(p);
-  if (st != WDD_OK) return st;
+  wdd_status st;
+  if (p->held.live) {
+    if (out_on_device == WDD_OUT_DEVICE_DEFERRED && !p->held.display_dst) {
+      // pipelined: the held update will leave the partial rows, the launch after it the image
+      p->held.display = true;
+      p->held.display_dst = reinterpret_cast<float2*>(out);
+      return WDD_OK;
+    }
+    if ((st = run_held(p, nullptr, true)) != WDD_OK) return st;  // the partial rows for this display
+  }
+  if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (reduce && p->order_mode == WDD_ORDER_SPECTRUM) {  // object order keeps D current
     WDD_HIP(p, stage_begin(p, kWiener, &end));
     WDD_HIP(p, wdd::launch_wiener(p->acc, p->w, p->kpad, p->freqs, p->n_freq, p->d, p->z, p->sy, p->stream));
@@ -828,11 +935,13 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
   const float2* src;
   int32_t sr, sm, nslot, slot_stride;
   column_source(p, &src, &sr, &sm, &nslot, &slot_stride);
-  if (out_on_device == WDD_OUT_DEVICE_DEFERRED && (can_defer(p) || can_defer_to_update(p))) {
+  // (pipelined pushes have no projection launch to carry it: only the update's)
+  if (out_on_device == WDD_OUT_DEVICE_DEFERRED &&
+      (p->pipeline ? can_defer_to_update(p) : can_defer(p) || can_defer_to_update(p))) {
     p->deferred_dst = dst;
     p->deferred_src = src, p->deferred_sr = sr, p->deferred_sm = sm, p->deferred_nslot = nslot;
     p->deferred_slot_stride = slot_stride;
-    p->deferred_in_update = !can_defer(p);
+    p->deferred_in_update = p->pipeline || !can_defer(p);
     p->deferred_d0 = p->deferred_in_update ? p->d0w : p->d;
   } else if ((st = column_pass(p, src, sr, sm, nslot, slot_stride, dst)) != WDD_OK) {
     return st;
@@ -1036,6 +1145,7 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info) {
   info->device_bytes = p->device_bytes;
   info->update_chunks = p->nchunks;
   info->display_slots = p->up ? p->nslot : 0;
+  info->pipelined = p->pipeline ? 1 : 0;
   return WDD_OK;
 }
 

@@ -184,6 +184,15 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
                                 float2* up, int nslot, bool in_order, float2* d0out, const DisplayColumns* dc,
                                 hipStream_t st);
 
+// launch_row_fused_obj with the projection `next` (a batch of the same plan, written to its own
+// h and upload block) in the same launch; next.n >= 1 and row_fused_next_supported.
+bool row_fused_next_supported(int dtype, int precision, int ny, int nx, int kpad);
+hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
+                                     int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                     int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo,
+                                     float2* z, float2* up, int nslot, bool in_order, float2* d0out,
+                                     const DisplayColumns* dc, const ProjectLaunch& next, hipStream_t st);
+
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
 // = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,
 // fy/fx = exp(+2 pi i m / n) for m < n / 2.  Row DFT: t[r][vx][k] = sum over the frames of

@@ -292,6 +292,115 @@ __device__ __forceinline__ void project_frame_tile(const T* __restrict__ frames,
   }
 }
 
+// project_frame_tile for workgroups with fewer waves than tiles (k_row_fused_obj_next's 8
+// waves): wave w takes the 16-row tiles w, w + nw, ..., each with all of its frame loads
+// issued before its MFMAs; frames of nx <= 32 NCH columns (FULL: nx = 32 NCH, no clamps).  Every frame
+// load is unconditional (indices clamped into the frame; lanes outside the frame get zero by
+// a select after their load), so the wait before chunk c's MFMAs counts exactly the later
+// loads of the tile: the MFMAs of early chunks run while the later chunks are still
+// arriving.  (Loads under a branch make the compiler wait for every load in flight before
+// the first use of any of them.)
+template <typename T, int NCH, bool FULL>
+__device__ __forceinline__ void project_frame_tiles(const T* __restrict__ frames, int ny, int nx,
+                                                   const float* __restrict__ psi, const int* __restrict__ kmap,
+                                                   int kpad, float* __restrict__ h, const uint64_t* __restrict__ fptr,
+                                                   float* smem, int b) {
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
+  const int nxp = nx + 4;
+  float* lpsxt = smem;                   // [16][nxp]: psi_x transposed
+  float* lg = lpsxt + 16 * nxp;          // [nw][256]: per-wave G
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T* f = fptr ? reinterpret_cast<const T*>(fptr[b]) : frames + (size_t)b * ny * nx;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int ntiles = (ny + 15) >> 4;
+  const int nsx = 16 * nx;
+  // Only psi_x goes through LDS (every wave reads all of it).  The kmap entries of the
+  // epilogue are loaded into registers here, the 4 psi_y values of a lane's stage-2 rows
+  // after each tile's frame loads.
+  float vx[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) vx[u] = gload(psi + (size_t)ny * 16 + min(u * nt + tid, nsx - 1));
+  int km[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) km[u] = gload(kmap + min(u * nt + tid, kpad - 1));
+  // The table reaches LDS, and the workgroup synchronises, before any frame load is issued: a
+  // barrier after the frame loads would hold every wave's MFMAs until all waves had issued
+  // all their loads (issue stalls while the memory pipeline is full), so that no MFMA could
+  // overlap the frame's arrival.  Every lane stores (lanes past the table write to their own
+  // slot of the per-wave G area, which is written again after the MFMAs).
+  float* spare = lg + tid;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = u * nt + tid;
+    float* dst = i < nsx ? lpsxt + (i & 15) * nxp + (i >> 4) : spare;
+    *dst = vx[u];
+  }
+  __syncthreads();
+  floatx4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int t = wave; t < ntiles; t += nw) {
+    // the basis row's offset passes through an empty asm statement: otherwise its LDS reads,
+    // the same for every tile, are hoisted out of the loop and held in 64 registers
+    int boff = r16 * nxp + (FULL ? 8 * q : 0);
+    asm volatile("" : "+v"(boff));
+    const float* brow = lpsxt + boff;
+    const int y = t * 16 + r16;
+    const bool row_ok = y < ny;
+    // FULL (nx = 32 NCH): chunk c of the lane's row starts 32 c past its first pixel, no clamps
+    const T* rowp = f + (size_t)min(y, ny - 1) * nx + (FULL ? 8 * q : 0);
+    Chunk<T> ch[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) ch[c].load(FULL ? rowp + 32 * c : rowp + min(32 * c + 8 * q, nx - 8));
+    float av[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = gload(psi + (size_t)min(t * 16 + 4 * q + r, ny - 1) * 16 + r16);
+    // all of the tile's loads go out before any MFMA: without this fence the scheduler moves
+    // each chunk's load next to its first use, and every chunk waits for its own round trip
+    __builtin_amdgcn_sched_barrier(0);
+
+    floatx4 tacc = {0.f, 0.f, 0.f, 0.f}, tacc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int xs = 32 * c + 8 * q;
+      ch[c].keep_if(FULL ? row_ok : row_ok && xs < nx);
+      // a valid table column; the zeroed pixels cancel it
+      const int xb = FULL ? 32 * c : min(xs, nx - 8);
+      const float4 b0 = *reinterpret_cast<const float4*>(brow + xb);
+      const float4 b1 = *reinterpret_cast<const float4*>(brow + xb + 4);
+      tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(0), b0.x, tacc, 0, 0, 0);
+      tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(1), b0.y, tacc2, 0, 0, 0);
+      tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(2), b0.z, tacc, 0, 0, 0);
+      tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(3), b0.w, tacc2, 0, 0, 0);
+      tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(4), b1.x, tacc, 0, 0, 0);
+      tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(5), b1.y, tacc2, 0, 0, 0);
+      tacc = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(6), b1.z, tacc, 0, 0, 0);
+      tacc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ch[c].get(7), b1.w, tacc2, 0, 0, 0);
+      // one chunk's basis values at a time (left free, the scheduler reads them all first)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tacc += tacc2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float a = (t * 16 + 4 * q + r < ny) ? av[r] : 0.f;
+      g = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tacc[r], g, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lg[wave * 256 + (4 * q + r) * 16 + r16] = g[r];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = u * nt + tid;
+    if (k < kpad) {
+      const int idx = km[u];
+      float sum = 0.f;
+      if (idx >= 0)
+        for (int w = 0; w < nw; ++w) sum += lg[w * 256 + idx];
+      h[(size_t)b * kpad + k] = sum;
+    }
+  }
+}
+
 // Whether project_frame_tile applies: one tile per wave, at most 256 columns, psi_x within
 // 8 loads per thread, kmap within 4.
 __host__ __device__ inline bool project_tile_form(int ny, int nx, int nw, int kpad) {
@@ -1540,6 +1649,68 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                      in_order, d0out, fsm);
 }
 
+// The object-order update of one batch with the projection of the next batch in the same
+// launch.  The two are independent (the update reads its own batch's projections and upload
+// block, the projection writes the next batch's into other buffers), so the projection's
+// frame stream from HBM overlaps the update's phases that leave HBM idle (the first, which
+// reads the projections from L2, and the partial display rows), and the launch boundary
+// between them goes away.  Workgroups [pfirst, pfirst + pa.n) project frames 0 .. pa.n - 1
+// (512 threads: up to two 16-row tiles per wave), workgroup pfirst + pa.n copies the upload
+// block when there is one; the others, in order, are the update's chunks and then the
+// display rows of k_row_fused_obj.
+// Where k_row_fused_obj_next's projection workgroups sit in its grid: 0 first, 1 after the
+// update's chunks, 2 after the display rows (last).  After the chunks: they start as the
+// first chunks finish their first phase.  Measured per pipelined step (first / after the
+// chunks / last): 512^2 scan, 256^2 frames 37.5 / 36.1 / 44.2 us; 256^2 scan, 128^2 frames
+// 15.2 / 13.6 / 14.6 us; 128^2 scan, 64^2 frames 12.2 / 12.3 / 12.3 us.
+constexpr int kNextProjFirst = 1;
+
+// The projection of k_row_fused_obj_next: frames of nx = 32 NCH columns (1 <= NCH <= 8) and at
+// most 256 rows (two 16-row tiles per wave), checked by its launcher.
+template <typename T>
+__device__ __forceinline__ void project_next(const ProjArgs& a, float* smem, int b) {
+  const T* fr = static_cast<const T*>(a.frames);
+  switch (a.nx >> 5) {
+    case 1: project_frame_tiles<T, 1, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 2: project_frame_tiles<T, 2, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 3: project_frame_tiles<T, 3, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 4: project_frame_tiles<T, 4, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 5: project_frame_tiles<T, 5, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 6: project_frame_tiles<T, 6, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    case 7: project_frame_tiles<T, 7, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+    default: project_frame_tiles<T, 8, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_row_fused_obj_next(
+    const float* __restrict__ h, int kpad, const int* __restrict__ order, const int* __restrict__ xs, RowSet rs,
+    int nrows, float tscale, int sx, int sy, const int4* __restrict__ chunks, const int2* __restrict__ jv,
+    const float2* __restrict__ w, float2* __restrict__ d, float2* __restrict__ dlo, float2* __restrict__ z,
+    int max_chunk, float2* __restrict__ up, int nslot, int log2sy, int in_order, float2* __restrict__ d0out,
+    int nchunks, DispArgs disp, ProjArgs pa, int pfirst) {
+  extern __shared__ float4 fsm[];
+  int b = (int)blockIdx.x;
+  const int nproj = pa.n + (pa.up_words > 0 ? 1 : 0);
+  if (b >= pfirst && b < pfirst + nproj) {
+    if (b - pfirst == pa.n)
+      upload_block(pa.up_src, pa.up_dst, pa.up_words, (int)threadIdx.x, kFusedThreads);
+    else
+      project_next<T>(pa, reinterpret_cast<float*>(fsm), b - pfirst);
+    return;
+  }
+  if (b >= pfirst) b -= nproj;
+  if (b >= nchunks) {
+    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
+                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nchunks,
+                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+    return;
+  }
+  const int4 ch = chunks[xcd_row(b, nchunks)];
+  row_fused_obj_body(h, kpad, order, xs, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
+                     in_order, d0out, fsm);
+}
+
 // Row passes of several object-order updates in one launch: workgroup b takes work item
 // items[b] = (pass, v_x, first jv index, count | slot << 16) of the pass descriptors
 // (each a row pass of one plan's frames: its own D, tables, rows and frame lists).
@@ -2113,27 +2284,34 @@ size_t row_fused_lds_bytes(int kpad, int nrows, int max_chunk) {
          (size_t)max_chunk * 16;
 }
 
-hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
-                                int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
-                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
-                                float2* up, int nslot, bool in_order, float2* d0out, const DisplayColumns* dc,
-                                hipStream_t st) {
+namespace {
+
+// Shared checks and set-up of the object-order update launches: the dynamic LDS, the display
+// rows' arguments (dc null: none) and log2 Sy for the partial rows.
+struct FusedSetup {
+  size_t lds;
+  DispArgs da;
+  int rows_disp;
+  int log2sy;
+};
+hipError_t fused_setup(int kpad, int nrows, int sy, int nchunks, int max_chunk, const float2* up, int nslot,
+                       const DisplayColumns* dc, FusedSetup* fs) {
   if (nrows < 1 || nrows > kRowSetMax || nchunks < 1 || max_chunk < 1 || max_chunk > kFusedThreads)
     return hipErrorInvalidValue;
-  int log2sy = 0;
+  fs->log2sy = 0;
   if (up) {  // the partial rows need a power-of-two Sy whose row and twiddles fit the group-sum buffer
-    while ((1 << log2sy) < sy) ++log2sy;
-    if ((1 << log2sy) != sy || sy > kDisplayRowMax || nslot < 1 || nslot > kMaxSlots)
+    while ((1 << fs->log2sy) < sy) ++fs->log2sy;
+    if ((1 << fs->log2sy) != sy || sy > kDisplayRowMax || nslot < 1 || nslot > kMaxSlots)
       return hipErrorInvalidValue;
   }
-  size_t lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
-  DispArgs da;
-  std::memset(&da, 0, sizeof(da));
-  int rows_disp = 0;
+  fs->lds = row_fused_lds_bytes(kpad, nrows, max_chunk);
+  std::memset(&fs->da, 0, sizeof(fs->da));
+  fs->rows_disp = 0;
   if (dc) {
     int lg = 0;
     while ((1 << lg) < dc->len) ++lg;
     if (dc->rows < 1 || (1 << lg) != dc->len || dc->nslot < 1 || dc->nslot > kMaxSlots) return hipErrorInvalidValue;
+    DispArgs& da = fs->da;
     da.din = dc->din;
     da.dout = dc->dout;
     da.len = dc->len;
@@ -2147,15 +2325,54 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
     da.out_sc = dc->out_sc;
     da.nslot = dc->nslot;
     da.slot_stride = dc->slot_stride;
-    rows_disp = dc->rows;
-    lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
+    fs->rows_disp = dc->rows;
+    fs->lds = std::max(fs->lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
   }
-  if (lds > kLdsBytes) return hipErrorInvalidValue;
-  const hipError_t e = allow_full_lds<k_row_fused_obj>();
+  if (fs->lds > kLdsBytes) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
+                                int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo, float2* z,
+                                float2* up, int nslot, bool in_order, float2* d0out, const DisplayColumns* dc,
+                                hipStream_t st) {
+  FusedSetup fs;
+  hipError_t e = fused_setup(kpad, nrows, sy, nchunks, max_chunk, up, nslot, dc, &fs);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks + rows_disp), dim3(kFusedThreads), lds, st, h, kpad, order, xs,
-                     rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
-                     in_order ? 1 : 0, d0out, nchunks, da);
+  if ((e = allow_full_lds<k_row_fused_obj>()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_fused_obj, dim3(nchunks + fs.rows_disp), dim3(kFusedThreads), fs.lds, st, h, kpad, order,
+                     xs, rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up, nslot, fs.log2sy,
+                     in_order ? 1 : 0, d0out, nchunks, fs.da);
+  return hipGetLastError();
+}
+
+bool row_fused_next_supported(int dtype, int precision, int ny, int nx, int kpad) {
+  return dtype == WDD_U16 && precision == WDD_FP32 && nx % 32 == 0 && nx >= 32 && nx <= 256 && ny >= 1 &&
+         ny <= 2 * 16 * (kFusedThreads / 64) && kpad <= 4 * kFusedThreads &&
+         project_lds_floats(ny, nx, kFusedThreads / 64, kpad) * sizeof(float) <= kLdsBytes;
+}
+
+hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
+                                     int nrows, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                     int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo,
+                                     float2* z, float2* up, int nslot, bool in_order, float2* d0out,
+                                     const DisplayColumns* dc, const ProjectLaunch& next, hipStream_t st) {
+  if (next.n < 1 || next.kpad != kpad || !row_fused_next_supported(next.dtype, next.precision, next.ny, next.nx, kpad))
+    return hipErrorInvalidValue;
+  FusedSetup fs;
+  hipError_t e = fused_setup(kpad, nrows, sy, nchunks, max_chunk, up, nslot, dc, &fs);
+  if (e != hipSuccess) return e;
+  const size_t lds = std::max(fs.lds, project_lds_floats(next.ny, next.nx, kFusedThreads / 64, kpad) * sizeof(float));
+  if ((e = allow_full_lds<k_row_fused_obj_next<uint16_t>>()) != hipSuccess) return e;
+  const ProjArgs pa = proj_args(next);
+  const int nproj = next.n + (pa.up_words > 0 ? 1 : 0);
+  const int pfirst = kNextProjFirst == 0 ? 0 : kNextProjFirst == 1 ? nchunks : nchunks + fs.rows_disp;
+  hipLaunchKernelGGL(k_row_fused_obj_next<uint16_t>, dim3(nchunks + fs.rows_disp + nproj), dim3(kFusedThreads), lds,
+                     st, h, kpad, order, xs, rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up,
+                     nslot, fs.log2sy, in_order ? 1 : 0, d0out, nchunks, fs.da, pa, pfirst);
   return hipGetLastError();
 }
 

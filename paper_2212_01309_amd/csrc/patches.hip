@@ -116,6 +116,7 @@ wdd_status wdd_patches_create(const wdd_probe* probe, const wdd_scan* scan, cons
   if (opts.basis != WDD_BASIS_HERMITE_GAUSS)
     return wdd::fail(WDD_EINVAL, "field-of-view patches use the Hermite-Gauss basis");
   opts.order = WDD_ORDER_OBJECT;  // the grouped update accumulates each patch's D
+  opts.pipeline = 0;              // the patch set orders its own launches
   wdd_status st = wdd::check_plan_options(det, opts);
   if (st != WDD_OK) return st;
   wdd_patches_s* s = new (std::nothrow) wdd_patches_s();

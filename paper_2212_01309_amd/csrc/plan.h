@@ -83,6 +83,20 @@ struct wdd_plan_impl {
   float2* deferred_dst = nullptr;
   const float2* deferred_src = nullptr;
   int32_t deferred_sr = 0, deferred_sm = 0, deferred_nslot = 1, deferred_slot_stride = 0;
+  // pipelined pushes (wdd_options.pipeline): the update of the last pushed batch is held
+  // (`held`) and runs in the next push's launch beside that push's projection, which writes
+  // the next batch's projections and upload block to h_alt / upload_alt (swapped with h /
+  // upload after each push: h and upload always hold the held batch's)
+  bool pipeline = false;
+  float* h_alt = nullptr;
+  char* upload_alt = nullptr;
+  struct Held {
+    bool live = false;
+    bool in_order = true;
+    std::vector<int4> rows;       // the batch's scan rows (y, first, count), row-sorted order
+    bool display = false;         // a deferred snapshot follows the batch
+    float2* display_dst = nullptr;
+  } held;
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
   float2* dlo = nullptr;  // object order: the rounding remainder of D (D = d + dlo, compensated sum)

@@ -740,6 +740,7 @@ wdd_status wdd_server_open(wdd_server_t s, const wdd_probe* probe, const wdd_sca
   wdd_default_options(&opts);
   if (opts_in) opts = *opts_in;
   opts.max_batch = std::max(opts.max_batch, s->opts.batch_frames);
+  opts.pipeline = 0;  // the server orders each acquisition's launches itself
   wdd_status st = wdd::check_plan_options(det, opts);
   if (st != WDD_OK) return st;
   TableKey key;

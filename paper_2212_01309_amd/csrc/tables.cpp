@@ -372,6 +372,7 @@ wdd_status wdd_default_options(wdd_options* opts) {
   opts->max_batch = 256;
   opts->order = WDD_ORDER_SPECTRUM;
   opts->basis = WDD_BASIS_HERMITE_GAUSS;
+  opts->pipeline = 0;
   return WDD_OK;
 }
 

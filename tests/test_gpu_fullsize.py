@@ -43,16 +43,18 @@ def large_whole_acquisition():
     return wl, pos, pool, all_f, pick, a, d
 
 
-@pytest.mark.parametrize("order", [wdd.WDD_ORDER_OBJECT, wdd.WDD_ORDER_SPECTRUM])
-def test_whole_large_acquisition(large_whole_acquisition, order):
+@pytest.mark.parametrize("order,pipeline", [(wdd.WDD_ORDER_OBJECT, False), (wdd.WDD_ORDER_OBJECT, True),
+                                            (wdd.WDD_ORDER_SPECTRUM, False)])
+def test_whole_large_acquisition(large_whole_acquisition, order, pipeline):
     import torch
     wl, pos, pool, all_f, pick, a_ref, d_ref = large_whole_acquisition
     obj = order == wdd.WDD_ORDER_OBJECT
-    say(f"[fullsize] large, {'object' if obj else 'spectrum'} order: {len(pos)} frames in batches of {wl.batch}")
+    say(f"[fullsize] large, {'object' if obj else 'spectrum'} order{', pipelined' if pipeline else ''}: "
+        f"{len(pos)} frames in batches of {wl.batch}")
     dev = device(pool)
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
     with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, amplitude=wl.aperture_amplitude(), max_batch=wl.batch,
-                  order=order) as plan:
+                  order=order, pipeline=pipeline) as plan:
         for i, b in enumerate(range(0, len(pos), wl.batch)):
             fr = dev[b % POOL:b % POOL + wl.batch]
             if obj:   # the bench's step: push, snapshot into HBM, image finished by the next push

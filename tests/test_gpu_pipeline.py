@@ -1,0 +1,120 @@
+"""Pipelined pushes (wdd_options.pipeline): each batch's object-order update runs in the next
+push's launch beside that push's projection (k_row_fused_obj_next).
+
+Detectors of at most 128 rows give every tile a wave of its own in both projections, so the
+pipelined plan must reproduce the unpipelined one bit for bit: D, every deferred image and
+every inspected state.  Larger detectors (two 16-row tiles per wave in the merged launch)
+sum the projection in another order and are compared with the oracle instead."""
+import numpy as np
+import pytest
+
+import oracle.wdd as O
+import paper_2212_01309_amd as wdd
+from gpu_util import device, rel_d, rel_img, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _case(seed, s, n, count, raster=False):
+    rng = np.random.default_rng(seed)
+    if raster:   # row-major walk: a batch covers one or two scan rows
+        lin = np.arange(count) % (s * s)
+    else:        # scattered: a batch of 64 touches most rows (several update passes)
+        lin = rng.integers(0, s * s, size=count)
+    pos = np.stack([lin // s, lin % s], axis=1).astype(np.int32)
+    frames = rng.poisson(20.0, size=(count, n, n)).astype(np.uint16)
+    return frames, pos
+
+
+@pytest.mark.parametrize("s,n,raster", [(32, 64, False), (32, 64, True), (64, 128, True), (16, 32, False)])
+def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster):
+    """Deferred snapshots after every push, then the calls that must run a held update first
+    (inspection of D and of the last projections, a blocking snapshot, a checkpoint, a reset):
+    everything equals the unpipelined plan bit for bit.  A blocking snapshot right after a
+    push equals the unpipelined wdd_push_snapshot."""
+    import torch
+    b, steps = 64, 9
+    say(f"[pipeline] scan {s}^2, detector {n}^2, {'raster' if raster else 'scattered'} batches of {b}")
+    frames, pos = _case(7 + s + n, s, n, b * (steps + 3), raster)
+    dev = device(frames)
+    blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+    img = lambda: torch.empty((s, s), dtype=torch.complex64, device="cuda")
+    outs = {True: [img() for _ in range(steps)], False: [img() for _ in range(steps)]}
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        assert p.info().pipelined == 1 and r.info().pipelined == 0
+        for i in range(steps):
+            p.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
+            r.push_snapshot(*blk(i), out=outs[False][i], wait=False, defer=True)
+        p.sync()
+        r.sync()
+        for i in range(steps):
+            assert torch.equal(outs[True][i], outs[False][i]), i
+        # held updates run before every call that reads the state
+        for q in (p, r):
+            q.push(*blk(steps))
+        assert np.array_equal(p.spectrum(), r.spectrum())
+        for q in (p, r):
+            q.push(*blk(steps + 1))
+        assert np.array_equal(p.projection(), r.projection())
+        assert np.array_equal(p.snapshot(), r.snapshot())
+        assert p.info().frames_seen == r.info().frames_seen == b * (steps + 2)
+        for q in (p, r):
+            q.push(*blk(steps + 2))
+        assert p.checkpoint() == r.checkpoint()
+        p.reset()
+        r.reset()
+        # a snapshot right after a push: the held update leaves the display's first pass, as
+        # wdd_push_snapshot's update does (not the two-pass display of push + snapshot)
+        p.push(*blk(0))
+        assert np.array_equal(p.snapshot(), r.push_snapshot(*blk(0)))
+
+
+def test_deferred_image_lands_two_pushes_later():
+    """A deferred snapshot after push i: the held update (in push i + 1's launch) leaves its
+    partial rows, push i + 2's launch writes the image; the stream alone then completes it."""
+    import torch
+    s, n, b = 32, 64, 64
+    frames, pos = _case(3, s, n, b * 4)
+    dev = device(frames)
+    blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+    outs = [torch.full((s, s), float("nan"), dtype=torch.complex64, device="cuda") for _ in range(2)]
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        p.push(*blk(0))
+        r.push(*blk(0))
+        p.push_snapshot(*blk(1), out=outs[0], wait=False, defer=True)
+        ref = r.push_snapshot(*blk(1))
+        p.push(*blk(2))
+        p.push(*blk(3))
+        torch.cuda.synchronize()     # no plan call in between: the pushes' launches wrote it
+        assert np.array_equal(outs[0].cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n,raster", [(160, True), (256, False)])
+def test_two_tiles_per_wave_against_the_oracle(n, raster):
+    """Detectors of more than 128 rows: the merged launch's 8 waves take two 16-row tiles each.
+    D and the images against the oracle, and against the unpipelined plan within FP32
+    rounding of the projection's summation order."""
+    import torch
+    s, b, steps, k, radius = 16, 32, 4, 64, 0.3 * n
+    say(f"[pipeline] detector {n}^2 (two tiles per wave), scan {s}^2")
+    frames, pos = _case(11 + n, s, n, b * steps, raster)
+    dev = device(frames)
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    outs = [torch.empty((s, s), dtype=torch.complex64, device="cuda") for _ in range(steps)]
+    with wdd.Plan(radius, s, s, n, n, k, pipeline=True, **kw) as p, wdd.Plan(radius, s, s, n, n, k, **kw) as r:
+        for i in range(steps):
+            p.push_snapshot(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b], out=outs[i], wait=False, defer=True)
+            r.push(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+        p.sync()
+        got_d, ref_d = p.spectrum(), r.spectrum()
+        got_o = outs[-1].cpu().numpy()
+    oplan = O.make_plan(s, s, n, n, radius, k)
+    live = O.Live(oplan, "N")
+    live.push(frames, pos)
+    errs = dict(D=rel_d(got_d, live.spectrum()), O=rel_img(got_o, live.snapshot()), D_vs_unpipelined=rel_d(got_d, ref_d))
+    say(f"[pipeline] errors {errs}")
+    assert errs["D"] <= TOL and errs["O"] <= TOL and errs["D_vs_unpipelined"] <= 1e-6

@@ -92,6 +92,7 @@ def test_default_options():
     assert wdd.load_library().wdd_default_options(ctypes.byref(o)) == 0
     assert o.eps_rel == 0.01 and o.sigma_px == 0.0 and o.max_batch == 256 and o.precision == wdd.WDD_FP32
     assert o.order == wdd.WDD_ORDER_SPECTRUM and o.basis == wdd.WDD_BASIS_HERMITE_GAUSS
+    assert o.pipeline == 0
 
 
 @pytest.mark.parametrize("radius,s,ny,nx,defocus", [
@@ -119,6 +120,36 @@ def test_fourier_plan_rejects_reduced_precision_before_touching_a_device():
     with pytest.raises(wdd.WddError) as ei:
         wdd.Plan(8.0, 16, 16, 32, 32, 1024, basis=wdd.WDD_BASIS_FOURIER, precision=wdd.WDD_BF16_HILO)
     assert ei.value.code == wdd.WDD_EINVAL
+
+
+@pytest.mark.parametrize("kw", [
+    dict(order=wdd.WDD_ORDER_SPECTRUM),                       # the update holds A, not D
+    dict(dtype=wdd.WDD_F32),                                  # uint16 frames only
+    dict(precision=wdd.WDD_BF16_HILO),                        # FP32 projection only
+    dict(nx=48),                                              # columns in multiples of 32
+    dict(nx=288),                                             # at most 256 columns
+    dict(ny=288),                                             # at most 256 rows
+])
+def test_pipelined_plan_rejects_unsupported_settings_before_touching_a_device(kw):
+    """wdd_options.pipeline: the merged update + projection launch exists for object order,
+    FP32 projections of uint16 frames of <= 256 rows and 32..256 columns in multiples of 32."""
+    args = dict(ny=64, nx=64, order=wdd.WDD_ORDER_OBJECT, dtype=wdd.WDD_U16)
+    args.update(kw)
+    ny, nx = args.pop("ny"), args.pop("nx")
+    with pytest.raises(wdd.WddError) as ei:
+        wdd.Plan(8.0, 16, 16, ny, nx, 64, pipeline=True, **args)
+    assert ei.value.code == wdd.WDD_EINVAL
+    assert "pipelined" in str(ei.value)
+
+
+def test_pipeline_option_takes_zero_or_one():
+    o = wdd._options(0.01, 0.0, 256, order=wdd.WDD_ORDER_OBJECT)
+    o.pipeline = 2
+    h = wdd._P()
+    st = wdd.load_library().wdd_plan(ctypes.byref(wdd._probe(8.0, 64, 64, None, 0.0, 1.0)),
+                                     ctypes.byref(wdd.Scan(16, 16, 1.0)), ctypes.byref(wdd.Detector(64, 64, 0)),
+                                     64, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == wdd.WDD_EINVAL and not h.value
 
 
 def test_binding_constants_match_the_header():
