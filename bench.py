@@ -97,7 +97,7 @@ def profile_record(kind, workload, kernel):
     return None
 
 
-def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0.0, pipelined=False):
+def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0.0, pipelined=False, rec=None):
     """Roofline entry of the accumulation kernel (the method's O(S^2 L^2) term and the
     largest kernel of every workload's kernel trace): algorithmic bytes per launch over the
     kernel's average duration from the rocprofv3 kernel trace recorded under profiles/ for
@@ -123,26 +123,27 @@ def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0
         # read and write A, read W (the Wiener reduction fused in before a snapshot)
         nbytes, kernel = 24.0 * n_freq * k, "k_row_update<true>"
         rule = "24 * n_freq * K (A read and written, W read)"
-    trace = profile_record("kernel_trace", wl.name + ("" if order == "object" else "_spectrum"), kernel)
+    rec = rec or wl.name + ("" if order == "object" else "_spectrum")
+    trace = profile_record("kernel_trace", rec, kernel)
     if trace is not None:
         us, source = float(trace["avg_us"]), f"rocprofv3 kernel trace, {trace['file']}"
     else:
         us, source = event_us, "HIP events (untimed stage pass; no kernel trace recorded for this kernel source)"
     ach = nbytes / (us * 1e-6) / 1e9
-    traffic = profile_record("traffic", wl.name + ("" if order == "object" else "_spectrum"), kernel)
+    traffic = profile_record("traffic", rec, kernel)
     return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": float(traffic["bytes_per_launch"]) if traffic else None,
             "avg_us": us, "avg_us_source": source, "hip_event_us": event_us, "algorithmic_bytes": nbytes,
             "algorithmic_bytes_rule": rule}
 
 
-def projection_roofline(wl, k, order, display_bytes=0.0):
+def projection_roofline(wl, k, order, display_bytes=0.0, rec=None):
     """The projection kernel against HBM: frame bytes + h written per launch (+ the previous
     image's column pass when it rides in the same launch), over the kernel-trace average
     recorded for this source (None without one)."""
     kernel = ("k_project_display" if display_bytes else "k_project") + (
         "<unsignedshort,0>" if wl.dose else "<float,0>")  # as recorded: no spaces
-    trace = profile_record("kernel_trace", wl.name + ("" if order == "object" else "_spectrum"), kernel)
+    trace = profile_record("kernel_trace", rec or wl.name + ("" if order == "object" else "_spectrum"), kernel)
     if trace is None:
         return None
     nbytes = (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch + display_bytes
@@ -614,11 +615,14 @@ def main():
         in_update = (defer and not fourier and args.order == "object" and (wl.n > 128 or pipelined)
                      and info.display_slots > 0)
         in_proj = defer and not fourier and wl.n <= 128 and pow2x and not pipelined
+        # records of the profiles: per workload and order, unpipelined runs of pipelinable ones apart
+        rec = wl.name + ("_spectrum" if args.order == "spectrum" else "_unpipelined" if can_pipe and not pipelined
+                         else "")
         out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"],
-                                   disp if in_update else 0.0, pipelined)
+                                   disp if in_update else 0.0, pipelined, rec)
         # (pipelined: the projection has no launch of its own in the timed steps)
         proj = (None if fourier or args.precision != "fp32" or pipelined
-                else projection_roofline(wl, k, args.order, disp if in_proj else 0.0))
+                else projection_roofline(wl, k, args.order, disp if in_proj else 0.0, rec))
         if proj is not None:
             out["roofline_projection"] = proj
     out.update(extras)
