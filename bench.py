@@ -49,8 +49,8 @@ def parse():
                          "queued at once (async)")
     ap.add_argument("--pipeline", default="auto", choices=["auto", "on", "off"],
                     help="pipelined pushes (each batch's update in the next push's launch, beside that push's "
-                         "projection); auto: on where the plan supports it (object order, FP32 projection of "
-                         "uint16 frames of <= 256 rows and 32..256 columns in multiples of 32)")
+                         "projection); auto: on where the plan supports it (object order, uint16 frames of "
+                         "32..256 columns in multiples of 32 and <= 256 rows, <= 128 with a reduced precision)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
     ap.add_argument("--serving", action="store_true", help="run the Poisson-paced serving mix instead")
@@ -237,8 +237,8 @@ def cpu_baseline(wl, frames, pos, seconds, fourier=False):
 
 def pipeline_supported(wl, order, precision, fourier):
     pow2 = (wl.sy & (wl.sy - 1)) == 0 and (wl.sx & (wl.sx - 1)) == 0
-    return (order == "object" and not fourier and precision == "fp32" and bool(wl.dose) and wl.n % 32 == 0
-            and 32 <= wl.n <= 256 and pow2 and wl.sy <= 1024)
+    return (order == "object" and not fourier and bool(wl.dose) and wl.n % 32 == 0 and pow2 and wl.sy <= 1024
+            and 32 <= wl.n <= (256 if precision == "fp32" else 128))
 
 
 def make_plan(wdd, wl, order, precision="fp32", fourier=False, max_batch=None, pipeline=False):
@@ -312,10 +312,11 @@ def precision_lines(torch, wdd, synth, steps, warmup):
     _, _, batches, _ = load_batches(torch, wl, 4)
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
     out = {"workload": "defocus: 256x256 scan, 128x128 uint16 detector (1e3 e/frame, pi rad defocus at the rim), "
-                       "K=64, 51167 kept frequencies, object order, batches of 256, snapshot after every batch",
+                       "K=64, 51167 kept frequencies, object order, batches of 256, snapshot after every batch, "
+                       "pipelined pushes",
            "steps": steps}
     for prec in ("fp32", "bf16_hilo", "fp16_hilo"):
-        with make_plan(wdd, wl, "object", prec) as plan:
+        with make_plan(wdd, wl, "object", prec, pipeline=pipeline_supported(wl, "object", prec, False)) as plan:
             el, _ = timed(torch, plan, batches, shown, warmup, steps, True)
         out[prec] = {"frames_per_s": steps * wl.batch / el, "us_per_step": el / steps * 1e6}
     return out

@@ -133,8 +133,9 @@ typedef struct {
  * snapshot then gives wdd_push_snapshot's image).  A WDD_OUT_DEVICE_DEFERRED snapshot after
  * push i is written during push i + 2 (its update runs in push i + 1's launch, its display's
  * last pass in push i + 2's), or by such a call.  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
- * basis, FP32 precision, uint16 frames of at most 256 rows and 32..256 columns in multiples
- * of 32, and power-of-two scan sides with Sy <= 1024; other plans: WDD_EINVAL. */
+ * basis, uint16 frames of 32..256 columns in multiples of 32 and at most 256 rows (128 with a
+ * reduced-precision projection), and power-of-two scan sides with Sy <= 1024; other plans:
+ * WDD_EINVAL. */
 
 typedef struct {
   int64_t n_freq;        /* number of kept scan frequencies */

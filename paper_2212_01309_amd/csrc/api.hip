@@ -481,8 +481,8 @@ wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) 
       (opts.order != WDD_ORDER_OBJECT || opts.basis != WDD_BASIS_HERMITE_GAUSS || !det ||
        !wdd::row_fused_next_supported(det->dtype, opts.precision, det->ny, det->nx, 256)))
     return wdd::fail(WDD_EINVAL,
-                     "pipelined pushes need object order, the Hermite-Gauss basis, FP32 precision and uint16 "
-                     "frames of at most 256 rows and 32..256 columns in multiples of 32");
+                     "pipelined pushes need object order, the Hermite-Gauss basis and uint16 frames of 32..256 "
+                     "columns in multiples of 32 and at most 256 rows (128 with a reduced-precision projection)");
   return WDD_OK;
 }
 

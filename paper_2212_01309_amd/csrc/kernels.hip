@@ -1665,24 +1665,48 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
 // 15.2 / 13.6 / 14.6 us; 128^2 scan, 64^2 frames 12.2 / 12.3 / 12.3 us.
 constexpr int kNextProjFirst = 1;
 
-// The projection of k_row_fused_obj_next: frames of nx = 32 NCH columns (1 <= NCH <= 8) and at
-// most 256 rows (two 16-row tiles per wave), checked by its launcher.
-template <typename T>
+// The projection of k_row_fused_obj_next (uint16 frames of nx = 32 NCH columns, 1 <= NCH <= 8,
+// checked by its launcher): FP32 with up to two 16-row tiles per wave (at most 256 rows), or a
+// reduced precision with one tile per wave (at most 128 rows).
+template <int PREC>
 __device__ __forceinline__ void project_next(const ProjArgs& a, float* smem, int b) {
-  const T* fr = static_cast<const T*>(a.frames);
-  switch (a.nx >> 5) {
-    case 1: project_frame_tiles<T, 1, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 2: project_frame_tiles<T, 2, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 3: project_frame_tiles<T, 3, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 4: project_frame_tiles<T, 4, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 5: project_frame_tiles<T, 5, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 6: project_frame_tiles<T, 6, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    case 7: project_frame_tiles<T, 7, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
-    default: project_frame_tiles<T, 8, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return;
+  const uint16_t* fr = static_cast<const uint16_t*>(a.frames);
+  if constexpr (PREC == WDD_FP32) {
+#define WDD_NEXT(N) \
+  project_frame_tiles<uint16_t, N, true>(fr, a.ny, a.nx, a.psi, a.kmap, a.kpad, a.h, a.fptr, smem, b); return
+    switch (a.nx >> 5) {
+      case 1: WDD_NEXT(1);
+      case 2: WDD_NEXT(2);
+      case 3: WDD_NEXT(3);
+      case 4: WDD_NEXT(4);
+      case 5: WDD_NEXT(5);
+      case 6: WDD_NEXT(6);
+      case 7: WDD_NEXT(7);
+      default: WDD_NEXT(8);
+    }
+#undef WDD_NEXT
+  } else {
+    constexpr bool bf = PREC == WDD_BF16_HILO || PREC == WDD_BF16;
+    constexpr bool hilo = PREC == WDD_BF16_HILO || PREC == WDD_FP16_HILO;
+#define WDD_NEXT(N)                                                                                               \
+  project_frame_lp_tile<bf, hilo, N>(fr, a.ny, a.nx, a.psi, a.psix_lp, a.psi_unscale, a.kmap, a.kpad, a.h, a.fptr, \
+                                     smem, b);                                                                    \
+  return
+    switch (a.nx >> 5) {
+      case 1: WDD_NEXT(1);
+      case 2: WDD_NEXT(2);
+      case 3: WDD_NEXT(3);
+      case 4: WDD_NEXT(4);
+      case 5: WDD_NEXT(5);
+      case 6: WDD_NEXT(6);
+      case 7: WDD_NEXT(7);
+      default: WDD_NEXT(8);
+    }
+#undef WDD_NEXT
   }
 }
 
-template <typename T>
+template <int PREC>
 __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_row_fused_obj_next(
     const float* __restrict__ h, int kpad, const int* __restrict__ order, const int* __restrict__ xs, RowSet rs,
     int nrows, float tscale, int sx, int sy, const int4* __restrict__ chunks, const int2* __restrict__ jv,
@@ -1696,7 +1720,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
     if (b - pfirst == pa.n)
       upload_block(pa.up_src, pa.up_dst, pa.up_words, (int)threadIdx.x, kFusedThreads);
     else
-      project_next<T>(pa, reinterpret_cast<float*>(fsm), b - pfirst);
+      project_next<PREC>(pa, reinterpret_cast<float*>(fsm), b - pfirst);
     return;
   }
   if (b >= pfirst) b -= nproj;
@@ -2349,10 +2373,26 @@ hipError_t launch_row_fused_obj(const float* h, int kpad, const int* order, cons
   return hipGetLastError();
 }
 
+namespace {
+constexpr int kNextWaves = kFusedThreads / 64;
+
+size_t next_project_lds(int precision, int ny, int nx, int kpad) {
+  return precision == WDD_FP32 ? project_lds_floats(ny, nx, kNextWaves, kpad) * sizeof(float)
+                               : project_lp_lds_bytes(ny, nx, kNextWaves, kpad);
+}
+}  // namespace
+
 bool row_fused_next_supported(int dtype, int precision, int ny, int nx, int kpad) {
-  return dtype == WDD_U16 && precision == WDD_FP32 && nx % 32 == 0 && nx >= 32 && nx <= 256 && ny >= 1 &&
-         ny <= 2 * 16 * (kFusedThreads / 64) && kpad <= 4 * kFusedThreads &&
-         project_lds_floats(ny, nx, kFusedThreads / 64, kpad) * sizeof(float) <= kLdsBytes;
+  if (dtype != WDD_U16 || nx % 32 != 0 || nx < 32 || nx > 256 || ny < 1 || kpad > 4 * kFusedThreads) return false;
+  if (precision == WDD_FP32) {
+    if (ny > 2 * 16 * kNextWaves) return false;
+  } else if (precision == WDD_BF16_HILO || precision == WDD_FP16_HILO || precision == WDD_BF16 ||
+             precision == WDD_FP16) {
+    if (!project_lp_tile_form(ny, nx, kNextWaves, kpad)) return false;
+  } else {
+    return false;
+  }
+  return next_project_lds(precision, ny, nx, kpad) <= kLdsBytes;
 }
 
 hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order, const int* xs, const RowSet& rows,
@@ -2365,14 +2405,26 @@ hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order,
   FusedSetup fs;
   hipError_t e = fused_setup(kpad, nrows, sy, nchunks, max_chunk, up, nslot, dc, &fs);
   if (e != hipSuccess) return e;
-  const size_t lds = std::max(fs.lds, project_lds_floats(next.ny, next.nx, kFusedThreads / 64, kpad) * sizeof(float));
-  if ((e = allow_full_lds<k_row_fused_obj_next<uint16_t>>()) != hipSuccess) return e;
+  const size_t lds = std::max(fs.lds, next_project_lds(next.precision, next.ny, next.nx, kpad));
   const ProjArgs pa = proj_args(next);
   const int nproj = next.n + (pa.up_words > 0 ? 1 : 0);
   const int pfirst = kNextProjFirst == 0 ? 0 : kNextProjFirst == 1 ? nchunks : nchunks + fs.rows_disp;
-  hipLaunchKernelGGL(k_row_fused_obj_next<uint16_t>, dim3(nchunks + fs.rows_disp + nproj), dim3(kFusedThreads), lds,
-                     st, h, kpad, order, xs, rows, nrows, tscale, sx, sy, chunks, jv, w, d, dlo, z, max_chunk, up,
-                     nslot, fs.log2sy, in_order ? 1 : 0, d0out, nchunks, fs.da, pa, pfirst);
+  const dim3 grid(nchunks + fs.rows_disp + nproj), block(kFusedThreads);
+#define WDD_LAUNCH(P)                                                                                               \
+  if ((e = allow_full_lds<k_row_fused_obj_next<P>>()) != hipSuccess) return e;                                      \
+  hipLaunchKernelGGL(k_row_fused_obj_next<P>, grid, block, lds, st, h, kpad, order, xs, rows, nrows, tscale, sx, sy, \
+                     chunks, jv, w, d, dlo, z, max_chunk, up, nslot, fs.log2sy, in_order ? 1 : 0, d0out, nchunks,  \
+                     fs.da, pa, pfirst);                                                                            \
+  break
+  switch (next.precision) {
+    case WDD_FP32: WDD_LAUNCH(WDD_FP32);
+    case WDD_BF16_HILO: WDD_LAUNCH(WDD_BF16_HILO);
+    case WDD_FP16_HILO: WDD_LAUNCH(WDD_FP16_HILO);
+    case WDD_BF16: WDD_LAUNCH(WDD_BF16);
+    case WDD_FP16: WDD_LAUNCH(WDD_FP16);
+    default: return hipErrorInvalidValue;
+  }
+#undef WDD_LAUNCH
   return hipGetLastError();
 }
 

@@ -28,21 +28,25 @@ def _case(seed, s, n, count, raster=False):
     return frames, pos
 
 
-@pytest.mark.parametrize("s,n,raster", [(32, 64, False), (32, 64, True), (64, 128, True), (16, 32, False)])
-def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster):
+@pytest.mark.parametrize("s,n,raster,precision", [(32, 64, False, "fp32"), (32, 64, True, "fp32"),
+                                                  (64, 128, True, "fp32"), (16, 32, False, "fp32"),
+                                                  (32, 64, False, "bf16_hilo"), (32, 128, True, "fp16_hilo"),
+                                                  (32, 96, True, "bf16")])
+def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision):
     """Deferred snapshots after every push, then the calls that must run a held update first
     (inspection of D and of the last projections, a blocking snapshot, a checkpoint, a reset):
-    everything equals the unpipelined plan bit for bit.  A blocking snapshot right after a
+    everything equals the unpipelined plan bit for bit, in FP32 and in the reduced-precision
+    projections (one tile per wave in both launches).  A blocking snapshot right after a
     push equals the unpipelined wdd_push_snapshot."""
     import torch
     b, steps = 64, 9
-    say(f"[pipeline] scan {s}^2, detector {n}^2, {'raster' if raster else 'scattered'} batches of {b}")
+    say(f"[pipeline] scan {s}^2, detector {n}^2, {precision}, {'raster' if raster else 'scattered'} batches of {b}")
     frames, pos = _case(7 + s + n, s, n, b * (steps + 3), raster)
     dev = device(frames)
     blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
     img = lambda: torch.empty((s, s), dtype=torch.complex64, device="cuda")
     outs = {True: [img() for _ in range(steps)], False: [img() for _ in range(steps)]}
-    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT, precision=precision)
     with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
         assert p.info().pipelined == 1 and r.info().pipelined == 0
         for i in range(steps):

@@ -125,14 +125,15 @@ def test_fourier_plan_rejects_reduced_precision_before_touching_a_device():
 @pytest.mark.parametrize("kw", [
     dict(order=wdd.WDD_ORDER_SPECTRUM),                       # the update holds A, not D
     dict(dtype=wdd.WDD_F32),                                  # uint16 frames only
-    dict(precision=wdd.WDD_BF16_HILO),                        # FP32 projection only
+    dict(precision=wdd.WDD_BF16_HILO, ny=160),                # reduced precision: at most 128 rows
     dict(nx=48),                                              # columns in multiples of 32
     dict(nx=288),                                             # at most 256 columns
     dict(ny=288),                                             # at most 256 rows
 ])
 def test_pipelined_plan_rejects_unsupported_settings_before_touching_a_device(kw):
-    """wdd_options.pipeline: the merged update + projection launch exists for object order,
-    FP32 projections of uint16 frames of <= 256 rows and 32..256 columns in multiples of 32."""
+    """wdd_options.pipeline: the merged update + projection launch exists for object order and
+    uint16 frames of 32..256 columns in multiples of 32 and <= 256 rows (128 with a reduced
+    precision)."""
     args = dict(ny=64, nx=64, order=wdd.WDD_ORDER_OBJECT, dtype=wdd.WDD_U16)
     args.update(kw)
     ny, nx = args.pop("ny"), args.pop("nx")
