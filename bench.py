@@ -117,7 +117,7 @@ def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0
                                                  "pass in the same launch)" if display_bytes else "")
         if pipelined:
             nbytes += (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
-            kernel = "k_row_fused_obj_next<unsignedshort>"  # as recorded: no spaces
+            kernel = "k_row_fused_obj_next<%d>" % PRECISION_CODES[precision]  # as recorded
             rule += " + frames + 4 * K * batch (the next batch's projection in the same launch)"
     else:
         # read and write A, read W (the Wiener reduction fused in before a snapshot)
@@ -233,6 +233,9 @@ def cpu_baseline(wl, frames, pos, seconds, fourier=False):
     except ImportError:
         pass
     return out
+
+
+PRECISION_CODES = {"fp32": 0, "bf16_hilo": 1, "fp16_hilo": 2, "bf16": 3, "fp16": 4}  # wdd_precision
 
 
 def pipeline_supported(wl, order, precision, fourier):
