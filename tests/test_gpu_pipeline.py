@@ -122,3 +122,30 @@ def test_two_tiles_per_wave_against_the_oracle(n, raster):
     errs = dict(D=rel_d(got_d, live.spectrum()), O=rel_img(got_o, live.snapshot()), D_vs_unpipelined=rel_d(got_d, ref_d))
     say(f"[pipeline] errors {errs}")
     assert errs["D"] <= TOL and errs["O"] <= TOL and errs["D_vs_unpipelined"] <= 1e-6
+
+
+def test_pipelined_host_frames_and_ragged_batches():
+    """Frames from host memory (staged through the plan's pinned slots) and batches of changing
+    size, some on many scan rows (several update passes): bit for bit the unpipelined plan."""
+    import torch
+    s, n = 32, 64
+    sizes = [64, 7, 33, 1, 64, 50, 2]
+    frames, pos = _case(23, s, n, sum(sizes))
+    dev = device(frames)
+    outs = {True: [], False: []}
+    kw = dict(max_batch=64, order=wdd.WDD_ORDER_OBJECT)
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        b0 = 0
+        for i, m in enumerate(sizes):
+            fr = frames[b0:b0 + m] if i % 2 == 0 else dev[b0:b0 + m]   # host and device frames in turn
+            for q, key in ((p, True), (r, False)):
+                out = torch.empty((s, s), dtype=torch.complex64, device="cuda")
+                q.push_snapshot(fr, pos[b0:b0 + m], out=out, wait=False, defer=True)
+                outs[key].append(out)
+            b0 += m
+        p.sync()
+        r.sync()
+        for i in range(len(sizes)):
+            assert torch.equal(outs[True][i], outs[False][i]), i
+        assert np.array_equal(p.spectrum(), r.spectrum())
+        assert p.info().frames_seen == r.info().frames_seen == sum(sizes)
