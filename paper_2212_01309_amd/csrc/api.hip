@@ -1007,6 +1007,10 @@ wdd_status plan_set_stream(wdd_plan_t p, void* stream) {
   return WDD_OK;
 }
 
+void plan_drop_stream(wdd_plan_t p) {
+  if (p && !p->own_stream) p->stream = nullptr;
+}
+
 wdd_status snapshot_finish(wdd_plan_t p, uint64_t* frames_seen) {
   wdd_status st = check_usable(p);
   if (st != WDD_OK) return st;

@@ -1654,16 +1654,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
 // block, the projection writes the next batch's into other buffers), so the projection's
 // frame stream from HBM overlaps the update's phases that leave HBM idle (the first, which
 // reads the projections from L2, and the partial display rows), and the launch boundary
-// between them goes away.  Workgroups [pfirst, pfirst + pa.n) project frames 0 .. pa.n - 1
-// (512 threads: up to two 16-row tiles per wave), workgroup pfirst + pa.n copies the upload
-// block when there is one; the others, in order, are the update's chunks and then the
-// display rows of k_row_fused_obj.
-// Where k_row_fused_obj_next's projection workgroups sit in its grid: 0 first, 1 after the
-// update's chunks, 2 after the display rows (last).  After the chunks: they start as the
-// first chunks finish their first phase.  Measured per pipelined step (first / after the
-// chunks / last): 512^2 scan, 256^2 frames 37.5 / 36.1 / 44.2 us; 256^2 scan, 128^2 frames
-// 15.2 / 13.6 / 14.6 us; 128^2 scan, 64^2 frames 12.2 / 12.3 / 12.3 us.
-constexpr int kNextProjFirst = 1;
+// between them goes away.  Grid: projections 0 .. pfront - 1, the update's nchunks chunks,
+// the other projections (512 threads: up to two 16-row tiles per wave; projection pa.n, when
+// there is an upload block, copies it), then the display rows of k_row_fused_obj.
+// How many of k_row_fused_obj_next's projection workgroups come before the update's chunks in
+// its grid (the others follow the chunks): a few at the front start their frame stream while
+// the chunks' first phase reads from L2; all of them there (or all after the display rows)
+// delay chunks or leave the tail to the projections.  Measured per pipelined step, 0 / 16 /
+// 32 / 64 / 96 in front: 512^2 scan, 256^2 frames 36.2 / 35.8 / 35.7 / 35.7 / 37.0 us;
+// 256^2 scan, 128^2 frames 13.7 / 13.7 / 13.5 / 14.6 / 14.6 us; 128^2 scan, 64^2 frames
+// 12.3 / 12.2 / 12.2 / 11.9 / 12.1 us (all in front: 37.5, 15.2, 12.2 us; all after the
+// display rows: 44.2, 14.6, 12.3 us).
+constexpr int kNextProjFront = 32;
 
 // The projection of k_row_fused_obj_next (uint16 frames of nx = 32 NCH columns, 1 <= NCH <= 8,
 // checked by its launcher): FP32 with up to two 16-row tiles per wave (at most 256 rows), or a
@@ -1712,25 +1714,26 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
     int nrows, float tscale, int sx, int sy, const int4* __restrict__ chunks, const int2* __restrict__ jv,
     const float2* __restrict__ w, float2* __restrict__ d, float2* __restrict__ dlo, float2* __restrict__ z,
     int max_chunk, float2* __restrict__ up, int nslot, int log2sy, int in_order, float2* __restrict__ d0out,
-    int nchunks, DispArgs disp, ProjArgs pa, int pfirst) {
+    int nchunks, DispArgs disp, ProjArgs pa, int pfront) {
   extern __shared__ float4 fsm[];
-  int b = (int)blockIdx.x;
+  const int b = (int)blockIdx.x;
   const int nproj = pa.n + (pa.up_words > 0 ? 1 : 0);
-  if (b >= pfirst && b < pfirst + nproj) {
-    if (b - pfirst == pa.n)
+  const int pi = b < pfront ? b : (b >= pfront + nchunks && b < nproj + nchunks) ? b - nchunks : -1;
+  if (pi >= 0) {
+    if (pi == pa.n)
       upload_block(pa.up_src, pa.up_dst, pa.up_words, (int)threadIdx.x, kFusedThreads);
     else
-      project_next<PREC>(pa, reinterpret_cast<float*>(fsm), b - pfirst);
+      project_next<PREC>(pa, reinterpret_cast<float*>(fsm), pi);
     return;
   }
-  if (b >= pfirst) b -= nproj;
-  if (b >= nchunks) {
+  if (b >= nproj + nchunks) {
     display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
-                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nchunks,
+                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nproj - nchunks,
                          reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
     return;
   }
-  const int4 ch = chunks[xcd_row(b, nchunks)];
+  // (pfront is a multiple of 8: the chunks keep the XCDs of k_row_fused_obj's mapping)
+  const int4 ch = chunks[xcd_row(b - pfront, nchunks)];
   row_fused_obj_body(h, kpad, order, xs, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
                      in_order, d0out, fsm);
 }
@@ -2408,13 +2411,14 @@ hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order,
   const size_t lds = std::max(fs.lds, next_project_lds(next.precision, next.ny, next.nx, kpad));
   const ProjArgs pa = proj_args(next);
   const int nproj = next.n + (pa.up_words > 0 ? 1 : 0);
-  const int pfirst = kNextProjFirst == 0 ? 0 : kNextProjFirst == 1 ? nchunks : nchunks + fs.rows_disp;
+  const int pfront = std::min(kNextProjFront, nproj) / 8 * 8;
+  static_assert(kNextProjFront % 8 == 0, "whole rounds of the 8 XCDs in front of the chunks");
   const dim3 grid(nchunks + fs.rows_disp + nproj), block(kFusedThreads);
 #define WDD_LAUNCH(P)                                                                                               \
   if ((e = allow_full_lds<k_row_fused_obj_next<P>>()) != hipSuccess) return e;                                      \
   hipLaunchKernelGGL(k_row_fused_obj_next<P>, grid, block, lds, st, h, kpad, order, xs, rows, nrows, tscale, sx, sy, \
                      chunks, jv, w, d, dlo, z, max_chunk, up, nslot, fs.log2sy, in_order ? 1 : 0, d0out, nchunks,  \
-                     fs.da, pa, pfirst);                                                                            \
+                     fs.da, pa, pfront);                                                                            \
   break
   switch (next.precision) {
     case WDD_FP32: WDD_LAUNCH(WDD_FP32);

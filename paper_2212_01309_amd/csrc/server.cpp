@@ -128,6 +128,9 @@ struct wdd_server_s {
   size_t blk_cap = 0;
   // the captured round and the shape it was captured for
   hipGraphExec_t exec = nullptr;
+  // held by a closer thread while it frees device memory: a round is captured only while the
+  // scheduling thread can take it at once, so that no free runs during a capture
+  std::mutex free_mu;
   bool failed = false;
 };
 
@@ -521,7 +524,9 @@ wdd_status drain_grouped(wdd_server_s* s, const std::vector<Acq*>& acqs, const s
     Round rd;
     wdd_status st = prepare_round(s, ms, &rd);
     if (st != WDD_OK) return st;
-    if (s->opts.launch_mode == WDD_SERVE_GRAPH) {
+    // (a round while a closer thread frees memory is launched directly instead of captured)
+    std::unique_lock<std::mutex> no_frees(s->free_mu, std::defer_lock);
+    if (s->opts.launch_mode == WDD_SERVE_GRAPH && no_frees.try_lock()) {
       // capture the round, then replay it (updating the instantiated graph's arguments when
       // the shape is the one captured before)
       SRV_HIP(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
@@ -669,7 +674,12 @@ void free_acq(wdd_server_s* s, Acq* a) {
   if (a->worker.joinable()) a->worker.join();
   wdd_plan_t plan = a->plan ? a->plan : (a->open_status == WDD_OK ? a->made : nullptr);
   if (plan) {
-    if (a->grouped) (void)hipStreamSynchronize(s->stream);  // its last rounds may still run
+    // The server's stream is not waited on here: the scheduling thread may be capturing it
+    // (WDD_SERVE_GRAPH), and a wait on a capturing stream from another thread invalidates the
+    // capture.  A plan with rounds behind it was synchronised by wdd_server_close or by the
+    // server's destruction; one that never ran a round has no work there.
+    if (a->grouped) wdd::plan_drop_stream(plan);
+    std::lock_guard<std::mutex> g(s->free_mu);
     wdd_destroy(plan);
   }
   if (a->snap_ev) (void)hipEventDestroy(a->snap_ev);
@@ -995,9 +1005,9 @@ wdd_status wdd_server_get_stats(wdd_server_t s, wdd_server_stats* out) {
 wdd_status wdd_server_destroy(wdd_server_t s) {
   if (!s) return WDD_OK;
   reap_closers(s, true);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);  // the open acquisitions' last rounds
   for (auto& kv : s->acqs) free_acq(s, kv.second);
   s->acqs.clear();
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   for (int i = 0; i < kRing; ++i) {
     if (s->pin[i]) (void)hipHostFree(s->pin[i]);

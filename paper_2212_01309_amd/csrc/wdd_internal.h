@@ -51,6 +51,10 @@ wdd_status plan_scan_shape(wdd_plan_t p, int32_t* sy, int32_t* sx);
 // Waits for the plan's work, then moves it to `stream` (the plan's own stream, if it had
 // one, is destroyed).
 wdd_status plan_set_stream(wdd_plan_t p, void* stream);
+// Forgets a plan's borrowed stream without waiting on it (no work of the plan may be queued
+// there: the caller has synchronised it, or the plan never ran on it); the plan may then only
+// be destroyed.  A plan that owns its stream keeps it.
+void plan_drop_stream(wdd_plan_t p);
 
 // The display of a spectrum grid (wdd_display): argument checks, the scratch it needs (in
 // floats: two sy x sx complex grids and the twiddles of both sides) and the launches, all
