@@ -214,3 +214,39 @@ def test_open_does_not_wait_for_the_tables():
         plan.push(dev[256:], pos[256:])
         alone = plan.snapshot()
     assert rel_img(got, alone) <= 1e-5
+
+
+def test_graph_rounds_while_acquisitions_close():
+    """WDD_SERVE_GRAPH while acquisitions are closed between steps: the plans are freed on
+    closer threads while the scheduling thread captures the next rounds.  A closer must not
+    wait on the server's stream (a wait on a capturing stream invalidates the capture) nor free
+    device memory during a capture; every step succeeds and the survivors' images match the
+    same acquisitions served alone."""
+    radius, s, n, k = 8.0, 32, 32, 64
+    frames, pos = _acquisition(7, radius, s, n, k)
+    dev = device(frames)
+    with wdd.Server(hbm_budget_bytes=1 << 30, batch_frames=128, launch_mode="graph") as srv:
+        keep = srv.open(radius, s, s, n, n, k, order=wdd.WDD_ORDER_OBJECT)
+        srv.wait_open(keep)
+        for cycle in range(12):
+            extra = [srv.open(radius, s, s, n, n, k, order=wdd.WDD_ORDER_OBJECT) for _ in range(3)]
+            for e in extra:
+                srv.wait_open(e)
+            b0 = (cycle * 64) % len(pos)
+            for e in extra:
+                srv.submit(e, dev[b0:b0 + 64], pos[b0:b0 + 64])
+            srv.submit(keep, dev[b0:b0 + 64], pos[b0:b0 + 64])
+            srv.step()
+            for e in extra:   # closed while the next steps capture their rounds
+                srv.close(e)
+            srv.step()
+        got = srv.snapshot(keep)
+        st = srv.stats()
+    with wdd.Plan(radius, s, s, n, n, k, order=wdd.WDD_ORDER_OBJECT, max_batch=128) as plan:
+        for cycle in range(12):
+            b0 = (cycle * 64) % len(pos)
+            plan.push(dev[b0:b0 + 64], pos[b0:b0 + 64])
+        ref = plan.snapshot()
+    say(f"[serving] graph rounds with closes: {st['group_rounds']} rounds, {st['graph_replays']} replays, "
+        f"error vs alone {rel_img(got, ref):.2e}")
+    assert rel_img(got, ref) <= 1e-5
