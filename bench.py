@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--display", default="deferred", choices=["deferred", "async"],
                     help="pipelined steps: each image written by the next push's first launch (deferred) or "
                          "queued at once (async)")
-    ap.add_argument("--pipeline", default="auto", choices=["auto", "on", "off"],
-                    help="pipelined pushes (each batch's update in the next push's launch, beside that push's "
-                         "projection); auto: on where the plan supports it (object order, uint16 frames of "
-                         "32..256 columns in multiples of 32 and <= 256 rows, <= 128 with a reduced precision)")
+    ap.add_argument("--pipeline", default="auto", choices=["auto", "on", "two", "off"],
+                    help="pipelined pushes (on: each batch's update in the next push's launch, beside that "
+                         "push's projection; two: also the batch's x-DFT one launch ahead of its update); auto: "
+                         "the pipelined form where the plan supports it (object order, uint16 frames of 32..256 "
+                         "columns in multiples of 32 and <= 256 rows, <= 128 with a reduced precision)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
     ap.add_argument("--serving", action="store_true", help="run the Poisson-paced serving mix instead")
@@ -117,7 +118,8 @@ def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0
                                                  "pass in the same launch)" if display_bytes else "")
         if pipelined:
             nbytes += (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
-            kernel = "k_row_fused_obj_next<%d>" % PRECISION_CODES[precision]  # as recorded
+            kernel = ("k_row_fused_obj_next2<%d>" if pipelined == 2 else "k_row_fused_obj_next<%d>") % \
+                PRECISION_CODES[precision]  # as recorded
             rule += " + frames + 4 * K * batch (the next batch's projection in the same launch)"
     else:
         # read and write A, read W (the Wiener reduction fused in before a snapshot)
@@ -236,6 +238,12 @@ def cpu_baseline(wl, frames, pos, seconds, fourier=False):
 
 
 PRECISION_CODES = {"fp32": 0, "bf16_hilo": 1, "fp16_hilo": 2, "bf16": 3, "fp16": 4}  # wdd_precision
+
+
+def auto_stages(info):
+    """Pipeline stages of --pipeline auto: two where the update's chunks share their columns'
+    x-DFT three or more to one (the second stage forms it once per column), else one."""
+    return 2 if info.update_chunks >= 3 * max(1, info.kept_columns) else 1
 
 
 def pipeline_supported(wl, order, precision, fourier):
@@ -522,10 +530,16 @@ def main():
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
     defer = args.display == "deferred"
     can_pipe = pipeline_supported(wl, args.order, args.precision, fourier)
-    if args.pipeline == "on" and not can_pipe:
-        sys.exit("--pipeline on: this workload / order / precision has no pipelined form")
-    pipelined = args.pipeline == "on" or (args.pipeline == "auto" and can_pipe)
-    plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipelined)
+    if args.pipeline in ("on", "two") and not can_pipe:
+        sys.exit(f"--pipeline {args.pipeline}: this workload / order / precision has no pipelined form")
+    pipe_stages = {"off": 0, "on": 1, "two": 2}.get(args.pipeline, 1 if can_pipe else 0)
+    plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipe_stages)
+    chosen = auto_stages(plan.info()) if can_pipe else 0   # the form --pipeline auto takes
+    if args.pipeline == "auto" and chosen != pipe_stages:
+        plan.close()
+        pipe_stages = chosen
+        plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipe_stages)
+    pipelined = pipe_stages > 0
     n_freq, k = plan.n_freq, plan.k
     plan_info = plan.info()
 
@@ -578,6 +592,12 @@ def main():
             el, _ = timed(torch, p2, batches, shown, args.warmup, args.steps, defer)
         extras["unpipelined" if pipelined else "pipelined"] = {
             "frames_per_s": args.steps * wl.batch / el, "us_per_step": el / args.steps * 1e6}
+        if pipelined:  # and with the other number of pipeline stages
+            other = 3 - pipe_stages
+            with make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=other) as p2:
+                el, _ = timed(torch, p2, batches, shown, args.warmup, args.steps, defer)
+            extras["pipeline_stages_%d" % other] = {
+                "frames_per_s": args.steps * wl.batch / el, "us_per_step": el / args.steps * 1e6}
 
     if not args.no_extras and not fourier:
         other = "spectrum" if args.order == "object" else "object"
@@ -598,6 +618,7 @@ def main():
         "config": {"workload": workload_label(wl, n_freq, k, fourier), "scan": [wl.sy, wl.sx], "detector": [wl.n, wl.n],
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
                    "wiener_order": args.order, "basis": args.basis, "pipelined": pipelined,
+                   "pipeline_stages": pipe_stages,
                    "display": "hbm" + ((", each batch's update in the next push's launch (with that push's "
                                         "projection), each image's last pass in the launch after" if pipelined else
                                         ", each image's last pass deferred to the next push's first launch "
@@ -621,9 +642,9 @@ def main():
         in_proj = defer and not fourier and wl.n <= 128 and pow2x and not pipelined
         # records of the profiles: per workload and order, unpipelined runs of pipelinable ones apart
         rec = wl.name + ("_spectrum" if args.order == "spectrum" else "_unpipelined" if can_pipe and not pipelined
-                         else "")
+                         else "_stages%d" % pipe_stages if pipelined and pipe_stages != chosen else "")
         out["roofline"] = roofline(wl, n_freq, k, args.order, fourier, args.precision, stages["accumulate"],
-                                   disp if in_update else 0.0, pipelined, rec)
+                                   disp if in_update else 0.0, pipe_stages, rec)
         # (pipelined: the projection has no launch of its own in the timed steps)
         proj = (None if fourier or args.precision != "fp32" or pipelined
                 else projection_roofline(wl, k, args.order, disp if in_proj else 0.0, rec))

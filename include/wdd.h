@@ -118,7 +118,7 @@ typedef struct {
   int32_t max_batch;  /* largest n accepted by wdd_push; default 256 */
   int32_t order;      /* wdd_order; default WDD_ORDER_SPECTRUM */
   int32_t basis;      /* wdd_basis; default WDD_BASIS_HERMITE_GAUSS */
-  int32_t pipeline;   /* 0 (default) or 1: pipelined pushes, see below */
+  int32_t pipeline;   /* 0 (default), 1 or 2: pipelined pushes, see below */
 } wdd_options;
 
 /* Pipelined pushes (wdd_options.pipeline = 1).  The update of a batch (its accumulation into
@@ -132,7 +132,14 @@ typedef struct {
  * the display's first pass from that batch's update, as wdd_push_snapshot does, so push +
  * snapshot then gives wdd_push_snapshot's image).  A WDD_OUT_DEVICE_DEFERRED snapshot after
  * push i is written during push i + 2 (its update runs in push i + 1's launch, its display's
- * last pass in push i + 2's), or by such a call.  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
+ * last pass in push i + 2's), or by such a call.  pipeline = 2 adds a stage: the x-DFT of a
+ * batch's projections along the scan rows (Section 6.1, the F_x factor of eq. outer_prod),
+ * formed once per kept v_x, runs one launch ahead of the update, which then streams W at
+ * once; a push's launch holds the update of batch i - 2, the x-DFT of batch i - 1 and the
+ * projection of batch i, results are the same as with pipeline = 1, and a deferred image
+ * lands three pushes later.  Batches on more than 16 scan rows run unpipelined after the held
+ * ones.  Two stages pay where several chunks share a column (update_chunks well above
+ * kept_columns in wdd_plan_info).  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
  * basis, uint16 frames of 32..256 columns in multiples of 32 and at most 256 rows (128 with a
  * reduced-precision projection), and power-of-two scan sides with Sy <= 1024; other plans:
  * WDD_EINVAL. */
@@ -147,7 +154,9 @@ typedef struct {
   int64_t device_bytes;  /* device memory held by the plan */
   int32_t update_chunks; /* object order: workgroups of a row pass (runs of kept frequencies of one v_x) */
   int32_t display_slots; /* object order: partial display rows kept per v_x (0: the two-pass display) */
-  int32_t pipelined;     /* pushes are pipelined (wdd_options.pipeline) */
+  int32_t pipelined;     /* pipeline stages of pushes (wdd_options.pipeline) */
+  int32_t kept_columns;  /* object order: the kept v_x (two-stage pipelining forms one x-DFT per column
+                            per batch; the update's chunks take update_chunks / kept_columns each) */
 } wdd_plan_info;
 
 typedef struct wdd_tables_s* wdd_tables_t;
@@ -247,7 +256,8 @@ wdd_status wdd_push_snapshot(wdd_plan_t p, const void* frames, const int32_t* po
  *                         one of that push's launches (its projection; for detectors of
  *                         more than 128 rows in object order, its first update: one
  *                         kernel boundary fewer per pipelined step; with pipelined
- *                         pushes, by the push after next), or else by the next
+ *                         pushes, by the push after next, or the third with two
+ *                         stages), or else by the next
  *                         call that waits for the plan's stream or changes its state
  *                         (wdd_snapshot, wdd_sync, wdd_get_*, wdd_profile_read,
  *                         checkpoints, wdd_update_probe, wdd_reset, wdd_destroy).  `out`

@@ -69,7 +69,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_freq", ctypes.c_int64), ("k", ctypes.c_int32), ("l", ctypes.c_int32),
                 ("sigma_px", ctypes.c_double), ("eps_abs", ctypes.c_double), ("frames_seen", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_int64), ("update_chunks", ctypes.c_int32), ("display_slots", ctypes.c_int32),
-                ("pipelined", ctypes.c_int32)]
+                ("pipelined", ctypes.c_int32), ("kept_columns", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -235,12 +235,12 @@ def _check(code: int) -> None:
 
 
 def _options(eps_rel: float, sigma_px: float, max_batch: int, precision: int = WDD_FP32,
-             order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, pipeline: bool = False) -> Options:
+             order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, pipeline=False) -> Options:
     o = Options()
     _check(load_library().wdd_default_options(ctypes.byref(o)))
     o.eps_rel, o.sigma_px, o.max_batch, o.precision, o.order = eps_rel, sigma_px, max_batch, precision, order
     o.basis = basis
-    o.pipeline = 1 if pipeline else 0
+    o.pipeline = int(pipeline)  # False / True / 2 (two-stage)
     return o
 
 
@@ -301,13 +301,14 @@ class Tables:
 class Plan:
     """A live reconstruction on the current HIP device (wdd_plan ... wdd_destroy).
     pipeline=True (object order): each push's update runs in the next push's launch, beside
-    that push's projection (wdd_options.pipeline)."""
+    that push's projection; pipeline=2: two stages, the x-DFT one launch ahead of the update
+    (wdd_options.pipeline)."""
 
     def __init__(self, radius: float, sy: int, sx: int, ny: int, nx: int, k: int, *, dtype: int = WDD_U16,
                  defocus: float = 0.0, amplitude: float = 1.0, step: float = 1.0, eps_rel: float = 0.01,
                  sigma: float = 0.0, max_batch: int = 256, stream: Optional[int] = None, precision: int = WDD_FP32,
                  order: int = WDD_ORDER_SPECTRUM, basis: int = WDD_BASIS_HERMITE_GAUSS, center=None,
-                 pipeline: bool = False):
+                 pipeline=False):
         lib = load_library()
         self._h = _P()
         self.sy, self.sx, self.ny, self.nx, self.dtype = sy, sx, ny, nx, dtype

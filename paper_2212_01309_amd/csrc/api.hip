@@ -188,17 +188,15 @@ bool can_defer(const wdd_plan_s* p) {
 
 bool can_defer_to_update(const wdd_plan_s* p) { return p->up_valid && p->up_alt && p->d0w; }
 
-wdd_status run_held(wdd_plan_s* p, const wdd::ProjectLaunch* next, bool for_display);
+wdd_status flush_held(wdd_plan_s* p, bool for_display);
 
 // Runs a held update (pipelined pushes) and writes a display left to the next push now;
 // every call that waits for the plan's stream or reads or changes its state goes through here
 // first (D has not changed since a display kept for the projection was queued, so p->d gives
 // its D[0]; one kept for the update reads its own copy of D[0]).
 wdd_status flush_deferred(wdd_plan_s* p) {
-  if (p->held.live) {
-    const wdd_status st = run_held(p, nullptr, false);
-    if (st != WDD_OK) return st;
-  }
+  const wdd_status st = flush_held(p, false);
+  if (st != WDD_OK) return st;
   if (!p->deferred_dst) return WDD_OK;
   float2* dst = p->deferred_dst;
   p->deferred_dst = nullptr;
@@ -378,6 +376,16 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
     ALLOC(p->h_alt, (size_t)p->max_batch * p->kpad);
     ALLOC(p->upload_alt, p->upload_bytes);
   }
+  std::vector<int32_t> xcols;  // the kept v_x, in chunk order
+  for (const int4& c : chunks)
+    if (xcols.empty() || xcols.back() != c.x) xcols.push_back(c.x);
+  p->ncols = (int32_t)xcols.size();
+  if (p->two_stage) {
+    const size_t tsz = (size_t)t.sx * wdd::row_fused_t_stride(p->kpad);
+    ALLOC(p->t_cur, tsz);
+    ALLOC(p->t_next, tsz);
+    ALLOC(p->xcols, xcols.size());
+  }
   if (partial_rows) ALLOC(p->up, (size_t)t.sx * p->nslot * t.sy);
   if (partial_rows && (t.ny > 128 || p->pipeline)) {  // see can_defer
     ALLOC(p->up_alt, (size_t)t.sx * p->nslot * t.sy);
@@ -435,6 +443,9 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   if (p->dlo) WDD_HIP(p, wdd::launch_zero(reinterpret_cast<float*>(p->dlo), (size_t)p->n_freq_pad * 2, p->stream));
   WDD_HIP(p, wdd::launch_zero(p->h, (size_t)p->max_batch * p->kpad * (p->fourier ? 2 : 1), p->stream));
   if (p->h_alt) WDD_HIP(p, wdd::launch_zero(p->h_alt, (size_t)p->max_batch * p->kpad, p->stream));
+  if (p->xcols)
+    WDD_HIP(p, hipMemcpyAsync(p->xcols, xcols.data(), xcols.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              p->stream));
 
   {
     const size_t slot_bytes = p->upload_bytes + (size_t)p->max_batch * sizeof(uint64_t);
@@ -476,7 +487,7 @@ wdd_status check_plan_options(const wdd_detector* det, const wdd_options& opts) 
     return wdd::fail(WDD_EINVAL, "unknown basis %d", opts.basis);
   if (opts.basis == WDD_BASIS_FOURIER && opts.precision != WDD_FP32)
     return wdd::fail(WDD_EINVAL, "the Fourier basis runs in FP32 only");
-  if (opts.pipeline != 0 && opts.pipeline != 1) return wdd::fail(WDD_EINVAL, "pipeline must be 0 or 1");
+  if (opts.pipeline < 0 || opts.pipeline > 2) return wdd::fail(WDD_EINVAL, "pipeline must be 0, 1 or 2");
   if (opts.pipeline &&
       (opts.order != WDD_ORDER_OBJECT || opts.basis != WDD_BASIS_HERMITE_GAUSS || !det ||
        !wdd::row_fused_next_supported(det->dtype, opts.precision, det->ny, det->nx, 256)))
@@ -513,6 +524,7 @@ int64_t plan_device_bytes(const wdd_tables_s& t, const wdd_options& opts, int32_
     b += t.ny > 128 || opts.pipeline ? 2 * up + a(16) : up;
   }
   if (opts.pipeline) b += a(mb * kpad * 4) + a(mb * 16 + 16 + mb * 16);  // h_alt, upload_alt
+  if (opts.pipeline == 2) b += 2 * a((int64_t)t.sx * wdd::row_fused_t_stride((int)kpad) * 16) + a(t.sx * 4);
   b += a(nfp * 8) + 2 * a(grid * 8);
   return b;
 }
@@ -545,6 +557,7 @@ wdd_status plan_create_from_tables(std::shared_ptr<const wdd_tables_s> tp, const
   p->order_mode = opts.order;
   p->fourier = t.basis == WDD_BASIS_FOURIER;
   p->pipeline = opts.pipeline != 0;
+  p->two_stage = opts.pipeline == 2;
   p->probe = *probe;
   p->scan = *scan;
   p->det = *det;
@@ -684,6 +697,101 @@ wdd_status run_held(wdd_plan_s* p, const wdd::ProjectLaunch* next, bool for_disp
   return WDD_OK;
 }
 
+// The deferred column pass kept for the update, as launch arguments (carry: there is one).
+bool carried_display(wdd_plan_s* p, wdd::DisplayColumns* dc) {
+  if (!p->deferred_dst || !p->deferred_in_update) return false;
+  dc->din = p->deferred_src;
+  dc->dout = p->deferred_dst;
+  dc->rows = p->sy;
+  dc->len = p->sx;
+  dc->e = p->ex;
+  dc->d0 = p->deferred_d0;
+  dc->s_total = (float)((double)p->sy * p->sx);
+  dc->in_sr = p->deferred_sr;
+  dc->in_sm = p->deferred_sm;
+  dc->out_sr = p->sx;
+  dc->out_sc = 1;
+  dc->nslot = p->deferred_nslot;
+  dc->slot_stride = p->deferred_slot_stride;
+  p->deferred_dst = nullptr;
+  p->deferred_in_update = false;
+  return true;
+}
+
+// One launch of two-stage pipelined pushes: the update of held2 (its x-DFT in t_cur), the
+// x-DFT of `held` into t_next when xdft is set, and `next`; a deferred column pass kept for
+// the update rides along.  held2's update leaves the display's first pass in `up` when a
+// deferred snapshot followed it or for_display asks for it.  Afterwards held2 is done and,
+// with xdft, `held` has moved to held2 (its x-DFT now in t_cur).
+wdd_status launch_stage2(wdd_plan_s* p, const wdd::ProjectLaunch* next, bool for_display, bool xdft) {
+  wdd_plan_s::Held& u = p->held2;
+  wdd_plan_s::Held& x = p->held;
+  wdd::RowSet urs, xrs;
+  std::memset(&urs, 0, sizeof(urs));
+  std::memset(&xrs, 0, sizeof(xrs));
+  const bool rows = u.live && (u.display || for_display) && p->up;
+  if (rows && p->up_alt) {
+    std::swap(p->up, p->up_alt);
+    std::swap(p->d0w, p->d0w_alt);
+  }
+  float2* up_pass = rows ? p->up : nullptr;
+  float2* d0out = up_pass && p->up_alt ? p->d0w : nullptr;
+  const int unrows = u.live ? (int)u.rows.size() : 0;
+  for (int i = 0; i < unrows; ++i) urs.r[i] = u.rows[i];
+  wdd::XdftPart xp;
+  std::memset(&xp, 0, sizeof(xp));
+  if (xdft && x.live) {
+    xp.h = p->h;
+    xp.order = p->order;
+    xp.xs = p->xs;
+    xp.nrows = (int)x.rows.size();
+    for (int i = 0; i < xp.nrows; ++i) xp.rows.r[i] = x.rows[i];
+    xp.in_order = x.in_order;
+    xp.xcols = p->xcols;
+    xp.ncols = p->ncols;
+    xp.tout = p->t_next;
+  }
+  wdd::DisplayColumns dc;
+  const bool carry = carried_display(p, &dc);
+  hipEvent_t end;
+  if (u.live && (p->profile_mask & (1 << kAccumulate)) && p->profile_now) p->factored_n += 1;
+  WDD_HIP(p, stage_begin(p, kAccumulate, &end));
+  WDD_HIP(p, wdd::launch_row_fused_obj_next2(p->kpad, p->tscale, p->sx, p->sy, p->chunks, u.live ? p->nchunks : 0,
+                                             p->max_chunk, p->jv, p->w, p->d, p->dlo, p->z, p->nslot, urs, unrows,
+                                             p->t_cur, up_pass, d0out, xp, carry ? &dc : nullptr, next, p->stream));
+  WDD_HIP(p, stage_end(p, end));
+  if (u.live) {
+    p->up_valid = rows;
+    if (u.display_dst) {
+      p->deferred_dst = u.display_dst;
+      column_source(p, &p->deferred_src, &p->deferred_sr, &p->deferred_sm, &p->deferred_nslot,
+                    &p->deferred_slot_stride);
+      p->deferred_in_update = true;
+      p->deferred_d0 = p->d0w;
+    }
+    u.live = false;
+    u.display = false;
+    u.display_dst = nullptr;
+  }
+  if (xdft && x.live) {
+    u = x;
+    x.live = false;
+    x.display = false;
+    x.display_dst = nullptr;
+    std::swap(p->t_cur, p->t_next);
+  }
+  return WDD_OK;
+}
+
+// Runs every held update, oldest first (held2's from its x-DFT, then held's with its own);
+// the newest leaves the display's first pass in `up` when for_display asks for it.
+wdd_status flush_held(wdd_plan_s* p, bool for_display) {
+  wdd_status st;
+  if (p->held2.live && (st = launch_stage2(p, nullptr, for_display && !p->held.live, false)) != WDD_OK) return st;
+  if (p->held.live && (st = run_held(p, nullptr, for_display)) != WDD_OK) return st;
+  return WDD_OK;
+}
+
 // Queues one batch.  With fuse_wiener the row-factored update also performs the Wiener
 // reduction of the updated spectrum; *fused reports whether it did.
 wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, int32_t n, int32_t frames_on_device,
@@ -780,6 +888,10 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
   }
   bool in_order = true;  // frames already grouped by row (a raster batch): no reordering
   for (int32_t i = 0; i < n && in_order; ++i) in_order = ord[i] == i;
+  // held for the next push's launch (pipelined pushes; two-stage ones hold batches of at
+  // most kFactorRows scan rows, one x-DFT's worth: others run unpipelined after the held ones)
+  const bool hold = p->pipeline && !(p->two_stage && nrows > kFactorRows);
+  if (p->pipeline && !hold && (st = flush_held(p, false)) != WDD_OK) return st;
   wdd::ProjectLaunch pl;
   if (!p->fourier) {
     pl.dtype = p->dtype;
@@ -793,16 +905,19 @@ wdd_status push_impl(wdd_plan_s* p, const void* frames, const int32_t* pos_yx, i
     pl.psi_unscale = p->psi_unscale;
     pl.kmap = p->kmap;
     pl.kpad = p->kpad;
-    pl.h = p->pipeline ? p->h_alt : p->h;
+    pl.h = hold ? p->h_alt : p->h;
     pl.up_src = up;
-    pl.up_dst = p->pipeline ? p->upload_alt : p->upload;
+    pl.up_dst = hold ? p->upload_alt : p->upload;
     pl.up_bytes = up_bytes;
     pl.fptr = ftab;
   }
-  if (p->pipeline) {
+  if (hold) {
     // the held batch's update, with this batch's projection in its first launch (or the
-    // projection alone when nothing is held); this batch's update is held in turn
-    if (p->held.live) {
+    // projection alone when nothing is held); this batch's update is held in turn.  Two-stage:
+    // held2's update, held's x-DFT and this projection in one launch
+    if (p->two_stage && (p->held.live || p->held2.live)) {
+      if ((st = launch_stage2(p, &pl, false, true)) != WDD_OK) return st;
+    } else if (!p->two_stage && p->held.live) {
       if ((st = run_held(p, &pl, false)) != WDD_OK) return st;
     } else {
       WDD_HIP(p, stage_begin(p, kProject, &end));
@@ -912,7 +1027,7 @@ wdd_status snapshot_enqueue_impl(wdd_plan_s* p, float* out, int32_t out_on_devic
       p->held.display_dst = reinterpret_cast<float2*>(out);
       return WDD_OK;
     }
-    if ((st = run_held(p, nullptr, true)) != WDD_OK) return st;  // the partial rows for this display
+    if ((st = flush_held(p, true)) != WDD_OK) return st;  // the partial rows for this display
   }
   if ((st = flush_deferred(p)) != WDD_OK) return st;
   if (reduce && p->order_mode == WDD_ORDER_SPECTRUM) {  // object order keeps D current
@@ -1149,7 +1264,8 @@ wdd_status wdd_plan_get_info(wdd_plan_t p, wdd_plan_info* info) {
   info->device_bytes = p->device_bytes;
   info->update_chunks = p->nchunks;
   info->display_slots = p->up ? p->nslot : 0;
-  info->pipelined = p->pipeline ? 1 : 0;
+  info->pipelined = p->two_stage ? 2 : p->pipeline ? 1 : 0;
+  info->kept_columns = p->ncols;
   return WDD_OK;
 }
 

@@ -193,6 +193,30 @@ hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order,
                                      float2* z, float2* up, int nslot, bool in_order, float2* d0out,
                                      const DisplayColumns* dc, const ProjectLaunch& next, hipStream_t st);
 
+// Two-stage pipelined pushes: one launch with the update of a batch whose x-DFT T (per kept
+// v_x: [kRowSetMax][kpad / 4][2] float4, row_fused_t_stride(kpad) apart) an earlier launch
+// wrote to tin, the x-DFT of the next batch into xp.tout (one workgroup per kept v_x, xcols),
+// and the projection of the batch after it (next, or null); nchunks = 0, xp.ncols = 0 leave
+// their parts out.  The update's rows are urows[0 .. unrows); up, d0out, dc as in
+// launch_row_fused_obj.
+struct XdftPart {
+  const float* h;
+  const int* order;
+  const int* xs;
+  RowSet rows;
+  int nrows;
+  bool in_order;
+  const int* xcols;
+  int ncols;
+  float4* tout;
+};
+int row_fused_t_stride(int kpad);
+hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                      int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo,
+                                      float2* z, int nslot, const RowSet& urows, int unrows, const float4* tin,
+                                      float2* up, float2* d0out, const XdftPart& xp, const DisplayColumns* dc,
+                                      const ProjectLaunch* next, hipStream_t st);
+
 // Full Fourier basis (K = ny nx, complex h; see kernels.hip).  Projection: h[b][k_y nx + k_x]
 // = 2D DFT of frame b with exp(+2 pi i ...) / (ny nx); ny, nx powers of two, ny nx <= 4096,
 // fy/fx = exp(+2 pi i m / n) for m < n / 2.  Row DFT: t[r][vx][k] = sum over the frames of

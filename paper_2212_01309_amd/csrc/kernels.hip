@@ -1458,7 +1458,13 @@ __device__ inline void add4(float4& a, const float4 b) {
   a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
 }
 
-template <typename Rows>
+// Modes of row_fused_obj_body: both phases (kFusedBoth); phase 2 from T_r given in global
+// memory (kFusedGivenT: t_io holds this v_x's [nrows][q][2] float4, written by a kFusedOnlyT
+// workgroup of an earlier launch from the same projections, so the results are the same bit
+// for bit); phase 1 alone, T_r written to t_io (kFusedOnlyT: ch.x the v_x, the rest unused).
+constexpr int kFusedBoth = 0, kFusedGivenT = 1, kFusedOnlyT = 2;
+
+template <int MODE = kFusedBoth, typename Rows>
 __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, int kpad, const int* __restrict__ order,
                                                    const int* __restrict__ xs, const Rows& rs, int nrows,
                                                    float tscale, int sx, int sy, const int4 ch,
@@ -1466,7 +1472,7 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
                                                    float2* __restrict__ d, float2* __restrict__ dlo,
                                                    float2* __restrict__ z, int max_chunk, float2* __restrict__ up,
                                                    int nslot, int log2sy, int in_order, float2* __restrict__ d0out,
-                                                   float4* fsm) {
+                                                   float4* fsm, float4* __restrict__ t_io = nullptr) {
   const int q = kpad >> 2, G = kFusedThreads / q;
   const int tid = threadIdx.x, kq = tid % q, grp = tid / q;
   float4* lt = fsm;                                           // [nrows][q][2]: T_r, 4 complex per float4 pair
@@ -1483,13 +1489,18 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
   // The first staging block's frame indices and x positions, and (frames already in row
   // order, order[i] = i) the projections of this lane group's first 8 frames, depend on the
   // kernel arguments only: their loads go out before anything waits for the chunk descriptor.
+  // (phase 1 only) the first staging block's frame indices and x positions, and the
+  // projections of this lane group's first 8 frames
   const float4* h4 = reinterpret_cast<const float4*>(h);
-  const int n_first = min(kFusedFrames, rs.r[0].z);
-  const int fi = rs.r[0].y + min(tid, n_first - 1);
-  const int first_b = gload(order + fi), first_x = gload(xs + fi);
-  const bool pre = in_order && grp + 7 * G < n_first;
+  int n_first = 0, first_b = 0, first_x = 0;
+  bool pre = false;
   float4 hv0[8];
-  {
+  if constexpr (MODE != kFusedGivenT) {
+    n_first = min(kFusedFrames, rs.r[0].z);
+    const int fi = rs.r[0].y + min(tid, n_first - 1);
+    first_b = gload(order + fi);
+    first_x = gload(xs + fi);
+    pre = in_order && grp + 7 * G < n_first;
     // (not in order: frame 0, always a valid row of h, stands in; these loads go unused)
     const int f0 = pre ? rs.r[0].y + grp : 0, fs = pre ? G : 0;
 #pragma unroll
@@ -1501,59 +1512,67 @@ __device__ __forceinline__ void row_fused_obj_body(const float* __restrict__ h, 
 
   // this thread's (j, v_y) of the chunk (cnt <= kFusedThreads): loaded now, stored to LDS
   // after phase 1, so that its round trip hides under phase 1's
-  const int2 myjv = gload(jv + i0 + min(tid, cnt - 1));
-
-  // phase 1: T_r for this vx; the first block of frames is staged here, the others in the loop
-  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-  if (tid < n_first) {
-    const int p = vx * first_x;
-    lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
-    lb[tid] = first_b;
-  }
-  __syncthreads();
-  if (pre) {
+  const int2 myjv = MODE == kFusedOnlyT ? make_int2(0, 0) : gload(jv + i0 + min(tid, cnt - 1));
+  if constexpr (MODE == kFusedGivenT) {
+    // T_r of this v_x, as a kFusedOnlyT workgroup left it
+    for (int e = tid; e < nrows * q * 2; e += kFusedThreads) lt[e] = t_io[e];
+  } else {
+    // phase 1: T_r for this vx; the first block of frames is staged here, the others in the loop
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+    if (tid < n_first) {
+      const int p = vx * first_x;
+      lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+      lb[tid] = first_b;
+    }
+    __syncthreads();
+    if (pre) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[grp + u * G], hv0[u]);
-  }
-  for (int r = 0; r < nrows; ++r) {
-    const int4 row = rs.r[r];
-    for (int f0 = 0; f0 < row.z; f0 += kFusedFrames) {
-      const int n = min(kFusedFrames, row.z - f0);
-      const bool first = r == 0 && f0 == 0;
-      if (!first) {
-        __syncthreads();
-        if (tid < n) {
-          const int at = row.y + f0 + tid;
-          const int b = order[at], p = vx * xs[at];
-          lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
-          lb[tid] = b;
+      for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[grp + u * G], hv0[u]);
+    }
+    for (int r = 0; r < nrows; ++r) {
+      const int4 row = rs.r[r];
+      for (int f0 = 0; f0 < row.z; f0 += kFusedFrames) {
+        const int n = min(kFusedFrames, row.z - f0);
+        const bool first = r == 0 && f0 == 0;
+        if (!first) {
+          __syncthreads();
+          if (tid < n) {
+            const int at = row.y + f0 + tid;
+            const int b = order[at], p = vx * xs[at];
+            lw[tid] = twiddle(px2 ? (p & (sx - 1)) : mod_small(p, sx, invx), sx, tscale);
+            lb[tid] = b;
+          }
+          __syncthreads();
         }
-        __syncthreads();
-      }
-      int i = grp + (first && pre ? 8 * G : 0);
-      for (; i + 7 * G < n; i += 8 * G) {
-        float4 hv[8];
+        int i = grp + (first && pre ? 8 * G : 0);
+        for (; i + 7 * G < n; i += 8 * G) {
+          float4 hv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = h4[(size_t)lb[i + u * G] * q + kq];
+          for (int u = 0; u < 8; ++u) hv[u] = h4[(size_t)lb[i + u * G] * q + kq];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[i + u * G], hv[u]);
+          for (int u = 0; u < 8; ++u) cmac4(a0, a1, lw[i + u * G], hv[u]);
+        }
+        for (; i < n; i += G) cmac4(a0, a1, lw[i], h4[(size_t)lb[i] * q + kq]);
       }
-      for (; i < n; i += G) cmac4(a0, a1, lw[i], h4[(size_t)lb[i] * q + kq]);
-    }
-    lsum[2 * tid] = a0;
-    lsum[2 * tid + 1] = a1;
-    __syncthreads();
-    if (grp == 0) {
-      for (int g = 1; g < G; ++g) {
-        add4(a0, lsum[2 * (g * q + kq)]);
-        add4(a1, lsum[2 * (g * q + kq) + 1]);
+      lsum[2 * tid] = a0;
+      lsum[2 * tid + 1] = a1;
+      __syncthreads();
+      if (grp == 0) {
+        for (int g = 1; g < G; ++g) {
+          add4(a0, lsum[2 * (g * q + kq)]);
+          add4(a1, lsum[2 * (g * q + kq) + 1]);
+        }
+        lt[(size_t)(r * q + kq) * 2] = a0;
+        lt[(size_t)(r * q + kq) * 2 + 1] = a1;
       }
-      lt[(size_t)(r * q + kq) * 2] = a0;
-      lt[(size_t)(r * q + kq) * 2 + 1] = a1;
+      __syncthreads();
+      a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      a1 = a0;
     }
-    __syncthreads();
-    a0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    a1 = a0;
+    if constexpr (MODE == kFusedOnlyT) {
+      for (int e = tid; e < nrows * q * 2; e += kFusedThreads) t_io[e] = lt[e];
+      return;
+    }
   }
 
   if (tid < cnt) {
@@ -1736,6 +1755,79 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
   const int4 ch = chunks[xcd_row(b - pfront, nchunks)];
   row_fused_obj_body(h, kpad, order, xs, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy,
                      in_order, d0out, fsm);
+}
+
+// Two-stage pipelined pushes: one launch holds the update of batch i - 2, whose x-DFT T_r
+// (one row of kFusedOnlyT output per kept v_x) an earlier launch left in tin; the x-DFT of
+// batch i - 1 into tout, one workgroup per kept v_x (xcols[0 .. ncols)), from the projections
+// the launch before wrote; and the projection of batch i.  None reads what another writes.
+// The chunks skip phase 1 (kFusedGivenT), so W streaming starts at once, and the x-DFT is
+// formed once per v_x instead of once per chunk.  Grid: projections 0 .. pfront - 1, the x-DFT
+// workgroups, the update's chunks, the other projections, then the display rows.  Any part
+// may be empty.  T per v_x: [kRowSetMax][kpad / 4][2] float4 at t + v_x * tstride.
+struct NextArgs {
+  const float* h;      // x-DFT part: the projections of batch i - 1 and their upload block
+  const int* order;
+  const int* xs;
+  RowSet rows;
+  int nrows, in_order, ncols;
+  const int* xcols;
+  float4* tout;
+};
+// Order of k_row_fused_obj_next2's grid segments: 0 front projections, 1 x-DFT columns, 2 the
+// update's chunks, 3 the other projections, 4 display rows.  Measured per two-stage step
+// (orders 01234 / 02134 / 02314 / 02341): 128^2 scan, 64^2 frames, K = 256 12.0 / 11.5 /
+// 11.4 / 11.5 us (one stage: 12.2 us); 512^2 scan, 256^2 frames 35.6 / 40.6 / 36.1 / 35.6 us
+// (one stage: 35.8 us); 256^2 scan, 128^2 frames 14.6 / 14.8 / 14.3 / 14.6 us (one stage:
+// 13.5 us).
+constexpr int kStage2Order[5] = {0, 2, 3, 1, 4};
+
+template <int PREC>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_row_fused_obj_next2(
+    int kpad, RowSet rs, int nrows, float tscale, int sx, int sy, const int4* __restrict__ chunks,
+    const int2* __restrict__ jv, const float2* __restrict__ w, float2* __restrict__ d, float2* __restrict__ dlo,
+    float2* __restrict__ z, int max_chunk, float2* __restrict__ up, int nslot, int log2sy,
+    float2* __restrict__ d0out, int nchunks, const float4* __restrict__ tin, int tstride, NextArgs xa,
+    DispArgs disp, ProjArgs pa, int pfront) {
+  extern __shared__ float4 fsm[];
+  const int b = (int)blockIdx.x;
+  const int nproj = pa.n > 0 ? pa.n + (pa.up_words > 0 ? 1 : 0) : 0;
+  // the grid's segments in kStage2Order: front projections, x-DFT columns, chunks, the other
+  // projections, display rows
+  const int len[5] = {pfront, xa.ncols, nchunks, nproj - pfront, (int)gridDim.x - xa.ncols - nchunks - nproj};
+  int seg = 0, off = b;
+  for (int k = 0; k < 5; ++k) {
+    seg = kStage2Order[k];
+    if (off < len[seg]) break;
+    off -= len[seg];
+  }
+  if (seg == 0 || seg == 3) {  // a projection
+    const int pi = seg == 0 ? off : pfront + off;
+    if (pi == pa.n)
+      upload_block(pa.up_src, pa.up_dst, pa.up_words, (int)threadIdx.x, kFusedThreads);
+    else
+      project_next<PREC>(pa, reinterpret_cast<float*>(fsm), pi);
+    return;
+  }
+  if (seg == 4) {
+    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
+                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, off,
+                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+    return;
+  }
+  if (seg == 1) {  // the x-DFT of one kept v_x of batch i - 1
+    const int vx = xa.xcols[off];
+    row_fused_obj_body<kFusedOnlyT>(xa.h, kpad, xa.order, xa.xs, xa.rows, xa.nrows, tscale, sx, sy,
+                                    make_int4(vx, 0, 1, 0), jv, w, d, dlo, z, max_chunk, nullptr, nslot, log2sy,
+                                    xa.in_order, nullptr, fsm, xa.tout + (size_t)vx * tstride);
+    return;
+  }
+  // (the chunks' first workgroup need not sit at a multiple of 8: their XCDs rotate, each XCD
+  // still taking a contiguous range of neighbouring v_x)
+  const int4 ch = chunks[xcd_row(off, nchunks)];
+  row_fused_obj_body<kFusedGivenT>(nullptr, kpad, nullptr, nullptr, rs, nrows, tscale, sx, sy, ch, jv, w, d, dlo, z,
+                                   max_chunk, up, nslot, log2sy, 1, d0out, fsm,
+                                   const_cast<float4*>(tin) + (size_t)ch.x * tstride);
 }
 
 // Row passes of several object-order updates in one launch: workgroup b takes work item
@@ -2421,6 +2513,95 @@ hipError_t launch_row_fused_obj_next(const float* h, int kpad, const int* order,
                      fs.da, pa, pfront);                                                                            \
   break
   switch (next.precision) {
+    case WDD_FP32: WDD_LAUNCH(WDD_FP32);
+    case WDD_BF16_HILO: WDD_LAUNCH(WDD_BF16_HILO);
+    case WDD_FP16_HILO: WDD_LAUNCH(WDD_FP16_HILO);
+    case WDD_BF16: WDD_LAUNCH(WDD_BF16);
+    case WDD_FP16: WDD_LAUNCH(WDD_FP16);
+    default: return hipErrorInvalidValue;
+  }
+#undef WDD_LAUNCH
+  return hipGetLastError();
+}
+
+int row_fused_t_stride(int kpad) { return kRowSetMax * (kpad / 4) * 2; }
+
+hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, const int4* chunks, int nchunks,
+                                      int max_chunk, const int2* jv, const float2* w, float2* d, float2* dlo,
+                                      float2* z, int nslot, const RowSet& urows, int unrows, const float4* tin,
+                                      float2* up, float2* d0out, const XdftPart& xp, const DisplayColumns* dc,
+                                      const ProjectLaunch* next, hipStream_t st) {
+  if (nchunks < 0 || max_chunk < 1 || max_chunk > kFusedThreads || xp.ncols < 0) return hipErrorInvalidValue;
+  if (nchunks > 0 && (unrows < 1 || unrows > kRowSetMax || !tin)) return hipErrorInvalidValue;
+  if (xp.ncols > 0 && (xp.nrows < 1 || xp.nrows > kRowSetMax || !xp.h || !xp.order || !xp.xs || !xp.xcols ||
+                       !xp.tout))
+    return hipErrorInvalidValue;
+  const int nproj_frames = next ? next->n : 0;
+  if (next && (next->n < 1 || next->kpad != kpad ||
+               !row_fused_next_supported(next->dtype, next->precision, next->ny, next->nx, kpad)))
+    return hipErrorInvalidValue;
+  int log2sy = 0;
+  if (up) {
+    while ((1 << log2sy) < sy) ++log2sy;
+    if ((1 << log2sy) != sy || sy > kDisplayRowMax || nslot < 1 || nslot > kMaxSlots) return hipErrorInvalidValue;
+  }
+  size_t lds = row_fused_lds_bytes(kpad, kRowSetMax, max_chunk);
+  DispArgs da;
+  std::memset(&da, 0, sizeof(da));
+  int rows_disp = 0;
+  if (dc) {
+    int lg = 0;
+    while ((1 << lg) < dc->len) ++lg;
+    if (dc->rows < 1 || (1 << lg) != dc->len || dc->nslot < 1 || dc->nslot > kMaxSlots) return hipErrorInvalidValue;
+    da.din = dc->din;
+    da.dout = dc->dout;
+    da.len = dc->len;
+    da.log2len = lg;
+    da.e = dc->e;
+    da.d0 = dc->d0;
+    da.s_total = dc->s_total;
+    da.in_sr = dc->in_sr;
+    da.in_sm = dc->in_sm;
+    da.out_sr = dc->out_sr;
+    da.out_sc = dc->out_sc;
+    da.nslot = dc->nslot;
+    da.slot_stride = dc->slot_stride;
+    rows_disp = dc->rows;
+    lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
+  }
+  ProjArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  int precision = WDD_FP32;
+  if (next) {
+    pa = proj_args(*next);
+    precision = next->precision;
+    lds = std::max(lds, next_project_lds(next->precision, next->ny, next->nx, kpad));
+  }
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  const int nproj = nproj_frames > 0 ? nproj_frames + (pa.up_words > 0 ? 1 : 0) : 0;
+  const int pfront = std::min(kNextProjFront, nproj) / 8 * 8;
+  const int total = nproj + xp.ncols + nchunks + rows_disp;
+  if (total < 1) return hipSuccess;
+  NextArgs xa;
+  std::memset(&xa, 0, sizeof(xa));
+  xa.h = xp.h;
+  xa.order = xp.order;
+  xa.xs = xp.xs;
+  xa.rows = xp.rows;
+  xa.nrows = xp.nrows;
+  xa.in_order = xp.in_order ? 1 : 0;
+  xa.ncols = xp.ncols;
+  xa.xcols = xp.xcols;
+  xa.tout = xp.tout;
+  hipError_t e;
+  const dim3 grid(total), block(kFusedThreads);
+#define WDD_LAUNCH(P)                                                                                           \
+  if ((e = allow_full_lds<k_row_fused_obj_next2<P>>()) != hipSuccess) return e;                                 \
+  hipLaunchKernelGGL(k_row_fused_obj_next2<P>, grid, block, lds, st, kpad, urows, unrows, tscale, sx, sy, chunks, \
+                     jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, d0out, nchunks, tin,                      \
+                     row_fused_t_stride(kpad), xa, da, pa, pfront);                                              \
+  break
+  switch (precision) {
     case WDD_FP32: WDD_LAUNCH(WDD_FP32);
     case WDD_BF16_HILO: WDD_LAUNCH(WDD_BF16_HILO);
     case WDD_FP16_HILO: WDD_LAUNCH(WDD_FP16_HILO);

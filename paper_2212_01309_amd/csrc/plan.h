@@ -97,6 +97,15 @@ struct wdd_plan_impl {
     bool display = false;         // a deferred snapshot follows the batch
     float2* display_dst = nullptr;
   } held;
+  // two-stage pipelined pushes (pipeline = 2): `held` is the last pushed batch (projected), and
+  // held2 the one before it, whose x-DFT (one row set per kept v_x, xcols) is in t_cur; each
+  // push's launch updates held2, forms the x-DFT of `held` into t_next and projects the new
+  // batch; t_cur and t_next then swap
+  bool two_stage = false;
+  Held held2;
+  float4 *t_cur = nullptr, *t_next = nullptr;
+  int32_t* xcols = nullptr;
+  int32_t ncols = 0;       // kept v_x columns (object order)
   void* frames = nullptr;
   float2 *d = nullptr, *z = nullptr, *u = nullptr;
   float2* dlo = nullptr;  // object order: the rounding remainder of D (D = d + dlo, compensated sum)

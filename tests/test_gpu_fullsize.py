@@ -43,13 +43,13 @@ def large_whole_acquisition():
     return wl, pos, pool, all_f, pick, a, d
 
 
-@pytest.mark.parametrize("order,pipeline", [(wdd.WDD_ORDER_OBJECT, False), (wdd.WDD_ORDER_OBJECT, True),
-                                            (wdd.WDD_ORDER_SPECTRUM, False)])
+@pytest.mark.parametrize("order,pipeline", [(wdd.WDD_ORDER_OBJECT, 0), (wdd.WDD_ORDER_OBJECT, 1),
+                                            (wdd.WDD_ORDER_OBJECT, 2), (wdd.WDD_ORDER_SPECTRUM, 0)])
 def test_whole_large_acquisition(large_whole_acquisition, order, pipeline):
     import torch
     wl, pos, pool, all_f, pick, a_ref, d_ref = large_whole_acquisition
     obj = order == wdd.WDD_ORDER_OBJECT
-    say(f"[fullsize] large, {'object' if obj else 'spectrum'} order{', pipelined' if pipeline else ''}: "
+    say(f"[fullsize] large, {'object' if obj else 'spectrum'} order, pipeline {pipeline}: "
         f"{len(pos)} frames in batches of {wl.batch}")
     dev = device(pool)
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")

@@ -1,5 +1,6 @@
 """Pipelined pushes (wdd_options.pipeline): each batch's object-order update runs in the next
-push's launch beside that push's projection (k_row_fused_obj_next).
+push's launch beside that push's projection (k_row_fused_obj_next); with two stages the
+batch's x-DFT runs one launch ahead of its update, once per kept v_x (k_row_fused_obj_next2).
 
 Detectors of at most 128 rows give every tile a wave of its own in both projections, so the
 pipelined plan must reproduce the unpipelined one bit for bit: D, every deferred image and
@@ -28,27 +29,30 @@ def _case(seed, s, n, count, raster=False):
     return frames, pos
 
 
+@pytest.mark.parametrize("stages", [1, 2])
 @pytest.mark.parametrize("s,n,raster,precision", [(32, 64, False, "fp32"), (32, 64, True, "fp32"),
                                                   (64, 128, True, "fp32"), (16, 32, False, "fp32"),
                                                   (32, 64, False, "bf16_hilo"), (32, 128, True, "fp16_hilo"),
                                                   (32, 96, True, "bf16")])
-def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision):
+def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision, stages):
     """Deferred snapshots after every push, then the calls that must run a held update first
     (inspection of D and of the last projections, a blocking snapshot, a checkpoint, a reset):
     everything equals the unpipelined plan bit for bit, in FP32 and in the reduced-precision
-    projections (one tile per wave in both launches).  A blocking snapshot right after a
+    projections (one tile per wave in both launches), with one stage or two (scattered batches
+    on more than 16 rows run unpipelined there, after the held ones).  A blocking snapshot right after a
     push equals the unpipelined wdd_push_snapshot."""
     import torch
     b, steps = 64, 9
-    say(f"[pipeline] scan {s}^2, detector {n}^2, {precision}, {'raster' if raster else 'scattered'} batches of {b}")
+    say(f"[pipeline] {stages} stage(s), scan {s}^2, detector {n}^2, {precision}, "
+        f"{'raster' if raster else 'scattered'} batches of {b}")
     frames, pos = _case(7 + s + n, s, n, b * (steps + 3), raster)
     dev = device(frames)
     blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
     img = lambda: torch.empty((s, s), dtype=torch.complex64, device="cuda")
     outs = {True: [img() for _ in range(steps)], False: [img() for _ in range(steps)]}
     kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT, precision=precision)
-    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
-        assert p.info().pipelined == 1 and r.info().pipelined == 0
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=stages, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        assert p.info().pipelined == stages and r.info().pipelined == 0
         for i in range(steps):
             p.push_snapshot(*blk(i), out=outs[True][i], wait=False, defer=True)
             r.push_snapshot(*blk(i), out=outs[False][i], wait=False, defer=True)
@@ -70,35 +74,45 @@ def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision):
         assert p.checkpoint() == r.checkpoint()
         p.reset()
         r.reset()
-        # a snapshot right after a push: the held update leaves the display's first pass, as
-        # wdd_push_snapshot's update does (not the two-pass display of push + snapshot)
+        # a snapshot right after a push: a held update leaves the display's first pass, as
+        # wdd_push_snapshot's update does (not the two-pass display of push + snapshot); two
+        # stages hold batches of at most 16 scan rows, others run at once
         p.push(*blk(0))
-        assert np.array_equal(p.snapshot(), r.push_snapshot(*blk(0)))
+        held = stages == 1 or len(np.unique(blk(0)[1][:, 0])) <= 16
+        if held:
+            ref = r.push_snapshot(*blk(0))
+        else:
+            r.push(*blk(0))
+            ref = r.snapshot()
+        assert np.array_equal(p.snapshot(), ref)
 
 
-def test_deferred_image_lands_two_pushes_later():
-    """A deferred snapshot after push i: the held update (in push i + 1's launch) leaves its
-    partial rows, push i + 2's launch writes the image; the stream alone then completes it."""
+@pytest.mark.parametrize("stages", [1, 2])
+def test_deferred_image_lands_stages_plus_one_pushes_later(stages):
+    """A deferred snapshot after push i: the held update (in push i + stages' launch) leaves
+    its partial rows, push i + stages + 1's launch writes the image; the stream alone then
+    completes it."""
     import torch
     s, n, b = 32, 64, 64
-    frames, pos = _case(3, s, n, b * 4)
+    frames, pos = _case(3, s, n, b * 5)
     dev = device(frames)
     blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
     outs = [torch.full((s, s), float("nan"), dtype=torch.complex64, device="cuda") for _ in range(2)]
     kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
-    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=stages, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
         p.push(*blk(0))
         r.push(*blk(0))
         p.push_snapshot(*blk(1), out=outs[0], wait=False, defer=True)
         ref = r.push_snapshot(*blk(1))
-        p.push(*blk(2))
-        p.push(*blk(3))
+        for i in range(stages + 1):
+            p.push(*blk(2 + i))
         torch.cuda.synchronize()     # no plan call in between: the pushes' launches wrote it
         assert np.array_equal(outs[0].cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("stages", [1, 2])
 @pytest.mark.parametrize("n,raster", [(160, True), (256, False)])
-def test_two_tiles_per_wave_against_the_oracle(n, raster):
+def test_two_tiles_per_wave_against_the_oracle(n, raster, stages):
     """Detectors of more than 128 rows: the merged launch's 8 waves take two 16-row tiles each.
     D and the images against the oracle, and against the unpipelined plan within FP32
     rounding of the projection's summation order."""
@@ -109,7 +123,7 @@ def test_two_tiles_per_wave_against_the_oracle(n, raster):
     dev = device(frames)
     kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
     outs = [torch.empty((s, s), dtype=torch.complex64, device="cuda") for _ in range(steps)]
-    with wdd.Plan(radius, s, s, n, n, k, pipeline=True, **kw) as p, wdd.Plan(radius, s, s, n, n, k, **kw) as r:
+    with wdd.Plan(radius, s, s, n, n, k, pipeline=stages, **kw) as p, wdd.Plan(radius, s, s, n, n, k, **kw) as r:
         for i in range(steps):
             p.push_snapshot(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b], out=outs[i], wait=False, defer=True)
             r.push(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
@@ -124,7 +138,8 @@ def test_two_tiles_per_wave_against_the_oracle(n, raster):
     assert errs["D"] <= TOL and errs["O"] <= TOL and errs["D_vs_unpipelined"] <= 1e-6
 
 
-def test_pipelined_host_frames_and_ragged_batches():
+@pytest.mark.parametrize("stages", [1, 2])
+def test_pipelined_host_frames_and_ragged_batches(stages):
     """Frames from host memory (staged through the plan's pinned slots) and batches of changing
     size, some on many scan rows (several update passes): bit for bit the unpipelined plan."""
     import torch
@@ -134,7 +149,7 @@ def test_pipelined_host_frames_and_ragged_batches():
     dev = device(frames)
     outs = {True: [], False: []}
     kw = dict(max_batch=64, order=wdd.WDD_ORDER_OBJECT)
-    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=True, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=stages, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
         b0 = 0
         for i, m in enumerate(sizes):
             fr = frames[b0:b0 + m] if i % 2 == 0 else dev[b0:b0 + m]   # host and device frames in turn

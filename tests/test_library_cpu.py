@@ -137,15 +137,17 @@ def test_pipelined_plan_rejects_unsupported_settings_before_touching_a_device(kw
     args = dict(ny=64, nx=64, order=wdd.WDD_ORDER_OBJECT, dtype=wdd.WDD_U16)
     args.update(kw)
     ny, nx = args.pop("ny"), args.pop("nx")
-    with pytest.raises(wdd.WddError) as ei:
-        wdd.Plan(8.0, 16, 16, ny, nx, 64, pipeline=True, **args)
-    assert ei.value.code == wdd.WDD_EINVAL
-    assert "pipelined" in str(ei.value)
+    for stages in (1, 2):
+        with pytest.raises(wdd.WddError) as ei:
+            wdd.Plan(8.0, 16, 16, ny, nx, 64, pipeline=stages, **args)
+        assert ei.value.code == wdd.WDD_EINVAL
+        assert "pipelined" in str(ei.value)
 
 
-def test_pipeline_option_takes_zero_or_one():
+@pytest.mark.parametrize("bad", [-1, 3])
+def test_pipeline_option_takes_zero_one_or_two(bad):
     o = wdd._options(0.01, 0.0, 256, order=wdd.WDD_ORDER_OBJECT)
-    o.pipeline = 2
+    o.pipeline = bad
     h = wdd._P()
     st = wdd.load_library().wdd_plan(ctypes.byref(wdd._probe(8.0, 64, 64, None, 0.0, 1.0)),
                                      ctypes.byref(wdd.Scan(16, 16, 1.0)), ctypes.byref(wdd.Detector(64, 64, 0)),
