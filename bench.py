@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--pipeline", default="auto", choices=["auto", "on", "two", "off"],
                     help="pipelined pushes (on: each batch's update in the next push's launch, beside that "
                          "push's projection; two: also the batch's x-DFT one launch ahead of its update); auto: "
-                         "the pipelined form where the plan supports it (object order, uint16 frames of 32..256 "
+                         "two stages where the plan supports them (object order, uint16 frames of 32..256 "
                          "columns in multiples of 32 and <= 256 rows, <= 128 with a reduced precision)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 5 plain device copies of MB megabytes (reference for HBM byte counters) and exit")
@@ -240,10 +240,10 @@ def cpu_baseline(wl, frames, pos, seconds, fourier=False):
 PRECISION_CODES = {"fp32": 0, "bf16_hilo": 1, "fp16_hilo": 2, "bf16": 3, "fp16": 4}  # wdd_precision
 
 
-def auto_stages(info):
-    """Pipeline stages of --pipeline auto: two where the update's chunks share their columns'
-    x-DFT three or more to one (the second stage forms it once per column), else one."""
-    return 2 if info.update_chunks >= 3 * max(1, info.kept_columns) else 1
+# Pipeline stages of --pipeline auto: two.  With the longer chunks of two-stage plans the second
+# stage measured faster than one on every workload here (per step: large 35.5 against 35.6 us,
+# medium 11.0 against 12.1 us, defocus 13.1 against 13.5 us).
+AUTO_STAGES = 2
 
 
 def pipeline_supported(wl, order, precision, fourier):
@@ -324,10 +324,11 @@ def precision_lines(torch, wdd, synth, steps, warmup):
     shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
     out = {"workload": "defocus: 256x256 scan, 128x128 uint16 detector (1e3 e/frame, pi rad defocus at the rim), "
                        "K=64, 51167 kept frequencies, object order, batches of 256, snapshot after every batch, "
-                       "pipelined pushes",
+                       "two pipeline stages",
            "steps": steps}
     for prec in ("fp32", "bf16_hilo", "fp16_hilo"):
-        with make_plan(wdd, wl, "object", prec, pipeline=pipeline_supported(wl, "object", prec, False)) as plan:
+        with make_plan(wdd, wl, "object", prec,
+                       pipeline=AUTO_STAGES if pipeline_supported(wl, "object", prec, False) else 0) as plan:
             el, _ = timed(torch, plan, batches, shown, warmup, steps, True)
         out[prec] = {"frames_per_s": steps * wl.batch / el, "us_per_step": el / steps * 1e6}
     return out
@@ -532,13 +533,9 @@ def main():
     can_pipe = pipeline_supported(wl, args.order, args.precision, fourier)
     if args.pipeline in ("on", "two") and not can_pipe:
         sys.exit(f"--pipeline {args.pipeline}: this workload / order / precision has no pipelined form")
-    pipe_stages = {"off": 0, "on": 1, "two": 2}.get(args.pipeline, 1 if can_pipe else 0)
+    chosen = AUTO_STAGES if can_pipe else 0   # the form --pipeline auto takes
+    pipe_stages = {"off": 0, "on": 1, "two": 2}.get(args.pipeline, chosen)
     plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipe_stages)
-    chosen = auto_stages(plan.info()) if can_pipe else 0   # the form --pipeline auto takes
-    if args.pipeline == "auto" and chosen != pipe_stages:
-        plan.close()
-        pipe_stages = chosen
-        plan = make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=pipe_stages)
     pipelined = pipe_stages > 0
     n_freq, k = plan.n_freq, plan.k
     plan_info = plan.info()
@@ -588,7 +585,7 @@ def main():
 
     if not args.no_extras and can_pipe:
         # the same steps with the other push form (pipelined or not)
-        with make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=not pipelined) as p2:
+        with make_plan(wdd, wl, args.order, args.precision, fourier, pipeline=0 if pipelined else AUTO_STAGES) as p2:
             el, _ = timed(torch, p2, batches, shown, args.warmup, args.steps, defer)
         extras["unpipelined" if pipelined else "pipelined"] = {
             "frames_per_s": args.steps * wl.batch / el, "us_per_step": el / args.steps * 1e6}

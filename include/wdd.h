@@ -136,10 +136,11 @@ typedef struct {
  * batch's projections along the scan rows (Section 6.1, the F_x factor of eq. outer_prod),
  * formed once per kept v_x, runs one launch ahead of the update, which then streams W at
  * once; a push's launch holds the update of batch i - 2, the x-DFT of batch i - 1 and the
- * projection of batch i, results are the same as with pipeline = 1, and a deferred image
- * lands three pushes later.  Batches on more than 16 scan rows run unpipelined after the held
- * ones.  Two stages pay where several chunks share a column (update_chunks well above
- * kept_columns in wdd_plan_info).  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
+ * projection of batch i, and a deferred image lands three pushes later.  With no x-DFT to
+ * repeat, the update is cut into longer chunks (at least four rounds of its frequency loop), so
+ * D is the same as with pipeline = 1 while the images, whose first display pass is summed over
+ * one partial row per chunk, differ from it by FP32 rounding.  Batches on more than 16 scan
+ * rows run unpipelined after the held ones.  Needs WDD_ORDER_OBJECT, the Hermite-Gauss
  * basis, uint16 frames of 32..256 columns in multiples of 32 and at most 256 rows (128 with a
  * reduced-precision projection), and power-of-two scan sides with Sy <= 1024; other plans:
  * WDD_EINVAL. */

@@ -291,9 +291,19 @@ wdd_status create(wdd_plan_s* p, const wdd_tables_s& t, const wdd_options& opts,
   // Short chunks (at most three such rounds) favour fewer, larger chunks, long ones more
   // workgroups: n_freq / 384 or n_freq / 512 per chunk (measured on 128^2, 256^2 and 512^2
   // scans: 23.0 -> 21.0, 23.7 -> 22.7 and 51.9 us per pipelined step).
+  // Two pipeline stages: no chunk forms the x-DFT (one workgroup per v_x does, a launch ahead),
+  // so chunks can be longer: at least four rounds, n_freq / 448 on large scans (measured per
+  // two-stage step: 512^2 scan, K = 128: n/384 (224) 36.2, n/448 (256) 35.5, n/400 (288) 35.4,
+  // 320 37.7, 384 38.6 us; 256^2 scan, K = 64: 128 14.3, 192 14.1, 256 13.1 us; 128^2 scan,
+  // K = 256: 32 11.6, 48 11.6, 64 11.0, 80 11.5, 96 13.4, 128 15.6 us).
   const int64_t per_round = 2 * (4 * wdd::kFusedThreads / p->kpad);
-  int64_t chunk = (p->n_freq + 383) / 384;
-  if (chunk > 3 * per_round) chunk = (p->n_freq + 511) / 512;
+  int64_t chunk;
+  if (p->two_stage) {
+    chunk = std::max<int64_t>(4 * per_round, (p->n_freq + 447) / 448);
+  } else {
+    chunk = (p->n_freq + 383) / 384;
+    if (chunk > 3 * per_round) chunk = (p->n_freq + 511) / 512;
+  }
   // a whole number of rounds: one frequency past a multiple of 2 G would cost its chunk a
   // further round trip to HBM for W, and the slowest chunks set the launch's duration
   if (chunk > per_round) chunk -= chunk % per_round;

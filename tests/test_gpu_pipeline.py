@@ -3,9 +3,12 @@ push's launch beside that push's projection (k_row_fused_obj_next); with two sta
 batch's x-DFT runs one launch ahead of its update, once per kept v_x (k_row_fused_obj_next2).
 
 Detectors of at most 128 rows give every tile a wave of its own in both projections, so the
-pipelined plan must reproduce the unpipelined one bit for bit: D, every deferred image and
-every inspected state.  Larger detectors (two 16-row tiles per wave in the merged launch)
-sum the projection in another order and are compared with the oracle instead."""
+pipelined plan must reproduce the unpipelined one bit for bit: D, the projections, the
+checkpoints, and with one stage every image.  Two-stage plans cut the update into longer
+chunks, so the display's partial rows (one per chunk) are summed in another grouping: their
+images equal the unpipelined plan's to FP32 rounding.  Larger detectors (two 16-row tiles
+per wave in the merged launch) sum the projection in another order and are compared with the
+oracle instead."""
 import numpy as np
 import pytest
 
@@ -16,6 +19,16 @@ from gpu_util import device, rel_d, rel_img, say
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+IMG_TOL = 1e-6   # two stages against the unpipelined plan: partial display rows grouped otherwise
+
+
+def same_image(a, b, stages):
+    """Bit for bit with one stage; to FP32 rounding of the display's partial-row sums with two."""
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    b = b.cpu().numpy() if hasattr(b, "cpu") else np.asarray(b)
+    if stages == 1:
+        return np.array_equal(a, b)
+    return np.isfinite(a).all() and rel_img(a, b) <= IMG_TOL
 
 
 def _case(seed, s, n, count, raster=False):
@@ -37,9 +50,10 @@ def _case(seed, s, n, count, raster=False):
 def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision, stages):
     """Deferred snapshots after every push, then the calls that must run a held update first
     (inspection of D and of the last projections, a blocking snapshot, a checkpoint, a reset):
-    everything equals the unpipelined plan bit for bit, in FP32 and in the reduced-precision
-    projections (one tile per wave in both launches), with one stage or two (scattered batches
-    on more than 16 rows run unpipelined there, after the held ones).  A blocking snapshot right after a
+    D, the projections and the checkpoints equal the unpipelined plan's bit for bit, in FP32 and
+    in the reduced-precision projections (one tile per wave in both launches), with one stage or
+    two (scattered batches on more than 16 rows run unpipelined there, after the held ones); the
+    images too with one stage, to FP32 rounding with two.  A blocking snapshot right after a
     push equals the unpipelined wdd_push_snapshot."""
     import torch
     b, steps = 64, 9
@@ -59,7 +73,7 @@ def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision, stages
         p.sync()
         r.sync()
         for i in range(steps):
-            assert torch.equal(outs[True][i], outs[False][i]), i
+            assert same_image(outs[True][i], outs[False][i], stages), i
         # held updates run before every call that reads the state
         for q in (p, r):
             q.push(*blk(steps))
@@ -67,7 +81,7 @@ def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision, stages
         for q in (p, r):
             q.push(*blk(steps + 1))
         assert np.array_equal(p.projection(), r.projection())
-        assert np.array_equal(p.snapshot(), r.snapshot())
+        assert same_image(p.snapshot(), r.snapshot(), stages)
         assert p.info().frames_seen == r.info().frames_seen == b * (steps + 2)
         for q in (p, r):
             q.push(*blk(steps + 2))
@@ -84,7 +98,7 @@ def test_pipelined_pushes_equal_unpipelined_ones(s, n, raster, precision, stages
         else:
             r.push(*blk(0))
             ref = r.snapshot()
-        assert np.array_equal(p.snapshot(), ref)
+        assert same_image(p.snapshot(), ref, stages)
 
 
 @pytest.mark.parametrize("stages", [1, 2])
@@ -107,7 +121,7 @@ def test_deferred_image_lands_stages_plus_one_pushes_later(stages):
         for i in range(stages + 1):
             p.push(*blk(2 + i))
         torch.cuda.synchronize()     # no plan call in between: the pushes' launches wrote it
-        assert np.array_equal(outs[0].cpu().numpy(), ref)
+        assert same_image(outs[0], ref, stages)
 
 
 @pytest.mark.parametrize("stages", [1, 2])
@@ -141,7 +155,8 @@ def test_two_tiles_per_wave_against_the_oracle(n, raster, stages):
 @pytest.mark.parametrize("stages", [1, 2])
 def test_pipelined_host_frames_and_ragged_batches(stages):
     """Frames from host memory (staged through the plan's pinned slots) and batches of changing
-    size, some on many scan rows (several update passes): bit for bit the unpipelined plan."""
+    size, some on many scan rows (several update passes): D bit for bit the unpipelined plan's,
+    the images as in the first test."""
     import torch
     s, n = 32, 64
     sizes = [64, 7, 33, 1, 64, 50, 2]
@@ -161,6 +176,6 @@ def test_pipelined_host_frames_and_ragged_batches(stages):
         p.sync()
         r.sync()
         for i in range(len(sizes)):
-            assert torch.equal(outs[True][i], outs[False][i]), i
+            assert same_image(outs[True][i], outs[False][i], stages), i
         assert np.array_equal(p.spectrum(), r.spectrum())
         assert p.info().frames_seen == r.info().frames_seen == sum(sizes)
