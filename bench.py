@@ -118,8 +118,11 @@ def roofline(wl, n_freq, k, order, fourier, precision, event_us, display_bytes=0
                                                  "pass in the same launch)" if display_bytes else "")
         if pipelined:
             nbytes += (2.0 if wl.dose else 4.0) * wl.n * wl.n * wl.batch + 4.0 * k * wl.batch
-            kernel = ("k_row_fused_obj_next2<%d>" if pipelined == 2 else "k_row_fused_obj_next<%d>") % \
-                PRECISION_CODES[precision]  # as recorded
+            if pipelined == 2:   # as recorded: precision, and frames of more than 128 rows
+                kernel = "k_row_fused_obj_next2<%d,%s>" % (PRECISION_CODES[precision],
+                                                         "true" if wl.n > 128 else "false")
+            else:
+                kernel = "k_row_fused_obj_next<%d>" % PRECISION_CODES[precision]
             rule += " + frames + 4 * K * batch (the next batch's projection in the same launch)"
     else:
         # read and write A, read W (the Wiener reduction fused in before a snapshot)

@@ -1762,9 +1762,10 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
 // batch i - 1 into tout, one workgroup per kept v_x (xcols[0 .. ncols)), from the projections
 // the launch before wrote; and the projection of batch i.  None reads what another writes.
 // The chunks skip phase 1 (kFusedGivenT), so W streaming starts at once, and the x-DFT is
-// formed once per v_x instead of once per chunk.  Grid: projections 0 .. pfront - 1, the x-DFT
-// workgroups, the update's chunks, the other projections, then the display rows.  Any part
-// may be empty.  T per v_x: [kRowSetMax][kpad / 4][2] float4 at t + v_x * tstride.
+// formed once per v_x instead of once per chunk.  Grid: five segments (projections
+// 0 .. pfront - 1, the x-DFT workgroups, the update's chunks, the other projections, the display
+// rows) in the order the launcher picks.  Any part may be empty.  T per v_x:
+// [kRowSetMax][kpad / 4][2] float4 at t + v_x * tstride.
 struct NextArgs {
   const float* h;      // x-DFT part: the projections of batch i - 1 and their upload block
   const int* order;
@@ -1774,15 +1775,22 @@ struct NextArgs {
   const int* xcols;
   float4* tout;
 };
-// Order of k_row_fused_obj_next2's grid segments: 0 front projections, 1 x-DFT columns, 2 the
-// update's chunks, 3 the other projections, 4 display rows.  Measured per two-stage step
-// (orders 01234 / 02134 / 02314 / 02341): 128^2 scan, 64^2 frames, K = 256 12.0 / 11.5 /
-// 11.4 / 11.5 us (one stage: 12.2 us); 512^2 scan, 256^2 frames 35.6 / 40.6 / 36.1 / 35.6 us
-// (one stage: 35.8 us); 256^2 scan, 128^2 frames 14.6 / 14.8 / 14.3 / 14.6 us (one stage:
-// 13.5 us).
-constexpr int kStage2Order[5] = {0, 2, 3, 1, 4};
+// Order of k_row_fused_obj_next2's grid segments, as octal digits, first segment lowest: 0 front
+// projections, 1 x-DFT columns, 2 the update's chunks, 3 the other projections, 4 display rows.
+// Measured per two-stage step with 32 projections in front, orders 02314 / 02341 / 02134 /
+// 01234: 512^2 scan, 256^2 frames, K = 128 35.4 / 34.9 / 42.0 / 35.4 us; 256^2 scan, 128^2
+// frames, K = 64 13.2 / 13.3 / 13.0 / 14.0 us; 128^2 scan, 64^2 frames, K = 256 11.1 / 11.4 /
+// 11.2 / 11.6 us; order 02314 with no projection in front 35.7 / 13.1 / 10.8 us, with 64
+// 35.3 / 13.1 / 11.2 us.  Frames of more than 128 rows (two tiles per wave: long projection
+// workgroups) take 32 in front and the x-DFT columns last, smaller ones none in front and the
+// x-DFT columns before the display rows.
+constexpr int stage2_order(int s0, int s1, int s2, int s3, int s4) {
+  return s0 | s1 << 3 | s2 << 6 | s3 << 9 | s4 << 12;
+}
+constexpr int kStage2LongProj = stage2_order(0, 2, 3, 4, 1), kStage2ShortProj = stage2_order(0, 2, 3, 1, 4);
+constexpr int kStage2FrontLong = 32;
 
-template <int PREC>
+template <int PREC, bool LONG_PROJ>
 __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_row_fused_obj_next2(
     int kpad, RowSet rs, int nrows, float tscale, int sx, int sy, const int4* __restrict__ chunks,
     const int2* __restrict__ jv, const float2* __restrict__ w, float2* __restrict__ d, float2* __restrict__ dlo,
@@ -1792,12 +1800,14 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
   extern __shared__ float4 fsm[];
   const int b = (int)blockIdx.x;
   const int nproj = pa.n > 0 ? pa.n + (pa.up_words > 0 ? 1 : 0) : 0;
-  // the grid's segments in kStage2Order: front projections, x-DFT columns, chunks, the other
-  // projections, display rows
+  // the grid's segments, in the order for LONG_PROJ (a compile-time order: measured 0.2-0.5 us
+  // per launch faster than the same order read from an argument): front projections, x-DFT
+  // columns, chunks, the other projections, display rows
+  constexpr int sorder = LONG_PROJ ? kStage2LongProj : kStage2ShortProj;
   const int len[5] = {pfront, xa.ncols, nchunks, nproj - pfront, (int)gridDim.x - xa.ncols - nchunks - nproj};
   int seg = 0, off = b;
   for (int k = 0; k < 5; ++k) {
-    seg = kStage2Order[k];
+    seg = (sorder >> (3 * k)) & 7;
     if (off < len[seg]) break;
     off -= len[seg];
   }
@@ -2579,7 +2589,8 @@ hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, co
   }
   if (lds > kLdsBytes) return hipErrorInvalidValue;
   const int nproj = nproj_frames > 0 ? nproj_frames + (pa.up_words > 0 ? 1 : 0) : 0;
-  const int pfront = std::min(kNextProjFront, nproj) / 8 * 8;
+  const bool long_proj = next && next->ny > 16 * kNextWaves;
+  const int pfront = long_proj ? std::min(kStage2FrontLong, nproj) / 8 * 8 : 0;
   const int total = nproj + xp.ncols + nchunks + rows_disp;
   if (total < 1) return hipSuccess;
   NextArgs xa;
@@ -2595,11 +2606,17 @@ hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, co
   xa.tout = xp.tout;
   hipError_t e;
   const dim3 grid(total), block(kFusedThreads);
+#define WDD_LAUNCH2(P, O)                                                                                       \
+  if ((e = allow_full_lds<k_row_fused_obj_next2<P, O>>()) != hipSuccess) return e;                              \
+  hipLaunchKernelGGL((k_row_fused_obj_next2<P, O>), grid, block, lds, st, kpad, urows, unrows, tscale, sx, sy,   \
+                     chunks, jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, d0out, nchunks, tin,              \
+                     row_fused_t_stride(kpad), xa, da, pa, pfront)
 #define WDD_LAUNCH(P)                                                                                           \
-  if ((e = allow_full_lds<k_row_fused_obj_next2<P>>()) != hipSuccess) return e;                                 \
-  hipLaunchKernelGGL(k_row_fused_obj_next2<P>, grid, block, lds, st, kpad, urows, unrows, tscale, sx, sy, chunks, \
-                     jv, w, d, dlo, z, max_chunk, up, nslot, log2sy, d0out, nchunks, tin,                      \
-                     row_fused_t_stride(kpad), xa, da, pa, pfront);                                              \
+  if (long_proj) {                                                                                              \
+    WDD_LAUNCH2(P, true);                                                                                       \
+  } else {                                                                                                      \
+    WDD_LAUNCH2(P, false);                                                                                      \
+  }                                                                                                             \
   break
   switch (precision) {
     case WDD_FP32: WDD_LAUNCH(WDD_FP32);
@@ -2609,6 +2626,7 @@ hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, co
     case WDD_FP16: WDD_LAUNCH(WDD_FP16);
     default: return hipErrorInvalidValue;
   }
+#undef WDD_LAUNCH2
 #undef WDD_LAUNCH
   return hipGetLastError();
 }
