@@ -1153,7 +1153,22 @@ struct DispArgs {
   const float2* d0;
   float s_total;
   int in_sr, in_sm, out_sr, out_sc, nslot, slot_stride;
+  int rows;  // output rows (the fused update launches)
 };
+
+// Rows of the previous image's column pass in the fused update launches, two per 512-thread
+// workgroup: each half takes one output row with its own LDS ([len] data, [len / 2] twiddles),
+// so the display holds half as many workgroup slots as with a row per workgroup, for the same
+// per-row time (a row's len / 2 butterflies per stage need no more than 256 threads).  An odd
+// last row is taken by both halves, which write the same values.
+static_assert(kFusedThreads == 512, "two 256-thread halves per display workgroup");
+__device__ __forceinline__ void display_row_pair(const DispArgs& d, int pair, float4* fsm, int tid) {
+  const int half = tid >> 8;
+  const int r = min(2 * pair + half, d.rows - 1);
+  float2* lbuf = reinterpret_cast<float2*>(fsm) + half * (d.len + d.len / 2);
+  display_row_partials(d.din, d.dout, d.len, d.log2len, d.e, d.d0, d.s_total, d.in_sr, d.in_sm, d.out_sr, d.out_sc,
+                       d.nslot, d.slot_stride, r, lbuf, tid & 255, 256);
+}
 
 // One launch for independent jobs: workgroups b < n project frame b of a batch, workgroup n
 // copies the upload block (when there is one), and the rest each write one output row of
@@ -1655,10 +1670,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_row_fused_obj(const float* __
                                                                  int nchunks, DispArgs disp) {
   extern __shared__ float4 fsm[];
   const int b = (int)blockIdx.x;
-  if (b >= nchunks) {  // a row of the previous step's image, left to this launch (see launch_row_fused_obj)
-    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
-                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nchunks,
-                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+  if (b >= nchunks) {  // two rows of the previous step's image, left to this launch (see launch_row_fused_obj)
+    display_row_pair(disp, b - nchunks, fsm, (int)threadIdx.x);
     return;
   }
   // consecutive chunks (the same or neighbouring v_x, whose z entries and display partials
@@ -1746,9 +1759,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
     return;
   }
   if (b >= nproj + nchunks) {
-    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
-                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, b - nproj - nchunks,
-                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+    display_row_pair(disp, b - nproj - nchunks, fsm, (int)threadIdx.x);
     return;
   }
   // (pfront is a multiple of 8: the chunks keep the XCDs of k_row_fused_obj's mapping)
@@ -1820,9 +1831,7 @@ __global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(6
     return;
   }
   if (seg == 4) {
-    display_row_partials(disp.din, disp.dout, disp.len, disp.log2len, disp.e, disp.d0, disp.s_total, disp.in_sr,
-                         disp.in_sm, disp.out_sr, disp.out_sc, disp.nslot, disp.slot_stride, off,
-                         reinterpret_cast<float2*>(fsm), (int)threadIdx.x, kFusedThreads);
+    display_row_pair(disp, off, fsm, (int)threadIdx.x);
     return;
   }
   if (seg == 1) {  // the x-DFT of one kept v_x of batch i - 1
@@ -2454,8 +2463,9 @@ hipError_t fused_setup(int kpad, int nrows, int sy, int nchunks, int max_chunk, 
     da.out_sc = dc->out_sc;
     da.nslot = dc->nslot;
     da.slot_stride = dc->slot_stride;
-    fs->rows_disp = dc->rows;
-    fs->lds = std::max(fs->lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
+    da.rows = dc->rows;
+    fs->rows_disp = (dc->rows + 1) / 2;  // two rows per workgroup (display_row_pair)
+    fs->lds = std::max(fs->lds, (size_t)dc->len * sizeof(float2) * 3);
   }
   if (fs->lds > kLdsBytes) return hipErrorInvalidValue;
   return hipSuccess;
@@ -2576,8 +2586,9 @@ hipError_t launch_row_fused_obj_next2(int kpad, float tscale, int sx, int sy, co
     da.out_sc = dc->out_sc;
     da.nslot = dc->nslot;
     da.slot_stride = dc->slot_stride;
-    rows_disp = dc->rows;
-    lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3 / 2);
+    da.rows = dc->rows;
+    rows_disp = (dc->rows + 1) / 2;  // two rows per workgroup (display_row_pair)
+    lds = std::max(lds, (size_t)dc->len * sizeof(float2) * 3);
   }
   ProjArgs pa;
   std::memset(&pa, 0, sizeof(pa));
