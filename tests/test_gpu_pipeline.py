@@ -179,3 +179,34 @@ def test_pipelined_host_frames_and_ragged_batches(stages):
             assert same_image(outs[True][i], outs[False][i], stages), i
         assert np.array_equal(p.spectrum(), r.spectrum())
         assert p.info().frames_seen == r.info().frames_seen == sum(sizes)
+
+
+@pytest.mark.parametrize("stages", [1, 2])
+@pytest.mark.parametrize("sy,sx", [(1, 1), (1, 8), (2, 4), (4, 16)])
+def test_deferred_images_on_short_scan_columns(sy, sx, stages):
+    """Deferred images of pipelined plans, whose column pass rides in the update launches with
+    two output rows per workgroup: a one-row scan (an odd row count: both halves of the
+    workgroup take the row), two and four rows; each image against the oracle."""
+    import torch
+    n, k = 32, 16
+    b = 3 * sy * sx
+    rng = np.random.default_rng(700 + 64 * sy + sx + stages)
+    lin = rng.integers(0, sy * sx, size=2 * b)
+    pos = np.stack([lin // sx, lin % sx], axis=1).astype(np.int32)
+    frames = rng.poisson(15.0, size=(2 * b, n, n)).astype(np.uint16)
+    dev = device(frames)
+    say(f"[pipeline] {stages} stage(s), deferred images on a {sy}x{sx} scan")
+    outs = [torch.full((sy, sx), float("nan"), dtype=torch.complex64, device="cuda") for _ in range(2)]
+    with wdd.Plan(4.0, sy, sx, n, n, k, max_batch=b, order=wdd.WDD_ORDER_OBJECT, pipeline=stages) as p:
+        for i in range(2):
+            p.push_snapshot(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b], out=outs[i], wait=False, defer=True)
+        p.sync()
+    oplan = O.make_plan(sy, sx, n, n, 4.0, k)
+    for i in range(2):
+        live = O.Live(oplan, "P")
+        live.push(frames[:(i + 1) * b], pos[:(i + 1) * b])
+        got = outs[i].cpu().numpy()
+        assert np.isfinite(got).all(), i
+        err = rel_img(got, live.snapshot())
+        say(f"[pipeline] image {i}: {err:.2e}")
+        assert err <= TOL
