@@ -619,7 +619,10 @@ def main():
                    "batch": wl.batch, "k": k, "n_freq": n_freq, "frames_dtype": str(frames.dtype),
                    "wiener_order": args.order, "basis": args.basis, "pipelined": pipelined,
                    "pipeline_stages": pipe_stages,
-                   "display": "hbm" + ((", each batch's update in the next push's launch (with that push's "
+                   "display": "hbm" + ((", each batch's x-DFT in the next push's launch and its update in the "
+                                        "one after (beside those pushes' projections), each image's last pass in "
+                                        "the launch after that" if pipe_stages == 2 else
+                                        ", each batch's update in the next push's launch (with that push's "
                                         "projection), each image's last pass in the launch after" if pipelined else
                                         ", each image's last pass deferred to the next push's first launch "
                                         "(its projection for detectors of <= 128 rows, else its first update; "
