@@ -15,10 +15,11 @@ TOL = 1e-5
 TOL_H = 1e-6
 
 
-def _plan_for(wl, max_batch=None, order=wdd.WDD_ORDER_SPECTRUM):
+def _plan_for(wl, max_batch=None, order=wdd.WDD_ORDER_SPECTRUM, pipeline=0):
     dtype = wdd.WDD_F32 if wl.dose is None else wdd.WDD_U16
     return wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=dtype, defocus=wl.defocus_edge,
-                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=max_batch or wl.batch, order=order)
+                    amplitude=wl.aperture_amplitude(), step=wl.step, max_batch=max_batch or wl.batch, order=order,
+                    pipeline=pipeline)
 
 
 @pytest.mark.parametrize("name", ["small", "medium"])
@@ -47,29 +48,41 @@ def test_full_raster_every_result(name):
     assert errs["A"] <= TOL and errs["D"] <= TOL and errs["O"] <= TOL
 
 
-def _sampled_case(name, n_frames, n_sample, seed, order=wdd.WDD_ORDER_SPECTRUM):
+def _sampled_case(name, n_frames, n_sample, seed, order=wdd.WDD_ORDER_SPECTRUM, pipeline=0):
     """Full-size geometry and launch configuration; n_frames frames at random raster
     positions; A and D compared on a random sample of kept frequencies.  In object order
     every batch goes through push_snapshot, as the bench drives it (the update then also
     performs the display's first pass), and the image must be the unitary inverse DFT of
     the plan's own D, normalised by |D[0]| (a property at any size), as well as satisfy
-    Parseval."""
+    Parseval.  With pipeline set (the bench's form), the frames follow the raster from a
+    random row, and every image is deferred into one device buffer."""
+    import torch
     wl = synth.WORKLOADS[name]
     g = golden_workload(name)
     rng = np.random.default_rng(seed)
-    lin = rng.choice(wl.sy * wl.sx, size=n_frames, replace=False)
+    if pipeline:
+        lin = (int(rng.integers(0, wl.sy)) * wl.sx + np.arange(n_frames)) % (wl.sy * wl.sx)
+    else:
+        lin = rng.choice(wl.sy * wl.sx, size=n_frames, replace=False)
     pos = np.stack([lin // wl.sx, lin % wl.sx], axis=1).astype(np.int32)
-    say(f"[parity] {name} sampled: {n_frames} frames of {wl.n}x{wl.n}, batch {wl.batch}")
+    say(f"[parity] {name} sampled: {n_frames} frames of {wl.n}x{wl.n}, batch {wl.batch}, pipeline {pipeline}")
     frames = wl.frames(pos)
     dev = device(frames)
     obj = order == wdd.WDD_ORDER_OBJECT
-    with _plan_for(wl, order=order) as plan:
+    with _plan_for(wl, order=order, pipeline=pipeline) as plan:
         assert plan.n_freq == g["n_freq"]
+        assert plan.info().pipelined == pipeline
+        shown = torch.empty((wl.sy, wl.sx), dtype=torch.complex64, device="cuda")
         for b in range(0, n_frames, wl.batch):
-            if obj:
+            if obj and pipeline:
+                plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch], out=shown, wait=False, defer=True)
+            elif obj:
                 got_o = plan.push_snapshot(dev[b:b + wl.batch], pos[b:b + wl.batch])
             else:
                 plan.push(dev[b:b + wl.batch], pos[b:b + wl.batch])
+        if pipeline:
+            plan.sync()
+            got_o = shown.cpu().numpy()
         if not obj:
             got_o = plan.snapshot()
         got_h = plan.projection()
@@ -111,3 +124,11 @@ def test_defocus_workload_sampled():
 @pytest.mark.parametrize("name,n_frames", [("large", 1024), ("defocus", 2048)])
 def test_object_order_full_size_sampled(name, n_frames):
     _sampled_case(name, n_frames, 256, 43, order=wdd.WDD_ORDER_OBJECT)
+
+
+@pytest.mark.parametrize("name,n_frames", [("large", 1024), ("defocus", 2048), ("medium", 1024)])
+def test_two_stage_full_size_sampled(name, n_frames):
+    """The bench's launch configuration: two pipeline stages (the update's grid order for
+    frames of more than 128 rows on the large workload, the other order below), raster
+    batches, each image deferred into HBM."""
+    _sampled_case(name, n_frames, 256, 44, order=wdd.WDD_ORDER_OBJECT, pipeline=2)
