@@ -54,6 +54,25 @@ def test_projection_precision_against_oracle(defocus_case, mode):
     assert max(errs.values()) <= BOUNDS[mode]
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16_hilo", "fp16_hilo"])
+def test_two_stage_precision_against_oracle(defocus_case, mode):
+    """The bench's precision lines run object order with two pipeline stages: D against the
+    FP64 oracle within the mode's bound (the first, raster batch held and pipelined, the
+    scattered ones, on more than 16 scan rows, unpipelined after it)."""
+    wl, pos, frames, pick, h, a, d = defocus_case
+    dev = device(frames)
+    with wdd.Plan(wl.radius, wl.sy, wl.sx, wl.n, wl.n, wl.k, dtype=wdd.WDD_U16, defocus=wl.defocus_edge,
+                  amplitude=wl.aperture_amplitude(), max_batch=wl.batch, precision=mode,
+                  order=wdd.WDD_ORDER_OBJECT, pipeline=2) as plan:
+        assert plan.info().pipelined == 2
+        for b in range(0, len(pos), wl.batch):
+            plan.push(dev[b:b + wl.batch], pos[b:b + wl.batch])
+        got_d = plan.spectrum()[pick]
+    err = rel_d(got_d, d)
+    say(f"[precision] {mode}, two pipeline stages: D {err:.2e}")
+    assert err <= BOUNDS[mode]
+
+
 # Full-range counts (up to 65535) through one-hot frames: every coefficient is
 # count * psi_y * psi_x at one pixel, including pixels in the basis tails where the
 # 16-bit parts of psi_x lose precision (FP16 flushes values below 6e-8).  The error of a
