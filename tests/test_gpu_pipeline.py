@@ -210,3 +210,32 @@ def test_deferred_images_on_short_scan_columns(sy, sx, stages):
         err = rel_img(got, live.snapshot())
         say(f"[pipeline] image {i}: {err:.2e}")
         assert err <= TOL
+
+
+@pytest.mark.parametrize("stages", [1, 2])
+def test_batches_on_few_rows_out_of_row_order(stages):
+    """Batches whose frames alternate between a few scan rows (held, but not in row order:
+    the update and the x-DFT read the projections through the batch's row grouping): D bit
+    for bit the unpipelined plan's, the images as in the first test."""
+    import torch
+    s, n, b, steps = 32, 64, 48, 6
+    rng = np.random.default_rng(31 + stages)
+    rows = [rng.choice(s, size=int(rng.integers(2, 5)), replace=False) for _ in range(steps)]
+    pos = np.concatenate([np.stack([r[rng.integers(0, len(r), size=b)], rng.integers(0, s, size=b)], axis=1)
+                          for r in rows]).astype(np.int32)
+    frames = rng.poisson(20.0, size=(b * steps, n, n)).astype(np.uint16)
+    dev = device(frames)
+    say(f"[pipeline] {stages} stage(s), batches on 2..4 rows out of row order")
+    outs = {True: [], False: []}
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=stages, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        for i in range(steps):
+            for q, key in ((p, True), (r, False)):
+                out = torch.empty((s, s), dtype=torch.complex64, device="cuda")
+                q.push_snapshot(dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b], out=out, wait=False, defer=True)
+                outs[key].append(out)
+        p.sync()
+        r.sync()
+        for i in range(steps):
+            assert same_image(outs[True][i], outs[False][i], stages), i
+        assert np.array_equal(p.spectrum(), r.spectrum())
