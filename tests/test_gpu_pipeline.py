@@ -239,3 +239,29 @@ def test_batches_on_few_rows_out_of_row_order(stages):
         for i in range(steps):
             assert same_image(outs[True][i], outs[False][i], stages), i
         assert np.array_equal(p.spectrum(), r.spectrum())
+
+
+@pytest.mark.parametrize("stages", [1, 2])
+def test_restore_while_batches_are_held(stages):
+    """A checkpoint restored into a pipelined plan that holds batches: the held updates run
+    first and are then replaced by the image, so the plan continues exactly as an
+    unpipelined plan given the same calls (D bit for bit, frame count)."""
+    s, n, b = 32, 64, 64
+    frames, pos = _case(41 + stages, s, n, b * 6, raster=True)
+    dev = device(frames)
+    blk = lambda i: (dev[i * b:(i + 1) * b], pos[i * b:(i + 1) * b])
+    kw = dict(max_batch=b, order=wdd.WDD_ORDER_OBJECT)
+    with wdd.Plan(8.0, s, s, n, n, 64, pipeline=stages, **kw) as p, wdd.Plan(8.0, s, s, n, n, 64, **kw) as r:
+        for q in (p, r):
+            q.push(*blk(0))
+        image = r.checkpoint()
+        for i in (1, 2):
+            for q in (p, r):
+                q.push(*blk(i))
+        for q in (p, r):           # p still holds batches 1 (and 2) here
+            q.restore(image)
+        for i in (3, 4, 5):
+            for q in (p, r):
+                q.push(*blk(i))
+        assert np.array_equal(p.spectrum(), r.spectrum())
+        assert p.info().frames_seen == r.info().frames_seen == 4 * b
